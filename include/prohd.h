@@ -1,0 +1,224 @@
+/*
+ * prohd.h -- C ABI of the MI355X (gfx950) ProHD hot path.
+ *
+ * ProHD (projection-based Hausdorff approximation, arXiv 2511.18207) keeps,
+ * for each of a few directions -- the centroid axis and the top principal
+ * components of the union of the two sets -- the points of each set whose
+ * projections are extreme, and computes the Hausdorff distance of the two
+ * kept subsets.  This library runs every step of that path, and the exact
+ * brute-force distance it approximates, as HIP kernels on one GPU:
+ *
+ *   prohd_project  centroid axis + top-m principal directions, projections
+ *                  (paper Alg. 1 centroid/axis/projection steps, Alg. 2
+ *                  stacking/PCA/normalisation/projection steps)
+ *   prohd_select   per-direction k smallest / k largest, union, unique
+ *                  (Alg. 1 and Alg. 2 argsort/extreme/union steps, Alg. 3
+ *                  union of the two index sets)
+ *   prohd_hd       directed and symmetric Hausdorff distance over the
+ *                  selected rows (Sec. II-A definition of H-hat, Alg. 3
+ *                  subset extraction and distance steps)
+ *   exact_hd       exact Hausdorff distance, Eq. (1)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Point sets are DEVICE pointers to row-major float32 arrays, n rows of
+ *    D floats, row stride D, 4-byte aligned (16-byte aligned is faster).
+ *    1 <= D <= PROHD_MAX_DIM.  Row counts are < 2^31.
+ *  - All device pointers are owned by the caller.  The library never frees
+ *    or retains them, and allocates no device memory: every scratch byte
+ *    comes from the caller's workspace `ws` (device memory, 256-byte
+ *    aligned, at least prohd_workspace_size() bytes).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *    the default stream).  Calls that share a workspace must be ordered on
+ *    one stream.  Distinct streams with distinct workspaces may run
+ *    concurrently from different host threads.
+ *  - Host-side argument errors are returned before anything is enqueued.
+ *    Errors found on the device (non-finite input) are written to the
+ *    `status` field of a prohd_result and, when PROHD_SYNC is set, the call
+ *    waits for the stream and returns that status.
+ *  - On any non-OK return, prohd_last_error() gives a message (per host
+ *    thread).
+ *  - Distances are Euclidean (not squared).  Index outputs are 0-based
+ *    int32, ascending and unique.  Witness indices refer to rows of the
+ *    ORIGINAL A and B.
+ */
+#ifndef PROHD_H
+#define PROHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PROHD_MAX_DIM 256
+#define PROHD_MAX_DIRS 64
+
+typedef enum {
+  PROHD_OK = 0,
+  PROHD_EINVAL = 1,       /* bad argument: NULL pointer, size, k, flag      */
+  PROHD_ENONFINITE = 2,   /* NaN or Inf found in an input set (device)      */
+  PROHD_EWORKSPACE = 3,   /* ws_bytes below the size the call needs         */
+  PROHD_EDEVICE = 4,      /* a HIP runtime call failed                      */
+  PROHD_EUNSUPPORTED = 5  /* D > PROHD_MAX_DIM or ndirs > PROHD_MAX_DIRS    */
+} prohd_status;
+
+/* Flags (bitwise OR). */
+enum {
+  PROHD_DIRS_GIVEN = 1u << 0, /* prohd_project: `dirs` is an input          */
+  PROHD_INNER_FULL = 1u << 1, /* prohd_hd: inner minimum over the whole other
+                                 set: max{h(A_sel,B), h(B_sel,A)} <= H(A,B)  */
+  PROHD_SYNC = 1u << 4        /* wait for the stream; return device status  */
+};
+
+/* Result of prohd_hd / exact_hd, written by the device into caller memory. */
+typedef struct {
+  double H;        /* max(hAB, hBA)                                          */
+  double hAB;      /* directed distance from (selected) A to (selected) B    */
+  double hBA;      /* directed distance from (selected) B to (selected) A    */
+  int64_t ab_a;    /* row of A realising hAB                                 */
+  int64_t ab_b;    /* its nearest row of B                                   */
+  int64_t ba_b;    /* row of B realising hBA                                 */
+  int64_t ba_a;    /* its nearest row of A                                   */
+  int64_t nA_sel;  /* rows of A taken part (nA for exact_hd)                 */
+  int64_t nB_sel;  /* rows of B taken part (nB for exact_hd)                 */
+  int32_t status;  /* prohd_status of the device-side work                   */
+  int32_t refined; /* rows re-measured per direction by the refinement pass  */
+} prohd_result;
+
+/*
+ * Bytes of workspace that any entry point needs for sets of nA and nB rows
+ * in dimension D with `ndirs` directions (m+1) and selection capacities
+ * capA / capB (0 lets the library use nA / nB).  Pure host function.
+ * Returns 0 for invalid sizes.
+ */
+size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs,
+                            int64_t capA, int64_t capB);
+
+/*
+ * prohd_project -- directions and projections.
+ *
+ * Computes, unless PROHD_DIRS_GIVEN is set:
+ *   dirs row 0   : the centroid axis u = (mean(B) - mean(A)) / ||.||, or the
+ *                  first basis vector e_1 when ||mean(B) - mean(A)|| < 1e-9
+ *                  (Alg. 1, axis step, with X = A and Y = B as Alg. 3 calls
+ *                  it);
+ *   dirs rows 1..m: the m principal components of the stacked union [A; B]
+ *                  (eigenvectors of its centred covariance, largest
+ *                  eigenvalue first), unit length, sign fixed so the
+ *                  largest-magnitude entry is positive (Alg. 2, PCA and
+ *                  normalisation steps).
+ * Means, covariance and eigensolve are float64 on the device.
+ * Then projA[d*nA + i] = A_i . dirs_d and projB[d*nB + j] = B_j . dirs_d
+ * (float32; Alg. 1 and Alg. 2 projection steps), for d = 0..m.
+ *
+ *   A, B     device float32, nA x D and nB x D
+ *   m        number of principal directions, 1 <= m <= D, m + 1 <= PROHD_MAX_DIRS
+ *   dirs     device float32, (m+1) x D row-major: output, or input when
+ *            PROHD_DIRS_GIVEN (rows are then used as given)
+ *   projA    device float32, (m+1) x nA (direction-major), output
+ *   projB    device float32, (m+1) x nB, output
+ *   evals    device float64, D entries, output (descending covariance
+ *            eigenvalues), or NULL; untouched when PROHD_DIRS_GIVEN
+ *   status   device int32, output: PROHD_OK or PROHD_ENONFINITE
+ *            (NaN/Inf in A or B), or NULL
+ * Errors: EINVAL (NULL, n < 1, m out of range), EUNSUPPORTED (D too large),
+ * EWORKSPACE, EDEVICE.
+ */
+prohd_status prohd_project(const float* A, int64_t nA, const float* B, int64_t nB,
+                           int32_t D, int32_t m, uint32_t flags, float* dirs,
+                           float* projA, float* projB, double* evals,
+                           int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * prohd_select -- extreme-candidate selection and union.
+ *
+ * For every direction d (0 <= d < ndirs) and each set, keeps the kA[d]
+ * (resp. kB[d]) smallest and the same number of largest projections, under
+ * the total order (value, index): ties go to the smaller index at BOTH ends;
+ * -0.0 equals +0.0.  k is clipped to the set size.  The kept indices of all
+ * directions and both ends are unioned into ascending unique lists
+ * (Alg. 1 and Alg. 2 extreme steps, Alg. 3 union step).
+ *
+ *   projA    device float32, ndirs x nA (as written by prohd_project)
+ *   projB    device float32, ndirs x nB
+ *   kA, kB   HOST int32 arrays of ndirs entries, each >= 1
+ *   idxA     device int32, capacity capA: output, ascending unique rows of A
+ *   nselA    device int64: output, number of entries written to idxA
+ *   idxB, capB, nselB: the same for B
+ * capA must be >= min(nA, sum_d 2*min(kA[d], nA)) (so the list cannot
+ * overflow); likewise capB.  Projections must be finite.
+ * Errors: EINVAL, EUNSUPPORTED (ndirs > PROHD_MAX_DIRS), EWORKSPACE, EDEVICE.
+ */
+prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, int64_t nB,
+                          int32_t ndirs, const int32_t* kA, const int32_t* kB,
+                          int32_t* idxA, int64_t capA, int64_t* nselA,
+                          int32_t* idxB, int64_t capB, int64_t* nselB,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * prohd_hd -- Hausdorff distance over the selected rows.
+ *
+ * Default: H-hat = max{ max_{a in A_sel} min_{b in B_sel} ||a-b||,
+ *                       max_{b in B_sel} min_{a in A_sel} ||b-a|| }
+ * (Sec. II-A definition of H-hat; Alg. 3 extraction and distance steps).
+ * With PROHD_INNER_FULL: max{ h(A_sel, B), h(B_sel, A) } (inner minimum
+ * over the whole other set), which never exceeds H(A,B).
+ *
+ * Distances are searched with float32 matrix-core tiles of
+ * |a|^2 + |b|^2 - 2 a.b on rows shifted by a common point; the rows with
+ * the largest approximate minima (up to 256 per direction) are re-measured
+ * against every inner row by float32 direct differences, and the final
+ * witness pair in float64.
+ *
+ *   A, B            device float32 point sets (nA x D, nB x D)
+ *   idxA, nselA     device: selected rows of A (ascending int32) and their
+ *                   count (int64), as written by prohd_select; likewise B
+ *   capA, capB      host: upper bounds of *nselA / *nselB (grid sizing);
+ *                   the device counts must not exceed them
+ *   out             device prohd_result, output
+ * Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE; with PROHD_SYNC the
+ * device status (ENONFINITE, or EINVAL for an empty selection).
+ */
+prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      const int32_t* idxA, const int64_t* nselA,
+                      const int32_t* idxB, const int64_t* nselB,
+                      int64_t capA, int64_t capB, uint32_t flags,
+                      prohd_result* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * exact_hd -- exact Hausdorff distance H(A,B) of Eq. (1), both directed
+ * parts and witnesses, by brute force over all nA x nB pairs (float32
+ * matrix-core tiles + refinement as in prohd_hd).
+ *
+ *   nn2A   device float32, nA entries, or NULL: per row of A the squared
+ *          distance to its nearest row of B, as found by the float32 tile
+ *          search (before refinement); likewise nn2B (nB entries).
+ * Errors: as prohd_hd.
+ */
+prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      uint32_t flags, prohd_result* out, float* nn2A, float* nn2B,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Message of the last non-OK return on this host thread ("" if none). */
+const char* prohd_last_error(void);
+
+/* Library version string. */
+const char* prohd_version(void);
+
+/*
+ * Kernel timing (host).  While enabled, every kernel the library launches
+ * is bracketed by HIP events on the stream it runs on.  prohd_profile_read
+ * waits for those events and returns, for kernels whose name contains
+ * `name`, the number of launches and their summed duration in ms since the
+ * last reset.  Returns PROHD_OK or EINVAL / EDEVICE.
+ */
+prohd_status prohd_profile_enable(int32_t on);
+prohd_status prohd_profile_reset(void);
+prohd_status prohd_profile_read(const char* name, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROHD_H */

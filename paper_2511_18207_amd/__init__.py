@@ -1,0 +1,30 @@
+"""ProHD hot path on MI355X (gfx950): thin Python binding over libprohd.so.
+
+The C ABI (include/prohd.h) does all the work in HIP kernels; this module only
+marshals torch tensors (device memory, the current HIP stream) into pointers
+and sizes.  It raises when the native library is missing -- there is no
+fallback path.
+"""
+
+from ._lib import (  # noqa: F401
+    ProhdError,
+    Workspace,
+    lib,
+    library_path,
+    workspace_size,
+    prohd_project,
+    prohd_select,
+    prohd_hd,
+    exact_hd,
+    prohd,
+    decode_result,
+    RESULT_BYTES,
+    k_rule,
+    profile_enable,
+    profile_reset,
+    profile_read,
+    version,
+    DIRS_GIVEN,
+    INNER_FULL,
+    SYNC,
+)

@@ -1,0 +1,287 @@
+"""ctypes binding of libprohd.so (see include/prohd.h for the contract).
+
+Argument marshalling only: tensors become device pointers, the current torch
+stream becomes the hipStream_t, host integer lists become int32 arrays.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+DIRS_GIVEN = 1 << 0
+INNER_FULL = 1 << 1
+SYNC = 1 << 4
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENONFINITE", 3: "EWORKSPACE", 4: "EDEVICE", 5: "EUNSUPPORTED"}
+
+# prohd_result, as laid out by the C struct
+RESULT_DTYPE = np.dtype([
+    ("H", "<f8"), ("hAB", "<f8"), ("hBA", "<f8"),
+    ("ab_a", "<i8"), ("ab_b", "<i8"), ("ba_b", "<i8"), ("ba_a", "<i8"),
+    ("nA_sel", "<i8"), ("nB_sel", "<i8"),
+    ("status", "<i4"), ("refined", "<i4"),
+])
+RESULT_BYTES = RESULT_DTYPE.itemsize
+
+
+class ProhdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libprohd.so")
+
+
+def lib() -> C.CDLL:
+    """Load libprohd.so (built in-tree).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ProhdError(5, f"{path} is missing: build it with "
+                            "`python -m paper_2511_18207_amd.build`")
+    L = C.CDLL(path)
+    i64, i32, u32, vp, sz = C.c_int64, C.c_int32, C.c_uint32, C.c_void_p, C.c_size_t
+    L.prohd_workspace_size.restype = sz
+    L.prohd_workspace_size.argtypes = [i64, i64, i32, i32, i64, i64]
+    L.prohd_project.restype = C.c_int
+    L.prohd_project.argtypes = [vp, i64, vp, i64, i32, i32, u32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.prohd_select.restype = C.c_int
+    L.prohd_select.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, i64, vp, vp, i64, vp, vp, sz, vp]
+    L.prohd_hd.restype = C.c_int
+    L.prohd_hd.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, vp, i64, i64, u32, vp, vp, sz, vp]
+    L.exact_hd.restype = C.c_int
+    L.exact_hd.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp, sz, vp]
+    L.prohd_last_error.restype = C.c_char_p
+    L.prohd_last_error.argtypes = []
+    L.prohd_version.restype = C.c_char_p
+    L.prohd_version.argtypes = []
+    L.prohd_profile_enable.restype = C.c_int
+    L.prohd_profile_enable.argtypes = [i32]
+    L.prohd_profile_reset.restype = C.c_int
+    L.prohd_profile_reset.argtypes = []
+    L.prohd_profile_read.restype = C.c_int
+    L.prohd_profile_read.argtypes = [C.c_char_p, C.POINTER(i64), C.POINTER(C.c_double)]
+    _LIB = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise ProhdError(code, lib().prohd_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _f32_2d(X, name):
+    torch = _torch()
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous 2-D float32 tensor")
+    return X
+
+
+def version() -> str:
+    return lib().prohd_version().decode()
+
+
+def workspace_size(nA, nB, D, ndirs=1, capA=0, capB=0) -> int:
+    return int(lib().prohd_workspace_size(nA, nB, D, ndirs, capA, capB))
+
+
+class Workspace:
+    """A device byte buffer reused across calls (grown on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_DEFAULT_WS = {}
+
+
+def _ws(ws, nbytes):
+    if ws is None:
+        dev = _torch().cuda.current_device()
+        ws = _DEFAULT_WS.setdefault(dev, Workspace(f"cuda:{dev}"))
+    buf = ws.get(nbytes)
+    return buf, buf.numel()
+
+
+def decode_result(res_dev) -> dict:
+    """Device prohd_result bytes (uint8 tensor) -> dict (synchronises)."""
+    arr = np.frombuffer(res_dev.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[0]
+    return {k: arr[k].item() for k in RESULT_DTYPE.names}
+
+
+def prohd_project(A, B, m, dirs=None, sync=False, ws=None, evals=True):
+    """Directions (row 0 centroid axis, rows 1..m principal components) and
+    projections of both sets.  With ``dirs`` given, uses them as is.
+    Returns ``(dirs, projA, projB, evals, status)`` (device tensors)."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[0]
+    flags = SYNC if sync else 0
+    if dirs is None:
+        dirs = torch.empty((m + 1, D), dtype=torch.float32, device=A.device)
+    else:
+        dirs = _f32_2d(dirs, "dirs")
+        if dirs.shape != (m + 1, D):
+            raise ValueError("dirs must be (m+1) x D")
+        flags |= DIRS_GIVEN
+    projA = torch.empty((m + 1, nA), dtype=torch.float32, device=A.device)
+    projB = torch.empty((m + 1, nB), dtype=torch.float32, device=A.device)
+    ev = torch.empty(D, dtype=torch.float64, device=A.device) if evals else None
+    status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    buf, nbytes = _ws(ws, workspace_size(nA, nB, D, m + 1))
+    _check(lib().prohd_project(A.data_ptr(), nA, B.data_ptr(), nB, D, m, flags, dirs.data_ptr(),
+                               projA.data_ptr(), projB.data_ptr(), _ptr(ev), status.data_ptr(),
+                               buf.data_ptr(), nbytes, _stream()))
+    return dirs, projA, projB, ev, status
+
+
+def prohd_select(projA, projB, kA, kB, capA=None, capB=None, ws=None):
+    """Union of per-direction extremes.  ``kA``/``kB``: one k per direction.
+    Returns ``(idxA, nselA, idxB, nselB)``; idx tensors have capacity length,
+    the device counts say how many entries are valid."""
+    torch = _torch()
+    ndirs, nA = projA.shape
+    nB = projB.shape[1]
+    kA = np.ascontiguousarray(kA, dtype=np.int32)
+    kB = np.ascontiguousarray(kB, dtype=np.int32)
+    if kA.size != ndirs or kB.size != ndirs:
+        raise ValueError("need one k per direction")
+    if capA is None:
+        capA = int(min(nA, 2 * np.minimum(kA.astype(np.int64), nA).sum()))
+    if capB is None:
+        capB = int(min(nB, 2 * np.minimum(kB.astype(np.int64), nB).sum()))
+    idxA = torch.empty(max(capA, 1), dtype=torch.int32, device=projA.device)
+    idxB = torch.empty(max(capB, 1), dtype=torch.int32, device=projA.device)
+    cnt = torch.zeros(2, dtype=torch.int64, device=projA.device)
+    D_dummy = 1
+    buf, nbytes = _ws(ws, workspace_size(nA, nB, D_dummy, ndirs))
+    _check(lib().prohd_select(projA.data_ptr(), nA, projB.data_ptr(), nB, ndirs,
+                              kA.ctypes.data, kB.ctypes.data, idxA.data_ptr(), capA,
+                              cnt.data_ptr(), idxB.data_ptr(), capB, cnt.data_ptr() + 8,
+                              buf.data_ptr(), nbytes, _stream()))
+    return idxA, cnt[0:1], idxB, cnt[1:2]
+
+
+def prohd_hd(A, B, idxA, nselA, idxB, nselB, capA=None, capB=None, inner_full=False,
+             sync=False, ws=None, out=None):
+    """Hausdorff distance over the selected rows.  Returns the device result
+    buffer (uint8[80]); decode with ``decode_result``."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[1 - 1]
+    capA = idxA.numel() if capA is None else capA
+    capB = idxB.numel() if capB is None else capB
+    flags = (INNER_FULL if inner_full else 0) | (SYNC if sync else 0)
+    if out is None:
+        out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    buf, nbytes = _ws(ws, workspace_size(nA, nB, D, 1, capA, capB))
+    _check(lib().prohd_hd(A.data_ptr(), nA, B.data_ptr(), nB, D, idxA.data_ptr(),
+                          nselA.data_ptr(), idxB.data_ptr(), nselB.data_ptr(), capA, capB, flags,
+                          out.data_ptr(), buf.data_ptr(), nbytes, _stream()))
+    return out
+
+
+def exact_hd(A, B, sync=False, ws=None, out=None, nn2=False):
+    """Exact Hausdorff distance.  Returns the device result buffer, and with
+    ``nn2=True`` also the per-row squared NN distance arrays."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[0]
+    if out is None:
+        out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    nnA = torch.empty(nA, dtype=torch.float32, device=A.device) if nn2 else None
+    nnB = torch.empty(nB, dtype=torch.float32, device=A.device) if nn2 else None
+    buf, nbytes = _ws(ws, workspace_size(nA, nB, D, 1))
+    _check(lib().exact_hd(A.data_ptr(), nA, B.data_ptr(), nB, D, SYNC if sync else 0,
+                          out.data_ptr(), _ptr(nnA), _ptr(nnB), buf.data_ptr(), nbytes,
+                          _stream()))
+    return (out, nnA, nnB) if nn2 else out
+
+
+def k_rule(alpha: float, n: int) -> int:
+    """k = max(1, floor(alpha * n)) per end (paper Alg. 1 / Alg. 2), <= n."""
+    return min(n, max(1, int(math.floor(alpha * n + 1e-9))))
+
+
+def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None):
+    """ProHD end to end on the device: project -> select -> hd.
+
+    alpha mode: m = floor(sqrt(D)), k = k_rule(alpha, n) on the centroid axis
+    and k_rule(alpha/m, n) per principal component.  explicit mode: ``k`` an
+    int (every direction end) or a list of m+1 ints.  Returns a dict with the
+    device tensors and the decoded result (one host synchronisation at the
+    end)."""
+    nA, D = A.shape
+    nB = B.shape[0]
+    if m is None:
+        m = math.isqrt(D) if dirs is None else dirs.shape[0] - 1
+    if k is None:
+        kA = [k_rule(alpha, nA)] + [k_rule(alpha / m, nA)] * m
+        kB = [k_rule(alpha, nB)] + [k_rule(alpha / m, nB)] * m
+    else:
+        ks = [int(k)] * (m + 1) if np.isscalar(k) else [int(x) for x in k]
+        kA = [min(max(1, x), nA) for x in ks]
+        kB = [min(max(1, x), nB) for x in ks]
+    d, pA, pB, ev, st = prohd_project(A, B, m, dirs=dirs, ws=ws)
+    idxA, nA_sel, idxB, nB_sel = prohd_select(pA, pB, kA, kB, ws=ws)
+    out = prohd_hd(A, B, idxA, nA_sel, idxB, nB_sel, inner_full=inner_full, ws=ws)
+    res = decode_result(out)
+    res.update({"dirs": d, "projA": pA, "projB": pB, "evals": ev, "project_status": st,
+                "idxA": idxA, "nselA": nA_sel, "idxB": idxB, "nselB": nB_sel,
+                "kA": kA, "kB": kB})
+    return res
+
+
+def profile_enable(on: bool = True):
+    _check(lib().prohd_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().prohd_profile_reset())
+
+
+def profile_read(name: str):
+    """(launches, total_ms) of kernels whose name contains ``name``."""
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    _check(lib().prohd_profile_read(name.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value

@@ -1,0 +1,285 @@
+// C-ABI entry points of libprohd: argument validation, workspace sizing,
+// error strings and kernel timing.  Kernels live in k_*.hip.
+
+#include <math.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace prohd {
+
+// Defined in k_hd.hip / k_project.hip.
+prohd_status hd_candidates(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                           const int32_t* idxA, const int64_t* dnA, int64_t capA,
+                           const int32_t* idxB, const int64_t* dnB, int64_t capB, bool full,
+                           prohd_result* out, void* ws, size_t ws_bytes, hipStream_t s);
+prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      prohd_result* out, float* nn2A, float* nn2B, void* ws, size_t ws_bytes,
+                      hipStream_t s);
+prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                         int32_t m, bool dirs_given, float* dirs, float* projA, float* projB,
+                         double* evals, int32_t* status, void* ws, size_t ws_bytes, hipStream_t s);
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+prohd_status fail(prohd_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// ------------------------------------------------------------ device info
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// ----------------------------------------------------------------- timing
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_pool;
+thread_local int g_open = -1;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+void profile_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfRec r{name, take_event(), take_event()};
+  if (!r.a || !r.b) return;
+  hipEventRecord(r.a, s);
+  g_prof.push_back(r);
+  g_open = (int)g_prof.size() - 1;
+}
+
+void profile_end(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_open >= 0 && g_open < (int)g_prof.size()) hipEventRecord(g_prof[g_open].b, s);
+  g_open = -1;
+}
+
+}  // namespace prohd
+
+using namespace prohd;
+
+namespace {
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+prohd_status check_sets(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D) {
+  if (bad_ptr(A) || bad_ptr(B)) return fail(PROHD_EINVAL, "A and B must be non-null device pointers");
+  if (nA < 1 || nB < 1) return fail(PROHD_EINVAL, "nA and nB must be >= 1");
+  if (nA >= (int64_t(1) << 31) || nB >= (int64_t(1) << 31))
+    return fail(PROHD_EINVAL, "nA and nB must be < 2^31");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  return PROHD_OK;
+}
+
+prohd_status finish(prohd_status st, uint32_t flags, hipStream_t s, const int32_t* dev_status) {
+  if (st != PROHD_OK) return st;
+  if (flags & PROHD_SYNC) {
+    PROHD_HIP(hipStreamSynchronize(s));
+    if (dev_status) {
+      int32_t h = 0;
+      PROHD_HIP(hipMemcpy(&h, dev_status, sizeof(h), hipMemcpyDeviceToHost));
+      if (h != PROHD_OK) return fail((prohd_status)h, "device reported status " + std::to_string(h));
+    }
+  }
+  return PROHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs, int64_t capA,
+                            int64_t capB) {
+  if (nA < 1 || nB < 1 || D < 1 || D > PROHD_MAX_DIM || ndirs < 1 || ndirs > PROHD_MAX_DIRS ||
+      capA < 0 || capB < 0)
+    return 0;
+  if (capA == 0 || capA > nA) capA = nA;
+  if (capB == 0 || capB > nB) capB = nB;
+  size_t need = project_ws_bytes(nA, nB, D, ndirs);
+  need = std::max(need, select_ws_bytes(2 * ndirs, std::max(nA, nB)) +
+                            compact_ws_bytes(std::max(nA, nB)) + (size_t)(nA + nB) + 1024);
+  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true));
+  need = std::max(need, exact_ws_bytes(nA, nB, D));
+  return need;
+}
+
+prohd_status prohd_project(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                           int32_t m, uint32_t flags, float* dirs, float* projA, float* projB,
+                           double* evals, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (flags & ~(uint32_t)(PROHD_DIRS_GIVEN | PROHD_SYNC)) return fail(PROHD_EINVAL, "unknown flag");
+  if (m < 1 || m > D) return fail(PROHD_EINVAL, "m must satisfy 1 <= m <= D");
+  if (m + 1 > PROHD_MAX_DIRS) return fail(PROHD_EUNSUPPORTED, "m + 1 exceeds PROHD_MAX_DIRS");
+  if (bad_ptr(dirs) || bad_ptr(projA) || bad_ptr(projB))
+    return fail(PROHD_EINVAL, "dirs, projA and projB must be non-null");
+  if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
+  if (ws_bytes < project_ws_bytes(nA, nB, D, m + 1)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  st = project_run(A, nA, B, nB, D, m, (flags & PROHD_DIRS_GIVEN) != 0, dirs, projA, projB, evals,
+                   status, ws, ws_bytes, s);
+  return finish(st, flags, s, status);
+}
+
+prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, int64_t nB,
+                          int32_t ndirs, const int32_t* kA, const int32_t* kB, int32_t* idxA,
+                          int64_t capA, int64_t* nselA, int32_t* idxB, int64_t capB, int64_t* nselB,
+                          void* ws, size_t ws_bytes, void* stream) {
+  if (bad_ptr(projA) || bad_ptr(projB)) return fail(PROHD_EINVAL, "projections must be non-null");
+  if (nA < 1 || nB < 1 || nA >= (int64_t(1) << 31) || nB >= (int64_t(1) << 31))
+    return fail(PROHD_EINVAL, "nA and nB must be in [1, 2^31)");
+  if (ndirs < 1) return fail(PROHD_EINVAL, "ndirs must be >= 1");
+  if (ndirs > PROHD_MAX_DIRS) return fail(PROHD_EUNSUPPORTED, "ndirs exceeds PROHD_MAX_DIRS");
+  if (bad_ptr(kA) || bad_ptr(kB)) return fail(PROHD_EINVAL, "kA and kB must be non-null host arrays");
+  if (bad_ptr(idxA) || bad_ptr(idxB) || bad_ptr(nselA) || bad_ptr(nselB))
+    return fail(PROHD_EINVAL, "index outputs must be non-null");
+  if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
+  int64_t boundA = 0, boundB = 0;
+  for (int d = 0; d < ndirs; ++d) {
+    if (kA[d] < 1 || kB[d] < 1) return fail(PROHD_EINVAL, "every k must be >= 1");
+    boundA += 2 * std::min<int64_t>(kA[d], nA);
+    boundB += 2 * std::min<int64_t>(kB[d], nB);
+  }
+  boundA = std::min(boundA, nA);
+  boundB = std::min(boundB, nB);
+  if (capA < boundA || capB < boundB)
+    return fail(PROHD_EINVAL, "capA/capB below min(n, sum 2k): the index list could overflow");
+  const int nseg = 2 * ndirs;
+  Arena ar(ws);
+  uint8_t* fA = ar.take<uint8_t>(nA);
+  uint8_t* fB = ar.take<uint8_t>(nB);
+  const size_t sel_bytes = select_ws_bytes(nseg, std::max(nA, nB));
+  void* sel_ws = ar.take<char>(sel_bytes);
+  const size_t cmp_bytes = compact_ws_bytes(std::max(nA, nB));
+  void* cmp_ws = ar.take<char>(cmp_bytes);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  prohd_status st = zero_bytes(fA, (size_t)nA, s);
+  if (st) return st;
+  st = zero_bytes(fB, (size_t)nB, s);
+  if (st) return st;
+  std::vector<SelSegment> segs;
+  segs.reserve(nseg);
+  for (int d = 0; d < ndirs; ++d) {
+    const int32_t ka = (int32_t)std::min<int64_t>(kA[d], nA);
+    const int32_t kb = (int32_t)std::min<int64_t>(kB[d], nB);
+    segs.push_back(SelSegment{projA + (size_t)d * nA, nA, nullptr, ka, ka, fA});
+    segs.push_back(SelSegment{projB + (size_t)d * nB, nB, nullptr, kb, kb, fB});
+  }
+  st = select_mark(segs.data(), nseg, sel_ws, sel_bytes, s);
+  if (st) return st;
+  st = compact_flags(fA, nA, nullptr, idxA, nselA, cmp_ws, cmp_bytes, s);
+  if (st) return st;
+  return compact_flags(fB, nB, nullptr, idxB, nselB, cmp_ws, cmp_bytes, s);
+}
+
+prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      const int32_t* idxA, const int64_t* nselA, const int32_t* idxB,
+                      const int64_t* nselB, int64_t capA, int64_t capB, uint32_t flags,
+                      prohd_result* out, void* ws, size_t ws_bytes, void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (flags & ~(uint32_t)(PROHD_INNER_FULL | PROHD_SYNC)) return fail(PROHD_EINVAL, "unknown flag");
+  if (bad_ptr(idxA) || bad_ptr(idxB) || bad_ptr(nselA) || bad_ptr(nselB))
+    return fail(PROHD_EINVAL, "index inputs must be non-null");
+  if (capA < 1 || capB < 1 || capA > nA || capB > nB)
+    return fail(PROHD_EINVAL, "capA/capB must be in [1, n]");
+  if (bad_ptr(out)) return fail(PROHD_EINVAL, "out must be non-null");
+  if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
+  const bool full = (flags & PROHD_INNER_FULL) != 0;
+  if (ws_bytes < hd_ws_bytes(nA, nB, D, capA, capB, full))
+    return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  st = hd_candidates(A, nA, B, nB, D, idxA, nselA, capA, idxB, nselB, capB, full, out, ws, ws_bytes, s);
+  return finish(st, flags, s, out ? &out->status : nullptr);
+}
+
+prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      uint32_t flags, prohd_result* out, float* nn2A, float* nn2B, void* ws,
+                      size_t ws_bytes, void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (flags & ~(uint32_t)PROHD_SYNC) return fail(PROHD_EINVAL, "unknown flag");
+  if (bad_ptr(out)) return fail(PROHD_EINVAL, "out must be non-null");
+  if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
+  if (ws_bytes < exact_ws_bytes(nA, nB, D)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  st = hd_exact(A, nA, B, nB, D, out, nn2A, nn2B, ws, ws_bytes, s);
+  return finish(st, flags, s, out ? &out->status : nullptr);
+}
+
+const char* prohd_last_error(void) { return g_err.c_str(); }
+
+const char* prohd_version(void) { return "prohd-gfx950 0.1.0"; }
+
+prohd_status prohd_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return PROHD_OK;
+}
+
+prohd_status prohd_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof) {
+    hipEventSynchronize(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_prof.clear();
+  return PROHD_OK;
+}
+
+prohd_status prohd_profile_read(const char* name, int64_t* launches, double* total_ms) {
+  if (!name || !launches || !total_ms) return fail(PROHD_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int64_t n = 0;
+  double ms = 0.0;
+  for (auto& r : g_prof) {
+    if (r.name.find(name) == std::string::npos) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(PROHD_EDEVICE, "event synchronize failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(PROHD_EDEVICE, "elapsed time failed");
+    ms += t;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return PROHD_OK;
+}
+
+}  // extern "C"

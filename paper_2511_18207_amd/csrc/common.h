@@ -1,0 +1,109 @@
+// Internal declarations shared by the translation units of libprohd.
+// Not part of the public ABI (see include/prohd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "prohd.h"
+
+namespace prohd {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+prohd_status fail(prohd_status code, const std::string& msg);
+
+#define PROHD_HIP(call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::prohd::fail(PROHD_EDEVICE, std::string(#call) + ": " +          \
+                                              hipGetErrorString(e_));          \
+  } while (0)
+
+// ------------------------------------------------------------ kernel timing
+bool profiling();
+void profile_begin(const char* name, hipStream_t s);
+void profile_end(hipStream_t s);
+
+// Launches a kernel (optionally bracketed by timing events) and checks the
+// launch.  Usage: PROHD_LAUNCH("name", kern, grid, block, lds, stream, args...)
+#define PROHD_LAUNCH(name, kern, grid, block, lds, stream, ...)                \
+  do {                                                                         \
+    const bool prof_ = ::prohd::profiling();                                   \
+    if (prof_) ::prohd::profile_begin(name, stream);                           \
+    hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);           \
+    hipError_t le_ = hipGetLastError();                                        \
+    if (le_ != hipSuccess)                                                     \
+      return ::prohd::fail(PROHD_EDEVICE,                                      \
+                           std::string("launch ") + name + ": " +              \
+                               hipGetErrorString(le_));                        \
+    if (prof_) ::prohd::profile_end(stream);                                   \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// counts bytes (used by the size queries).
+struct Arena {
+  char* base;
+  size_t used = 0;
+  explicit Arena(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+// Device properties needed for launch shaping (cached per device).
+int cu_count();
+
+// Padded dimension used by the tile kernels: 16, 32, 64, 128 or 256.
+inline int pad_dim(int D) {
+  int p = 16;
+  while (p < D) p *= 2;
+  return p;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device status word values (int32), shared by kernels.
+constexpr int32_t ST_OK = PROHD_OK;
+constexpr int32_t ST_NONFINITE = PROHD_ENONFINITE;
+constexpr int32_t ST_EMPTY = PROHD_EINVAL;
+
+// ------------------------------------------------------------- sub-systems
+// Extreme selection (k_select.hip).  Each segment is a float32 array;
+// `lo`/`hi` are the numbers of smallest / largest entries to keep under the
+// order (value, index), ties to the smaller index at both ends.  Kept
+// entries set flag bytes; `n` may be read from device (dev_n) when non-null.
+struct SelSegment {
+  const float* vals;
+  int64_t n;        // host bound on the length
+  const int64_t* dev_n;  // device length, or nullptr (use n)
+  int32_t lo, hi;   // counts per end (0 = none); clipped to the length
+  uint8_t* flags;   // flag bytes to set (length >= n)
+};
+size_t select_ws_bytes(int nseg, int64_t max_n);
+prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_bytes,
+                         hipStream_t s);
+// Compaction of flag bytes into an ascending index list + device count.
+size_t compact_ws_bytes(int64_t n);
+prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n,
+                           int32_t* idx, int64_t* count, void* ws, size_t ws_bytes,
+                           hipStream_t s);
+// Fill bytes with zero through a kernel (graph-friendly; no memset nodes).
+prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s);
+
+// Distance core (k_hd.hip).
+size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full);
+size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D);
+
+// Direction finding and projection (k_stats.hip, k_eig.hip, k_project.hip).
+size_t project_ws_bytes(int64_t nA, int64_t nB, int32_t D, int32_t ndirs);
+
+}  // namespace prohd

@@ -1,0 +1,423 @@
+// Extreme selection: the k smallest and k largest entries of float32 arrays
+// under the total order (value, index), by radix selection on the device.
+//
+// This is the "argsort, keep the first k and the last k, keep the unique
+// indices" step of the paper's Alg. 1 and Alg. 2, without a sort: only the
+// k-th key from each end is located (three histogram passes over 11/11/10
+// bits of an order-preserving 32-bit key), then every entry is compared with
+// it.  Entries equal to the k-th key are taken in index order until the
+// count is reached, so ties go to the smaller index at both ends.
+//
+// Kept entries set a flag byte; flags of several arrays (directions) may
+// point to one buffer, which yields their union.  compact_flags() turns the
+// flags into an ascending index list with a device-side count.
+//
+// Every launch reads its array lengths from device memory when asked to, so
+// a whole chain runs without a host synchronisation.
+
+#include "common.h"
+
+namespace prohd {
+namespace {
+
+constexpr int kBins = 2048;          // 11-bit digits
+constexpr int kHistChunk = 16384;    // elements per histogram work-group
+constexpr int kMarkChunk = 4096;     // elements per tie-count / mark work-group
+constexpr int kThreads = 256;
+
+struct EndState {
+  uint32_t prefix;  // key bits fixed so far
+  uint32_t mask;    // which bits of prefix are fixed
+  int32_t need;     // entries still to take among those matching prefix
+  int32_t active;   // 1 if this end selects anything
+};
+
+struct SegDev {
+  const float* vals;
+  const int64_t* dev_n;
+  int64_t n;
+  uint8_t* flags;
+  int32_t lo, hi;
+};
+
+// Segment descriptors travel as a kernel argument (no host-to-device copy,
+// so a chain of launches can be captured in a graph).
+constexpr int kSegPerLaunch = 32;
+struct SegPack {
+  SegDev s[kSegPerLaunch];
+  int32_t nseg;   // segments in this pack
+  int32_t base;   // global index of s[0] (state / histogram slot)
+};
+
+// Order-preserving key: a < b (as floats, -0 == +0) <=> key(a) < key(b).
+__device__ __forceinline__ uint32_t fkey(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u << 1) == 0u) u = 0u;  // -0.0 -> +0.0
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ int64_t seg_len(const SegDev& s) {
+  return s.dev_n ? min(*s.dev_n, s.n) : s.n;
+}
+
+__global__ void init_state(const SegPack P, EndState* __restrict__ st, uint32_t* __restrict__ hist) {
+  const int lid = blockIdx.x;
+  if (lid >= P.nseg) return;
+  const SegDev s = P.s[lid];
+  const int sid = P.base + lid;
+  const int64_t n = seg_len(s);
+  if (threadIdx.x < 2) {
+    const int e = threadIdx.x;
+    const int64_t k = e == 0 ? s.lo : s.hi;
+    const int64_t need = k < n ? k : n;
+    EndState es;
+    es.prefix = 0u;
+    es.mask = 0u;
+    es.need = (int32_t)(need > 0 ? need : 0);
+    es.active = need > 0 ? 1 : 0;
+    st[2 * sid + e] = es;
+  }
+  uint32_t* h = hist + (size_t)sid * 2 * kBins;
+  for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) h[i] = 0u;
+}
+
+// One digit pass: histogram of the digit at `shift` over entries whose key
+// matches the prefix fixed so far, separately for the two ends.
+__global__ __launch_bounds__(kThreads) void digit_hist(const SegPack P,
+                                                      const EndState* __restrict__ st,
+                                                      uint32_t* __restrict__ hist,
+                                                      int shift, uint32_t dmask) {
+  __shared__ uint32_t h[2][kBins];
+  const SegDev s = P.s[blockIdx.y];
+  const int sid = P.base + blockIdx.y;
+  const int64_t n = seg_len(s);
+  const int64_t base = (int64_t)blockIdx.x * kHistChunk;
+  if (base >= n) return;
+  const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
+  if (!e0.active && !e1.active) return;
+  for (int i = threadIdx.x; i < 2 * kBins; i += kThreads) (&h[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t end = min(n, base + kHistChunk);
+  for (int64_t i = base + threadIdx.x; i < end; i += kThreads) {
+    const uint32_t key = fkey(s.vals[i]);
+    const uint32_t d = (key >> shift) & dmask;
+    if (e0.active && (key & e0.mask) == e0.prefix) atomicAdd(&h[0][d], 1u);
+    if (e1.active && (key & e1.mask) == e1.prefix) atomicAdd(&h[1][d], 1u);
+  }
+  __syncthreads();
+  uint32_t* g = hist + (size_t)sid * 2 * kBins;
+  for (int i = threadIdx.x; i < 2 * kBins; i += kThreads) {
+    const uint32_t v = (&h[0][0])[i];
+    if (v) atomicAdd(&g[i], v);
+  }
+}
+
+// Finds, per (segment, end), the digit holding the need-th entry, fixes it in
+// the prefix, and clears the histogram for the next pass.
+__global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st,
+                                                      uint32_t* __restrict__ hist,
+                                                      int shift, uint32_t dmask) {
+  const int sid = blockIdx.x >> 1;
+  const int e = blockIdx.x & 1;
+  uint32_t* h = hist + (size_t)sid * 2 * kBins + (size_t)e * kBins;
+  EndState es = st[2 * sid + e];
+  __shared__ uint32_t part[kThreads];
+  __shared__ uint32_t sel[2];
+  constexpr int per = kBins / kThreads;  // 8 bins per thread
+  const int nb = (int)dmask + 1;
+  // ascending order of digits for the bottom end, descending for the top
+  uint32_t v[per];
+  uint32_t tot = 0;
+  for (int j = 0; j < per; ++j) {
+    const int pos = threadIdx.x * per + j;  // position in scan order
+    const int bin = e == 0 ? pos : (nb - 1 - pos);
+    v[j] = (pos < nb) ? h[bin] : 0u;
+    tot += v[j];
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      const uint32_t x = part[t];
+      part[t] = acc;
+      acc += x;
+    }
+  }
+  __syncthreads();
+  if (es.active) {
+    uint32_t acc = part[threadIdx.x];
+    const uint32_t need = (uint32_t)es.need;
+    for (int j = 0; j < per; ++j) {
+      if (acc < need && acc + v[j] >= need) {
+        const int pos = threadIdx.x * per + j;
+        sel[0] = (uint32_t)(e == 0 ? pos : (nb - 1 - pos));
+        sel[1] = acc;
+      }
+      acc += v[j];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && es.active) {
+    es.prefix |= sel[0] << shift;
+    es.mask |= dmask << shift;
+    es.need -= (int32_t)sel[1];
+    st[2 * sid + e] = es;
+  }
+  for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0u;
+}
+
+// Number of entries equal to the located key, per chunk and end.
+__global__ __launch_bounds__(kThreads) void tie_count(const SegPack P,
+                                                     const EndState* __restrict__ st,
+                                                     uint32_t* __restrict__ tcnt,
+                                                     int nchunks) {
+  const SegDev s = P.s[blockIdx.y];
+  const int sid = P.base + blockIdx.y;
+  const int64_t n = seg_len(s);
+  const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
+  __shared__ uint32_t c[2];
+  if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+  __syncthreads();
+  const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
+  uint32_t m0 = 0, m1 = 0;
+  const int64_t end = min(n, base + kMarkChunk);
+  for (int64_t i = base + threadIdx.x; i < end; i += kThreads) {
+    const uint32_t key = fkey(s.vals[i]);
+    m0 += (e0.active && key == e0.prefix);
+    m1 += (e1.active && key == e1.prefix);
+  }
+  if (m0) atomicAdd(&c[0], m0);
+  if (m1) atomicAdd(&c[1], m1);
+  __syncthreads();
+  if (threadIdx.x < 2) tcnt[((size_t)sid * 2 + threadIdx.x) * nchunks + blockIdx.x] = c[threadIdx.x];
+}
+
+// Exclusive prefix over chunks (per segment and end), in place.
+__global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cnt, int nchunks,
+                                                      int64_t* __restrict__ total) {
+  uint32_t* c = cnt + (size_t)blockIdx.x * nchunks;
+  __shared__ uint32_t part[kThreads];
+  const int per = (nchunks + kThreads - 1) / kThreads;
+  uint32_t s = 0;
+  for (int j = 0; j < per; ++j) {
+    const int i = threadIdx.x * per + j;
+    if (i < nchunks) s += c[i];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      const uint32_t x = part[t];
+      part[t] = acc;
+      acc += x;
+    }
+    if (total) total[blockIdx.x] = acc;
+  }
+  __syncthreads();
+  uint32_t acc = part[threadIdx.x];
+  for (int j = 0; j < per; ++j) {
+    const int i = threadIdx.x * per + j;
+    if (i < nchunks) {
+      const uint32_t x = c[i];
+      c[i] = acc;
+      acc += x;
+    }
+  }
+}
+
+// Block-wide exclusive prefix of a 0/1 predicate in thread order; returns the
+// prefix for this thread and writes the block total to *tot.
+__device__ __forceinline__ uint32_t block_excl_scan(bool p, uint32_t* wsum, uint32_t* tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(p);
+  const uint32_t in_wave = (uint32_t)__popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  if (lane == 0) wsum[wave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t x = wsum[w];
+    before += (w < wave) ? x : 0u;
+    all += x;
+  }
+  *tot = all;
+  __syncthreads();
+  return before + in_wave;
+}
+
+__global__ __launch_bounds__(kThreads) void mark(const SegPack P,
+                                                const EndState* __restrict__ st,
+                                                const uint32_t* __restrict__ toff,
+                                                int nchunks) {
+  const SegDev s = P.s[blockIdx.y];
+  const int sid = P.base + blockIdx.y;
+  const int64_t n = seg_len(s);
+  const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
+  if (base >= n) return;
+  const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
+  if (!e0.active && !e1.active) return;
+  __shared__ uint32_t wsum[kThreads / 64];
+  uint32_t r0 = toff[((size_t)sid * 2 + 0) * nchunks + blockIdx.x];
+  uint32_t r1 = toff[((size_t)sid * 2 + 1) * nchunks + blockIdx.x];
+  for (int it = 0; it < kMarkChunk / kThreads; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + threadIdx.x;
+    const bool in = i < n;
+    const uint32_t key = in ? fkey(s.vals[i]) : 0u;
+    const bool t0 = in && e0.active && key == e0.prefix;
+    const bool t1 = in && e1.active && key == e1.prefix;
+    uint32_t tot0, tot1;
+    const uint32_t p0 = block_excl_scan(t0, wsum, &tot0);
+    const uint32_t p1 = block_excl_scan(t1, wsum, &tot1);
+    bool keep = false;
+    if (in && e0.active) keep |= key < e0.prefix || (t0 && r0 + p0 < (uint32_t)e0.need);
+    if (in && e1.active) keep |= key > e1.prefix || (t1 && r1 + p1 < (uint32_t)e1.need);
+    if (keep) s.flags[i] = 1;
+    r0 += tot0;
+    r1 += tot1;
+  }
+}
+
+// ------------------------------------------------------------- compaction
+__global__ __launch_bounds__(kThreads) void flag_count(const uint8_t* __restrict__ f, int64_t hn,
+                                                      const int64_t* __restrict__ dn,
+                                                      uint32_t* __restrict__ cnt) {
+  const int64_t n = dn ? min(*dn, hn) : hn;
+  const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
+  uint32_t m = 0;
+  for (int64_t i = base + threadIdx.x; i < min(n, base + kMarkChunk); i += kThreads) m += f[i] != 0;
+  __shared__ uint32_t c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  if (m) atomicAdd(&c, m);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict__ f, int64_t hn,
+                                                      const int64_t* __restrict__ dn,
+                                                      const uint32_t* __restrict__ off,
+                                                      int32_t* __restrict__ idx) {
+  const int64_t n = dn ? min(*dn, hn) : hn;
+  const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
+  if (base >= n) return;
+  __shared__ uint32_t wsum[kThreads / 64];
+  uint32_t r = off[blockIdx.x];
+  for (int it = 0; it < kMarkChunk / kThreads; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + threadIdx.x;
+    const bool p = i < n && f[i] != 0;
+    uint32_t tot;
+    const uint32_t pre = block_excl_scan(p, wsum, &tot);
+    if (p) idx[r + pre] = (int32_t)i;
+    r += tot;
+  }
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, size_t words, uint8_t* __restrict__ tail,
+                            int tail_bytes) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < tail_bytes) tail[threadIdx.x] = 0;
+}
+
+struct SelLayout {
+  EndState* st;
+  uint32_t* hist;
+  uint32_t* tie;
+  int nchunks;
+};
+
+SelLayout sel_layout(Arena& ar, int nseg, int64_t max_n) {
+  SelLayout L;
+  L.nchunks = (int)std::max<int64_t>(1, cdiv(max_n, kMarkChunk));
+  L.st = ar.take<EndState>(2 * nseg);
+  L.hist = ar.take<uint32_t>((size_t)nseg * 2 * kBins);
+  L.tie = ar.take<uint32_t>((size_t)nseg * 2 * L.nchunks);
+  return L;
+}
+
+}  // namespace
+
+size_t select_ws_bytes(int nseg, int64_t max_n) {
+  Arena ar(nullptr);
+  sel_layout(ar, nseg, max_n);
+  return ar.used + 256;
+}
+
+prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_bytes,
+                         hipStream_t s) {
+  if (nseg <= 0) return PROHD_OK;
+  int64_t max_n = 1;
+  for (int i = 0; i < nseg; ++i) max_n = std::max<int64_t>(max_n, segs[i].n);
+  Arena ar(ws);
+  SelLayout L = sel_layout(ar, nseg, max_n);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "select: workspace too small");
+  const int hchunks = (int)std::max<int64_t>(1, cdiv(max_n, kHistChunk));
+  const int shifts[3] = {21, 10, 0};
+  const uint32_t masks[3] = {0x7FFu, 0x7FFu, 0x3FFu};
+  for (int g0 = 0; g0 < nseg; g0 += kSegPerLaunch) {
+    SegPack P;
+    P.nseg = std::min(kSegPerLaunch, nseg - g0);
+    P.base = g0;
+    for (int i = 0; i < kSegPerLaunch; ++i) {
+      SegDev d{};
+      if (i < P.nseg) {
+        const SelSegment& q = segs[g0 + i];
+        d.vals = q.vals;
+        d.dev_n = q.dev_n;
+        d.n = q.n;
+        d.flags = q.flags;
+        d.lo = q.lo;
+        d.hi = q.hi;
+      }
+      P.s[i] = d;
+    }
+    const int ns = P.nseg;
+    PROHD_LAUNCH("select_init", init_state, dim3(ns), dim3(kThreads), 0, s, P, L.st, L.hist);
+    for (int p = 0; p < 3; ++p) {
+      PROHD_LAUNCH("select_hist", digit_hist, dim3(hchunks, ns), dim3(kThreads), 0, s, P, L.st,
+                   L.hist, shifts[p], masks[p]);
+      PROHD_LAUNCH("select_scan", digit_scan, dim3(2 * ns), dim3(kThreads), 0, s,
+                   L.st + 2 * g0, L.hist + (size_t)g0 * 2 * kBins, shifts[p], masks[p]);
+    }
+    PROHD_LAUNCH("select_ties", tie_count, dim3(L.nchunks, ns), dim3(kThreads), 0, s, P, L.st,
+                 L.tie, L.nchunks);
+    PROHD_LAUNCH("select_tiescan", chunk_scan, dim3(2 * ns), dim3(kThreads), 0, s,
+                 L.tie + (size_t)g0 * 2 * L.nchunks, L.nchunks, (int64_t*)nullptr);
+    PROHD_LAUNCH("select_mark", mark, dim3(L.nchunks, ns), dim3(kThreads), 0, s, P, L.st, L.tie,
+                 L.nchunks);
+  }
+  return PROHD_OK;
+}
+
+size_t compact_ws_bytes(int64_t n) {
+  Arena ar(nullptr);
+  ar.take<uint32_t>((size_t)std::max<int64_t>(1, cdiv(n, kMarkChunk)));
+  return ar.used + 256;
+}
+
+prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n, int32_t* idx,
+                           int64_t* count, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int nch = (int)std::max<int64_t>(1, cdiv(n, kMarkChunk));
+  Arena ar(ws);
+  uint32_t* cnt = ar.take<uint32_t>(nch);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "compact: workspace too small");
+  PROHD_LAUNCH("compact_count", flag_count, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt);
+  PROHD_LAUNCH("compact_scan", chunk_scan, dim3(1), dim3(kThreads), 0, s, cnt, nch, count);
+  PROHD_LAUNCH("compact_write", flag_write, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt, idx);
+  return PROHD_OK;
+}
+
+prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return PROHD_OK;
+  // Workspace carve-outs are 256-byte aligned; whole words first, then bytes.
+  const size_t words = bytes / 4;
+  const int tail = (int)(bytes - words * 4);
+  const int grid = (int)std::min<size_t>(4096, std::max<size_t>(1, cdiv((int64_t)words, 256 * 4)));
+  PROHD_LAUNCH("zero", zero_kernel, dim3(grid), dim3(256), 0, s, (uint32_t*)p, words,
+               (uint8_t*)p + words * 4, tail);
+  return PROHD_OK;
+}
+
+}  // namespace prohd

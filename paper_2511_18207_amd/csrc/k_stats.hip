@@ -1,0 +1,342 @@
+// First pass over the two point sets: per-set sums (centroids, paper Alg. 1)
+// and the Gram matrix of the stacked union [A; B] (covariance for the
+// principal components, Alg. 2), in float64 on the matrix cores.
+//
+// Rows are shifted by s = A[0] (converted to float64; the difference of two
+// float32 values is exact in float64), so the accumulated Gram
+//   G = sum_r (z_r - s)(z_r - s)^T
+// stays well conditioned when the data sit far from the origin; the
+// covariance is then C = (G - N mu_w mu_w^T) / (N - 1) with mu_w the mean of
+// the shifted rows.
+//
+// gram_partial: one work-group per slice of rows of one set (8 waves, 16
+// at D > 128).  For every group
+// of four rows, lane l holds w[row l/16][16*I + l%16] for each 16-column block
+// I; the 16x16 Gram block (I, J) gains one v_mfma_f64_16x16x4_f64 with A
+// operand = block I and B operand = block J (the four rows are the k index).
+// Only blocks with I <= J are formed.  The work-group writes its partial
+// blocks and per-set column sums; gram_reduce adds the partials in a fixed
+// order (deterministic) and writes C (padded to DP x DP: rows/columns >= D
+// hold -1 on the diagonal, which keeps those padding directions below every
+// real eigenvalue), the centroid axis (dirs row 0) and the status word.
+
+#include <utility>
+
+#include "common.h"
+
+namespace prohd {
+
+size_t stats_ws_bytes(int64_t nA, int64_t nB, int32_t D);
+prohd_status stats_run(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                       double* C, double* u0, int32_t* status, void* ws, size_t ws_bytes,
+                       hipStream_t s);
+
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int DP>
+struct GramShape {
+  static constexpr int WAVES = DP >= 256 ? 16 : 8;      // waves per work-group
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int NB = DP / 16;                    // 16-column blocks
+  static constexpr int T = NB * (NB + 1) / 2;           // blocks with I <= J
+  static constexpr int TPW = (T + WAVES - 1) / WAVES;   // blocks per wave
+};
+
+// Block t (0..T-1) -> (I, J), I <= J, enumerated row by row (compile time).
+constexpr int cblock_i(int t, int nb) {
+  int i = 0;
+  while (i < nb && t >= nb - i) { t -= nb - i; ++i; }
+  return i < nb ? i : 0;
+}
+constexpr int cblock_j(int t, int nb) {
+  int i = 0;
+  while (i < nb && t >= nb - i) { t -= nb - i; ++i; }
+  return i < nb ? i + t : 0;
+}
+
+// The Gram blocks of wave W: t = W + WAVES*u.  Operands come from v[] with
+// compile-time indices, so every value stays in a register.
+template <int NB, int T, int WAVES, int W, int... U>
+__device__ __forceinline__ void wave_blocks(doublex4* acc, const double* v,
+                                            std::integer_sequence<int, U...>) {
+  ((acc[U] = (W + WAVES * U < T)
+                 ? __builtin_amdgcn_mfma_f64_16x16x4f64(v[cblock_i(W + WAVES * U, NB)],
+                                                        v[cblock_j(W + WAVES * U, NB)], acc[U],
+                                                        0, 0, 0)
+                 : acc[U]),
+   ...);
+}
+
+// Block t (0..T-1) -> (I, J), I <= J, enumerated row by row.
+__device__ __forceinline__ void block_ij(int t, int nb, int& I, int& J) {
+  int i = 0, rem = t;
+  while (rem >= nb - i) {
+    rem -= nb - i;
+    ++i;
+  }
+  I = i;
+  J = i + rem;
+}
+
+template <int DP>
+__global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const float* __restrict__ A, int64_t nA,
+                                                    const float* __restrict__ B, int64_t nB,
+                                                    int D, int64_t rows_per_wg,
+                                                    double* __restrict__ gpart,
+                                                    double* __restrict__ spart,
+                                                    int32_t* __restrict__ status) {
+  using S = GramShape<DP>;
+  constexpr int NB = S::NB;
+  constexpr int NT = S::THREADS;
+  constexpr int kWaves = S::WAVES;
+  constexpr int RC = 32;                      // rows staged per chunk
+  constexpr int PER = RC * DP / NT;           // staged elements per thread
+  __shared__ double wbuf[RC * DP];            // shifted rows, float64
+  __shared__ double sred[NT];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int col = lane & 15;   // column within a 16-block
+  const int rsub = lane >> 4;  // row within a group of four
+  // work-groups [0, wgA) take rows of A, the rest rows of B
+  const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
+  const bool setA = (int64_t)blockIdx.x < wgA;
+  const float* X = setA ? A : B;
+  const int64_t nX = setA ? nA : nB;
+  const int64_t r_begin = (setA ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - wgA) * rows_per_wg;
+  const int64_t r_end = min(nX, r_begin + rows_per_wg);
+
+  // staging: thread tid handles elements e = tid + NT i of a chunk, i.e.
+  // row tid/DP + (NT/DP) i and the fixed column tid % DP (DP divides NT).
+  const int mycol = tid % DP;
+  const int myrow = tid / DP;
+  constexpr int RSTEP = NT / DP;
+  const double sh = (mycol < D) ? (double)A[mycol] : 0.0;   // shift s = A[0]
+  double sum = 0.0;
+  bool bad = false;
+  float raw[PER];
+  auto fetch = [&](int64_t r0) {
+    const float* base = X + r0 * D;            // uniform
+    const int lim = (int)min<int64_t>(RC, r_end - r0);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int rr = myrow + RSTEP * i;
+      raw[i] = (rr < lim && mycol < D) ? base[rr * D + mycol] : 0.f;
+    }
+  };
+  auto stage = [&](int64_t r0) {
+    const int lim = (int)min<int64_t>(RC, r_end - r0);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int rr = myrow + RSTEP * i;
+      const float x = raw[i];
+      bad |= !(x - x == 0.f);
+      const double w = (rr < lim && mycol < D) ? ((double)x - sh) : 0.0;
+      wbuf[tid + NT * i] = w;
+      sum += w;
+    }
+  };
+
+  doublex4 acc[S::TPW];
+#pragma unroll
+  for (int u = 0; u < S::TPW; ++u) acc[u] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  if (r_begin < r_end) fetch(r_begin);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += RC) {
+    __syncthreads();
+    stage(r0);
+    __syncthreads();
+    if (r0 + RC < r_end) fetch(r0 + RC);
+#pragma unroll 1
+    for (int q = 0; q < RC / 4; ++q) {
+      const double* rowp = &wbuf[(4 * q + rsub) * DP + col];
+      double v[NB];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) v[I] = rowp[16 * I];
+      using Seq = std::make_integer_sequence<int, S::TPW>;
+      if constexpr (kWaves == 8) {
+        switch (wave) {
+          case 0: wave_blocks<NB, S::T, 8, 0>(acc, v, Seq{}); break;
+          case 1: wave_blocks<NB, S::T, 8, 1>(acc, v, Seq{}); break;
+          case 2: wave_blocks<NB, S::T, 8, 2>(acc, v, Seq{}); break;
+          case 3: wave_blocks<NB, S::T, 8, 3>(acc, v, Seq{}); break;
+          case 4: wave_blocks<NB, S::T, 8, 4>(acc, v, Seq{}); break;
+          case 5: wave_blocks<NB, S::T, 8, 5>(acc, v, Seq{}); break;
+          case 6: wave_blocks<NB, S::T, 8, 6>(acc, v, Seq{}); break;
+          default: wave_blocks<NB, S::T, 8, 7>(acc, v, Seq{}); break;
+        }
+      } else {
+        switch (wave) {
+          case 0: wave_blocks<NB, S::T, 16, 0>(acc, v, Seq{}); break;
+          case 1: wave_blocks<NB, S::T, 16, 1>(acc, v, Seq{}); break;
+          case 2: wave_blocks<NB, S::T, 16, 2>(acc, v, Seq{}); break;
+          case 3: wave_blocks<NB, S::T, 16, 3>(acc, v, Seq{}); break;
+          case 4: wave_blocks<NB, S::T, 16, 4>(acc, v, Seq{}); break;
+          case 5: wave_blocks<NB, S::T, 16, 5>(acc, v, Seq{}); break;
+          case 6: wave_blocks<NB, S::T, 16, 6>(acc, v, Seq{}); break;
+          case 7: wave_blocks<NB, S::T, 16, 7>(acc, v, Seq{}); break;
+          case 8: wave_blocks<NB, S::T, 16, 8>(acc, v, Seq{}); break;
+          case 9: wave_blocks<NB, S::T, 16, 9>(acc, v, Seq{}); break;
+          case 10: wave_blocks<NB, S::T, 16, 10>(acc, v, Seq{}); break;
+          case 11: wave_blocks<NB, S::T, 16, 11>(acc, v, Seq{}); break;
+          case 12: wave_blocks<NB, S::T, 16, 12>(acc, v, Seq{}); break;
+          case 13: wave_blocks<NB, S::T, 16, 13>(acc, v, Seq{}); break;
+          case 14: wave_blocks<NB, S::T, 16, 14>(acc, v, Seq{}); break;
+          default: wave_blocks<NB, S::T, 16, 15>(acc, v, Seq{}); break;
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
+
+  // partial Gram blocks: the 16x16x4 f64 result puts element v of lane l at
+  // row l/16 + 4 v, column l%16
+  double* gp = gpart + (size_t)blockIdx.x * S::T * 256;
+#pragma unroll
+  for (int u = 0; u < S::TPW; ++u) {
+    const int t = wave + kWaves * u;
+    if (t < S::T) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[u][v];
+    }
+  }
+  // partial column sums: the NT/DP threads of each column combine in LDS
+  __syncthreads();
+  sred[tid] = sum;
+  __syncthreads();
+  if (tid < DP) {
+    double a = 0.0;
+    for (int t = tid; t < NT; t += DP) a += sred[t];
+    double* sp = spart + (size_t)blockIdx.x * 2 * DP;
+    sp[setA ? tid : DP + tid] = a;
+    sp[setA ? DP + tid : tid] = 0.0;
+  }
+}
+
+// Sums the partials (fixed order), forms the covariance and the centroid axis.
+template <int DP>
+__global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gpart,
+                                                   const double* __restrict__ spart, int nwg,
+                                                   int64_t nA, int64_t nB, int D,
+                                                   double* __restrict__ C, double* __restrict__ u0) {
+  using S = GramShape<DP>;
+  constexpr int NB = S::NB;
+  __shared__ double sA[DP], sB[DP];
+  __shared__ double red[256];
+  for (int k = threadIdx.x; k < DP; k += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int g = 0; g < nwg; ++g) {
+      a += spart[(size_t)g * 2 * DP + k];
+      b += spart[(size_t)g * 2 * DP + DP + k];
+    }
+    sA[k] = a;
+    sB[k] = b;
+  }
+  __syncthreads();
+  const double N = (double)(nA + nB);
+  const double inv = 1.0 / (double)((nA + nB) > 1 ? (nA + nB - 1) : 1);
+  // covariance entries, one Gram element per thread iteration
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < S::T * 256; e += gridDim.x * blockDim.x) {
+    const int t = e >> 8;
+    const int i = (e >> 4) & 15;
+    const int j = e & 15;
+    int I, J;
+    block_ij(t, NB, I, J);
+    double g = 0.0;
+    for (int w = 0; w < nwg; ++w) g += gpart[((size_t)w * S::T + t) * 256 + i * 16 + j];
+    const int r = 16 * I + i, c = 16 * J + j;
+    double v;
+    if (r < D && c < D) {
+      const double mr = (sA[r] + sB[r]) / N, mc = (sA[c] + sB[c]) / N;
+      v = (g - N * mr * mc) * inv;
+    } else {
+      v = (r == c) ? -1.0 : 0.0;
+    }
+    C[(size_t)r * DP + c] = v;
+    C[(size_t)c * DP + r] = v;
+  }
+  if (blockIdx.x != 0) return;
+  // centroid axis: mean(B) - mean(A) = sB/nB - sA/nA (the shift cancels)
+  double nrm2 = 0.0;
+  for (int k = threadIdx.x; k < D; k += blockDim.x) {
+    const double d = sB[k] / (double)nB - sA[k] / (double)nA;
+    nrm2 += d * d;
+  }
+  red[threadIdx.x] = nrm2;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  for (int k = threadIdx.x; k < D; k += blockDim.x) {
+    const double d = sB[k] / (double)nB - sA[k] / (double)nA;
+    u0[k] = (nrm < 1e-9) ? (k == 0 ? 1.0 : 0.0) : d / nrm;
+  }
+}
+
+struct StatsLayout {
+  double* gpart;
+  double* spart;
+  int64_t rows;  // rows per work-group (multiple of the 32-row chunk)
+  int nwg;       // work-groups: ceil(nA/rows) over A, then ceil(nB/rows) over B
+};
+
+StatsLayout stats_layout(Arena& ar, int64_t nA, int64_t nB, int DP, int cus) {
+  StatsLayout L;
+  const int64_t N = nA + nB;
+  const int64_t target = std::max<int64_t>(1, std::min<int64_t>(cus, cdiv(N, 1024)));
+  L.rows = cdiv(cdiv(N, target), 32) * 32;
+  L.nwg = (int)(cdiv(nA, L.rows) + cdiv(nB, L.rows));
+  const int nb = DP / 16;
+  const int T = nb * (nb + 1) / 2;
+  L.gpart = ar.take<double>((size_t)L.nwg * T * 256);
+  L.spart = ar.take<double>((size_t)L.nwg * 2 * DP);
+  return L;
+}
+
+template <int DP>
+prohd_status stats_dp(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D, double* C,
+                      double* u0, int32_t* status, void* ws, size_t ws_bytes, hipStream_t s) {
+  Arena ar(ws);
+  StatsLayout L = stats_layout(ar, nA, nB, DP, cu_count());
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "stats: workspace too small");
+  const int nwg = L.nwg;
+  PROHD_LAUNCH("stats_gram", gram_partial<DP>, dim3(nwg), dim3(GramShape<DP>::THREADS), 0, s, A, nA,
+               B, nB, D, L.rows, L.gpart, L.spart, status);
+  const int nb = DP / 16;
+  const int T = nb * (nb + 1) / 2;
+  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)T * 256, 256), 256));
+  PROHD_LAUNCH("stats_reduce", gram_reduce<DP>, dim3(rgrid), dim3(256), 0, s, L.gpart, L.spart, nwg,
+               nA, nB, D, C, u0);
+  return PROHD_OK;
+}
+
+}  // namespace
+
+size_t stats_ws_bytes(int64_t nA, int64_t nB, int32_t D) {
+  Arena ar(nullptr);
+  // the run uses at most as many work-groups as with this CU count
+  stats_layout(ar, nA, nB, pad_dim(D), 1);
+  Arena ar2(nullptr);
+  stats_layout(ar2, nA, nB, pad_dim(D), 1024);
+  ar.used = std::max(ar.used, ar2.used);
+  return ar.used + 256;
+}
+
+prohd_status stats_run(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                       double* C, double* u0, int32_t* status, void* ws, size_t ws_bytes,
+                       hipStream_t s) {
+  switch (pad_dim(D)) {
+    case 16: return stats_dp<16>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
+    case 32: return stats_dp<32>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
+    case 64: return stats_dp<64>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
+    case 128: return stats_dp<128>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
+    case 256: return stats_dp<256>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
+    default: return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM");
+  }
+}
+
+}  // namespace prohd

@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports every symbol include/prohd.h declares;
+host-side validation rejects bad arguments before touching a device.
+
+No compute call runs here (no GPU on this machine): every call below fails
+validation, which happens before any HIP call.
+"""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2511_18207_amd as ph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prohd.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(prohd_\w+|exact_hd)\s*\(", src)) - {"prohd_status"})
+
+
+def test_library_exports_every_declared_symbol():
+    L = ph.lib()
+    names = _declared_functions()
+    assert {"prohd_project", "prohd_select", "prohd_hd", "exact_hd"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    # and nm agrees (C linkage, not mangled)
+    out = os.popen(f"nm -D --defined-only {ph.library_path()}").read()
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_version_and_result_layout():
+    assert ph.version().startswith("prohd-gfx950")
+    assert ph.RESULT_BYTES == 80
+
+
+def test_workspace_size_rules():
+    assert ph.workspace_size(0, 5, 8) == 0
+    assert ph.workspace_size(5, 5, 0) == 0
+    assert ph.workspace_size(5, 5, 257) == 0
+    assert ph.workspace_size(5, 5, 8, ndirs=65) == 0
+    small = ph.workspace_size(1000, 1000, 32, 4)
+    big = ph.workspace_size(100000, 100000, 32, 4)
+    assert 0 < small < big
+    # 2M x 2M, D=256: dominated by the padded float32 copies of both sets
+    full = ph.workspace_size(2_000_000, 2_000_000, 256, 17, 80_000, 80_000)
+    assert 4.0e9 < full < 5.0e9
+
+
+def _err(code_fn):
+    L = ph.lib()
+    code = code_fn(L)
+    return code, L.prohd_last_error().decode()
+
+
+FAKE = 0x1000  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("call,code,msg", [
+    (lambda L: L.exact_hd(None, 1, FAKE, 1, 4, 0, FAKE, None, None, FAKE, 1 << 20, None), 1, "non-null"),
+    (lambda L: L.exact_hd(FAKE, 0, FAKE, 1, 4, 0, FAKE, None, None, FAKE, 1 << 20, None), 1, ">= 1"),
+    (lambda L: L.exact_hd(FAKE, 1, FAKE, 1, 0, 0, FAKE, None, None, FAKE, 1 << 20, None), 1, "D must"),
+    (lambda L: L.exact_hd(FAKE, 1, FAKE, 1, 300, 0, FAKE, None, None, FAKE, 1 << 20, None), 5, "MAX_DIM"),
+    (lambda L: L.exact_hd(FAKE, 1, FAKE, 1, 4, 1 << 9, FAKE, None, None, FAKE, 1 << 20, None), 1, "flag"),
+    (lambda L: L.exact_hd(FAKE, 10, FAKE, 10, 4, 0, FAKE, None, None, FAKE, 16, None), 3, "workspace"),
+    (lambda L: L.exact_hd(FAKE, 10, FAKE, 10, 4, 0, None, None, None, FAKE, 1 << 20, None), 1, "out"),
+    (lambda L: L.prohd_project(FAKE, 10, FAKE, 10, 4, 0, 0, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 24, None), 1, "m must"),
+    (lambda L: L.prohd_project(FAKE, 10, FAKE, 10, 4, 5, 0, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 24, None), 1, "m must"),
+    (lambda L: L.prohd_project(FAKE, 10, FAKE, 10, 200, 64, 0, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 30, None), 5, "MAX_DIRS"),
+    (lambda L: L.prohd_project(FAKE, 10, FAKE, 10, 4, 2, 0, None, FAKE, FAKE, None, None, FAKE, 1 << 24, None), 1, "non-null"),
+    (lambda L: L.prohd_project(FAKE, 10, FAKE, 10, 4, 2, 0, FAKE, FAKE, FAKE, None, None, FAKE, 8, None), 3, "workspace"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 0, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 11, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, None, FAKE, FAKE, FAKE, 5, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "index"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 3, FAKE, FAKE, 1 << 24, None), 1, "flag"),
+])
+def test_validation_errors(call, code, msg):
+    got, text = _err(call)
+    assert got == code, text
+    assert msg in text
+
+
+def test_select_validation():
+    L = ph.lib()
+    k = (C.c_int32 * 2)(10, 10)
+    k0 = (C.c_int32 * 2)(10, 0)
+    # capacity below min(n, sum 2k)
+    assert L.prohd_select(FAKE, 100, FAKE, 100, 2, k, k, FAKE, 39, FAKE, FAKE, 40, FAKE, FAKE, 1 << 24, None) == 1
+    assert "capA" in L.prohd_last_error().decode()
+    # k < 1
+    assert L.prohd_select(FAKE, 100, FAKE, 100, 2, k0, k, FAKE, 40, FAKE, FAKE, 40, FAKE, FAKE, 1 << 24, None) == 1
+    # too many directions
+    assert L.prohd_select(FAKE, 100, FAKE, 100, 65, k, k, FAKE, 40, FAKE, FAKE, 40, FAKE, FAKE, 1 << 24, None) == 5
+
+
+def test_k_rule_matches_oracle():
+    import oracle
+    for a, n in [(0.01, 2_000_000), (0.01 / 16, 2_000_000), (0.29, 100), (0.5, 3), (0.001, 10)]:
+        assert ph.k_rule(a, n) == oracle.k_rule(a, n)
+
+
+def test_profile_api_without_gpu():
+    ph.profile_enable(False)
+    ph.profile_reset()
+    assert ph.profile_read("hd_tile") == (0, 0.0)

@@ -1,0 +1,149 @@
+"""GPU parity: exact_hd and prohd_hd (through the C ABI) against the FP64 oracle.
+
+Tolerance: the stated bar is 1e-4 relative for float32 data.  Values are the
+float64 distance of the witness pair the GPU picks, so when it picks the
+oracle's pair they agree to rounding; a different pair is accepted only when
+its oracle distance is within the tolerance of the oracle's maximum (a
+near-tie).  Sizes span several 256-row work-group tiles, 32-row Y blocks and
+ragged tails, and every padded width 16..256.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import banner, rel, to_dev, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5   # tighter than the 1e-4 bar at these sizes
+
+
+def _check_dir(A, B, got_h, wa, wb, want_h, nn_of_wa):
+    """got_h realised by pair (wa, wb), which must be a NN pair within tol."""
+    A64 = np.asarray(A, dtype=np.float64)
+    B64 = np.asarray(B, dtype=np.float64)
+    d = np.linalg.norm(A64[wa] - B64[wb])
+    assert abs(d - got_h) <= 1e-12 * max(d, 1e-30) + 1e-300
+    assert rel(got_h, want_h) <= TOL or abs(got_h - want_h) <= 1e-6
+    assert abs(d - nn_of_wa) <= TOL * max(nn_of_wa, 1e-30) + 1e-6
+
+
+CASES = [
+    (1, 1, 1), (5, 3, 2), (300, 257, 3), (1000, 700, 32), (777, 1234, 100),
+    (2000, 1500, 128), (600, 900, 256), (513, 300, 16), (4099, 33, 64), (40, 5000, 48),
+]
+
+
+@pytest.mark.parametrize("nA,nB,D", CASES)
+def test_exact_small(nA, nB, D):
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"exact_hd nA={nA} nB={nB} D={D}")
+    g = np.random.default_rng(nA * 7 + nB + D)
+    A = (g.standard_normal((nA, D)) * 2 + 1).astype(np.float32)
+    B = (g.standard_normal((nB, D)) * 2 + 1.3).astype(np.float32)
+    out, n2A, n2B = ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True, nn2=True)
+    r = ph.decode_result(out)
+    o = oracle.exact_hd(A, B)
+    assert r["status"] == 0
+    assert (r["nA_sel"], r["nB_sel"]) == (nA, nB)
+    _check_dir(A, B, r["hAB"], r["ab_a"], r["ab_b"], o["hAB"], o["nnA"][r["ab_a"]])
+    _check_dir(B, A, r["hBA"], r["ba_b"], r["ba_a"], o["hBA"], o["nnB"][r["ba_b"]])
+    assert r["H"] == max(r["hAB"], r["hBA"])
+    # approximate per-row squared NN distances from the matrix-core search
+    s = A[0].astype(np.float64)
+    scale = max(np.max(np.sum((A - s) ** 2, 1)), np.max(np.sum((B - s) ** 2, 1)))
+    tol2 = 4e-6 * scale + 1e-5 * o["nnA"].max() ** 2
+    assert np.max(np.abs(n2A.cpu().numpy() - o["nnA"] ** 2)) <= tol2
+    assert np.max(np.abs(n2B.cpu().numpy() - o["nnB"] ** 2)) <= tol2
+
+
+def test_exact_identical_sets_zero():
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd identical / permuted sets")
+    A = synth.mixture(3000, 10, 64, seed=5, K=8)[0]
+    perm = np.random.default_rng(1).permutation(3000)
+    for B in (A, A[perm]):
+        r = ph.decode_result(ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True))
+        assert r["H"] == 0.0 and r["status"] == 0
+
+
+def test_exact_concentric_shells_cancellation():
+    # gap of 2^-10 of the radius: the float32 expansion loses most digits of
+    # d^2 here; the refinement by direct differences restores them.
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd shells r2 = (1 + 2^-10) r1")
+    A, B = synth.shells(4000, 32, seed=3, r1=1.0, r2=1.0 + 2.0 ** -10)
+    o = oracle.exact_hd(A, B)
+    r = ph.decode_result(ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True))
+    assert rel(r["H"], o["H"]) <= 1e-4
+
+
+def test_exact_symmetry():
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd symmetry")
+    A, B = synth.gauss_outliers(3000, 2500, 32, seed=2)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    r1 = ph.decode_result(ph.exact_hd(dA, dB, sync=True))
+    r2 = ph.decode_result(ph.exact_hd(dB, dA, sync=True))
+    assert r1["hAB"] == r2["hBA"] and r1["hBA"] == r2["hAB"]
+
+
+def test_exact_nonfinite_status():
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd non-finite input")
+    A = np.ones((64, 8), np.float32)
+    A[5, 3] = np.nan
+    B = np.zeros((40, 8), np.float32)
+    with pytest.raises(ph.ProhdError) as e:
+        ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True)
+    assert e.value.code == 2
+
+
+@pytest.mark.parametrize("inner_full", [False, True])
+@pytest.mark.parametrize("nA,nB,D,kk", [(3000, 2600, 32, 40), (20000, 18000, 128, 300), (5000, 7000, 256, 64)])
+def test_prohd_hd_given_indices(nA, nB, D, kk, inner_full):
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"prohd_hd nA={nA} nB={nB} D={D} full={inner_full}")
+    A, B = synth.mixture(nA, nB, D, seed=D + kk, K=16, outlier_frac=0.001)
+    g = np.random.default_rng(kk)
+    IA = np.sort(g.choice(nA, size=min(nA, 7 * kk + 13), replace=False))
+    IB = np.sort(g.choice(nB, size=min(nB, 5 * kk + 29), replace=False))
+    o = oracle.subset_hd(A, B, IA, IB, inner="full" if inner_full else "candidates")
+    iA = torch.from_numpy(IA.astype(np.int32)).cuda()
+    iB = torch.from_numpy(IB.astype(np.int32)).cuda()
+    cnt = torch.tensor([IA.size, IB.size], dtype=torch.int64, device=dev)
+    out = ph.prohd_hd(to_dev(torch, A), to_dev(torch, B), iA, cnt[0:1], iB, cnt[1:2],
+                      inner_full=inner_full, sync=True)
+    r = ph.decode_result(out)
+    assert r["status"] == 0 and (r["nA_sel"], r["nB_sel"]) == (IA.size, IB.size)
+    assert rel(r["H"], o["H"]) <= TOL
+    assert rel(r["hAB"], o["hAB"]) <= TOL and rel(r["hBA"], o["hBA"]) <= TOL
+    assert r["ab_a"] in set(IA.tolist()) and r["ba_b"] in set(IB.tolist())
+    if not inner_full:
+        assert r["ab_b"] in set(IB.tolist()) and r["ba_a"] in set(IA.tolist())
+    d = np.linalg.norm(A[r["ab_a"]].astype(np.float64) - B[r["ab_b"]].astype(np.float64))
+    assert abs(d - r["hAB"]) <= 1e-12 * d
+
+
+def test_prohd_hd_capacity_larger_than_count():
+    # device count below the capacity: only the first count entries are used
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("prohd_hd count < capacity")
+    A, B = synth.gauss_outliers(4000, 4000, 32, seed=7)
+    IA = np.arange(0, 4000, 7)
+    IB = np.arange(3, 4000, 5)
+    o = oracle.subset_hd(A, B, IA, IB)
+    pad = lambda I: np.concatenate([I, np.full(500, 123)]).astype(np.int32)
+    iA, iB = torch.from_numpy(pad(IA)).cuda(), torch.from_numpy(pad(IB)).cuda()
+    cnt = torch.tensor([IA.size, IB.size], dtype=torch.int64, device=dev)
+    r = ph.decode_result(ph.prohd_hd(to_dev(torch, A), to_dev(torch, B), iA, cnt[0:1], iB, cnt[1:2], sync=True))
+    assert rel(r["H"], o["H"]) <= TOL and (r["nA_sel"], r["nB_sel"]) == (IA.size, IB.size)
