@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (HBM-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -141,6 +143,12 @@ def main():
         kB = [ph.k_rule(alpha, nB)] + [ph.k_rule(alpha / m, nB)] * m
     dA = torch.from_numpy(A).to(dev)
     dB = torch.from_numpy(B).to(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     capA = int(min(nA, 2 * sum(min(k, nA) for k in kA)))
     capB = int(min(nB, 2 * sum(min(k, nB) for k in kB)))
     ws = ph.Workspace(dev)

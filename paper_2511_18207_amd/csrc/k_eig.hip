@@ -97,9 +97,13 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
   // ---------------------------------------------------- 1. tridiagonalise
   const int ci = t % DP;        // column owned in the matvec / update
   const int cq = t / DP;        // row block of that column
+  const int k0 = cq * S::QS;
+  const int k1 = k0 + S::QS;
+  __shared__ double sq[S::NQ];
+  // sigma of column 0 below the subdiagonal
+  double sigma = block_sum<NT>((t > 1 && t < DP) ? M[(size_t)t * DP] * M[(size_t)t * DP] : 0.0, red);
   for (int j = 0; j < DP - 2; ++j) {
     const double xk = (t > j + 1 && t < DP) ? M[(size_t)t * DP + j] : 0.0;
-    const double sigma = block_sum<NT>(xk * xk, red);
     const double alpha = M[(size_t)(j + 1) * DP + j];
     double tj = 0.0, beta = alpha, scale = 0.0;
     if (sigma > 0.0) {
@@ -120,13 +124,12 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
     }
     __syncthreads();
     if (tj != 0.0) {  // uniform
-      // p = tau * M v over the trailing block
-      if (cq < S::NQ && ci > j) {
+      // p = tau * M v over the trailing block (rows k > j, columns > j)
+      if (ci > j) {
         double acc = 0.0;
-        const int k0 = cq * S::QS;
+        const int kb = k0 > j + 1 ? k0 : j + 1;
 #pragma unroll 8
-        for (int k = k0; k < k0 + S::QS; ++k)
-          if (k > j) acc += M[(size_t)k * DP + ci] * vs[k];
+        for (int k = kb; k < k1; ++k) acc += M[(size_t)k * DP + ci] * vs[k];
         part[cq][ci] = acc;
       }
       __syncthreads();
@@ -140,15 +143,27 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
       const double K = 0.5 * tj * block_sum<NT>(p * v, red);
       if (t < DP) wv[t] = (t > j) ? p - K * v : 0.0;
       __syncthreads();
-      // M -= v w^T + w v^T on the trailing block
-      if (cq < S::NQ && ci > j) {
+      // M -= v w^T + w v^T on the trailing block; the owners of column j+1
+      // also sum its squares below the next subdiagonal (next step's sigma)
+      double s2 = 0.0;
+      if (ci > j) {
         const double vi = vs[ci], wi = wv[ci];
-        const int k0 = cq * S::QS;
+        const int kb = k0 > j + 1 ? k0 : j + 1;
 #pragma unroll 8
-        for (int k = k0; k < k0 + S::QS; ++k)
-          if (k > j) M[(size_t)k * DP + ci] -= vs[k] * wi + wv[k] * vi;
+        for (int k = kb; k < k1; ++k) {
+          const double nv = M[(size_t)k * DP + ci] - (vs[k] * wi + wv[k] * vi);
+          M[(size_t)k * DP + ci] = nv;
+          s2 += (k > j + 2) ? nv * nv : 0.0;
+        }
       }
+      if (ci == j + 1) sq[cq] = s2;
       __syncthreads();
+      sigma = 0.0;
+#pragma unroll
+      for (int q = 0; q < S::NQ; ++q) sigma += sq[q];
+    } else {
+      const double nx = (t > j + 2 && t < DP) ? M[(size_t)t * DP + j + 1] : 0.0;
+      sigma = block_sum<NT>(nx * nx, red);
     }
   }
   if (t == 0) {
@@ -184,7 +199,9 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
       for (int i = 1; i < DP; ++i) {
-        q = dd[i] - mid - e2[i - 1] / q;
+        double r = __builtin_amdgcn_rcp(q);   // 1/q, refined by one Newton step
+        r = fma(r, fma(-q, r, 1.0), r);
+        q = dd[i] - mid - e2[i - 1] * r;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
       }

@@ -37,11 +37,14 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int DP>
 struct GramShape {
-  static constexpr int WAVES = DP >= 256 ? 16 : 8;      // waves per work-group
+  static constexpr int WAVES = 8;                       // waves per work-group
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int NB = DP / 16;                    // 16-column blocks
   static constexpr int T = NB * (NB + 1) / 2;           // blocks with I <= J
-  static constexpr int TPW = (T + WAVES - 1) / WAVES;   // blocks per wave
+  static constexpr int TSPLIT = DP >= 256 ? 4 : (DP >= 128 ? 2 : 1);  // work-groups per row slice
+  static constexpr int TT = (T + TSPLIT - 1) / TSPLIT;  // blocks per work-group
+  static constexpr int TPW = (TT + WAVES - 1) / WAVES;  // blocks per wave
+  static constexpr int ST = DP + 16;                    // LDS row stride (doubles)
 };
 
 // Block t (0..T-1) -> (I, J), I <= J, enumerated row by row (compile time).
@@ -56,17 +59,33 @@ constexpr int cblock_j(int t, int nb) {
   return i < nb ? i + t : 0;
 }
 
-// The Gram blocks of wave W: t = W + WAVES*u.  Operands come from v[] with
-// compile-time indices, so every value stays in a register.
-template <int NB, int T, int WAVES, int W, int... U>
+// The Gram blocks of wave W in tile group TS: t = TS*TT + W + WAVES*u.
+// Operands come from v[] with compile-time indices, so every value stays in
+// a register.
+template <int NB, int T, int TT, int WAVES, int TS, int W, int... U>
 __device__ __forceinline__ void wave_blocks(doublex4* acc, const double* v,
                                             std::integer_sequence<int, U...>) {
-  ((acc[U] = (W + WAVES * U < T)
-                 ? __builtin_amdgcn_mfma_f64_16x16x4f64(v[cblock_i(W + WAVES * U, NB)],
-                                                        v[cblock_j(W + WAVES * U, NB)], acc[U],
-                                                        0, 0, 0)
+  ((acc[U] = (W + WAVES * U < TT && TS * TT + W + WAVES * U < T)
+                 ? __builtin_amdgcn_mfma_f64_16x16x4f64(
+                       v[cblock_i(TS * TT + W + WAVES * U, NB)],
+                       v[cblock_j(TS * TT + W + WAVES * U, NB)], acc[U], 0, 0, 0)
                  : acc[U]),
    ...);
+}
+
+template <int NB, int T, int TT, int WAVES, int TS, int TPW>
+__device__ __forceinline__ void wave_dispatch(int wave, doublex4* acc, const double* v) {
+  using Seq = std::make_integer_sequence<int, TPW>;
+  switch (wave) {
+    case 0: wave_blocks<NB, T, TT, WAVES, TS, 0>(acc, v, Seq{}); break;
+    case 1: wave_blocks<NB, T, TT, WAVES, TS, 1>(acc, v, Seq{}); break;
+    case 2: wave_blocks<NB, T, TT, WAVES, TS, 2>(acc, v, Seq{}); break;
+    case 3: wave_blocks<NB, T, TT, WAVES, TS, 3>(acc, v, Seq{}); break;
+    case 4: wave_blocks<NB, T, TT, WAVES, TS, 4>(acc, v, Seq{}); break;
+    case 5: wave_blocks<NB, T, TT, WAVES, TS, 5>(acc, v, Seq{}); break;
+    case 6: wave_blocks<NB, T, TT, WAVES, TS, 6>(acc, v, Seq{}); break;
+    default: wave_blocks<NB, T, TT, WAVES, TS, 7>(acc, v, Seq{}); break;
+  }
 }
 
 // Block t (0..T-1) -> (I, J), I <= J, enumerated row by row.
@@ -83,7 +102,7 @@ __device__ __forceinline__ void block_ij(int t, int nb, int& I, int& J) {
 template <int DP>
 __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const float* __restrict__ A, int64_t nA,
                                                     const float* __restrict__ B, int64_t nB,
-                                                    int D, int64_t rows_per_wg,
+                                                    int D, int64_t rows_per_wg, int nslices,
                                                     double* __restrict__ gpart,
                                                     double* __restrict__ spart,
                                                     int32_t* __restrict__ status) {
@@ -93,19 +112,27 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   constexpr int kWaves = S::WAVES;
   constexpr int RC = 32;                      // rows staged per chunk
   constexpr int PER = RC * DP / NT;           // staged elements per thread
-  __shared__ double wbuf[RC * DP];            // shifted rows, float64
+  constexpr int ST = S::ST;
+  __shared__ double wbuf[RC * ST];            // shifted rows, float64
   __shared__ double sred[NT];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int col = lane & 15;   // column within a 16-block
   const int rsub = lane >> 4;  // row within a group of four
-  // work-groups [0, wgA) take rows of A, the rest rows of B
+  // row slices [0, wgA) of A, then of B; TSPLIT work-groups per slice, each
+  // forming its share of the Gram blocks.  The work-groups of one slice get
+  // ids congruent mod 8, so they run on one XCD and share its L2.
+  const int xcd = blockIdx.x & 7;
+  const int q8 = blockIdx.x >> 3;
+  const int ts = q8 % S::TSPLIT;
+  const int slice = (q8 / S::TSPLIT) * 8 + xcd;
+  if (slice >= nslices) return;
   const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
-  const bool setA = (int64_t)blockIdx.x < wgA;
+  const bool setA = (int64_t)slice < wgA;
   const float* X = setA ? A : B;
   const int64_t nX = setA ? nA : nB;
-  const int64_t r_begin = (setA ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - wgA) * rows_per_wg;
+  const int64_t r_begin = (setA ? (int64_t)slice : (int64_t)slice - wgA) * rows_per_wg;
   const int64_t r_end = min(nX, r_begin + rows_per_wg);
 
   // staging: thread tid handles elements e = tid + NT i of a chunk, i.e.
@@ -118,12 +145,16 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   bool bad = false;
   float raw[PER];
   auto fetch = [&](int64_t r0) {
-    const float* base = X + r0 * D;            // uniform
+    // one per-thread base pointer, 32-bit offsets stepping by a uniform stride
+    const float* base = X + r0 * D + mycol;
     const int lim = (int)min<int64_t>(RC, r_end - r0);
+    const int step = RSTEP * D;
+    int off = myrow * D;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int rr = myrow + RSTEP * i;
-      raw[i] = (rr < lim && mycol < D) ? base[rr * D + mycol] : 0.f;
+      raw[i] = (rr < lim && mycol < D) ? base[off] : 0.f;
+      off += step;
     }
   };
   auto stage = [&](int64_t r0) {
@@ -134,7 +165,7 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
       const float x = raw[i];
       bad |= !(x - x == 0.f);
       const double w = (rr < lim && mycol < D) ? ((double)x - sh) : 0.0;
-      wbuf[tid + NT * i] = w;
+      wbuf[(myrow + RSTEP * i) * ST + mycol] = w;
       sum += w;
     }
   };
@@ -151,40 +182,17 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
     if (r0 + RC < r_end) fetch(r0 + RC);
 #pragma unroll 1
     for (int q = 0; q < RC / 4; ++q) {
-      const double* rowp = &wbuf[(4 * q + rsub) * DP + col];
+      const double* rowp = &wbuf[(4 * q + rsub) * ST + col];
       double v[NB];
 #pragma unroll
       for (int I = 0; I < NB; ++I) v[I] = rowp[16 * I];
-      using Seq = std::make_integer_sequence<int, S::TPW>;
-      if constexpr (kWaves == 8) {
-        switch (wave) {
-          case 0: wave_blocks<NB, S::T, 8, 0>(acc, v, Seq{}); break;
-          case 1: wave_blocks<NB, S::T, 8, 1>(acc, v, Seq{}); break;
-          case 2: wave_blocks<NB, S::T, 8, 2>(acc, v, Seq{}); break;
-          case 3: wave_blocks<NB, S::T, 8, 3>(acc, v, Seq{}); break;
-          case 4: wave_blocks<NB, S::T, 8, 4>(acc, v, Seq{}); break;
-          case 5: wave_blocks<NB, S::T, 8, 5>(acc, v, Seq{}); break;
-          case 6: wave_blocks<NB, S::T, 8, 6>(acc, v, Seq{}); break;
-          default: wave_blocks<NB, S::T, 8, 7>(acc, v, Seq{}); break;
-        }
-      } else {
-        switch (wave) {
-          case 0: wave_blocks<NB, S::T, 16, 0>(acc, v, Seq{}); break;
-          case 1: wave_blocks<NB, S::T, 16, 1>(acc, v, Seq{}); break;
-          case 2: wave_blocks<NB, S::T, 16, 2>(acc, v, Seq{}); break;
-          case 3: wave_blocks<NB, S::T, 16, 3>(acc, v, Seq{}); break;
-          case 4: wave_blocks<NB, S::T, 16, 4>(acc, v, Seq{}); break;
-          case 5: wave_blocks<NB, S::T, 16, 5>(acc, v, Seq{}); break;
-          case 6: wave_blocks<NB, S::T, 16, 6>(acc, v, Seq{}); break;
-          case 7: wave_blocks<NB, S::T, 16, 7>(acc, v, Seq{}); break;
-          case 8: wave_blocks<NB, S::T, 16, 8>(acc, v, Seq{}); break;
-          case 9: wave_blocks<NB, S::T, 16, 9>(acc, v, Seq{}); break;
-          case 10: wave_blocks<NB, S::T, 16, 10>(acc, v, Seq{}); break;
-          case 11: wave_blocks<NB, S::T, 16, 11>(acc, v, Seq{}); break;
-          case 12: wave_blocks<NB, S::T, 16, 12>(acc, v, Seq{}); break;
-          case 13: wave_blocks<NB, S::T, 16, 13>(acc, v, Seq{}); break;
-          case 14: wave_blocks<NB, S::T, 16, 14>(acc, v, Seq{}); break;
-          default: wave_blocks<NB, S::T, 16, 15>(acc, v, Seq{}); break;
+      if (ts == 0) {
+        wave_dispatch<NB, S::T, S::TT, kWaves, 0, S::TPW>(wave, acc, v);
+      } else if constexpr (S::TSPLIT > 1) {
+        if (ts == 1) wave_dispatch<NB, S::T, S::TT, kWaves, 1, S::TPW>(wave, acc, v);
+        if constexpr (S::TSPLIT > 2) {
+          if (ts == 2) wave_dispatch<NB, S::T, S::TT, kWaves, 2, S::TPW>(wave, acc, v);
+          if (ts == 3) wave_dispatch<NB, S::T, S::TT, kWaves, 3, S::TPW>(wave, acc, v);
         }
       }
     }
@@ -193,11 +201,12 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
 
   // partial Gram blocks: the 16x16x4 f64 result puts element v of lane l at
   // row l/16 + 4 v, column l%16
-  double* gp = gpart + (size_t)blockIdx.x * S::T * 256;
+  double* gp = gpart + (size_t)slice * S::T * 256;
 #pragma unroll
   for (int u = 0; u < S::TPW; ++u) {
-    const int t = wave + kWaves * u;
-    if (t < S::T) {
+    const int tl = wave + kWaves * u;
+    const int t = ts * S::TT + tl;
+    if (tl < S::TT && t < S::T) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[u][v];
     }
@@ -206,10 +215,10 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   __syncthreads();
   sred[tid] = sum;
   __syncthreads();
-  if (tid < DP) {
+  if (tid < DP && ts == 0) {
     double a = 0.0;
     for (int t = tid; t < NT; t += DP) a += sred[t];
-    double* sp = spart + (size_t)blockIdx.x * 2 * DP;
+    double* sp = spart + (size_t)slice * 2 * DP;
     sp[setA ? tid : DP + tid] = a;
     sp[setA ? DP + tid : tid] = 0.0;
   }
@@ -304,8 +313,9 @@ prohd_status stats_dp(const float* A, int64_t nA, const float* B, int64_t nB, in
   StatsLayout L = stats_layout(ar, nA, nB, DP, cu_count());
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "stats: workspace too small");
   const int nwg = L.nwg;
-  PROHD_LAUNCH("stats_gram", gram_partial<DP>, dim3(nwg), dim3(GramShape<DP>::THREADS), 0, s, A, nA,
-               B, nB, D, L.rows, L.gpart, L.spart, status);
+  const int grid = (int)(cdiv(nwg, 8) * 8) * GramShape<DP>::TSPLIT;
+  PROHD_LAUNCH("stats_gram", gram_partial<DP>, dim3(grid), dim3(GramShape<DP>::THREADS), 0, s, A,
+               nA, B, nB, D, L.rows, nwg, L.gpart, L.spart, status);
   const int nb = DP / 16;
   const int T = nb * (nb + 1) / 2;
   const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)T * 256, 256), 256));
