@@ -3,13 +3,13 @@
 // both sets, plus the driver that chains statistics -> eigensolve ->
 // projection without a host synchronisation.
 //
-// project_rows streams the n x D rows once from HBM (coalesced float4 loads
-// into an LDS tile of 64 rows, the next tile prefetched in registers while
-// the current one is used).  Each of the four waves takes a quarter of the
-// columns; lane = row.  Directions are read transposed (D x 8 per group), so
-// the eight values a k-step needs are wave-uniform scalar loads and the inner
-// loop is eight FMAs per LDS read.  Quarter sums meet in LDS and are written
-// direction-major: P[d * n + i], one coalesced store per direction.
+// project_rows streams the n x D rows once from HBM: a work-group of 512
+// threads owns 512 rows (one per thread) and walks their columns in chunks of
+// 32 (coalesced 128-byte row segments staged through LDS, the next chunk
+// prefetched in registers while the current one is used).  The directions
+// (up to 32 per launch) sit in LDS k-major, so a k-step is one LDS read of x
+// and a few broadcast float4 reads of direction values feeding 8-32 FMAs; the
+// finished row writes P[d * n + i] (coalesced across the wave per direction).
 // This pass is bound by HBM bandwidth: 4 D bytes read and 4 (m+1) bytes
 // written per row.
 
@@ -27,131 +27,126 @@ prohd_status eig_run(double* C, int32_t D, int32_t m, const double* u0, float* d
 
 namespace {
 
-constexpr int kRows = 64;     // rows per tile
-constexpr int kThreads = 256;
+constexpr int kTileRows = 512;  // rows per tile: one per thread
+constexpr int kThreads = 512;
 
-// Ut[k * ndp + d] = dirs[d * D + k] for d < ndirs, zero elsewhere.
-__global__ void transpose_dirs(const float* __restrict__ dirs, int ndirs, int D, int DP, int ndp,
+// Directions in blocks of 32: block b (directions 32b..) is stored k-major,
+// Ut[32 b DP + k nd8 + j] = dirs[32 b + j][k], nd8 = 8 ceil(nd/8) for the
+// nd directions of that block; zero for k >= D.
+__global__ void transpose_dirs(const float* __restrict__ dirs, int ndirs, int D, int DP,
                                float* __restrict__ Ut) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < DP * ndp; e += gridDim.x * blockDim.x) {
-    const int k = e / ndp, d = e - k * ndp;
-    Ut[e] = (d < ndirs && k < D) ? dirs[(size_t)d * D + k] : 0.f;
+  const int nblk = (ndirs + 31) / 32;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nblk * 32 * DP; e += gridDim.x * blockDim.x) {
+    const int b = e / (32 * DP);
+    const int r = e - b * 32 * DP;
+    const int nd = min(32, ndirs - 32 * b);
+    const int nd8 = 8 * ((nd + 7) / 8);
+    const int k = r / nd8, j = r - k * nd8;
+    if (k >= DP) continue;
+    Ut[(size_t)b * 32 * DP + r] = (j < nd && k < D) ? dirs[(size_t)(32 * b + j) * D + k] : 0.f;
   }
 }
 
-template <int DP, bool VEC>
+template <int DP, int NG, bool VEC>
 __global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict__ A, int64_t nA,
                                                          const float* __restrict__ B, int64_t nB,
                                                          int D, const float* __restrict__ Ut,
-                                                         int ndirs, int ndp,
+                                                         int ndirs,
                                                          float* __restrict__ PA,
                                                          float* __restrict__ PB) {
-  constexpr int ST = DP + 4;                        // LDS row stride (floats)
-  constexpr int KW = DP / 4;                        // columns per wave
-  constexpr int NF = VEC ? (kRows * DP / 4 + kThreads - 1) / kThreads   // float4 per thread
-                         : (kRows * DP + kThreads - 1) / kThreads;      // floats per thread
-  __shared__ __attribute__((aligned(16))) float tile[kRows * ST];
-  __shared__ float red[4][8][kRows];
+  constexpr int KC = DP < 32 ? DP : 32;             // columns per chunk
+  constexpr int NCH = DP / KC;                      // chunks per row
+  constexpr int ST = KC + 4;                        // LDS row stride (floats)
+  constexpr int ND = 8 * NG;                        // directions, padded
+  constexpr int F4R = KC / 4;                       // float4 per row chunk
+  constexpr int NF = kTileRows * F4R / kThreads;    // float4 per thread per chunk
+  __shared__ __attribute__((aligned(16))) float xt[kTileRows * ST];
+  __shared__ __attribute__((aligned(16))) float us[DP * ND];   // directions, k-major
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int64_t tilesA = (nA + kRows - 1) / kRows;
-  const int64_t tiles = tilesA + (nB + kRows - 1) / kRows;
-  const int ngroups = (ndirs + 7) / 8;
+  const int64_t tilesA = (nA + kTileRows - 1) / kTileRows;
+  const int64_t tiles = tilesA + (nB + kTileRows - 1) / kTileRows;
 
-  // LDS destinations of this thread's loads (identical for every tile)
-  int dst[NF];
-  const int D4 = D / 4;
-#pragma unroll
-  for (int i = 0; i < NF; ++i) {
-    const int f = tid + kThreads * i;
-    if (VEC) {
-      const int r = f / (D4 > 0 ? D4 : 1), c4 = f - r * D4;
-      dst[i] = (f < kRows * D4) ? r * ST + 4 * c4 : -1;
-    } else {
-      const int r = f / D, c = f - r * D;
-      dst[i] = (f < kRows * D) ? r * ST + c : -1;
-    }
-  }
-  float4 buf4[VEC ? NF : 1];
-  float buf1[VEC ? 1 : NF];
+  for (int e = tid; e < DP * ND; e += kThreads) us[e] = Ut[e];
 
-  auto load = [&](int64_t tl) {
+  float4 buf[NF];
+  // chunk c of tile tl: row f / F4R, float4 f % F4R of columns [c KC, c KC + KC)
+  auto load = [&](int64_t tl, int c) {
     const bool inA = tl < tilesA;
     const float* X = inA ? A : B;
     const int64_t n = inA ? nA : nB;
-    const int64_t r0 = (inA ? tl : tl - tilesA) * kRows;
-    const int64_t lim = (min<int64_t>(n, r0 + kRows) - r0) * D;  // valid floats in the tile
-    const float* base = X + r0 * D;
+    const int64_t r0 = (inA ? tl : tl - tilesA) * kTileRows;
+    const int rows = (int)min<int64_t>(kTileRows, n - r0);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const int f = tid + kThreads * i;
-      if (VEC) {
-        buf4[i] = (4 * (int64_t)f < lim && dst[i] >= 0)
-                      ? reinterpret_cast<const float4*>(base)[f]
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        buf1[i] = ((int64_t)f < lim && dst[i] >= 0) ? base[f] : 0.f;
+      const int r = f / F4R, j = f - r * F4R;
+      const int k = c * KC + 4 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < rows) {
+        const float* src = X + (r0 + r) * D + k;
+        if (VEC) {
+          if (k < D) v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (k + 0 < D) v.x = src[0];
+          if (k + 1 < D) v.y = src[1];
+          if (k + 2 < D) v.z = src[2];
+          if (k + 3 < D) v.w = src[3];
+        }
       }
+      buf[i] = v;
     }
   };
   auto store = [&]() {
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      if (dst[i] >= 0) {
-        if (VEC) *reinterpret_cast<float4*>(&tile[dst[i]]) = buf4[i];
-        else tile[dst[i]] = buf1[i];
-      }
+      const int f = tid + kThreads * i;
+      const int r = f / F4R, j = f - r * F4R;
+      *reinterpret_cast<float4*>(&xt[r * ST + 4 * j]) = buf[i];
     }
   };
 
   int64_t tl = blockIdx.x;
-  if (tl < tiles) load(tl);
+  if (tl < tiles) load(tl, 0);
   for (; tl < tiles; tl += gridDim.x) {
-    // pad columns D..DP stay zero: clear once per tile when D < DP
-    __syncthreads();
-    if (D < DP) {
-      for (int e = tid; e < kRows * ST; e += kThreads) tile[e] = 0.f;
+    float acc[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = 0.f;
+    for (int c = 0; c < NCH; ++c) {
       __syncthreads();
-    }
-    store();
-    __syncthreads();
-    const int64_t nxt = tl + gridDim.x;
-    if (nxt < tiles) load(nxt);
-
-    const bool inA = tl < tilesA;
-    const int64_t n = inA ? nA : nB;
-    const int64_t r0 = (inA ? tl : tl - tilesA) * kRows;
-    float* P = inA ? PA : PB;
-    const float* xr = &tile[lane * ST + wave * KW];
-    for (int g = 0; g < ngroups; ++g) {
-      float acc[8];
-#pragma unroll
-      for (int d = 0; d < 8; ++d) acc[d] = 0.f;
-      const float* u = Ut + (size_t)(wave * KW) * ndp + 8 * g;
-#pragma unroll 4
-      for (int k = 0; k < KW; ++k) {
-        const float x = xr[k];
-        const float* uk = u + (size_t)k * ndp;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) acc[d] = fmaf(x, uk[d], acc[d]);
-      }
-#pragma unroll
-      for (int d = 0; d < 8; ++d) red[wave][d][lane] = acc[d];
+      store();
       __syncthreads();
-      // 256 threads: row = tid % 64, two directions each
-      {
-        const int row = tid & 63;
-        const int d0 = (tid >> 6) * 2;
+      // prefetch the next chunk (or the first chunk of the next tile)
+      if (c + 1 < NCH) load(tl, c + 1);
+      else if (tl + gridDim.x < tiles) load(tl + gridDim.x, 0);
+      // row tid: x from LDS, direction values as broadcast float4 reads
+      const float* xr = &xt[tid * ST];
+      const float* uc = &us[(c * KC) * ND];
+#pragma unroll 2
+      for (int k4 = 0; k4 < KC / 4; ++k4) {
+        const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
+        const float xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-        for (int dd = 0; dd < 2; ++dd) {
-          const int d = d0 + dd;
-          const float v = (red[0][d][row] + red[1][d][row]) + (red[2][d][row] + red[3][d][row]);
-          const int dir = 8 * g + d;
-          if (dir < ndirs && r0 + row < n) P[(size_t)dir * n + r0 + row] = v;
+        for (int kk = 0; kk < 4; ++kk) {
+          const float* uk = uc + (4 * k4 + kk) * ND;
+#pragma unroll
+          for (int d4 = 0; d4 < ND / 4; ++d4) {
+            const float4 u = *reinterpret_cast<const float4*>(uk + 4 * d4);
+            acc[4 * d4 + 0] = fmaf(xs[kk], u.x, acc[4 * d4 + 0]);
+            acc[4 * d4 + 1] = fmaf(xs[kk], u.y, acc[4 * d4 + 1]);
+            acc[4 * d4 + 2] = fmaf(xs[kk], u.z, acc[4 * d4 + 2]);
+            acc[4 * d4 + 3] = fmaf(xs[kk], u.w, acc[4 * d4 + 3]);
+          }
         }
       }
-      __syncthreads();
+    }
+    const bool inA = tl < tilesA;
+    const int64_t n = inA ? nA : nB;
+    const int64_t row = (inA ? tl : tl - tilesA) * kTileRows + tid;
+    float* P = inA ? PA : PB;
+    if (row < n) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        if (d < ndirs) P[(size_t)d * n + row] = acc[d];
     }
   }
 }
@@ -172,26 +167,49 @@ ProjLayout proj_layout(Arena& ar, int64_t nA, int64_t nB, int D, int ndirs) {
   L.status = ar.take<int32_t>(64);
   L.C = ar.take<double>((size_t)DP * DP);
   L.u0 = ar.take<double>(DP);
-  L.Ut = ar.take<float>((size_t)DP * ndp);
+  L.Ut = ar.take<float>((size_t)DP * ((ndirs + 31) / 32) * 32);
   L.sub_bytes = std::max(stats_ws_bytes(nA, nB, D), eig_ws_bytes(D, ndirs - 1));
   L.sub = ar.take<char>(L.sub_bytes);
   return L;
 }
 
+template <int DP, int NG>
+prohd_status launch_project_ng(const float* A, int64_t nA, const float* B, int64_t nB, int D,
+                               const float* Ut, int ndirs, float* PA, float* PB, hipStream_t s) {
+  const int64_t tiles = cdiv(nA, kTileRows) + cdiv(nB, kTileRows);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cu_count()));
+  const bool vec = (D % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+  if (vec) {
+    PROHD_LAUNCH("project_rows", (project_rows<DP, NG, true>), dim3(grid), dim3(kThreads), 0, s, A, nA,
+                 B, nB, D, Ut, ndirs, PA, PB);
+  } else {
+    PROHD_LAUNCH("project_rows", (project_rows<DP, NG, false>), dim3(grid), dim3(kThreads), 0, s, A,
+                 nA, B, nB, D, Ut, ndirs, PA, PB);
+  }
+  return PROHD_OK;
+}
+
+// Direction groups of 8 per launch: 1, 2, 3 or 4 groups (up to 32 directions).
 template <int DP>
 prohd_status launch_project(const float* A, int64_t nA, const float* B, int64_t nB, int D,
                             const float* Ut, int ndirs, int ndp, float* PA, float* PB,
                             hipStream_t s) {
-  const int64_t tiles = cdiv(nA, kRows) + cdiv(nB, kRows);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 2 * cu_count()));
-  const bool vec = (D % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
-  if (vec) {
-    PROHD_LAUNCH("project_rows", (project_rows<DP, true>), dim3(grid), dim3(kThreads), 0, s, A, nA, B,
-                 nB, D, Ut, ndirs, ndp, PA, PB);
-  } else {
-    PROHD_LAUNCH("project_rows", (project_rows<DP, false>), dim3(grid), dim3(kThreads), 0, s, A, nA, B,
-                 nB, D, Ut, ndirs, ndp, PA, PB);
+  for (int d0 = 0; d0 < ndirs; d0 += 32) {
+    const int nd = std::min(32, ndirs - d0);
+    const int ng = (nd + 7) / 8;
+    const float* U = Ut + (size_t)d0 * DP;   // Ut is stored per 32-direction block
+    float* pa = PA + (size_t)d0 * nA;
+    float* pb = PB + (size_t)d0 * nB;
+    prohd_status r;
+    switch (ng) {
+      case 1: r = launch_project_ng<DP, 1>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
+      case 2: r = launch_project_ng<DP, 2>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
+      case 3: r = launch_project_ng<DP, 3>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
+      default: r = launch_project_ng<DP, 4>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
+    }
+    if (r) return r;
   }
+  (void)ndp;
   return PROHD_OK;
 }
 
@@ -222,7 +240,7 @@ prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB,
   const int DP = pad_dim(D);
   const int ndp = ((ndirs + 7) / 8) * 8;
   PROHD_LAUNCH("project_dirs", transpose_dirs, dim3(std::max(1, std::min(64, DP * ndp / 256))),
-               dim3(256), 0, s, dirs, ndirs, D, DP, ndp, L.Ut);
+               dim3(256), 0, s, dirs, ndirs, D, DP, L.Ut);
   switch (DP) {
     case 16: return launch_project<16>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
     case 32: return launch_project<32>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);

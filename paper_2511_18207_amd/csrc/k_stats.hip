@@ -9,8 +9,8 @@
 // covariance is then C = (G - N mu_w mu_w^T) / (N - 1) with mu_w the mean of
 // the shifted rows.
 //
-// gram_partial: one work-group per slice of rows of one set (8 waves, 16
-// at D > 128).  For every group
+// gram_partial: one work-group per slice of rows of one set (12 waves at
+// D >= 128, else 8).  For every group
 // of four rows, lane l holds w[row l/16][16*I + l%16] for each 16-column block
 // I; the 16x16 Gram block (I, J) gains one v_mfma_f64_16x16x4_f64 with A
 // operand = block I and B operand = block J (the four rows are the k index).
@@ -37,55 +37,44 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int DP>
 struct GramShape {
-  static constexpr int WAVES = 8;                       // waves per work-group
+  static constexpr int WAVES = DP >= 128 ? 12 : 8;      // waves per work-group
   static constexpr int THREADS = 64 * WAVES;
+  static constexpr int RC = DP >= 128 ? 48 : 32;        // rows staged per chunk
   static constexpr int NB = DP / 16;                    // 16-column blocks
   static constexpr int T = NB * (NB + 1) / 2;           // blocks with I <= J
-  static constexpr int TSPLIT = DP >= 256 ? 4 : (DP >= 128 ? 2 : 1);  // work-groups per row slice
-  static constexpr int TT = (T + TSPLIT - 1) / TSPLIT;  // blocks per work-group
-  static constexpr int TPW = (TT + WAVES - 1) / WAVES;  // blocks per wave
+  static constexpr int SB = NB >= 2 ? 2 : 1;            // super-block edge (blocks)
+  static constexpr int NS = NB / SB;                    // super-blocks per edge
+  static constexpr int TS = NS * (NS + 1) / 2;          // upper super-blocks
+  static constexpr int TSPLIT = DP >= 256 ? 3 : 1;      // work-groups per row slice
+  static constexpr int TSW = (TS + TSPLIT - 1) / TSPLIT;  // super-blocks per work-group
+  static constexpr int SPW = (TSW + WAVES - 1) / WAVES;   // super-blocks per wave
   static constexpr int ST = DP + 16;                    // LDS row stride (doubles)
 };
 
-// Block t (0..T-1) -> (I, J), I <= J, enumerated row by row (compile time).
-constexpr int cblock_i(int t, int nb) {
+// Upper-triangle index of block (I, J), I <= J, rows enumerated in order.
+__host__ __device__ constexpr int cblock_t(int I, int J, int nb) { return I * nb - I * (I - 1) / 2 + (J - I); }
+
+// Super-block s (0..TS-1) -> (P, Q), P <= Q, in units of SB blocks.
+constexpr int csb_p(int s, int ns) {
   int i = 0;
-  while (i < nb && t >= nb - i) { t -= nb - i; ++i; }
-  return i < nb ? i : 0;
+  while (i < ns && s >= ns - i) { s -= ns - i; ++i; }
+  return i < ns ? i : 0;
 }
-constexpr int cblock_j(int t, int nb) {
+constexpr int csb_q(int s, int ns) {
   int i = 0;
-  while (i < nb && t >= nb - i) { t -= nb - i; ++i; }
-  return i < nb ? i + t : 0;
+  while (i < ns && s >= ns - i) { s -= ns - i; ++i; }
+  return i < ns ? i + s : 0;
 }
 
-// The Gram blocks of wave W in tile group TS: t = TS*TT + W + WAVES*u.
-// Operands come from v[] with compile-time indices, so every value stays in
-// a register.
-template <int NB, int T, int TT, int WAVES, int TS, int W, int... U>
-__device__ __forceinline__ void wave_blocks(doublex4* acc, const double* v,
-                                            std::integer_sequence<int, U...>) {
-  ((acc[U] = (W + WAVES * U < TT && TS * TT + W + WAVES * U < T)
-                 ? __builtin_amdgcn_mfma_f64_16x16x4f64(
-                       v[cblock_i(TS * TT + W + WAVES * U, NB)],
-                       v[cblock_j(TS * TT + W + WAVES * U, NB)], acc[U], 0, 0, 0)
-                 : acc[U]),
-   ...);
-}
-
-template <int NB, int T, int TT, int WAVES, int TS, int TPW>
-__device__ __forceinline__ void wave_dispatch(int wave, doublex4* acc, const double* v) {
-  using Seq = std::make_integer_sequence<int, TPW>;
-  switch (wave) {
-    case 0: wave_blocks<NB, T, TT, WAVES, TS, 0>(acc, v, Seq{}); break;
-    case 1: wave_blocks<NB, T, TT, WAVES, TS, 1>(acc, v, Seq{}); break;
-    case 2: wave_blocks<NB, T, TT, WAVES, TS, 2>(acc, v, Seq{}); break;
-    case 3: wave_blocks<NB, T, TT, WAVES, TS, 3>(acc, v, Seq{}); break;
-    case 4: wave_blocks<NB, T, TT, WAVES, TS, 4>(acc, v, Seq{}); break;
-    case 5: wave_blocks<NB, T, TT, WAVES, TS, 5>(acc, v, Seq{}); break;
-    case 6: wave_blocks<NB, T, TT, WAVES, TS, 6>(acc, v, Seq{}); break;
-    default: wave_blocks<NB, T, TT, WAVES, TS, 7>(acc, v, Seq{}); break;
+// Super-block s -> (P, Q), P <= Q (wave-uniform values).
+__device__ __forceinline__ void sb_pq(int s, int ns, int& P, int& Q) {
+  int i = 0, rem = s;
+  while (rem >= ns - i) {
+    rem -= ns - i;
+    ++i;
   }
+  P = i;
+  Q = i + rem;
 }
 
 // Block t (0..T-1) -> (I, J), I <= J, enumerated row by row.
@@ -107,11 +96,10 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
                                                     double* __restrict__ spart,
                                                     int32_t* __restrict__ status) {
   using S = GramShape<DP>;
-  constexpr int NB = S::NB;
   constexpr int NT = S::THREADS;
-  constexpr int kWaves = S::WAVES;
-  constexpr int RC = 32;                      // rows staged per chunk
+  constexpr int RC = S::RC;
   constexpr int PER = RC * DP / NT;           // staged elements per thread
+  static_assert(NT % DP == 0 && (RC * DP) % NT == 0 && RC % 4 == 0, "staging shape");
   constexpr int ST = S::ST;
   __shared__ double wbuf[RC * ST];            // shifted rows, float64
   __shared__ double sred[NT];
@@ -120,9 +108,8 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int col = lane & 15;   // column within a 16-block
   const int rsub = lane >> 4;  // row within a group of four
-  // row slices [0, wgA) of A, then of B; TSPLIT work-groups per slice, each
-  // forming its share of the Gram blocks.  The work-groups of one slice get
-  // ids congruent mod 8, so they run on one XCD and share its L2.
+  // row slices [0, wgA) of A, then of B; TSPLIT work-groups per slice share
+  // its super-blocks and get ids congruent mod 8 (one XCD, one L2)
   const int xcd = blockIdx.x & 7;
   const int q8 = blockIdx.x >> 3;
   const int ts = q8 % S::TSPLIT;
@@ -170,9 +157,24 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
     }
   };
 
-  doublex4 acc[S::TPW];
+  // this wave's super-blocks s = wave + WAVES u: block rows P*SB.., columns Q*SB..
+  int sp[S::SPW], sq[S::SPW];
 #pragma unroll
-  for (int u = 0; u < S::TPW; ++u) acc[u] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < S::SPW; ++u) {
+    const int sl = wave + S::WAVES * u;
+    const int sidx = ts * S::TSW + sl;
+    if (sl < S::TSW && sidx < S::TS) {
+      sb_pq(sidx, S::NS, sp[u], sq[u]);
+    } else {
+      sp[u] = -1;
+      sq[u] = -1;
+    }
+  }
+  doublex4 acc[S::SPW][S::SB * S::SB];
+#pragma unroll
+  for (int u = 0; u < S::SPW; ++u)
+#pragma unroll
+    for (int x = 0; x < S::SB * S::SB; ++x) acc[u][x] = doublex4{0.0, 0.0, 0.0, 0.0};
 
   if (r_begin < r_end) fetch(r_begin);
   for (int64_t r0 = r_begin; r0 < r_end; r0 += RC) {
@@ -183,32 +185,47 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
 #pragma unroll 1
     for (int q = 0; q < RC / 4; ++q) {
       const double* rowp = &wbuf[(4 * q + rsub) * ST + col];
-      double v[NB];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I] = rowp[16 * I];
-      if (ts == 0) {
-        wave_dispatch<NB, S::T, S::TT, kWaves, 0, S::TPW>(wave, acc, v);
-      } else if constexpr (S::TSPLIT > 1) {
-        if (ts == 1) wave_dispatch<NB, S::T, S::TT, kWaves, 1, S::TPW>(wave, acc, v);
-        if constexpr (S::TSPLIT > 2) {
-          if (ts == 2) wave_dispatch<NB, S::T, S::TT, kWaves, 2, S::TPW>(wave, acc, v);
-          if (ts == 3) wave_dispatch<NB, S::T, S::TT, kWaves, 3, S::TPW>(wave, acc, v);
+      for (int u = 0; u < S::SPW; ++u) {
+        if (sp[u] >= 0) {
+          double a[S::SB], b[S::SB];
+#pragma unroll
+          for (int x = 0; x < S::SB; ++x) {
+            a[x] = rowp[16 * (sp[u] * S::SB + x)];
+            b[x] = rowp[16 * (sq[u] * S::SB + x)];
+          }
+          const bool diag = sp[u] == sq[u];
+#pragma unroll
+          for (int x = 0; x < S::SB; ++x)
+#pragma unroll
+            for (int y = 0; y < S::SB; ++y)
+              if (!diag || x <= y)
+                acc[u][x * S::SB + y] =
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[u][x * S::SB + y], 0, 0, 0);
         }
       }
     }
   }
   if (bad) atomicOr(status, ST_NONFINITE);
 
-  // partial Gram blocks: the 16x16x4 f64 result puts element v of lane l at
-  // row l/16 + 4 v, column l%16
+  // live blocks: element v of lane l of the 16x16x4 f64 result is row
+  // l/16 + 4 v, column l%16
   double* gp = gpart + (size_t)slice * S::T * 256;
 #pragma unroll
-  for (int u = 0; u < S::TPW; ++u) {
-    const int tl = wave + kWaves * u;
-    const int t = ts * S::TT + tl;
-    if (tl < S::TT && t < S::T) {
+  for (int u = 0; u < S::SPW; ++u) {
+    if (sp[u] >= 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[u][v];
+      for (int x = 0; x < S::SB; ++x)
+#pragma unroll
+        for (int y = 0; y < S::SB; ++y) {
+          const int I = sp[u] * S::SB + x, J = sq[u] * S::SB + y;
+          if (I <= J) {
+            const int t = cblock_t(I, J, S::NB);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[u][x * S::SB + y][v];
+          }
+        }
     }
   }
   // partial column sums: the NT/DP threads of each column combine in LDS
