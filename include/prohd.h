@@ -69,6 +69,10 @@ enum {
   PROHD_DIRS_GIVEN = 1u << 0, /* prohd_project: `dirs` is an input          */
   PROHD_INNER_FULL = 1u << 1, /* prohd_hd: inner minimum over the whole other
                                  set: max{h(A_sel,B), h(B_sel,A)} <= H(A,B)  */
+  PROHD_PREC_BF16 = 1u << 2,  /* prohd_hd / exact_hd: distance search tiles
+                                 in bfloat16 (float32 accumulation)          */
+  PROHD_PREC_FP8 = 1u << 3,   /* ... in float8 e4m3 with one power-of-two
+                                 scale (float32 accumulation)                */
   PROHD_SYNC = 1u << 4        /* wait for the stream; return device status  */
 };
 

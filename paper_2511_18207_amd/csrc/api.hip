@@ -14,11 +14,11 @@ namespace prohd {
 // Defined in k_hd.hip / k_project.hip.
 prohd_status hd_candidates(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
                            const int32_t* idxA, const int64_t* dnA, int64_t capA,
-                           const int32_t* idxB, const int64_t* dnB, int64_t capB, bool full,
+                           const int32_t* idxB, const int64_t* dnB, int64_t capB, uint32_t flags,
                            prohd_result* out, void* ws, size_t ws_bytes, hipStream_t s);
 prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
-                      prohd_result* out, float* nn2A, float* nn2B, void* ws, size_t ws_bytes,
-                      hipStream_t s);
+                      uint32_t flags, prohd_result* out, float* nn2A, float* nn2B, void* ws,
+                      size_t ws_bytes, hipStream_t s);
 prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
                          int32_t m, bool dirs_given, float* dirs, float* projA, float* projB,
                          double* evals, int32_t* status, void* ws, size_t ws_bytes, hipStream_t s);
@@ -133,8 +133,8 @@ size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs, in
   size_t need = project_ws_bytes(nA, nB, D, ndirs);
   need = std::max(need, select_ws_bytes(2 * ndirs, std::max(nA, nB)) +
                             compact_ws_bytes(std::max(nA, nB)) + (size_t)(nA + nB) + 1024);
-  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true));
-  need = std::max(need, exact_ws_bytes(nA, nB, D));
+  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true, PROHD_PREC_BF16));
+  need = std::max(need, exact_ws_bytes(nA, nB, D, PROHD_PREC_BF16));
   return need;
 }
 
@@ -214,7 +214,10 @@ prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       prohd_result* out, void* ws, size_t ws_bytes, void* stream) {
   prohd_status st = check_sets(A, nA, B, nB, D);
   if (st) return st;
-  if (flags & ~(uint32_t)(PROHD_INNER_FULL | PROHD_SYNC)) return fail(PROHD_EINVAL, "unknown flag");
+  if (flags & ~(uint32_t)(PROHD_INNER_FULL | PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC))
+    return fail(PROHD_EINVAL, "unknown flag");
+  if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
+    return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");
   if (bad_ptr(idxA) || bad_ptr(idxB) || bad_ptr(nselA) || bad_ptr(nselB))
     return fail(PROHD_EINVAL, "index inputs must be non-null");
   if (capA < 1 || capB < 1 || capA > nA || capB > nB)
@@ -222,10 +225,10 @@ prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
   if (bad_ptr(out)) return fail(PROHD_EINVAL, "out must be non-null");
   if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
   const bool full = (flags & PROHD_INNER_FULL) != 0;
-  if (ws_bytes < hd_ws_bytes(nA, nB, D, capA, capB, full))
+  if (ws_bytes < hd_ws_bytes(nA, nB, D, capA, capB, full, flags))
     return fail(PROHD_EWORKSPACE, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
-  st = hd_candidates(A, nA, B, nB, D, idxA, nselA, capA, idxB, nselB, capB, full, out, ws, ws_bytes, s);
+  st = hd_candidates(A, nA, B, nB, D, idxA, nselA, capA, idxB, nselB, capB, flags, out, ws, ws_bytes, s);
   return finish(st, flags, s, out ? &out->status : nullptr);
 }
 
@@ -234,12 +237,15 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       size_t ws_bytes, void* stream) {
   prohd_status st = check_sets(A, nA, B, nB, D);
   if (st) return st;
-  if (flags & ~(uint32_t)PROHD_SYNC) return fail(PROHD_EINVAL, "unknown flag");
+  if (flags & ~(uint32_t)(PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC))
+    return fail(PROHD_EINVAL, "unknown flag");
+  if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
+    return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");
   if (bad_ptr(out)) return fail(PROHD_EINVAL, "out must be non-null");
   if (bad_ptr(ws)) return fail(PROHD_EINVAL, "workspace must be non-null");
-  if (ws_bytes < exact_ws_bytes(nA, nB, D)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  if (ws_bytes < exact_ws_bytes(nA, nB, D, flags)) return fail(PROHD_EWORKSPACE, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
-  st = hd_exact(A, nA, B, nB, D, out, nn2A, nn2B, ws, ws_bytes, s);
+  st = hd_exact(A, nA, B, nB, D, flags, out, nn2A, nn2B, ws, ws_bytes, s);
   return finish(st, flags, s, out ? &out->status : nullptr);
 }
 

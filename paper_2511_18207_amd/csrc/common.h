@@ -100,8 +100,9 @@ prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n
 prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s);
 
 // Distance core (k_hd.hip).
-size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full);
-size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D);
+size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
+                   uint32_t flags);
+size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags);
 
 // Direction finding and projection (k_stats.hip, k_eig.hip, k_project.hip).
 size_t project_ws_bytes(int64_t nA, int64_t nB, int32_t D, int32_t ndirs);

@@ -24,9 +24,9 @@
 //            Minima are kept as float bit patterns of non-negative values,
 //            whose unsigned order is the float order.
 //   refine   the R rows with the largest approximate minimum (R = 256, or all
-//            rows if fewer) are re-measured against every row of Y by float32
-//            direct differences sum (x_k - y_k)^2, keeping the arg-min (smallest
-//            index on ties).
+//            rows if fewer) are re-measured against every row of Y in float64
+//            (matrix-core float64 expansion of the exactly converted rows),
+//            keeping the arg-min (smallest index on ties).
 //   finalize the largest refined minimum per direction gives the witness pair,
 //            whose distance is recomputed in float64 from the original rows.
 
@@ -65,7 +65,8 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
                                                  const int32_t* __restrict__ sidx,
                                                  const int64_t* __restrict__ sdn,
                                                  float* __restrict__ Xp, float* __restrict__ xn,
-                                                 int32_t* __restrict__ status) {
+                                                 int32_t* __restrict__ status,
+                                                 uint32_t* __restrict__ maxabs) {
   const int64_t n = dev_or(dn, hn);
   if (n <= 0) return;
   const int lane = threadIdx.x & 63;
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     sv[c] = (k < D) ? srow[k] : 0.f;
   }
   bool bad = false;
+  float amax = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
     const int64_t src = idx ? (int64_t)idx[i] : i;
     const float* xr = X + src * D;
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         }
         Xp[i * DP + k] = v;
         acc = fmaf(v, v, acc);
+        amax = fmaxf(amax, fabsf(v));
       }
     }
 #pragma unroll
@@ -103,6 +106,11 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     if (lane == 0) xn[i] = acc;
   }
   if (bad) atomicOr(status, ST_NONFINITE);
+  if (maxabs) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    if ((threadIdx.x & 63) == 0 && amax == amax) atomicMax(maxabs, __float_as_uint(amax));
+  }
 }
 
 __global__ void fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -271,9 +279,267 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
   }
 }
 
+// ------------------------------------------------- low-precision copies
+// Matrix-core input formats: bfloat16 (round to nearest even) and OCP
+// float8 e4m3 with one power-of-two scale for both sets, chosen from the
+// largest |shifted value| so that scaled values stay below 224 (e4m3 max 448).
+enum { FMT_F32 = 0, FMT_BF16 = 1, FMT_FP8 = 2 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+// Row length of the low-precision copies: float8 ops take 64 k per op, so
+// rows are padded to at least 64 columns.
+__host__ __device__ constexpr int qdim(int DP, int fmt) { return fmt == FMT_FP8 && DP < 64 ? 64 : DP; }
+
+__device__ __forceinline__ float fp8_scale(const uint32_t* maxabs) {
+  const float m = __uint_as_float(*maxabs);
+  if (!(m > 0.f) || !(m < 3.0e38f)) return 1.f;
+  return exp2f(floorf(log2f(224.f / m)));
+}
+
+// Xq[i] = quantised Xp[i] (DP elements), qn[i] = |dequantised row|^2.
+template <int DP, int FMT>
+__global__ __launch_bounds__(256) void quant_rows(const float* __restrict__ Xp,
+                                                  const int64_t* __restrict__ dn, int64_t hn,
+                                                  const uint32_t* __restrict__ maxabs,
+                                                  void* __restrict__ Xq, float* __restrict__ qn) {
+  constexpr int QD = qdim(DP, FMT);
+  const int64_t n = dev_or(dn, hn);
+  const int lane = threadIdx.x & 63;
+  const float sc = (FMT == FMT_FP8) ? fp8_scale(maxabs) : 1.f;
+  const float isc = 1.f / sc;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    float acc = 0.f;
+    // each lane converts pairs of elements k = 2 (lane + 64 c)
+    for (int k = 2 * lane; k < QD; k += 128) {
+      const float v0 = k < DP ? Xp[i * DP + k] : 0.f;
+      const float v1 = k + 1 < DP ? Xp[i * DP + k + 1] : 0.f;
+      if (FMT == FMT_BF16) {
+        const __bf16 b0 = (__bf16)v0, b1 = (__bf16)v1;
+        __bf16* q = reinterpret_cast<__bf16*>(Xq) + i * QD + k;
+        q[0] = b0;
+        q[1] = b1;
+        const float d0 = (float)b0, d1 = (float)b1;
+        acc = fmaf(d0, d0, acc);
+        acc = fmaf(d1, d1, acc);
+      } else {
+        const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(v0 * sc, v1 * sc, 0, false);
+        uint8_t* q = reinterpret_cast<uint8_t*>(Xq) + i * QD + k;
+        q[0] = (uint8_t)(pk & 0xff);
+        q[1] = (uint8_t)((pk >> 8) & 0xff);
+        const float d0 = __builtin_amdgcn_cvt_f32_fp8(pk, 0) * isc;
+        const float d1 = __builtin_amdgcn_cvt_f32_fp8(pk, 1) * isc;
+        acc = fmaf(d0, d0, acc);
+        acc = fmaf(d1, d1, acc);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) qn[i] = acc;
+  }
+}
+
+// Same contract as dist_tile, on bfloat16 / float8 inputs with float32
+// accumulation: v_mfma_f32_32x32x16_bf16 (K = 16) or
+// v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales (K = 64).  Each lane
+// supplies K/2 consecutive k of its half-wave's k range per op.  Y blocks of
+// 128 rows (four 32-column subtiles) per LDS buffer; two accumulators let
+// the epilogue of one subtile run while the next subtile's ops execute.
+template <int FMT>
+struct LpFmt {
+  static constexpr int KPM = FMT == FMT_BF16 ? 16 : 64;   // k per op
+  static constexpr int EB = FMT == FMT_BF16 ? 2 : 1;      // bytes per element
+  static constexpr int LB = KPM / 2 * EB;                 // bytes per lane per op (16 or 32)
+};
+
+constexpr int kLpBN = 128;   // Y rows per LDS buffer
+
+template <int DP, int FMT, bool COLMIN>
+__global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
+                                                    const float* __restrict__ xn,
+                                                    const int64_t* __restrict__ dnX, int64_t hnX,
+                                                    const uint8_t* __restrict__ Yq,
+                                                    const float* __restrict__ yn,
+                                                    const int64_t* __restrict__ dnY, int64_t hnY,
+                                                    int ysplit, const uint32_t* __restrict__ maxabs,
+                                                    uint32_t* __restrict__ rowmin,
+                                                    uint32_t* __restrict__ colmin) {
+  using F = LpFmt<FMT>;
+  constexpr int RB = DP * F::EB;            // bytes per row
+  constexpr int STB = RB + 16;              // LDS row stride (bytes): conflict-free b128
+  constexpr int NS = DP / F::KPM;           // ops per 32x32 subtile
+  constexpr int NA = RB / 2 / 16;           // 16-byte chunks of a lane's A operand
+  constexpr int NV = kLpBN * RB / 16;       // 16-byte chunks per Y buffer
+  constexpr int PF = (NV + 511) / 512;      // per thread
+  __shared__ __attribute__((aligned(16))) uint8_t ys[2][kLpBN * STB];
+  __shared__ float yns[2][kLpBN];
+  __shared__ uint32_t cmin[2][kLpBN];
+
+  const int64_t nX = dev_or(dnX, hnX);
+  const int64_t nY = dev_or(dnY, hnY);
+  const int xblk = blockIdx.x / ysplit;
+  const int ysi = blockIdx.x - xblk * ysplit;
+  const int64_t x0 = (int64_t)xblk * kTileRows;
+  if (x0 >= nX) return;
+  const int64_t chunk = ((nY + ysplit - 1) / ysplit + kLpBN - 1) / kLpBN * kLpBN;
+  const int64_t yb = (int64_t)ysi * chunk;
+  const int64_t ye = min(nY, yb + chunk);
+  if (yb >= ye) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 5;
+  const int c = lane & 31;
+  float dscale = -2.f;
+  if (FMT == FMT_FP8) {
+    const float sc = fp8_scale(maxabs);
+    dscale = -2.f / (sc * sc);
+  }
+
+  uint4 a[NA];
+  {
+    const int64_t xr = x0 + 32 * wave + c;
+    if (xr < nX) {
+      const uint4* src = reinterpret_cast<const uint4*>(Xq + xr * RB + g * (RB / 2));
+#pragma unroll
+      for (int j = 0; j < NA; ++j) a[j] = src[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) a[j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  float xq[16], rmin[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t r = x0 + 32 * wave + 8 * (v >> 2) + 4 * g + (v & 3);
+    xq[v] = (r < nX) ? xn[r] : __uint_as_float(kInfBits);
+    rmin[v] = __uint_as_float(kInfBits);
+  }
+
+  auto load_block = [&](int64_t y0, uint4 (&buf)[PF], float& ynv) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int f = tid + 512 * p;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (f < NV) {
+        const int r = f / (RB / 16);
+        const int q = f - r * (RB / 16);
+        if (y0 + r < ye) v = reinterpret_cast<const uint4*>(Yq + (y0 + r) * RB)[q];
+      }
+      buf[p] = v;
+    }
+    ynv = (tid < kLpBN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
+  };
+  auto store_block = [&](int b, const uint4 (&buf)[PF], float ynv) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int f = tid + 512 * p;
+      if (f < NV) {
+        const int r = f / (RB / 16);
+        const int q = f - r * (RB / 16);
+        *reinterpret_cast<uint4*>(&ys[b][r * STB + 16 * q]) = buf[p];
+      }
+    }
+    if (tid < kLpBN) {
+      yns[b][tid] = ynv;
+      cmin[b][tid] = kInfBits;
+    }
+  };
+  auto subtile = [&](int b, int t) {
+    floatx16 acc = {0.f};
+    const uint8_t* yrow = &ys[b][(32 * t + c) * STB + g * (RB / 2)];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if constexpr (FMT == FMT_BF16) {
+        const uint4 bv = *reinterpret_cast<const uint4*>(yrow + 16 * s);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]),
+                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+      } else {
+        const uint4 b0 = *reinterpret_cast<const uint4*>(yrow + 32 * s);
+        const uint4 b1 = *reinterpret_cast<const uint4*>(yrow + 32 * s + 16);
+        const intx8 av = {(int)a[2 * s].x, (int)a[2 * s].y, (int)a[2 * s].z, (int)a[2 * s].w,
+                          (int)a[2 * s + 1].x, (int)a[2 * s + 1].y, (int)a[2 * s + 1].z,
+                          (int)a[2 * s + 1].w};
+        const intx8 bw = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                          (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+        // formats 0/0 = e4m3 for both operands; scales 0x7f = 2^0
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bw, acc, 0, 0, 0, 0x7f7f7f7f, 0,
+                                                               0x7f7f7f7f);
+      }
+    }
+    return acc;
+  };
+  auto epilogue = [&](int b, int t, const floatx16& acc) {
+    const float ynv = yns[b][32 * t + c];
+    float cm = __uint_as_float(kInfBits);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float d = fmaf(dscale, acc[v], xq[v] + ynv);
+      rmin[v] = fminf(rmin[v], d);
+      cm = fminf(cm, d);
+    }
+    if (COLMIN) {
+      cm = fminf(cm, __shfl_xor(cm, 32));
+      if (g == 0) atomicMin(&cmin[b][32 * t + c], clamp_bits(cm));
+    }
+  };
+
+  uint4 pf[PF];
+  float pyn;
+  load_block(yb, pf, pyn);
+  store_block(0, pf, pyn);
+  __syncthreads();
+
+  int cur = 0;
+  for (int64_t y0 = yb; y0 < ye; y0 += kLpBN) {
+    const bool more = y0 + kLpBN < ye;
+    if (more) load_block(y0 + kLpBN, pf, pyn);
+    const int nsub = (int)min<int64_t>(4, (ye - y0 + 31) / 32);
+    floatx16 acc0 = subtile(cur, 0);
+    floatx16 acc1;
+    if (nsub > 1) acc1 = subtile(cur, 1);
+    epilogue(cur, 0, acc0);
+    if (nsub > 2) acc0 = subtile(cur, 2);
+    if (nsub > 1) epilogue(cur, 1, acc1);
+    if (nsub > 3) acc1 = subtile(cur, 3);
+    if (nsub > 2) epilogue(cur, 2, acc0);
+    if (nsub > 3) epilogue(cur, 3, acc1);
+    if (more) store_block(cur ^ 1, pf, pyn);
+    __syncthreads();
+    if (COLMIN && tid < kLpBN) {
+      const uint32_t v = cmin[cur][tid];
+      if (y0 + tid < ye) atomicMin(&colmin[y0 + tid], v);
+    }
+    cur ^= 1;
+  }
+
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    float x = rmin[v];
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) x = fminf(x, __shfl_xor(x, off));
+    rmin[v] = x;
+  }
+  float mine = __uint_as_float(kInfBits);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) mine = (c == v) ? rmin[v] : mine;
+  if (c < 16) {
+    const int64_t r = x0 + 32 * wave + 8 * (c >> 2) + 4 * g + (c & 3);
+    if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
+  }
+}
+
 // ---------------------------------------------------------------- refine
-// best[r] = min over y of (bits(sum_k (x_k - y_k)^2) << 32 | y) for the
-// candidate rows cand[r], r < R.
+// best[r] = min over y of (bits(float(d2)) << 32 | y), ties to the smallest y,
+// for candidate rows cand[r], r < R, with d2 = |x|^2 + |y|^2 - 2 x.y evaluated
+// in float64 (v_mfma_f64_16x16x4f64 on the exactly converted float32 rows):
+// the expansion's rounding is ~1e-16 |x|^2, far below float32 resolution.
+// A wave owns 16 candidate rows (A operands in registers); Y streams through
+// LDS as float64, 32 rows per block (two 16-column accumulators).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 template <int DP>
 __global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
                                                    const int32_t* __restrict__ cand,
@@ -282,78 +548,101 @@ __global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
                                                    const int64_t* __restrict__ dnY, int64_t hnY,
                                                    int ysplit,
                                                    unsigned long long* __restrict__ best) {
-  constexpr int RB = 8;     // candidate rows per work-group
-  constexpr int BN = 64;    // Y rows per LDS block
-  constexpr int ST = DP + 4;
-  __shared__ __attribute__((aligned(16))) float xs[RB * DP];
-  __shared__ __attribute__((aligned(16))) float ysm[BN * ST];
+  constexpr int KS = DP / 4;        // k steps of the 16x16x4 op
+  constexpr int BNY = 32;           // Y rows per LDS block
+  constexpr int STY = DP + 4;       // LDS row stride (doubles)
+  __shared__ double ys[BNY * STY];
+  __shared__ double yq[BNY];
   const int64_t R = *dR;
   const int64_t nY = dev_or(dnY, hnY);
   const int cb = blockIdx.x / ysplit;
   const int ysi = blockIdx.x - cb * ysplit;
-  if ((int64_t)cb * RB >= R) return;
-  const int64_t chunk = ((nY + ysplit - 1) / ysplit + BN - 1) / BN * BN;
+  if ((int64_t)cb * 64 >= R) return;
+  const int64_t chunk = ((nY + ysplit - 1) / ysplit + BNY - 1) / BNY * BNY;
   const int64_t yb = (int64_t)ysi * chunk;
   const int64_t ye = min(nY, yb + chunk);
   if (yb >= ye) return;
   const int tid = threadIdx.x;
-  for (int f = tid; f < RB * DP; f += 256) {
-    const int r = f / DP, k = f - r * DP;
-    const int64_t cr = (int64_t)cb * RB + r;
-    xs[f] = (cr < R) ? Xp[(int64_t)cand[cr] * DP + k] : 0.f;
-  }
-  const int q = tid >> 6;   // candidate pair 2q, 2q+1 (one per wave: broadcast reads)
-  const int j = tid & 63;   // Y row within the block
-  float b0 = __uint_as_float(kInfBits), b1 = b0;
-  int64_t i0 = 0, i1 = 0;
-  for (int64_t y0 = yb; y0 < ye; y0 += BN) {
-    __syncthreads();
-    for (int f = tid; f < BN * DP / 4; f += 256) {
-      const int r = f / (DP / 4), k4 = f - r * (DP / 4);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (y0 + r < ye) v = reinterpret_cast<const float4*>(Yp + (y0 + r) * DP)[k4];
-      *reinterpret_cast<float4*>(&ysm[r * ST + 4 * k4]) = v;
-    }
-    __syncthreads();
-    if (y0 + j < ye) {
-      float s0[4] = {0.f, 0.f, 0.f, 0.f}, s1[4] = {0.f, 0.f, 0.f, 0.f};
-      const float* yr = &ysm[j * ST];
-      const float* x0r = &xs[(2 * q) * DP];
-      const float* x1r = &xs[(2 * q + 1) * DP];
-#pragma unroll 8
-      for (int k = 0; k < DP; k += 4) {
-        const float4 y = *reinterpret_cast<const float4*>(yr + k);
-        const float4 u = *reinterpret_cast<const float4*>(x0r + k);
-        const float4 w = *reinterpret_cast<const float4*>(x1r + k);
-        float t;
-        t = u.x - y.x; s0[0] = fmaf(t, t, s0[0]);
-        t = u.y - y.y; s0[1] = fmaf(t, t, s0[1]);
-        t = u.z - y.z; s0[2] = fmaf(t, t, s0[2]);
-        t = u.w - y.w; s0[3] = fmaf(t, t, s0[3]);
-        t = w.x - y.x; s1[0] = fmaf(t, t, s1[0]);
-        t = w.y - y.y; s1[1] = fmaf(t, t, s1[1]);
-        t = w.z - y.z; s1[2] = fmaf(t, t, s1[2]);
-        t = w.w - y.w; s1[3] = fmaf(t, t, s1[3]);
-      }
-      const float d0 = (s0[0] + s0[1]) + (s0[2] + s0[3]);
-      const float d1 = (s1[0] + s1[1]) + (s1[2] + s1[3]);
-      if (d0 < b0) { b0 = d0; i0 = y0 + j; }
-      if (d1 < b1) { b1 = d1; i1 = y0 + j; }
-    }
-  }
-  unsigned long long p0 = ((unsigned long long)__float_as_uint(b0) << 32) | (unsigned long long)(uint32_t)i0;
-  unsigned long long p1 = ((unsigned long long)__float_as_uint(b1) << 32) | (unsigned long long)(uint32_t)i1;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int i16 = lane & 15;   // A row / B column within the 16-block
+  const int kq = lane >> 4;    // k within the group of four
+
+  // A operands: candidate row 64 cb + 16 wave + i16, k = 4 s + kq
+  const int64_t cr = (int64_t)cb * 64 + 16 * wave + i16;
+  const float* xrow = (cr < R) ? (Xp + (int64_t)cand[cr] * DP) : nullptr;
+  double a[KS];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o0 = __shfl_xor(p0, off);
-    const unsigned long long o1 = __shfl_xor(p1, off);
-    p0 = o0 < p0 ? o0 : p0;
-    p1 = o1 < p1 ? o1 : p1;
+  for (int s = 0; s < KS; ++s) a[s] = xrow ? (double)xrow[4 * s + kq] : 0.0;
+  // |x|^2 in float64 for the four rows this lane's results cover (l/16 + 4v)
+  double xq[4];
+  {
+    double part = 0.0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) part = fma(a[s], a[s], part);
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);   // lanes with equal i16 hold |x_row i16|^2
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xq[v] = __shfl(part, kq + 4 * v);
   }
-  if (j == 0) {
-    const int64_t r0 = (int64_t)cb * RB + 2 * q;
-    if (r0 < R) atomicMin(&best[r0], p0);
-    if (r0 + 1 < R) atomicMin(&best[r0 + 1], p1);
+  double bv[4];
+  int bi[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    bv[v] = __longlong_as_double(0x7ff0000000000000ll);
+    bi[v] = 0x7fffffff;
+  }
+  for (int64_t y0 = yb; y0 < ye; y0 += BNY) {
+    __syncthreads();
+    // stage 32 rows as float64 and their squared norms (8 threads per row)
+    {
+      const int r = tid >> 3, part = tid & 7;
+      const bool ok = y0 + r < ye;
+      const float* src = Yp + (y0 + r) * DP;
+      double sq = 0.0;
+#pragma unroll 4
+      for (int k = part; k < DP; k += 8) {
+        const double v = ok ? (double)src[k] : 0.0;
+        ys[r * STY + k] = v;
+        sq = fma(v, v, sq);
+      }
+      sq += __shfl_xor(sq, 1);
+      sq += __shfl_xor(sq, 2);
+      sq += __shfl_xor(sq, 4);
+      if (part == 0) yq[r] = ok ? sq : __longlong_as_double(0x7ff0000000000000ll);
+    }
+    __syncthreads();
+    doublex4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    const double* b0 = &ys[i16 * STY + kq];
+    const double* b1 = &ys[(16 + i16) * STY + kq];
+#pragma unroll 16
+    for (int s = 0; s < KS; ++s) {
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b0[4 * s], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b1[4 * s], c1, 0, 0, 0);
+    }
+    // element v of lane l: row l/16 + 4 v, column l%16 (of each 16 block)
+    const double q0 = yq[i16], q1 = yq[16 + i16];
+    const int j0 = (int)(y0 + i16), j1 = (int)(y0 + 16 + i16);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double d0 = xq[v] + q0 - 2.0 * c0[v];
+      const double d1 = xq[v] + q1 - 2.0 * c1[v];
+      if (d0 < bv[v]) { bv[v] = d0; bi[v] = j0; }
+      if (d1 < bv[v]) { bv[v] = d1; bi[v] = j1; }
+    }
+  }
+  // reduce over the 16 lanes sharing rows; ties -> smallest index
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float f = bv[v] > 0.0 ? (float)bv[v] : 0.f;
+    unsigned long long p = ((unsigned long long)__float_as_uint(f) << 32) | (uint32_t)bi[v];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const unsigned long long o = __shfl_xor(p, off);
+      p = o < p ? o : p;
+    }
+    const int64_t r = (int64_t)cb * 64 + 16 * wave + kq + 4 * v;
+    if (i16 == 0 && r < R) atomicMin(&best[r], p);
   }
 }
 
@@ -450,12 +739,14 @@ __global__ void store_refined(prohd_result* out, const int64_t* dR1, const int64
 
 // ------------------------------------------------------------ host side
 struct PrepSet {
-  float* p;       // padded rows, cap x DP
-  float* n;       // squared norms, cap
+  float* p = nullptr;      // padded float32 rows, cap x DP
+  float* n = nullptr;      // squared norms, cap
+  uint8_t* q = nullptr;    // low-precision rows (bf16 / fp8), cap x DP
+  float* qn = nullptr;     // squared norms of the dequantised rows
 };
 
 // ysplit so that (x blocks) x (ysplit) fills the compute units in whole waves
-// of work-groups, with at least `min_blocks` Y blocks per work-group.
+// of work-groups, with at least `min_rows` Y rows per work-group.
 int choose_split(int64_t xblocks, int64_t ny, int64_t min_rows) {
   const int64_t cus = cu_count();
   const int64_t max_split = std::max<int64_t>(1, ny / std::max<int64_t>(1, min_rows));
@@ -478,26 +769,60 @@ int choose_split(int64_t xblocks, int64_t ny, int64_t min_rows) {
 template <int DP>
 prohd_status launch_prep(const float* X, int D, const int32_t* idx, const int64_t* dn, int64_t cap,
                          const float* S, const int32_t* sidx, const int64_t* sdn, PrepSet o,
-                         int32_t* status, hipStream_t s) {
+                         int32_t* status, uint32_t* maxabs, hipStream_t s) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 4), 8 * cu_count()));
   PROHD_LAUNCH("hd_prep", prep_rows<DP>, dim3(grid), dim3(256), 0, s, X, D, idx, dn, cap, S, sidx,
-               sdn, o.p, o.n, status);
+               sdn, o.p, o.n, status, maxabs);
   return PROHD_OK;
 }
 
 template <int DP>
-prohd_status launch_tile(PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y, const int64_t* dnY,
-                         int64_t capY, uint32_t* rowmin, uint32_t* colmin, hipStream_t s) {
+prohd_status launch_quant(int fmt, PrepSet o, const int64_t* dn, int64_t cap, const uint32_t* maxabs,
+                          hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 4), 8 * cu_count()));
+  if (fmt == FMT_BF16) {
+    PROHD_LAUNCH("hd_quant", (quant_rows<DP, FMT_BF16>), dim3(grid), dim3(256), 0, s, o.p, dn, cap,
+                 maxabs, (void*)o.q, o.qn);
+  } else {
+    PROHD_LAUNCH("hd_quant", (quant_rows<DP, FMT_FP8>), dim3(grid), dim3(256), 0, s, o.p, dn, cap,
+                 maxabs, (void*)o.q, o.qn);
+  }
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
+                         const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
+                         uint32_t* colmin, hipStream_t s) {
   const int64_t xblocks = cdiv(capX, kTileRows);
-  const int split = choose_split(xblocks, capY, 4 * kBN);
+  const int split = choose_split(xblocks, capY, fmt == FMT_F32 ? 4 * kBN : 2 * kLpBN);
   const int64_t grid = xblocks * split;
   if (grid > 0x7fffffff) return fail(PROHD_EUNSUPPORTED, "tile grid too large");
-  if (colmin) {
-    PROHD_LAUNCH("hd_tile", (dist_tile<DP, true>), dim3((unsigned)grid), dim3(512), 0, s, X.p, X.n,
-                 dnX, capX, Y.p, Y.n, dnY, capY, split, rowmin, colmin);
+  const dim3 G((unsigned)grid), T(512);
+  if (fmt == FMT_F32) {
+    if (colmin) {
+      PROHD_LAUNCH("hd_tile", (dist_tile<DP, true>), G, T, 0, s, X.p, X.n, dnX, capX, Y.p, Y.n, dnY,
+                   capY, split, rowmin, colmin);
+    } else {
+      PROHD_LAUNCH("hd_tile", (dist_tile<DP, false>), G, T, 0, s, X.p, X.n, dnX, capX, Y.p, Y.n, dnY,
+                   capY, split, rowmin, colmin);
+    }
+  } else if (fmt == FMT_BF16) {
+    if (colmin) {
+      PROHD_LAUNCH("hd_tile_bf16", (dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, true>), G, T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+    } else {
+      PROHD_LAUNCH("hd_tile_bf16", (dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, false>), G, T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+    }
   } else {
-    PROHD_LAUNCH("hd_tile", (dist_tile<DP, false>), dim3((unsigned)grid), dim3(512), 0, s, X.p, X.n,
-                 dnX, capX, Y.p, Y.n, dnY, capY, split, rowmin, colmin);
+    if (colmin) {
+      PROHD_LAUNCH("hd_tile_fp8", (dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, true>), G, T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+    } else {
+      PROHD_LAUNCH("hd_tile_fp8", (dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, false>), G, T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+    }
   }
   return PROHD_OK;
 }
@@ -506,7 +831,7 @@ template <int DP>
 prohd_status launch_refine(const float* Xp, const int32_t* cand, const int64_t* dR, const float* Yp,
                            const int64_t* dnY, int64_t capY, unsigned long long* best,
                            hipStream_t s) {
-  const int64_t cblocks = cdiv(kRefineRows, 8);
+  const int64_t cblocks = cdiv(kRefineRows, 64);
   const int split = choose_split(cblocks, capY, 256);
   PROHD_LAUNCH("hd_refine", refine_rows<DP>, dim3((unsigned)(cblocks * split)), dim3(256), 0, s, Xp,
                cand, dR, Yp, dnY, capY, split, best);
@@ -528,23 +853,30 @@ struct HdLayout {
   uint32_t* rowB;          // minima of B-side rows
   DirWork w[2];
   int32_t* status;
+  uint32_t* maxabs;        // largest |shifted value| (float bits), fp8 scale
   void* sel_ws;
   size_t sel_bytes;
 };
 
+void take_set(Arena& ar, PrepSet& o, int64_t rows, int DP, int fmt) {
+  o.p = ar.take<float>((size_t)rows * DP);
+  o.n = ar.take<float>(rows);
+  if (fmt != FMT_F32) {
+    o.q = ar.take<uint8_t>((size_t)rows * qdim(DP, fmt) * (fmt == FMT_BF16 ? 2 : 1));
+    o.qn = ar.take<float>(rows);
+  }
+}
+
 HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB, int DP,
-                   bool full) {
+                   bool full, int fmt) {
   HdLayout L{};
   L.status = ar.take<int32_t>(64);
-  L.xa.p = ar.take<float>((size_t)capA * DP);
-  L.xa.n = ar.take<float>(capA);
-  L.xb.p = ar.take<float>((size_t)capB * DP);
-  L.xb.n = ar.take<float>(capB);
+  L.maxabs = ar.take<uint32_t>(64);
+  take_set(ar, L.xa, capA, DP, fmt);
+  take_set(ar, L.xb, capB, DP, fmt);
   if (full) {
-    L.fa.p = ar.take<float>((size_t)nA * DP);
-    L.fa.n = ar.take<float>(nA);
-    L.fb.p = ar.take<float>((size_t)nB * DP);
-    L.fb.n = ar.take<float>(nB);
+    take_set(ar, L.fa, nA, DP, fmt);
+    take_set(ar, L.fb, nB, DP, fmt);
   }
   L.rowA = ar.take<uint32_t>(capA);
   L.rowB = ar.take<uint32_t>(capB);
@@ -590,26 +922,40 @@ prohd_status init_best(unsigned long long* p, hipStream_t s) {
   } while (0)
 
 // Shared driver.  Mode: exact (idx null), candidates, or candidates with the
-// inner minimum over the full other set.
+// inner minimum over the full other set; fmt selects the tile input format.
 template <int DP>
 prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int D,
                     const int32_t* idxA, const int64_t* dnA, int64_t capA, const int32_t* idxB,
-                    const int64_t* dnB, int64_t capB, bool full, prohd_result* out, float* nn2A,
-                    float* nn2B, void* ws, size_t ws_bytes, hipStream_t s) {
+                    const int64_t* dnB, int64_t capB, bool full, int fmt, prohd_result* out,
+                    float* nn2A, float* nn2B, void* ws, size_t ws_bytes, hipStream_t s) {
   Arena ar(ws);
-  HdLayout L = hd_layout(ar, capA, capB, nA, nB, DP, full);
+  HdLayout L = hd_layout(ar, capA, capB, nA, nB, DP, full, fmt);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "hd: workspace too small");
-  PROHD_TRY(zero_bytes(L.status, sizeof(int32_t) * 64, s));
+  PROHD_TRY(zero_bytes(L.status, 256, s));
+  PROHD_TRY(zero_bytes(L.maxabs, 256, s));
+  uint32_t* mx = fmt == FMT_FP8 ? L.maxabs : nullptr;
   // common shift: the first (selected) row of A
   const int32_t* sidx = idxA;
-  PROHD_TRY(launch_prep<DP>(A, D, idxA, dnA, capA, A, sidx, dnA, L.xa, L.status, s));
-  PROHD_TRY(launch_prep<DP>(B, D, idxB, dnB, capB, A, sidx, dnA, L.xb, L.status, s));
+  PROHD_TRY(launch_prep<DP>(A, D, idxA, dnA, capA, A, sidx, dnA, L.xa, L.status, mx, s));
+  PROHD_TRY(launch_prep<DP>(B, D, idxB, dnB, capB, A, sidx, dnA, L.xb, L.status, mx, s));
+  if (full) {
+    PROHD_TRY(launch_prep<DP>(A, D, nullptr, nullptr, nA, A, sidx, dnA, L.fa, L.status, mx, s));
+    PROHD_TRY(launch_prep<DP>(B, D, nullptr, nullptr, nB, A, sidx, dnA, L.fb, L.status, mx, s));
+  }
+  if (fmt != FMT_F32) {
+    PROHD_TRY(launch_quant<DP>(fmt, L.xa, dnA, capA, L.maxabs, s));
+    PROHD_TRY(launch_quant<DP>(fmt, L.xb, dnB, capB, L.maxabs, s));
+    if (full) {
+      PROHD_TRY(launch_quant<DP>(fmt, L.fa, nullptr, nA, L.maxabs, s));
+      PROHD_TRY(launch_quant<DP>(fmt, L.fb, nullptr, nB, L.maxabs, s));
+    }
+  }
   PROHD_TRY(init_mins(L.rowA, capA, s));
   PROHD_TRY(init_mins(L.rowB, capB, s));
   for (int d = 0; d < 2; ++d) PROHD_TRY(init_best(L.w[d].best, s));
   DirIn ab{}, ba{};
   if (!full) {
-    PROHD_TRY(launch_tile<DP>(L.xa, dnA, capA, L.xb, dnB, capB, L.rowA, L.rowB, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
     PROHD_TRY(top_rows(L.rowA, capA, dnA, L.w[0], L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(top_rows(L.rowB, capB, dnB, L.w[1], L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.xb.p, dnB, capB, L.w[0].best, s));
@@ -617,10 +963,8 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
     ab = DirIn{L.w[0].best, L.w[0].cand, L.w[0].count, idxA, idxB, A, B};
     ba = DirIn{L.w[1].best, L.w[1].cand, L.w[1].count, idxB, idxA, B, A};
   } else {
-    PROHD_TRY(launch_prep<DP>(A, D, nullptr, nullptr, nA, A, sidx, dnA, L.fa, L.status, s));
-    PROHD_TRY(launch_prep<DP>(B, D, nullptr, nullptr, nB, A, sidx, dnA, L.fb, L.status, s));
-    PROHD_TRY(launch_tile<DP>(L.xa, dnA, capA, L.fb, nullptr, nB, L.rowA, nullptr, s));
-    PROHD_TRY(launch_tile<DP>(L.xb, dnB, capB, L.fa, nullptr, nA, L.rowB, nullptr, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.fa, nullptr, nA, L.maxabs, L.rowB, nullptr, s));
     PROHD_TRY(top_rows(L.rowA, capA, dnA, L.w[0], L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(top_rows(L.rowB, capB, dnB, L.w[1], L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.fb.p, nullptr, nB, L.w[0].best, s));
@@ -648,36 +992,46 @@ prohd_status by_dp(int D, F&& f) {
   }
 }
 
+int fmt_of(uint32_t flags) {
+  if (flags & PROHD_PREC_FP8) return FMT_FP8;
+  if (flags & PROHD_PREC_BF16) return FMT_BF16;
+  return FMT_F32;
+}
+
 }  // namespace
 
-size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full) {
+size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
+                   uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full);
+  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full, fmt_of(flags));
   return ar.used + 256;
 }
 
-size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D) {
+size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false);
+  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false, fmt_of(flags));
   return ar.used + 256;
 }
 
 prohd_status hd_candidates(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
                            const int32_t* idxA, const int64_t* dnA, int64_t capA,
-                           const int32_t* idxB, const int64_t* dnB, int64_t capB, bool full,
+                           const int32_t* idxB, const int64_t* dnB, int64_t capB, uint32_t flags,
                            prohd_result* out, void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool full = (flags & PROHD_INNER_FULL) != 0;
+  const int fmt = fmt_of(flags);
   return by_dp(D, [&](auto dp) {
-    return run_hd<decltype(dp)::value>(A, nA, B, nB, D, idxA, dnA, capA, idxB, dnB, capB, full, out,
-                                       nullptr, nullptr, ws, ws_bytes, s);
+    return run_hd<decltype(dp)::value>(A, nA, B, nB, D, idxA, dnA, capA, idxB, dnB, capB, full, fmt,
+                                       out, nullptr, nullptr, ws, ws_bytes, s);
   });
 }
 
 prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
-                      prohd_result* out, float* nn2A, float* nn2B, void* ws, size_t ws_bytes,
-                      hipStream_t s) {
+                      uint32_t flags, prohd_result* out, float* nn2A, float* nn2B, void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+  const int fmt = fmt_of(flags);
   return by_dp(D, [&](auto dp) {
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, nullptr, nullptr, nA, nullptr, nullptr, nB,
-                                       false, out, nn2A, nn2B, ws, ws_bytes, s);
+                                       false, fmt, out, nn2A, nn2B, ws, ws_bytes, s);
   });
 }
 

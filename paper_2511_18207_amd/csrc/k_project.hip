@@ -7,9 +7,10 @@
 // threads owns 512 rows (one per thread) and walks their columns in chunks of
 // 32 (coalesced 128-byte row segments staged through LDS, the next chunk
 // prefetched in registers while the current one is used).  The directions
-// (up to 32 per launch) sit in LDS k-major, so a k-step is one LDS read of x
-// and a few broadcast float4 reads of direction values feeding 8-32 FMAs; the
-// finished row writes P[d * n + i] (coalesced across the wave per direction).
+// (up to 32 per launch) are stored k-major and read as wave-uniform scalar
+// loads, so a k-step is one LDS read of x feeding 8-32 FMAs with scalar
+// operands; the finished row writes P[d * n + i] (coalesced across the wave
+// per direction).
 // This pass is bound by HBM bandwidth: 4 D bytes read and 4 (m+1) bytes
 // written per row.
 
@@ -61,12 +62,9 @@ __global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict
   constexpr int F4R = KC / 4;                       // float4 per row chunk
   constexpr int NF = kTileRows * F4R / kThreads;    // float4 per thread per chunk
   __shared__ __attribute__((aligned(16))) float xt[kTileRows * ST];
-  __shared__ __attribute__((aligned(16))) float us[DP * ND];   // directions, k-major
   const int tid = threadIdx.x;
   const int64_t tilesA = (nA + kTileRows - 1) / kTileRows;
   const int64_t tiles = tilesA + (nB + kTileRows - 1) / kTileRows;
-
-  for (int e = tid; e < DP * ND; e += kThreads) us[e] = Ut[e];
 
   float4 buf[NF];
   // chunk c of tile tl: row f / F4R, float4 f % F4R of columns [c KC, c KC + KC)
@@ -118,9 +116,11 @@ __global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict
       // prefetch the next chunk (or the first chunk of the next tile)
       if (c + 1 < NCH) load(tl, c + 1);
       else if (tl + gridDim.x < tiles) load(tl + gridDim.x, 0);
-      // row tid: x from LDS, direction values as broadcast float4 reads
+      // row tid: x from LDS; direction values are wave-uniform scalar loads
+      // (all waves work on the same chunk, so its KC x ND values stay in the
+      // scalar cache)
       const float* xr = &xt[tid * ST];
-      const float* uc = &us[(c * KC) * ND];
+      const float* uc = Ut + (size_t)(c * KC) * ND;
 #pragma unroll 2
       for (int k4 = 0; k4 < KC / 4; ++k4) {
         const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
