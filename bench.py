@@ -215,35 +215,80 @@ def main():
             "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
             "per_launch": {"algorithmic_flops": flops, "avg_ms": tile_avg, "launches": tile_n}}
 
-    exact = None
-    if not args.no_exact:
-        ph.profile_reset()
-        ph.profile_enable(True)
+    def time_prohd(prec, kA_, kB_, reps):
+        capA_ = int(min(nA, 2 * sum(min(k, nA) for k in kA_)))
+        capB_ = int(min(nB, 2 * sum(min(k, nB) for k in kB_)))
+        o = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
+
+        def run():
+            _, pA, pB, _, _ = ph.prohd_project(dA, dB, m, ws=ws, evals=False)
+            iA_, cA_, iB_, cB_ = ph.prohd_select(pA, pB, kA_, kB_, capA=capA_, capB=capB_, ws=ws)
+            ph.prohd_hd(dA, dB, iA_, cA_, iB_, cB_, capA=capA_, capB=capB_, ws=ws, out=o, prec=prec)
+        run()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        eout = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
         e0.record()
-        for _ in range(args.exact_steps):
-            ph.exact_hd(dA, dB, ws=ws, out=eout)
+        for _ in range(reps):
+            run()
         e1.record()
         torch.cuda.synchronize()
-        ph.profile_enable(False)
-        ems = e0.elapsed_time(e1) / args.exact_steps
-        er = ph.decode_result(eout)
-        en, ems_tile = ph.profile_read("hd_tile")
-        ph.profile_reset()
-        eflops = 2.0 * nA * nB * D
-        # sampled parity: witness row's NN over all of B in float64
+        return e0.elapsed_time(e1) / reps, ph.decode_result(o)
+
+    exact = None
+    if not args.no_exact:
+        exact = {}
         Bd = B.astype(np.float64)
-        wnn = np.sqrt(((Bd - A[er["ab_a"]].astype(np.float64)) ** 2).sum(1)).min()
+        for prec in ("fp32", "bf16", "fp8"):
+            ph.profile_reset()
+            ph.profile_enable(True)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            eout = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
+            reps = args.exact_steps if prec == "fp32" else max(1, args.exact_steps)
+            e0.record()
+            for _ in range(reps):
+                ph.exact_hd(dA, dB, ws=ws, out=eout, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ph.profile_enable(False)
+            ems = e0.elapsed_time(e1) / reps
+            er = ph.decode_result(eout)
+            en, ems_tile = ph.profile_read("hd_tile")
+            ph.profile_reset()
+            eflops = 2.0 * nA * nB * D
+            peak = {"fp32": PEAK_FP32_MFMA, "bf16": 2500.0, "fp8": 5000.0}[prec]
+            tile_ms = ems_tile / max(en, 1)
+            # sampled parity: the witness row's NN over all of B in float64
+            wnn = np.sqrt(((Bd - A[er["ab_a"]].astype(np.float64)) ** 2).sum(1)).min()
+            exact[prec] = {"ms": ems, "pairs_per_s": 1e3 / ems, "H": er["H"], "hAB": er["hAB"],
+                           "hBA": er["hBA"], "tile_ms": tile_ms,
+                           "tile_tflops": eflops / (tile_ms * 1e-3) / 1e12,
+                           "tile_frac": eflops / (tile_ms * 1e-3) / 1e12 / peak,
+                           "witness_nn_rel_err": float(abs(wnn - er["hAB"]) / er["hAB"])}
+            log(f"exact[{prec}] {ems:.1f} ms, H={er['H']:.6f}, tile {exact[prec]['tile_tflops']:.1f} TF/s")
         del Bd
-        exact = {"ms": ems, "pairs_per_s": 1e3 / ems, "H": er["H"], "hAB": er["hAB"], "hBA": er["hBA"],
-                 "tile_ms": ems_tile / max(en, 1), "tile_tflops": eflops / (ems_tile / max(en, 1) * 1e-3) / 1e12,
-                 "tile_frac": eflops / (ems_tile / max(en, 1) * 1e-3) / 1e12 / PEAK_FP32_MFMA,
-                 "witness_nn_rel_err": float(abs(wnn - er["hAB"]) / er["hAB"]),
-                 "prohd_rel_err_vs_exact": abs(res["H"] - er["H"]) / er["H"]}
-        log(f"exact {ems:.1f} ms, H={er['H']:.6f}, tile {exact['tile_tflops']:.1f} TF/s")
+        Hx = exact["fp32"]["H"]
+        for prec in ("bf16", "fp8"):
+            exact[prec]["rel_err_vs_fp32_exact"] = abs(exact[prec]["H"] - Hx) / Hx
+        exact["prohd_fp32_rel_err_vs_exact"] = abs(res["H"] - Hx) / Hx
+        # precision form: ProHD with low-precision tiles, at the same budget and
+        # at a 4x larger alpha (about the same time as the float32 path)
+        forms = []
+        for prec, mult in (("bf16", 1), ("fp8", 1), ("bf16", 4), ("fp8", 4)):
+            if alpha is None:
+                kA_, kB_ = [k * mult for k in kA], [k * mult for k in kB]
+            else:
+                a_ = alpha * mult
+                kA_ = [ph.k_rule(a_, nA)] + [ph.k_rule(a_ / m, nA)] * m
+                kB_ = [ph.k_rule(a_, nB)] + [ph.k_rule(a_ / m, nB)] * m
+            ms_, r_ = time_prohd(prec, kA_, kB_, 3)
+            forms.append({"prec": prec, "alpha": None if alpha is None else alpha * mult, "ms": ms_,
+                          "H": r_["H"], "nA_sel": r_["nA_sel"], "nB_sel": r_["nB_sel"],
+                          "rel_err_vs_exact": abs(r_["H"] - Hx) / Hx})
+            log(f"prohd[{prec}, alpha x{mult}] {ms_:.2f} ms H={r_['H']:.6f} err={forms[-1]['rel_err_vs_exact']:.2e}")
+        exact["precision_form"] = forms
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -27,4 +27,6 @@ from ._lib import (  # noqa: F401
     DIRS_GIVEN,
     INNER_FULL,
     SYNC,
+    PREC_BF16,
+    PREC_FP8,
 )

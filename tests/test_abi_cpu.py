@@ -49,8 +49,9 @@ def test_workspace_size_rules():
     big = ph.workspace_size(100000, 100000, 32, 4)
     assert 0 < small < big
     # 2M x 2M, D=256: dominated by the padded float32 copies of both sets
+    # (4.1 GB) plus their bfloat16 copies for the precision form (2.0 GB)
     full = ph.workspace_size(2_000_000, 2_000_000, 256, 17, 80_000, 80_000)
-    assert 4.0e9 < full < 5.0e9
+    assert 6.0e9 < full < 7.0e9
 
 
 def _err(code_fn):
@@ -78,7 +79,9 @@ FAKE = 0x1000  # never dereferenced: validation fails first
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 0, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 11, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, None, FAKE, FAKE, FAKE, 5, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "index"),
-    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 3, FAKE, FAKE, 1 << 24, None), 1, "flag"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 5, FAKE, FAKE, 1 << 24, None), 1, "flag"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 12, FAKE, FAKE, 1 << 24, None), 1, "exclusive"),
+    (lambda L: L.exact_hd(FAKE, 10, FAKE, 10, 4, 2, FAKE, None, None, FAKE, 1 << 24, None), 1, "flag"),
 ])
 def test_validation_errors(call, code, msg):
     got, text = _err(call)

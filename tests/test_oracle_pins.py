@@ -272,3 +272,51 @@ def test_bounds_theorems_random():
             assert f <= H + 1e-12
             assert f >= prev - 1e-15
             prev = f
+
+
+# ------------------------------------------------ learned-proposal scorer
+def test_mlp_finite_differences():
+    # the manual backward of the FP64 scorer against central differences
+    from oracle import mlp
+    D = 3
+    g = np.random.default_rng(21)
+    p = g.standard_normal(mlp.param_count(D)) * 0.2
+    F = mlp.features(g.standard_normal((7, D)), g.standard_normal(D))
+    y = np.array([1, 0, 0, 1, 0, 0, 0], dtype=np.float64)
+    loss, grad = mlp.loss_grad(p, F, y, D, pos_weight=3.0)
+    idx = g.choice(p.size, size=60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (mlp.loss_grad(p + e, F, y, D, 3.0)[0] - mlp.loss_grad(p - e, F, y, D, 3.0)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(grad[i])) + 1e-9, (i, fd, grad[i])
+
+
+def test_mlp_hand_example():
+    # all weights zero except b3 = s0: every score is s0, the loss is
+    # pw*y*softplus(-s0) + (1-y)*softplus(s0); only b3 has a gradient,
+    # mean(pw*y*(sig-1) + (1-y)*sig)
+    from oracle import mlp
+    D = 2
+    p = np.zeros(mlp.param_count(D))
+    p[-1] = 0.3
+    F = mlp.features(np.ones((4, D)), np.zeros(D))
+    y = np.array([1.0, 0.0, 0.0, 0.0])
+    loss, grad = mlp.loss_grad(p, F, y, D, pos_weight=2.0)
+    sig = 1.0 / (1.0 + math.exp(-0.3))
+    want = (2.0 * math.log1p(math.exp(-0.3)) + 3 * math.log1p(math.exp(0.3))) / 4
+    assert loss == pytest.approx(want, rel=1e-14)
+    assert grad[-1] == pytest.approx((2.0 * (sig - 1.0) + 3 * sig) / 4, rel=1e-14)
+    assert np.count_nonzero(grad[:-1]) == 0
+    # features of a point: [x, x - c]
+    assert np.array_equal(mlp.features([[1.0, 2.0]], [0.5, -1.0]), [[1.0, 2.0, 0.5, 3.0]])
+
+
+def test_adamw_first_step():
+    # first step moves each weight by lr * sign(g) (bias-corrected m/sqrt v = g/|g|) plus decay
+    from oracle import mlp
+    p = np.array([1.0, -2.0])
+    g = np.array([0.5, -4.0])
+    p2, m, v = mlp.adamw(p, g, np.zeros(2), np.zeros(2), t=1, lr=0.1, wd=0.01, eps=0.0)
+    assert np.allclose(p2, p - 0.1 * (np.sign(g) + 0.01 * p), rtol=1e-14)
