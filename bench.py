@@ -42,11 +42,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _source_block(src, start):
+    """Text from the line holding `start` (and its template line) to the
+    closing brace of that function."""
+    i = src.index(start)
+    i = src.rfind("\ntemplate", 0, i) if src.rfind("\ntemplate", 0, i) > src.rfind("\n}\n", 0, i) else src.rfind("\n", 0, i)
+    j = src.index("\n}\n", i) + 3
+    return src[i:j]
+
+
 def kernel_source_hash():
+    """Hash of the dominant kernel's source and of the host code that picks
+    its launch shape: the counter summary is valid while this is unchanged."""
+    with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", "k_hd.hip")) as fh:
+        src = fh.read()
     h = hashlib.sha256()
-    for f in ("k_hd.hip", "common.h"):
-        with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for start in ("void dist_tile(", "int choose_split(", "prohd_status launch_tile("):
+        h.update(_source_block(src, start).encode())
     return h.hexdigest()[:16]
 
 

@@ -205,6 +205,49 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       uint32_t flags, prohd_result* out, float* nn2A, float* nn2B,
                       void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Learned candidate proposal (an extension of the candidate selection of
+ * Alg. 1 / Alg. 2, not in the paper).  A scorer MLP 2D -> 256 -> 128 -> 1
+ * with GELU activations reads the per-point features f = [x, x - c_other]
+ * (c_other: centroid of the other set) and scores how likely a point is to
+ * be a Hausdorff witness.  Matrix products run on bfloat16 weights and
+ * activations with float32 accumulation; parameters are a float32 master
+ * vector, layout [W1 (256 x 2D row-major), b1 (256), W2 (128 x 256),
+ * b2 (128), w3 (128), b3 (1)].  All pointers are device memory.
+ */
+/* Number of float32 parameters for dimension D (host). */
+size_t prohd_mlp_param_count(int32_t D);
+/* Workspace bytes for scoring or a gradient step over up to `rows` rows. */
+size_t prohd_mlp_workspace_size(int64_t rows, int32_t D);
+/* Deterministic initialisation of `params` (uniform Glorot weights, zero
+ * biases) from `seed`. */
+prohd_status prohd_mlp_init(float* params, int32_t D, uint64_t seed, void* stream);
+/* scores[i] = network(f(X_i)) for i < n. */
+prohd_status prohd_mlp_score(const float* X, int64_t n, int32_t D, const float* c_other,
+                             const float* params, float* scores, void* ws, size_t ws_bytes,
+                             void* stream);
+/* Gradient of the mean weighted binary cross-entropy with logits
+ *   l = pos_weight * y softplus(-s) + (1 - y) softplus(s)
+ * over the batch rows X[idx[i]] (labels[idx[i]] in {0, 1}), i < batch
+ * (batch <= 65536).  grad: param_count floats (overwritten); loss: one float. */
+prohd_status prohd_mlp_grad(const float* X, int32_t D, const float* c_other, const float* labels,
+                            const int32_t* idx, int64_t batch, float pos_weight,
+                            const float* params, float* grad, float* loss, void* ws,
+                            size_t ws_bytes, void* stream);
+/* One AdamW step (decoupled weight decay) at step number t >= 1. */
+prohd_status prohd_mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t D,
+                             int64_t t, float lr, float weight_decay, float beta1, float beta2,
+                             float eps, void* stream);
+/* Adds the sA (sB) highest-scoring rows of A (B) to the selected lists
+ * idxA/nselA (idxB/nselB) in place: the result is the ascending unique union.
+ * Ties in the scores go to the smaller index.  capA must be >= min(nA,
+ * capacity bound of the existing list + sA); likewise capB. */
+prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
+                                 const float* scoresB, int64_t nB, int32_t sB,
+                                 int32_t* idxA, int64_t capA, int64_t* nselA,
+                                 int32_t* idxB, int64_t capB, int64_t* nselB,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* Message of the last non-OK return on this host thread ("" if none). */
 const char* prohd_last_error(void);
 

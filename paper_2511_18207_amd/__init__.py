@@ -20,6 +20,13 @@ from ._lib import (  # noqa: F401
     decode_result,
     RESULT_BYTES,
     k_rule,
+    mlp_param_count,
+    mlp_workspace_size,
+    mlp_init,
+    mlp_score,
+    mlp_grad,
+    mlp_adamw,
+    select_scored,
     profile_enable,
     profile_reset,
     profile_read,

@@ -65,6 +65,22 @@ def lib() -> C.CDLL:
     L.prohd_hd.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, vp, i64, i64, u32, vp, vp, sz, vp]
     L.exact_hd.restype = C.c_int
     L.exact_hd.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp, sz, vp]
+    L.prohd_mlp_param_count.restype = sz
+    L.prohd_mlp_param_count.argtypes = [i32]
+    L.prohd_mlp_workspace_size.restype = sz
+    L.prohd_mlp_workspace_size.argtypes = [i64, i32]
+    L.prohd_mlp_init.restype = C.c_int
+    L.prohd_mlp_init.argtypes = [vp, i32, C.c_uint64, vp]
+    L.prohd_mlp_score.restype = C.c_int
+    L.prohd_mlp_score.argtypes = [vp, i64, i32, vp, vp, vp, vp, sz, vp]
+    L.prohd_mlp_grad.restype = C.c_int
+    L.prohd_mlp_grad.argtypes = [vp, i32, vp, vp, vp, i64, C.c_float, vp, vp, vp, vp, sz, vp]
+    L.prohd_mlp_adamw.restype = C.c_int
+    L.prohd_mlp_adamw.argtypes = [vp, vp, vp, vp, i32, i64, C.c_float, C.c_float, C.c_float,
+                                  C.c_float, C.c_float, vp]
+    L.prohd_select_scored.restype = C.c_int
+    L.prohd_select_scored.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp, vp, i64, vp, vp, sz,
+                                      vp]
     L.prohd_last_error.restype = C.c_char_p
     L.prohd_last_error.argtypes = []
     L.prohd_version.restype = C.c_char_p
@@ -275,6 +291,97 @@ def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None
                 "idxA": idxA, "nselA": nA_sel, "idxB": idxB, "nselB": nB_sel,
                 "kA": kA, "kB": kB})
     return res
+
+
+def mlp_param_count(D: int) -> int:
+    return int(lib().prohd_mlp_param_count(D))
+
+
+def mlp_workspace_size(rows: int, D: int) -> int:
+    return int(lib().prohd_mlp_workspace_size(rows, D))
+
+
+def _f32_1d(t, name, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+            or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA (HIP) tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return t
+
+
+def mlp_init(D: int, seed: int = 0, device="cuda"):
+    """A fresh float32 parameter vector (Glorot-uniform weights, zero biases)."""
+    torch = _torch()
+    p = torch.empty(mlp_param_count(D), dtype=torch.float32, device=device)
+    _check(lib().prohd_mlp_init(p.data_ptr(), D, seed, _stream()))
+    return p
+
+
+def mlp_score(X, c_other, params, out=None, ws=None):
+    """Scores of every row of X (features [x, x - c_other])."""
+    torch = _torch()
+    X = _f32_2d(X, "X")
+    n, D = X.shape
+    _f32_1d(c_other, "c_other", D)
+    _f32_1d(params, "params", mlp_param_count(D))
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=X.device)
+    buf, nbytes = _ws(ws, mlp_workspace_size(min(n, 65536), D))
+    _check(lib().prohd_mlp_score(X.data_ptr(), n, D, c_other.data_ptr(), params.data_ptr(),
+                                 out.data_ptr(), buf.data_ptr(), nbytes, _stream()))
+    return out
+
+
+def mlp_grad(X, c_other, labels, idx, params, pos_weight=1.0, grad=None, loss=None, ws=None):
+    """Gradient and loss of the weighted BCE over rows X[idx] (device int32
+    idx, float32 0/1 labels per row of X).  Returns (grad, loss) tensors."""
+    torch = _torch()
+    X = _f32_2d(X, "X")
+    n, D = X.shape
+    _f32_1d(c_other, "c_other", D)
+    _f32_1d(labels, "labels", n)
+    P = mlp_param_count(D)
+    _f32_1d(params, "params", P)
+    if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+        raise TypeError("idx must be a contiguous int32 CUDA (HIP) tensor")
+    batch = idx.numel()
+    if grad is None:
+        grad = torch.empty(P, dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    buf, nbytes = _ws(ws, mlp_workspace_size(max(batch, 1), D))
+    _check(lib().prohd_mlp_grad(X.data_ptr(), D, c_other.data_ptr(), labels.data_ptr(),
+                                idx.data_ptr(), batch, float(pos_weight), params.data_ptr(),
+                                grad.data_ptr(), loss.data_ptr(), buf.data_ptr(), nbytes,
+                                _stream()))
+    return grad, loss
+
+
+def mlp_adamw(params, grad, m, v, D, t, lr, weight_decay=0.01, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One AdamW step, in place on params, m and v."""
+    P = mlp_param_count(D)
+    for name, x in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _f32_1d(x, name, P)
+    _check(lib().prohd_mlp_adamw(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                 D, t, lr, weight_decay, beta1, beta2, eps, _stream()))
+
+
+def select_scored(scoresA, sA, scoresB, sB, idxA, nselA, idxB, nselB, ws=None):
+    """Adds the sA / sB best-scoring rows to the selected index lists, in
+    place (ascending unique union).  The index tensors' lengths are their
+    capacities."""
+    nA = scoresA.numel()
+    nB = scoresB.numel()
+    _f32_1d(scoresA, "scoresA")
+    _f32_1d(scoresB, "scoresB")
+    need = workspace_size(nA, nB, 1, 2)
+    buf, nbytes = _ws(ws, need)
+    _check(lib().prohd_select_scored(scoresA.data_ptr(), nA, int(sA), scoresB.data_ptr(), nB,
+                                     int(sB), idxA.data_ptr(), idxA.numel(), nselA.data_ptr(),
+                                     idxB.data_ptr(), idxB.numel(), nselB.data_ptr(),
+                                     buf.data_ptr(), nbytes, _stream()))
 
 
 def profile_enable(on: bool = True):

@@ -203,9 +203,9 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
   }
   st = select_mark(segs.data(), nseg, sel_ws, sel_bytes, s);
   if (st) return st;
-  st = compact_flags(fA, nA, nullptr, idxA, nselA, cmp_ws, cmp_bytes, s);
+  st = compact_flags(fA, nA, nullptr, idxA, capA, nselA, cmp_ws, cmp_bytes, s);
   if (st) return st;
-  return compact_flags(fB, nB, nullptr, idxB, nselB, cmp_ws, cmp_bytes, s);
+  return compact_flags(fB, nB, nullptr, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
 }
 
 prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
@@ -247,6 +247,99 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
   hipStream_t s = (hipStream_t)stream;
   st = hd_exact(A, nA, B, nB, D, flags, out, nn2A, nn2B, ws, ws_bytes, s);
   return finish(st, flags, s, out ? &out->status : nullptr);
+}
+
+size_t prohd_mlp_param_count(int32_t D) {
+  if (D < 1 || D > PROHD_MAX_DIM) return 0;
+  return mlp_param_count(D);
+}
+
+size_t prohd_mlp_workspace_size(int64_t rows, int32_t D) {
+  if (rows < 1 || D < 1 || D > PROHD_MAX_DIM) return 0;
+  return mlp_ws_bytes(rows, D);
+}
+
+prohd_status prohd_mlp_init(float* params, int32_t D, uint64_t seed, void* stream) {
+  if (bad_ptr(params)) return fail(PROHD_EINVAL, "params must be non-null");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  return mlp_init(params, D, seed, (hipStream_t)stream);
+}
+
+prohd_status prohd_mlp_score(const float* X, int64_t n, int32_t D, const float* c_other,
+                             const float* params, float* scores, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (bad_ptr(X) || bad_ptr(c_other) || bad_ptr(params) || bad_ptr(scores) || bad_ptr(ws))
+    return fail(PROHD_EINVAL, "null pointer");
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(PROHD_EINVAL, "n must be in [1, 2^31)");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  if (ws_bytes < mlp_ws_bytes(n, D)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  return mlp_score(X, n, D, c_other, params, scores, ws, ws_bytes, (hipStream_t)stream);
+}
+
+prohd_status prohd_mlp_grad(const float* X, int32_t D, const float* c_other, const float* labels,
+                            const int32_t* idx, int64_t batch, float pos_weight,
+                            const float* params, float* grad, float* loss, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (bad_ptr(X) || bad_ptr(c_other) || bad_ptr(labels) || bad_ptr(idx) || bad_ptr(params) ||
+      bad_ptr(grad) || bad_ptr(loss) || bad_ptr(ws))
+    return fail(PROHD_EINVAL, "null pointer");
+  if (batch < 1 || batch > 65536) return fail(PROHD_EINVAL, "batch must be in [1, 65536]");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  if (!(pos_weight > 0.f)) return fail(PROHD_EINVAL, "pos_weight must be > 0");
+  if (ws_bytes < mlp_ws_bytes(batch, D)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  return mlp_grad(X, D, c_other, labels, idx, batch, pos_weight, params, grad, loss, ws, ws_bytes,
+                  (hipStream_t)stream);
+}
+
+prohd_status prohd_mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t D,
+                             int64_t t, float lr, float weight_decay, float beta1, float beta2,
+                             float eps, void* stream) {
+  if (bad_ptr(params) || bad_ptr(grad) || bad_ptr(m) || bad_ptr(v)) return fail(PROHD_EINVAL, "null pointer");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  if (t < 1) return fail(PROHD_EINVAL, "t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f && lr >= 0.f))
+    return fail(PROHD_EINVAL, "bad AdamW hyper-parameters");
+  return mlp_adamw(params, grad, m, v, D, t, lr, weight_decay, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
+                                 const float* scoresB, int64_t nB, int32_t sB,
+                                 int32_t* idxA, int64_t capA, int64_t* nselA,
+                                 int32_t* idxB, int64_t capB, int64_t* nselB,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  if (bad_ptr(scoresA) || bad_ptr(scoresB) || bad_ptr(idxA) || bad_ptr(idxB) || bad_ptr(nselA) ||
+      bad_ptr(nselB) || bad_ptr(ws))
+    return fail(PROHD_EINVAL, "null pointer");
+  if (nA < 1 || nB < 1 || nA >= (int64_t(1) << 31) || nB >= (int64_t(1) << 31))
+    return fail(PROHD_EINVAL, "nA and nB must be in [1, 2^31)");
+  if (sA < 0 || sB < 0) return fail(PROHD_EINVAL, "sA and sB must be >= 0");
+  if (capA < std::min<int64_t>(nA, sA) || capB < std::min<int64_t>(nB, sB) || capA > nA || capB > nB)
+    return fail(PROHD_EINVAL, "capacities must lie in [min(n, s), n]");
+  Arena ar(ws);
+  uint8_t* fA = ar.take<uint8_t>(nA);
+  uint8_t* fB = ar.take<uint8_t>(nB);
+  const size_t sel_bytes = select_ws_bytes(2, std::max(nA, nB));
+  void* sel_ws = ar.take<char>(sel_bytes);
+  const size_t cmp_bytes = compact_ws_bytes(std::max(nA, nB));
+  void* cmp_ws = ar.take<char>(cmp_bytes);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  prohd_status st = zero_bytes(fA, (size_t)nA, s);
+  if (!st) st = zero_bytes(fB, (size_t)nB, s);
+  if (!st) st = scatter_index_flags(idxA, nselA, capA, fA, s);
+  if (!st) st = scatter_index_flags(idxB, nselB, capB, fB, s);
+  if (st) return st;
+  SelSegment segs[2] = {
+      SelSegment{scoresA, nA, nullptr, 0, (int32_t)std::min<int64_t>(sA, nA), fA},
+      SelSegment{scoresB, nB, nullptr, 0, (int32_t)std::min<int64_t>(sB, nB), fB}};
+  st = select_mark(segs, 2, sel_ws, sel_bytes, s);
+  if (!st) st = compact_flags(fA, nA, nullptr, idxA, capA, nselA, cmp_ws, cmp_bytes, s);
+  if (!st) st = compact_flags(fB, nB, nullptr, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
+  return st;
 }
 
 const char* prohd_last_error(void) { return g_err.c_str(); }

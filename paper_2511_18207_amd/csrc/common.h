@@ -91,11 +91,15 @@ struct SelSegment {
 size_t select_ws_bytes(int nseg, int64_t max_n);
 prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_bytes,
                          hipStream_t s);
-// Compaction of flag bytes into an ascending index list + device count.
+// Compaction of flag bytes into an ascending index list + device count;
+// at most `cap` entries are written (and counted).
 size_t compact_ws_bytes(int64_t n);
 prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n,
-                           int32_t* idx, int64_t* count, void* ws, size_t ws_bytes,
+                           int32_t* idx, int64_t cap, int64_t* count, void* ws, size_t ws_bytes,
                            hipStream_t s);
+// flags[idx[i]] = 1 for the first *count entries (count clipped to cap).
+prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64_t cap,
+                                 uint8_t* flags, hipStream_t s);
 // Fill bytes with zero through a kernel (graph-friendly; no memset nodes).
 prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s);
 
@@ -103,6 +107,19 @@ prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s);
 size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
                    uint32_t flags);
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags);
+
+// Learned proposal scorer (k_mlp.hip).
+size_t mlp_param_count(int32_t D);
+size_t mlp_ws_bytes(int64_t rows, int32_t D);
+prohd_status mlp_init(float* params, int32_t D, uint64_t seed, hipStream_t s);
+prohd_status mlp_score(const float* X, int64_t n, int32_t D, const float* c_other,
+                       const float* params, float* scores, void* ws, size_t ws_bytes,
+                       hipStream_t s);
+prohd_status mlp_grad(const float* X, int32_t D, const float* c_other, const float* labels,
+                      const int32_t* idx, int64_t batch, float pos_weight, const float* params,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t s);
+prohd_status mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t D, int64_t t,
+                       float lr, float wd, float b1, float b2, float eps, hipStream_t s);
 
 // Direction finding and projection (k_stats.hip, k_eig.hip, k_project.hip).
 size_t project_ws_bytes(int64_t nA, int64_t nB, int32_t D, int32_t ndirs);

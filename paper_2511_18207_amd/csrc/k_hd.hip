@@ -901,7 +901,7 @@ prohd_status top_rows(const uint32_t* mins, int64_t n, const int64_t* dn, DirWor
   SelSegment seg{reinterpret_cast<const float*>(mins), n, dn, 0, kRefineRows, w.flags};
   st = select_mark(&seg, 1, sel_ws, sel_bytes, s);
   if (st) return st;
-  return compact_flags(w.flags, n, dn, w.cand, w.count, sel_ws, sel_bytes, s);
+  return compact_flags(w.flags, n, dn, w.cand, kRefineRows, w.count, sel_ws, sel_bytes, s);
 }
 
 prohd_status init_mins(uint32_t* p, int64_t n, hipStream_t s) {

@@ -1,0 +1,394 @@
+// Learned candidate proposal: a scorer MLP 2D -> 256 -> 128 -> 1 (GELU,
+// bfloat16 weights and activations into the matrix cores, float32
+// accumulation and master weights) over the per-point features
+// f = [x, x - c_other], with its own forward, backward and AdamW kernels.
+//
+// This extends the paper's candidate selection (the per-direction extremes
+// of Alg. 1 / Alg. 2): the highest-scoring points of each set are added to
+// the selected rows before the candidate distance is taken.
+//
+// Flat float32 parameter layout: [W1 (256 x 2D), b1 (256), W2 (128 x 256),
+// b2 (128), w3 (128), b3 (1)].
+//
+// One general bfloat16 GEMM (64 x 64 output tile per 4-wave work-group,
+// v_mfma_f32_32x32x16_bf16, K staged through LDS 32 at a time, operands at
+// arbitrary strides) serves every product; epilogues add the bias and GELU
+// (forward), multiply by GELU' (backward through an activation) or store the
+// float32 sums (weight gradients).
+
+#include <math.h>
+
+#include "common.h"
+
+namespace prohd {
+namespace {
+
+constexpr int kH1 = 256;
+constexpr int kH2 = 128;
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_BWD = 2 };
+
+struct GemmArgs {
+  const __bf16* A;
+  int64_t lam, lak;   // A(m, k) = A[m lam + k lak]
+  const __bf16* B;
+  int64_t lbk, lbn;   // B(k, n) = B[k lbk + n lbn]
+  int M, N, K;
+  int64_t ldc;
+  float* outf;        // EPI_F32: sums; EPI_BIAS_GELU: pre-activation z (may be null)
+  __bf16* outh;       // EPI_BIAS_GELU: gelu(z); EPI_GELU_BWD: acc * gelu'(zin)
+  const float* bias;  // EPI_BIAS_GELU
+  const float* zin;   // EPI_GELU_BWD: pre-activation, same layout as the output
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
+  constexpr int KC = 32;
+  constexpr int ST = KC + 8;   // LDS row stride (bf16): 80 bytes, 16-byte aligned rows
+  __shared__ __attribute__((aligned(16))) __bf16 As[64 * ST];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64 * ST];   // n-major: Bs[n][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = 32 * (wave >> 1), wn = 32 * (wave & 1);
+  const int gsel = lane >> 5, c = lane & 31;
+  floatx16 acc = {0.f};
+  // staging: thread -> (row r = tid / 4, k group of 8 = (tid % 4) * 8)
+  const int sr = tid >> 2, sk = (tid & 3) * 8;
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
+    __syncthreads();
+    {
+      const int m = m0 + sr, n = n0 + sr;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + sk + j;
+        As[sr * ST + sk + j] = (m < g.M && k < g.K) ? g.A[m * g.lam + k * g.lak] : (__bf16)0.f;
+        Bs[sr * ST + sk + j] = (n < g.N && k < g.K) ? g.B[k * g.lbk + n * g.lbn] : (__bf16)0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KC / 16; ++s) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[(wm + c) * ST + 16 * s + 8 * gsel]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[(wn + c) * ST + 16 * s + 8 * gsel]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+  }
+  // lane holds column wn + c, rows wm + 8 (v/4) + 4 gsel + v%4
+  const int n = n0 + wn + c;
+  if (n >= g.N) return;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm + 8 * (v >> 2) + 4 * gsel + (v & 3);
+    if (m >= g.M) continue;
+    const int64_t o = (int64_t)m * g.ldc + n;
+    if (EPI == EPI_F32) {
+      g.outf[o] = acc[v];
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float z = acc[v] + g.bias[n];
+      if (g.outf) g.outf[o] = z;
+      g.outh[o] = (__bf16)gelu(z);
+    } else {
+      g.outh[o] = (__bf16)(acc[v] * gelu_grad(g.zin[o]));
+    }
+  }
+}
+
+// F[i] = [x, x - c] of row idx[i] (or i), bfloat16, 2D per row.
+__global__ void features(const float* __restrict__ X, int D, const int32_t* __restrict__ idx,
+                         int64_t n, const float* __restrict__ c, __bf16* __restrict__ F) {
+  const int64_t total = n * 2 * D;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / (2 * D);
+    const int k = (int)(e - i * 2 * D);
+    const int64_t r = idx ? (int64_t)idx[i] : i;
+    const float v = k < D ? X[r * D + k] : X[r * D + (k - D)] - c[k - D];
+    F[e] = (__bf16)v;
+  }
+}
+
+// s[i] = w3 . h2[i] + b3 (one wave per row).
+__global__ void head_fwd(const __bf16* __restrict__ H2, int64_t n, const float* __restrict__ w3,
+                         const float* __restrict__ b3, float* __restrict__ s) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < n;
+       i += (int64_t)gridDim.x * (blockDim.x / 64)) {
+    float a = (float)H2[i * kH2 + lane] * w3[lane] + (float)H2[i * kH2 + 64 + lane] * w3[64 + lane];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) s[i] = a + b3[0];
+  }
+}
+
+// Loss and the gradient at the head: ds = (pw y (sig - 1) + (1 - y) sig) / n,
+// dZ2 = ds w3 * gelu'(z2), grads of w3 and b3, summed loss.  A work-group
+// of 256 threads handles 64 rows; thread j < 128 owns hidden unit j.
+__global__ __launch_bounds__(256) void head_bwd(const __bf16* __restrict__ H2,
+                                                const float* __restrict__ Z2,
+                                                const float* __restrict__ s,
+                                                const float* __restrict__ labels,
+                                                const int32_t* __restrict__ idx, int64_t n,
+                                                float pos_weight, const float* __restrict__ w3,
+                                                __bf16* __restrict__ dZ2, float* __restrict__ gw3,
+                                                float* __restrict__ gb3, float* __restrict__ loss) {
+  __shared__ float dsv[64];
+  __shared__ float lsum[64];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int64_t i = r0 + tid;
+    float ds = 0.f, l = 0.f;
+    if (i < n) {
+      const float y = labels[idx ? idx[i] : i];
+      const float sv = s[i];
+      const float sig = 1.f / (1.f + expf(-sv));
+      // softplus(-s) and softplus(s), stable
+      const float spn = fmaxf(-sv, 0.f) + log1pf(expf(-fabsf(sv)));
+      const float spp = fmaxf(sv, 0.f) + log1pf(expf(-fabsf(sv)));
+      l = pos_weight * y * spn + (1.f - y) * spp;
+      ds = (pos_weight * y * (sig - 1.f) + (1.f - y) * sig) / (float)n;
+    }
+    dsv[tid] = ds;
+    lsum[tid] = l;
+  }
+  __syncthreads();
+  const int j = tid & 127, half = tid >> 7;
+  float g = 0.f;
+  for (int rr = half; rr < 64; rr += 2) {
+    const int64_t i = r0 + rr;
+    if (i >= n) break;
+    const float ds = dsv[rr];
+    g += ds * (float)H2[i * kH2 + j];
+    dZ2[i * kH2 + j] = (__bf16)(ds * w3[j] * gelu_grad(Z2[i * kH2 + j]));
+  }
+  atomicAdd(&gw3[j], g);
+  if (tid == 0) {
+    float a = 0.f, b = 0.f;
+    for (int rr = 0; rr < 64; ++rr) {
+      a += dsv[rr];
+      b += lsum[rr];
+    }
+    atomicAdd(gb3, a);
+    atomicAdd(loss, b / (float)n);
+  }
+}
+
+// Column sums of a bfloat16 matrix (n x N) into float32 out[N].
+__global__ void colsum(const __bf16* __restrict__ M, int64_t n, int N, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float a = 0.f;
+  for (int64_t i = 0; i < n; ++i) a += (float)M[i * N + j];
+  out[j] = a;
+}
+
+// bfloat16 copies of W1 and W2 from the float32 master.
+__global__ void to_bf16(const float* __restrict__ src, int64_t n, __bf16* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (__bf16)src[e];
+}
+
+__global__ void fill_f32(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void adamw_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                             float* __restrict__ v, int64_t n, float lr, float wd, float b1, float b2,
+                             float eps, float c1, float c2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float ge = g[e];
+    const float me = b1 * m[e] + (1.f - b1) * ge;
+    const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    const float mh = me / c1, vh = ve / c2;
+    p[e] -= lr * (mh / (sqrtf(vh) + eps) + wd * p[e]);
+  }
+}
+
+// Deterministic initialisation: U(-a, a) with a = sqrt(6 / (fan_in + fan_out))
+// for the weight matrices (counter-based hash of (seed, index)); biases 0.
+__device__ __forceinline__ float hash_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed * 0x9E3779B97F4A7C15ull + i * 0xBF58476D1CE4E5B9ull + 0x94D049BB133111EBull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (float)((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.f - 1.f;
+}
+
+__global__ void init_params(float* __restrict__ p, int D, uint64_t seed) {
+  const int64_t F = 2 * D;
+  const int64_t oW1 = 0, ob1 = kH1 * F, oW2 = ob1 + kH1, ob2 = oW2 + kH2 * kH1, ow3 = ob2 + kH2,
+                ob3 = ow3 + kH2, total = ob3 + 1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    float a = 0.f;
+    if (e < ob1) a = sqrtf(6.f / (float)(F + kH1));
+    else if (e >= oW2 && e < ob2) a = sqrtf(6.f / (float)(kH1 + kH2));
+    else if (e >= ow3 && e < ob3) a = sqrtf(6.f / (float)(kH2 + 1));
+    p[e] = a * hash_uniform(seed, (uint64_t)e);
+  }
+}
+
+struct Layout {
+  int64_t F, oW1, ob1, oW2, ob2, ow3, ob3, total;
+};
+
+Layout layout(int D) {
+  Layout L;
+  L.F = 2 * D;
+  L.oW1 = 0;
+  L.ob1 = kH1 * L.F;
+  L.oW2 = L.ob1 + kH1;
+  L.ob2 = L.oW2 + (int64_t)kH2 * kH1;
+  L.ow3 = L.ob2 + kH2;
+  L.ob3 = L.ow3 + kH2;
+  L.total = L.ob3 + 1;
+  return L;
+}
+
+struct MlpWs {
+  __bf16* Fb;    // chunk x 2D
+  float* Z1;     // chunk x 256
+  __bf16* H1;
+  float* Z2;     // chunk x 128
+  __bf16* H2;
+  __bf16* dZ2;
+  __bf16* dZ1;
+  __bf16* W1b;
+  __bf16* W2b;
+  float* s;      // chunk
+};
+
+constexpr int64_t kChunk = 65536;   // rows per forward chunk
+
+MlpWs mlp_layout(Arena& ar, int64_t rows, int D) {
+  MlpWs W;
+  W.Fb = ar.take<__bf16>((size_t)rows * 2 * D);
+  W.Z1 = ar.take<float>((size_t)rows * kH1);
+  W.H1 = ar.take<__bf16>((size_t)rows * kH1);
+  W.Z2 = ar.take<float>((size_t)rows * kH2);
+  W.H2 = ar.take<__bf16>((size_t)rows * kH2);
+  W.dZ2 = ar.take<__bf16>((size_t)rows * kH2);
+  W.dZ1 = ar.take<__bf16>((size_t)rows * kH1);
+  W.W1b = ar.take<__bf16>((size_t)kH1 * 2 * D);
+  W.W2b = ar.take<__bf16>((size_t)kH2 * kH1);
+  W.s = ar.take<float>(rows);
+  return W;
+}
+
+template <int EPI>
+prohd_status gemm(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(g.N, 64), (unsigned)cdiv(g.M, 64));
+  PROHD_LAUNCH("mlp_gemm", gemm_bf16<EPI>, grid, dim3(256), 0, s, g);
+  return PROHD_OK;
+}
+
+#define MLP_TRY(x)                   \
+  do {                               \
+    prohd_status st_ = (x);          \
+    if (st_ != PROHD_OK) return st_; \
+  } while (0)
+
+// Forward over rows [0, n) of a chunk (features already in W.Fb).
+prohd_status forward(const MlpWs& W, int64_t n, int D, const float* params, hipStream_t s) {
+  const Layout L = layout(D);
+  GemmArgs g1{W.Fb, L.F, 1, W.W1b, 1, L.F, (int)n, kH1, (int)L.F, kH1, W.Z1, W.H1, params + L.ob1, nullptr};
+  MLP_TRY(gemm<EPI_BIAS_GELU>(g1, s));
+  GemmArgs g2{W.H1, kH1, 1, W.W2b, 1, kH1, (int)n, kH2, kH1, kH2, W.Z2, W.H2, params + L.ob2, nullptr};
+  MLP_TRY(gemm<EPI_BIAS_GELU>(g2, s));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4), 4096));
+  PROHD_LAUNCH("mlp_head", head_fwd, dim3(grid), dim3(256), 0, s, W.H2, n, params + L.ow3,
+               params + L.ob3, W.s);
+  return PROHD_OK;
+}
+
+prohd_status weights_bf16(const MlpWs& W, int D, const float* params, hipStream_t s) {
+  const Layout L = layout(D);
+  PROHD_LAUNCH("mlp_cvt", to_bf16, dim3(256), dim3(256), 0, s, params + L.oW1, (int64_t)kH1 * L.F, W.W1b);
+  PROHD_LAUNCH("mlp_cvt", to_bf16, dim3(128), dim3(256), 0, s, params + L.oW2, (int64_t)kH2 * kH1, W.W2b);
+  return PROHD_OK;
+}
+
+}  // namespace
+
+size_t mlp_param_count(int32_t D) { return (size_t)layout(D).total; }
+
+size_t mlp_ws_bytes(int64_t rows, int32_t D) {
+  Arena ar(nullptr);
+  mlp_layout(ar, std::min<int64_t>(std::max<int64_t>(rows, 1), kChunk), D);
+  return ar.used + 256;
+}
+
+prohd_status mlp_init(float* params, int32_t D, uint64_t seed, hipStream_t s) {
+  PROHD_LAUNCH("mlp_init", init_params, dim3(256), dim3(256), 0, s, params, D, seed);
+  return PROHD_OK;
+}
+
+prohd_status mlp_score(const float* X, int64_t n, int32_t D, const float* c_other,
+                       const float* params, float* scores, void* ws, size_t ws_bytes,
+                       hipStream_t s) {
+  Arena ar(ws);
+  MlpWs W = mlp_layout(ar, std::min<int64_t>(n, kChunk), D);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "mlp: workspace too small");
+  MLP_TRY(weights_bf16(W, D, params, s));
+  for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
+    const int64_t rows = std::min<int64_t>(kChunk, n - r0);
+    PROHD_LAUNCH("mlp_features", features, dim3(2048), dim3(256), 0, s, X + r0 * D, D,
+                 (const int32_t*)nullptr, rows, c_other, W.Fb);
+    MLP_TRY(forward(W, rows, D, params, s));
+    PROHD_HIP(hipMemcpyAsync(scores + r0, W.s, sizeof(float) * rows, hipMemcpyDeviceToDevice, s));
+  }
+  return PROHD_OK;
+}
+
+prohd_status mlp_grad(const float* X, int32_t D, const float* c_other, const float* labels,
+                      const int32_t* idx, int64_t batch, float pos_weight, const float* params,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t s) {
+  const Layout L = layout(D);
+  if (batch > kChunk) return fail(PROHD_EINVAL, "mlp: batch exceeds 65536 rows");
+  Arena ar(ws);
+  MlpWs W = mlp_layout(ar, batch, D);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "mlp: workspace too small");
+  MLP_TRY(weights_bf16(W, D, params, s));
+  PROHD_LAUNCH("mlp_features", features, dim3(2048), dim3(256), 0, s, X, D, idx, batch, c_other, W.Fb);
+  MLP_TRY(forward(W, batch, D, params, s));
+  PROHD_LAUNCH("mlp_fill", fill_f32, dim3(1), dim3(256), 0, s, grad + L.ow3, (int64_t)(kH2 + 1), 0.f);
+  PROHD_LAUNCH("mlp_fill", fill_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1, 0.f);
+  PROHD_LAUNCH("mlp_head_bwd", head_bwd, dim3((unsigned)cdiv(batch, 64)), dim3(256), 0, s, W.H2, W.Z2,
+               W.s, labels, idx, batch, pos_weight, params + L.ow3, W.dZ2, grad + L.ow3, grad + L.ob3,
+               loss);
+  // dW2 = dZ2^T H1 ; db2 = colsum dZ2
+  GemmArgs gw2{W.dZ2, 1, kH2, W.H1, kH1, 1, kH2, kH1, (int)batch, kH1, grad + L.oW2, nullptr, nullptr, nullptr};
+  MLP_TRY(gemm<EPI_F32>(gw2, s));
+  PROHD_LAUNCH("mlp_colsum", colsum, dim3(1), dim3(kH2), 0, s, W.dZ2, batch, kH2, grad + L.ob2);
+  // dZ1 = (dZ2 W2) * gelu'(z1)
+  GemmArgs gd1{W.dZ2, kH2, 1, W.W2b, kH1, 1, (int)batch, kH1, kH2, kH1, nullptr, W.dZ1, nullptr, W.Z1};
+  MLP_TRY(gemm<EPI_GELU_BWD>(gd1, s));
+  // dW1 = dZ1^T F ; db1 = colsum dZ1
+  GemmArgs gw1{W.dZ1, 1, kH1, W.Fb, L.F, 1, kH1, (int)L.F, (int)batch, L.F, grad + L.oW1, nullptr, nullptr, nullptr};
+  MLP_TRY(gemm<EPI_F32>(gw1, s));
+  PROHD_LAUNCH("mlp_colsum", colsum, dim3(1), dim3(kH1), 0, s, W.dZ1, batch, kH1, grad + L.ob1);
+  return PROHD_OK;
+}
+
+prohd_status mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t D, int64_t t,
+                       float lr, float wd, float b1, float b2, float eps, hipStream_t s) {
+  const int64_t n = layout(D).total;
+  const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+  PROHD_LAUNCH("mlp_adamw", adamw_kernel, dim3(256), dim3(256), 0, s, params, grad, m, v, n, lr, wd, b1,
+               b2, eps, c1, c2);
+  return PROHD_OK;
+}
+
+}  // namespace prohd

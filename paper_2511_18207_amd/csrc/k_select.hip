@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void tie_count(const SegPack P,
 
 // Exclusive prefix over chunks (per segment and end), in place.
 __global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cnt, int nchunks,
-                                                      int64_t* __restrict__ total) {
+                                                      int64_t* __restrict__ total, int64_t cap) {
   uint32_t* c = cnt + (size_t)blockIdx.x * nchunks;
   __shared__ uint32_t part[kThreads];
   const int per = (nchunks + kThreads - 1) / kThreads;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cn
       part[t] = acc;
       acc += x;
     }
-    if (total) total[blockIdx.x] = acc;
+    if (total) total[blockIdx.x] = (int64_t)acc < cap ? (int64_t)acc : cap;
   }
   __syncthreads();
   uint32_t acc = part[threadIdx.x];
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void flag_count(const uint8_t* __restrict
 __global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict__ f, int64_t hn,
                                                       const int64_t* __restrict__ dn,
                                                       const uint32_t* __restrict__ off,
-                                                      int32_t* __restrict__ idx) {
+                                                      int32_t* __restrict__ idx, int64_t cap) {
   const int64_t n = dn ? min(*dn, hn) : hn;
   const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
   if (base >= n) return;
@@ -308,9 +308,17 @@ __global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict
     const bool p = i < n && f[i] != 0;
     uint32_t tot;
     const uint32_t pre = block_excl_scan(p, wsum, &tot);
-    if (p) idx[r + pre] = (int32_t)i;
+    if (p && (int64_t)(r + pre) < cap) idx[r + pre] = (int32_t)i;
     r += tot;
   }
+}
+
+// flags[idx[i]] = 1 for i < *count
+__global__ void scatter_flags(const int32_t* __restrict__ idx, const int64_t* __restrict__ count,
+                              int64_t cap, uint8_t* __restrict__ flags) {
+  const int64_t n = min(*count, cap);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flags[idx[i]] = 1;
 }
 
 __global__ void zero_kernel(uint32_t* __restrict__ p, size_t words, uint8_t* __restrict__ tail,
@@ -384,7 +392,7 @@ prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_b
     PROHD_LAUNCH("select_ties", tie_count, dim3(L.nchunks, ns), dim3(kThreads), 0, s, P, L.st,
                  L.tie, L.nchunks);
     PROHD_LAUNCH("select_tiescan", chunk_scan, dim3(2 * ns), dim3(kThreads), 0, s,
-                 L.tie + (size_t)g0 * 2 * L.nchunks, L.nchunks, (int64_t*)nullptr);
+                 L.tie + (size_t)g0 * 2 * L.nchunks, L.nchunks, (int64_t*)nullptr, (int64_t)0);
     PROHD_LAUNCH("select_mark", mark, dim3(L.nchunks, ns), dim3(kThreads), 0, s, P, L.st, L.tie,
                  L.nchunks);
   }
@@ -398,14 +406,22 @@ size_t compact_ws_bytes(int64_t n) {
 }
 
 prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n, int32_t* idx,
-                           int64_t* count, void* ws, size_t ws_bytes, hipStream_t s) {
+                           int64_t cap, int64_t* count, void* ws, size_t ws_bytes, hipStream_t s) {
   const int nch = (int)std::max<int64_t>(1, cdiv(n, kMarkChunk));
   Arena ar(ws);
   uint32_t* cnt = ar.take<uint32_t>(nch);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "compact: workspace too small");
   PROHD_LAUNCH("compact_count", flag_count, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt);
-  PROHD_LAUNCH("compact_scan", chunk_scan, dim3(1), dim3(kThreads), 0, s, cnt, nch, count);
-  PROHD_LAUNCH("compact_write", flag_write, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt, idx);
+  PROHD_LAUNCH("compact_scan", chunk_scan, dim3(1), dim3(kThreads), 0, s, cnt, nch, count, cap);
+  PROHD_LAUNCH("compact_write", flag_write, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt, idx,
+               cap);
+  return PROHD_OK;
+}
+
+prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64_t cap, uint8_t* flags,
+                                 hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 1024));
+  PROHD_LAUNCH("select_scatter", scatter_flags, dim3(grid), dim3(256), 0, s, idx, count, cap, flags);
   return PROHD_OK;
 }
 

@@ -102,6 +102,30 @@ def test_select_validation():
     assert L.prohd_select(FAKE, 100, FAKE, 100, 65, k, k, FAKE, 40, FAKE, FAKE, 40, FAKE, FAKE, 1 << 24, None) == 5
 
 
+def test_mlp_and_scored_validation():
+    import oracle.mlp as om
+    L = ph.lib()
+    for D in (1, 17, 256):
+        assert ph.mlp_param_count(D) == om.param_count(D)
+    assert ph.mlp_param_count(0) == 0 and ph.mlp_param_count(257) == 0
+    assert ph.mlp_workspace_size(0, 8) == 0
+    assert ph.mlp_workspace_size(1000, 8) < ph.mlp_workspace_size(100000, 8)
+    assert L.prohd_mlp_init(None, 8, 0, None) == 1
+    assert L.prohd_mlp_init(FAKE, 300, 0, None) == 5
+    assert L.prohd_mlp_score(FAKE, 0, 8, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == 1
+    assert L.prohd_mlp_score(FAKE, 100, 8, FAKE, FAKE, FAKE, FAKE, 16, None) == 3
+    assert L.prohd_mlp_grad(FAKE, 8, FAKE, FAKE, FAKE, 65537, 1.0, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == 1
+    assert "batch" in L.prohd_last_error().decode()
+    assert L.prohd_mlp_grad(FAKE, 8, FAKE, FAKE, FAKE, 64, 0.0, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == 1
+    assert L.prohd_mlp_adamw(FAKE, FAKE, FAKE, FAKE, 8, 0, 1e-3, 0.0, 0.9, 0.999, 1e-8, None) == 1
+    assert L.prohd_mlp_adamw(FAKE, FAKE, FAKE, FAKE, 8, 1, 1e-3, 0.0, 1.0, 0.999, 1e-8, None) == 1
+    assert L.prohd_select_scored(FAKE, 100, 5, FAKE, 100, 5, FAKE, 4, FAKE, FAKE, 10, FAKE, FAKE,
+                                 1 << 30, None) == 1
+    assert "capacities" in L.prohd_last_error().decode()
+    assert L.prohd_select_scored(FAKE, 100, -1, FAKE, 100, 5, FAKE, 10, FAKE, FAKE, 10, FAKE, FAKE,
+                                 1 << 30, None) == 1
+
+
 def test_k_rule_matches_oracle():
     import oracle
     for a, n in [(0.01, 2_000_000), (0.01 / 16, 2_000_000), (0.29, 100), (0.5, 3), (0.001, 10)]:
