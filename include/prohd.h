@@ -238,6 +238,19 @@ prohd_status prohd_mlp_grad(const float* X, int32_t D, const float* c_other, con
 prohd_status prohd_mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t D,
                              int64_t t, float lr, float weight_decay, float beta1, float beta2,
                              float eps, void* stream);
+/* One training step: prohd_mlp_grad, then prohd_mlp_adamw at step t with
+ * the gradient it wrote (grad is overwritten). */
+prohd_status prohd_mlp_train_step(const float* X, int32_t D, const float* c_other,
+                                  const float* labels, const int32_t* idx, int64_t batch,
+                                  float pos_weight, float* params, float* grad, float* m, float* v,
+                                  int64_t t, float lr, float weight_decay, float beta1, float beta2,
+                                  float eps, float* loss, void* ws, size_t ws_bytes, void* stream);
+/* Centroid (column mean, float64 accumulation, float32 result) of the n x D
+ * set X (Alg. 1 forms it for both sets); the scorer's c_other.  `mean`: D
+ * floats, device.  ws_bytes must be >= PROHD_CENTROID_WS_BYTES(D). */
+#define PROHD_CENTROID_WS_BYTES(D) ((size_t)1024 * (size_t)(D) * 8u + 256u)
+prohd_status prohd_centroid(const float* X, int64_t n, int32_t D, float* mean, void* ws,
+                            size_t ws_bytes, void* stream);
 /* Adds the sA (sB) highest-scoring rows of A (B) to the selected lists
  * idxA/nselA (idxB/nselB) in place: the result is the ascending unique union.
  * Ties in the scores go to the smaller index.  capA must be >= min(nA,

@@ -26,6 +26,8 @@ from ._lib import (  # noqa: F401
     mlp_score,
     mlp_grad,
     mlp_adamw,
+    mlp_train_step,
+    centroid,
     select_scored,
     profile_enable,
     profile_reset,

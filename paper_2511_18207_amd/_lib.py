@@ -78,6 +78,12 @@ def lib() -> C.CDLL:
     L.prohd_mlp_adamw.restype = C.c_int
     L.prohd_mlp_adamw.argtypes = [vp, vp, vp, vp, i32, i64, C.c_float, C.c_float, C.c_float,
                                   C.c_float, C.c_float, vp]
+    L.prohd_mlp_train_step.restype = C.c_int
+    L.prohd_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i64, C.c_float, vp, vp, vp, vp, i64,
+                                       C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp,
+                                       vp, sz, vp]
+    L.prohd_centroid.restype = C.c_int
+    L.prohd_centroid.argtypes = [vp, i64, i32, vp, vp, sz, vp]
     L.prohd_select_scored.restype = C.c_int
     L.prohd_select_scored.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp, vp, i64, vp, vp, sz,
                                       vp]
@@ -366,6 +372,45 @@ def mlp_adamw(params, grad, m, v, D, t, lr, weight_decay=0.01, beta1=0.9, beta2=
         _f32_1d(x, name, P)
     _check(lib().prohd_mlp_adamw(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
                                  D, t, lr, weight_decay, beta1, beta2, eps, _stream()))
+
+
+def mlp_train_step(X, c_other, labels, idx, params, grad, m, v, t, lr, pos_weight=1.0,
+                   weight_decay=0.01, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, ws=None):
+    """prohd_mlp_grad followed by prohd_mlp_adamw (in place); returns the
+    device loss tensor."""
+    torch = _torch()
+    X = _f32_2d(X, "X")
+    n, D = X.shape
+    P = mlp_param_count(D)
+    _f32_1d(c_other, "c_other", D)
+    _f32_1d(labels, "labels", n)
+    for name, x in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _f32_1d(x, name, P)
+    if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+        raise TypeError("idx must be a contiguous int32 CUDA (HIP) tensor")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    batch = idx.numel()
+    buf, nbytes = _ws(ws, mlp_workspace_size(max(batch, 1), D))
+    _check(lib().prohd_mlp_train_step(X.data_ptr(), D, c_other.data_ptr(), labels.data_ptr(),
+                                      idx.data_ptr(), batch, float(pos_weight), params.data_ptr(),
+                                      grad.data_ptr(), m.data_ptr(), v.data_ptr(), int(t), lr,
+                                      weight_decay, beta1, beta2, eps, loss.data_ptr(),
+                                      buf.data_ptr(), nbytes, _stream()))
+    return loss
+
+
+def centroid(X, out=None, ws=None):
+    """Column mean of X (float64 accumulation) as a float32 device vector."""
+    torch = _torch()
+    X = _f32_2d(X, "X")
+    n, D = X.shape
+    if out is None:
+        out = torch.empty(D, dtype=torch.float32, device=X.device)
+    buf, nbytes = _ws(ws, 1024 * D * 8 + 256)
+    _check(lib().prohd_centroid(X.data_ptr(), n, D, out.data_ptr(), buf.data_ptr(), nbytes,
+                                _stream()))
+    return out
 
 
 def select_scored(scoresA, sA, scoresB, sB, idxA, nselA, idxB, nselB, ws=None):

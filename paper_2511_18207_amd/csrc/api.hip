@@ -306,6 +306,32 @@ prohd_status prohd_mlp_adamw(float* params, const float* grad, float* m, float* 
   return mlp_adamw(params, grad, m, v, D, t, lr, weight_decay, beta1, beta2, eps, (hipStream_t)stream);
 }
 
+prohd_status prohd_mlp_train_step(const float* X, int32_t D, const float* c_other,
+                                  const float* labels, const int32_t* idx, int64_t batch,
+                                  float pos_weight, float* params, float* grad, float* m, float* v,
+                                  int64_t t, float lr, float weight_decay, float beta1, float beta2,
+                                  float eps, float* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (bad_ptr(m) || bad_ptr(v)) return fail(PROHD_EINVAL, "null pointer");
+  if (t < 1) return fail(PROHD_EINVAL, "t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f && lr >= 0.f))
+    return fail(PROHD_EINVAL, "bad AdamW hyper-parameters");
+  prohd_status st = prohd_mlp_grad(X, D, c_other, labels, idx, batch, pos_weight, params, grad, loss,
+                                   ws, ws_bytes, stream);
+  if (st) return st;
+  return prohd_mlp_adamw(params, grad, m, v, D, t, lr, weight_decay, beta1, beta2, eps, stream);
+}
+
+prohd_status prohd_centroid(const float* X, int64_t n, int32_t D, float* mean, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (bad_ptr(X) || bad_ptr(mean) || bad_ptr(ws)) return fail(PROHD_EINVAL, "null pointer");
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(PROHD_EINVAL, "n must be in [1, 2^31)");
+  if (D < 1) return fail(PROHD_EINVAL, "D must be >= 1");
+  if (D > PROHD_MAX_DIM) return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM (256)");
+  if (ws_bytes < PROHD_CENTROID_WS_BYTES(D) || ws_bytes < centroid_ws_bytes(D))
+    return fail(PROHD_EWORKSPACE, "workspace too small");
+  return centroid_run(X, n, D, mean, ws, ws_bytes, (hipStream_t)stream);
+}
+
 prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
                                  const float* scoresB, int64_t nB, int32_t sB,
                                  int32_t* idxA, int64_t capA, int64_t* nselA,

@@ -108,6 +108,11 @@ size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB
                    uint32_t flags);
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags);
 
+// Column means of one set (k_mean.hip).
+size_t centroid_ws_bytes(int32_t D);
+prohd_status centroid_run(const float* X, int64_t n, int32_t D, float* mean, void* ws,
+                          size_t ws_bytes, hipStream_t s);
+
 // Learned proposal scorer (k_mlp.hip).
 size_t mlp_param_count(int32_t D);
 size_t mlp_ws_bytes(int64_t rows, int32_t D);

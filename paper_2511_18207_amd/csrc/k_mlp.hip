@@ -25,6 +25,8 @@ namespace {
 
 constexpr int kH1 = 256;
 constexpr int kH2 = 128;
+constexpr int kHeadPart = kH2 + 2;             // head partial: gw3, gb3, loss
+constexpr int64_t kPartFloats = 4 << 20;       // split-K / column-sum partials (16 MiB)
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -47,7 +49,38 @@ struct GemmArgs {
   __bf16* outh;       // EPI_BIAS_GELU: gelu(z); EPI_GELU_BWD: acc * gelu'(zin)
   const float* bias;  // EPI_BIAS_GELU
   const float* zin;   // EPI_GELU_BWD: pre-activation, same layout as the output
+  int kper;           // K range of split z = blockIdx.z: [z kper, (z + 1) kper)
+  float* part;        // EPI_F32 with several splits: partial sums [z][M][N]
+  int amode, bmode;   // operand staging: 0 scalar, 1 K-contiguous, 2 M/N-contiguous
 };
+
+// Stage the 64 x 32 tile X(r0 + r, k0 + k) = P[r lr + k lk] into S[r][k]
+// (row stride ST).  Full tiles of a vector-friendly operand move 8 values
+// per thread in one 16-byte load; edge tiles and other layouts go element by
+// element with zero fill.
+template <int ST>
+__device__ __forceinline__ void stage(const __bf16* __restrict__ P, int64_t lr, int64_t lk, int R,
+                                      int kend, int r0, int k0, int mode, __bf16* __restrict__ S,
+                                      int tid) {
+  const bool full = (r0 + 64 <= R) && (k0 + 32 <= kend);
+  if (full && mode == 1) {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    *reinterpret_cast<bf16x8*>(&S[r * ST + kk]) =
+        *reinterpret_cast<const bf16x8*>(&P[(int64_t)(r0 + r) * lr + (k0 + kk)]);
+  } else if (full && mode == 2) {
+    const int kk = tid >> 3, rr = (tid & 7) * 8;
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(&P[(r0 + rr) + (int64_t)(k0 + kk) * lk]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) S[(rr + j) * ST + kk] = v[j];
+  } else {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + kk + j;
+      S[r * ST + kk + j] = (r0 + r < R && k < kend) ? P[(int64_t)(r0 + r) * lr + (int64_t)k * lk] : (__bf16)0.f;
+    }
+  }
+}
 
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
@@ -62,18 +95,12 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
   const int gsel = lane >> 5, c = lane & 31;
   floatx16 acc = {0.f};
   // staging: thread -> (row r = tid / 4, k group of 8 = (tid % 4) * 8)
-  const int sr = tid >> 2, sk = (tid & 3) * 8;
-  for (int k0 = 0; k0 < g.K; k0 += KC) {
+  const int kbeg = blockIdx.z * g.kper;
+  const int kend = min(g.K, kbeg + g.kper);
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
     __syncthreads();
-    {
-      const int m = m0 + sr, n = n0 + sr;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + sk + j;
-        As[sr * ST + sk + j] = (m < g.M && k < g.K) ? g.A[m * g.lam + k * g.lak] : (__bf16)0.f;
-        Bs[sr * ST + sk + j] = (n < g.N && k < g.K) ? g.B[k * g.lbk + n * g.lbn] : (__bf16)0.f;
-      }
-    }
+    stage<ST>(g.A, g.lam, g.lak, g.M, kend, m0, k0, g.amode, As, tid);
+    stage<ST>(g.B, g.lbn, g.lbk, g.N, kend, n0, k0, g.bmode, Bs, tid);
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
@@ -91,7 +118,10 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
     if (m >= g.M) continue;
     const int64_t o = (int64_t)m * g.ldc + n;
     if (EPI == EPI_F32) {
-      g.outf[o] = acc[v];
+      if (g.part)
+        g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[v];
+      else
+        g.outf[o] = acc[v];
     } else if (EPI == EPI_BIAS_GELU) {
       const float z = acc[v] + g.bias[n];
       if (g.outf) g.outf[o] = z;
@@ -138,8 +168,7 @@ __global__ __launch_bounds__(256) void head_bwd(const __bf16* __restrict__ H2,
                                                 const float* __restrict__ labels,
                                                 const int32_t* __restrict__ idx, int64_t n,
                                                 float pos_weight, const float* __restrict__ w3,
-                                                __bf16* __restrict__ dZ2, float* __restrict__ gw3,
-                                                float* __restrict__ gb3, float* __restrict__ loss) {
+                                                __bf16* __restrict__ dZ2, float* __restrict__ part) {
   __shared__ float dsv[64];
   __shared__ float lsum[64];
   const int64_t r0 = (int64_t)blockIdx.x * 64;
@@ -170,36 +199,63 @@ __global__ __launch_bounds__(256) void head_bwd(const __bf16* __restrict__ H2,
     g += ds * (float)H2[i * kH2 + j];
     dZ2[i * kH2 + j] = (__bf16)(ds * w3[j] * gelu_grad(Z2[i * kH2 + j]));
   }
-  atomicAdd(&gw3[j], g);
+  // per-block partials [130]: gw3 (128), gb3, loss; halves combine in LDS
+  __shared__ float gsum[256];
+  gsum[tid] = g;
+  __syncthreads();
+  float* pp = part + (size_t)blockIdx.x * kHeadPart;
+  if (tid < 128) pp[tid] = gsum[tid] + gsum[tid + 128];
   if (tid == 0) {
     float a = 0.f, b = 0.f;
     for (int rr = 0; rr < 64; ++rr) {
       a += dsv[rr];
       b += lsum[rr];
     }
-    atomicAdd(gb3, a);
-    atomicAdd(loss, b / (float)n);
+    pp[128] = a;
+    pp[129] = b / (float)n;
   }
 }
 
-// Column sums of a bfloat16 matrix (n x N) into float32 out[N].
-__global__ void colsum(const __bf16* __restrict__ M, int64_t n, int N, float* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// Sums of the head partials over blocks, in block order.
+__global__ void head_reduce(const float* __restrict__ part, int nblk, float* __restrict__ gw3,
+                            float* __restrict__ gb3, float* __restrict__ loss) {
+  const int j = threadIdx.x;
+  if (j >= kHeadPart) return;
   float a = 0.f;
-  for (int64_t i = 0; i < n; ++i) a += (float)M[i * N + j];
-  out[j] = a;
+  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * kHeadPart + j];
+  if (j < 128) gw3[j] = a;
+  else if (j == 128) gb3[0] = a;
+  else loss[0] = a;
+}
+
+// out[m ldc + n] = sum over z of part[z][m][n] (split order, deterministic).
+__global__ void split_reduce(const float* __restrict__ part, int splits, int M, int N,
+                             float* __restrict__ out, int64_t ldc) {
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float a = 0.f;
+    for (int z = 0; z < splits; ++z) a += part[(int64_t)z * MN + e];
+    out[(e / N) * ldc + (e % N)] = a;
+  }
+}
+
+// Partial column sums of a bfloat16 matrix (n x N, N <= 256): block g sums
+// rows [256 g, 256 g + 256) into part[g][N].
+__global__ void colsum_part(const __bf16* __restrict__ M, int64_t n, int N, float* __restrict__ part) {
+  const int j = threadIdx.x;
+  if (j >= N) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
+  float a = 0.f;
+  for (int64_t i = r0; i < r1; ++i) a += (float)M[i * N + j];
+  part[(size_t)blockIdx.x * N + j] = a;
 }
 
 // bfloat16 copies of W1 and W2 from the float32 master.
 __global__ void to_bf16(const float* __restrict__ src, int64_t n, __bf16* __restrict__ dst) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = (__bf16)src[e];
-}
-
-__global__ void fill_f32(float* __restrict__ p, int64_t n, float v) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = v;
 }
 
 __global__ void adamw_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -267,6 +323,7 @@ struct MlpWs {
   __bf16* W1b;
   __bf16* W2b;
   float* s;      // chunk
+  float* part;   // split-K, column-sum and head partials
 };
 
 constexpr int64_t kChunk = 65536;   // rows per forward chunk
@@ -283,13 +340,48 @@ MlpWs mlp_layout(Arena& ar, int64_t rows, int D) {
   W.W1b = ar.take<__bf16>((size_t)kH1 * 2 * D);
   W.W2b = ar.take<__bf16>((size_t)kH2 * kH1);
   W.s = ar.take<float>(rows);
+  W.part = ar.take<float>((size_t)kPartFloats);
   return W;
 }
 
+int vec_mode(const __bf16* P, int64_t lr, int64_t lk) {
+  if (((uintptr_t)P & 15) != 0) return 0;
+  if (lk == 1 && lr % 8 == 0) return 1;
+  if (lr == 1 && lk % 8 == 0) return 2;
+  return 0;
+}
+
+// Launches one product.  With `part` (EPI_F32 only) a long K is split over
+// blockIdx.z so that the grid has ~2048 work-groups; the partial sums are
+// then added in split order.
 template <int EPI>
-prohd_status gemm(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(g.N, 64), (unsigned)cdiv(g.M, 64));
+prohd_status gemm(GemmArgs g, hipStream_t s, float* part = nullptr) {
+  g.amode = vec_mode(g.A, g.lam, g.lak);
+  g.bmode = vec_mode(g.B, g.lbn, g.lbk);
+  const int64_t tiles = cdiv(g.N, 64) * cdiv(g.M, 64);
+  int64_t splits = 1;
+  if (EPI == EPI_F32 && part) {
+    splits = std::min<int64_t>(cdiv(g.K, 128), cdiv(2048, tiles));
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, kPartFloats / ((int64_t)g.M * g.N)));
+  }
+  g.kper = (int)(cdiv(cdiv(g.K, splits), 32) * 32);
+  splits = std::max<int64_t>(1, cdiv(g.K, g.kper));
+  g.part = splits > 1 ? part : nullptr;
+  const dim3 grid((unsigned)cdiv(g.N, 64), (unsigned)cdiv(g.M, 64), (unsigned)splits);
   PROHD_LAUNCH("mlp_gemm", gemm_bf16<EPI>, grid, dim3(256), 0, s, g);
+  if (splits > 1) {
+    const int64_t MN = (int64_t)g.M * g.N;
+    PROHD_LAUNCH("mlp_split_reduce", split_reduce, dim3((unsigned)std::min<int64_t>(cdiv(MN, 256), 1024)),
+                 dim3(256), 0, s, (const float*)part, (int)splits, g.M, g.N, g.outf, g.ldc);
+  }
+  return PROHD_OK;
+}
+
+prohd_status colsum(const __bf16* M, int64_t n, int N, float* out, float* part, hipStream_t s) {
+  const int nblk = (int)cdiv(n, 256);
+  PROHD_LAUNCH("mlp_colsum", colsum_part, dim3(nblk), dim3(256), 0, s, M, n, N, part);
+  PROHD_LAUNCH("mlp_split_reduce", split_reduce, dim3(1), dim3(256), 0, s, (const float*)part, nblk, 1,
+               N, out, (int64_t)N);
   return PROHD_OK;
 }
 
@@ -362,22 +454,22 @@ prohd_status mlp_grad(const float* X, int32_t D, const float* c_other, const flo
   MLP_TRY(weights_bf16(W, D, params, s));
   PROHD_LAUNCH("mlp_features", features, dim3(2048), dim3(256), 0, s, X, D, idx, batch, c_other, W.Fb);
   MLP_TRY(forward(W, batch, D, params, s));
-  PROHD_LAUNCH("mlp_fill", fill_f32, dim3(1), dim3(256), 0, s, grad + L.ow3, (int64_t)(kH2 + 1), 0.f);
-  PROHD_LAUNCH("mlp_fill", fill_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1, 0.f);
-  PROHD_LAUNCH("mlp_head_bwd", head_bwd, dim3((unsigned)cdiv(batch, 64)), dim3(256), 0, s, W.H2, W.Z2,
-               W.s, labels, idx, batch, pos_weight, params + L.ow3, W.dZ2, grad + L.ow3, grad + L.ob3,
-               loss);
+  const int hblk = (int)cdiv(batch, 64);
+  PROHD_LAUNCH("mlp_head_bwd", head_bwd, dim3((unsigned)hblk), dim3(256), 0, s, W.H2, W.Z2, W.s, labels,
+               idx, batch, pos_weight, params + L.ow3, W.dZ2, W.part);
+  PROHD_LAUNCH("mlp_head_reduce", head_reduce, dim3(1), dim3(192), 0, s, (const float*)W.part, hblk,
+               grad + L.ow3, grad + L.ob3, loss);
   // dW2 = dZ2^T H1 ; db2 = colsum dZ2
   GemmArgs gw2{W.dZ2, 1, kH2, W.H1, kH1, 1, kH2, kH1, (int)batch, kH1, grad + L.oW2, nullptr, nullptr, nullptr};
-  MLP_TRY(gemm<EPI_F32>(gw2, s));
-  PROHD_LAUNCH("mlp_colsum", colsum, dim3(1), dim3(kH2), 0, s, W.dZ2, batch, kH2, grad + L.ob2);
+  MLP_TRY(gemm<EPI_F32>(gw2, s, W.part));
+  MLP_TRY(colsum(W.dZ2, batch, kH2, grad + L.ob2, W.part, s));
   // dZ1 = (dZ2 W2) * gelu'(z1)
   GemmArgs gd1{W.dZ2, kH2, 1, W.W2b, kH1, 1, (int)batch, kH1, kH2, kH1, nullptr, W.dZ1, nullptr, W.Z1};
   MLP_TRY(gemm<EPI_GELU_BWD>(gd1, s));
   // dW1 = dZ1^T F ; db1 = colsum dZ1
   GemmArgs gw1{W.dZ1, 1, kH1, W.Fb, L.F, 1, kH1, (int)L.F, (int)batch, L.F, grad + L.oW1, nullptr, nullptr, nullptr};
-  MLP_TRY(gemm<EPI_F32>(gw1, s));
-  PROHD_LAUNCH("mlp_colsum", colsum, dim3(1), dim3(kH1), 0, s, W.dZ1, batch, kH1, grad + L.ob1);
+  MLP_TRY(gemm<EPI_F32>(gw1, s, W.part));
+  MLP_TRY(colsum(W.dZ1, batch, kH1, grad + L.ob1, W.part, s));
   return PROHD_OK;
 }
 

@@ -104,9 +104,11 @@ def _centres(seed: int, K: int, D: int, centre_std: float, b_centre_std: float):
 def mixture(nA: int, nB: int, D: int, seed: int, K: int = 64,
             centre_std: float = 2.0, b_centre_std: float = 0.5,
             sigma: float = 1.0, normalize: bool = False,
-            outlier_frac: float = 0.0, nu: float = 3.0):
-    """Gaussian-cluster mixture pair, optionally with Student-t outliers."""
-    cA, cB = _centres(seed, K, D, centre_std, b_centre_std)
+            outlier_frac: float = 0.0, nu: float = 3.0, centre_seed: int | None = None):
+    """Gaussian-cluster mixture pair, optionally with Student-t outliers.
+    ``centre_seed`` (default: ``seed``) fixes the cluster centres, so that
+    several pairs can be drawn from one distribution."""
+    cA, cB = _centres(seed if centre_seed is None else centre_seed, K, D, centre_std, b_centre_std)
 
     def make(centres):
         def f(g, r, o):
@@ -135,9 +137,10 @@ def mixture(nA: int, nB: int, D: int, seed: int, K: int = 64,
 
 def t_mixture(nA: int, nB: int, D: int, seed: int, K: int = 128,
               centre_std: float = 2.0, b_centre_std: float = 0.5,
-              sigma: float = 1.0, nu: float = 3.0):
-    """Mixture where every point is its centre plus multivariate t(nu) noise."""
-    cA, cB = _centres(seed, K, D, centre_std, b_centre_std)
+              sigma: float = 1.0, nu: float = 3.0, centre_seed: int | None = None):
+    """Mixture where every point is its centre plus multivariate t(nu) noise
+    (``centre_seed`` as in ``mixture``)."""
+    cA, cB = _centres(seed if centre_seed is None else centre_seed, K, D, centre_std, b_centre_std)
 
     def make(centres):
         def f(g, r, o):
