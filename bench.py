@@ -110,6 +110,109 @@ def cpu_baseline(A, B, m, alpha, n_sample):
     }
 
 
+LEARNED_LAW = {"K": 128, "nu": 30.0, "centre_seed": 77, "D": 256}
+
+
+def learned_form(args, dev):
+    """Learned proposal: train the scorer on pairs of one Student-t mixture
+    (fixed centres, new samples per pair), then compare ProHD + top-scored
+    points with plain ProHD at an equal candidate budget on held-out pairs,
+    exact HD as judge."""
+    import numpy as np
+    import torch
+
+    import paper_2511_18207_amd as ph
+    import synth
+    from paper_2511_18207_amd import learned as LN
+
+    n, D = args.learned_n, LEARNED_LAW["D"]
+
+    def draw(seed):
+        A, B = synth.t_mixture(n, n, D, seed, K=LEARNED_LAW["K"], nu=LEARNED_LAW["nu"],
+                               centre_seed=LEARNED_LAW["centre_seed"])
+        return torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+
+    ws = ph.Workspace(dev)
+    t0 = time.perf_counter()
+    pairs = []
+    label_ms = 0.0
+    for i in range(args.learned_pairs):
+        dA, dB = draw(10_000 + i)
+        torch.cuda.synchronize()
+        l0 = time.perf_counter()
+        pairs.append(LN.TrainPair(dA, dB, ws=ws))
+        torch.cuda.synchronize()
+        label_ms += 1e3 * (time.perf_counter() - l0)
+    log(f"learned: {len(pairs)} training pairs {n}x{n} labelled in {label_ms:.0f} ms "
+        f"(total {time.perf_counter() - t0:.1f}s)")
+    sc = LN.Scorer(D, seed=1)
+    batch = 16384
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = LN.train(sc, pairs, args.learned_steps, batch=batch, lr=2e-3, lr_final=1e-4,
+                      pos_share=0.5, seed=0, ws=ws)
+    torch.cuda.synchronize()
+    train_ms = 1e3 * (time.perf_counter() - t1)
+    # training step FLOPs: forward 2 n (2D*256 + 256*128 + 128), backward about twice that
+    fwd_flops = 2.0 * (2 * D * 256 + 256 * 128 + 128)
+    log(f"learned: {args.learned_steps} steps in {train_ms:.0f} ms, loss {losses[:50].mean():.4f} -> "
+        f"{losses[-100:].mean():.4f}")
+    del pairs
+    torch.cuda.empty_cache()
+
+    evals = []
+    e = torch.cuda.Event
+    for i in range(args.learned_eval):
+        dA, dB = draw(20_000 + i)
+        H = ph.decode_result(ph.exact_hd(dA, dB, ws=ws))["H"]
+        rep = LN.equal_budget(dA, dB, sc, alpha=0.01, H=H, ws=ws)
+        # time plain ProHD and the learned form (score both sets, merge, hd)
+        base = ph.prohd(dA, dB, alpha=0.01, inner_full=False, ws=ws)
+        e0, e1, e2 = e(enable_timing=True), e(enable_timing=True), e(enable_timing=True)
+        e0.record()
+        ph.prohd(dA, dB, alpha=0.01, ws=ws)
+        e1.record()
+        LN.proposal(dA, dB, sc, alpha=0.01, ws=ws, base=base)
+        e2.record()
+        torch.cuda.synchronize()
+        rep["prohd_ms"] = e0.elapsed_time(e1)
+        rep["learned_extra_ms"] = e1.elapsed_time(e2)
+        evals.append(rep)
+        log(f"learned eval {i}: H={H:.5f} full err prohd {rep['full']['prohd_err']:.3e} learned "
+            f"{rep['full']['learned_err']:.3e} plain {rep['full']['plain_err']:.3e} | candidates "
+            f"prohd {rep['candidates']['prohd_err']:.3e} learned {rep['candidates']['learned_err']:.3e} "
+            f"plain {rep['candidates']['plain_err']:.3e}")
+    # scoring throughput on one set
+    X = dA
+    cB = ph.centroid(dB, ws=ws)
+    sc.score(X, cB, ws=ws)
+    e0, e1 = e(enable_timing=True), e(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        sc.score(X, cB, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    score_ms = e0.elapsed_time(e1) / 5
+
+    def mean(mode, key):
+        return float(np.mean([r[mode][key] for r in evals]))
+
+    return {
+        "law": f"Student-t({LEARNED_LAW['nu']:g}) mixture, {LEARNED_LAW['K']} clusters, D={D}, "
+               "centres N(0,4I) fixed across pairs, B centres + N(0,0.25I)",
+        "train": {"pairs": args.learned_pairs, "n_per_set": n, "points": 2 * n * args.learned_pairs,
+                  "label_frac": LN.LABEL_FRAC, "label_ms": label_ms, "steps": args.learned_steps,
+                  "batch": batch, "train_ms": train_ms,
+                  "ms_per_step": train_ms / args.learned_steps,
+                  "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-100:].mean())},
+        "score": {"rows": int(X.shape[0]), "ms": score_ms,
+                  "tflops": X.shape[0] * fwd_flops / (score_ms * 1e-3) / 1e12},
+        "eval": evals,
+        "mean_rel_err": {mode: {k: mean(mode, k + "_err") for k in ("prohd", "learned", "plain")}
+                         for mode in ("candidates", "full")},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +224,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=10)
+    ap.add_argument("--learned-eval", type=int, default=4)
+    ap.add_argument("--learned-n", type=int, default=500_000)
+    ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (HBM-counter calibration)")
     args = ap.parse_args()
@@ -302,6 +410,13 @@ def main():
             log(f"prohd[{prec}, alpha x{mult}] {ms_:.2f} ms H={r_['H']:.6f} err={forms[-1]['rel_err_vs_exact']:.2e}")
         exact["precision_form"] = forms
 
+    learned = None
+    if not args.no_learned:
+        del ws
+        torch.cuda.empty_cache()
+        learned = learned_form(args, dev)
+        ws = None
+
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -330,6 +445,7 @@ def main():
         "roofline": roof,
         "exact": exact,
         "kernels": kernels,
+        "learned": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
