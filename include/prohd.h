@@ -261,6 +261,50 @@ prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
                                  int32_t* idxB, int64_t capB, int64_t* nselB,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Batched form: P independent pairs (uneven sizes, each with its own D) in
+ * one graph of persistent launches.  Pair i's rows are packed row-major:
+ * A holds nA[0] x D[0] floats, then nA[1] x D[1], ...; likewise B.
+ *
+ *   prohd_batch_create   host plan for fixed sizes; alpha-mode ProHD with
+ *                        m = floor(sqrt(D)) per pair (Alg. 1-3).  The plan
+ *                        owns a small device table area and a private
+ *                        capture stream (freed by prohd_batch_destroy).
+ *   prohd_batch_run      mode PROHD_BATCH_PROHD: Alg. 3's candidate value
+ *                        per pair (as prohd_project + prohd_select +
+ *                        prohd_hd); PROHD_BATCH_EXACT: Eq. (1) per pair (as
+ *                        exact_hd).  out[i] receives pair i's result (device
+ *                        memory, P entries).  The first run with a given
+ *                        (mode, A, B, out, ws) builds the work tables and
+ *                        captures the launches into a graph; later runs
+ *                        launch that graph on `stream`.  PROHD_BATCH_EAGER
+ *                        launches the kernels directly instead; PROHD_SYNC
+ *                        waits for completion.  Not thread-safe per plan.
+ *   prohd_batch_tune     times candidate work shapes (rows per covariance
+ *                        slice, rows per distance item, work-groups per
+ *                        compute unit) on the bound batch with the kernel
+ *                        timers, keeps the fastest and, when json_path is
+ *                        non-null, writes them with the trials as JSON.
+ *   prohd_batch_load_tuning  reads such a file back.
+ * Errors: EINVAL (arguments), EUNSUPPORTED (D > 256), EWORKSPACE,
+ * EDEVICE.  Device-detected errors (non-finite rows) go to out[i].status.
+ */
+typedef struct prohd_batch prohd_batch;
+#define PROHD_BATCH_PROHD 0u
+#define PROHD_BATCH_EXACT 1u
+#define PROHD_BATCH_EAGER (1u << 5)
+prohd_status prohd_batch_create(int32_t P, const int64_t* nA, const int64_t* nB, const int32_t* D,
+                                double alpha, prohd_batch** plan);
+void prohd_batch_destroy(prohd_batch* plan);
+size_t prohd_batch_workspace_size(const prohd_batch* plan, uint32_t mode);
+prohd_status prohd_batch_run(prohd_batch* plan, uint32_t mode, const float* A, const float* B,
+                             prohd_result* out, void* ws, size_t ws_bytes, uint32_t flags,
+                             void* stream);
+prohd_status prohd_batch_tune(prohd_batch* plan, uint32_t mode, const float* A, const float* B,
+                              prohd_result* out, void* ws, size_t ws_bytes, void* stream,
+                              const char* json_path);
+prohd_status prohd_batch_load_tuning(prohd_batch* plan, const char* json_path);
+
 /* Message of the last non-OK return on this host thread ("" if none). */
 const char* prohd_last_error(void);
 

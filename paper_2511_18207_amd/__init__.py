@@ -29,6 +29,7 @@ from ._lib import (  # noqa: F401
     mlp_train_step,
     centroid,
     select_scored,
+    BatchPlan,
     profile_enable,
     profile_reset,
     profile_read,

@@ -87,6 +87,18 @@ def lib() -> C.CDLL:
     L.prohd_select_scored.restype = C.c_int
     L.prohd_select_scored.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp, vp, i64, vp, vp, sz,
                                       vp]
+    L.prohd_batch_create.restype = C.c_int
+    L.prohd_batch_create.argtypes = [i32, vp, vp, vp, C.c_double, C.POINTER(vp)]
+    L.prohd_batch_destroy.restype = None
+    L.prohd_batch_destroy.argtypes = [vp]
+    L.prohd_batch_workspace_size.restype = sz
+    L.prohd_batch_workspace_size.argtypes = [vp, u32]
+    L.prohd_batch_run.restype = C.c_int
+    L.prohd_batch_run.argtypes = [vp, u32, vp, vp, vp, vp, sz, u32, vp]
+    L.prohd_batch_tune.restype = C.c_int
+    L.prohd_batch_tune.argtypes = [vp, u32, vp, vp, vp, vp, sz, vp, C.c_char_p]
+    L.prohd_batch_load_tuning.restype = C.c_int
+    L.prohd_batch_load_tuning.argtypes = [vp, C.c_char_p]
     L.prohd_last_error.restype = C.c_char_p
     L.prohd_last_error.argtypes = []
     L.prohd_version.restype = C.c_char_p
@@ -427,6 +439,91 @@ def select_scored(scoresA, sA, scoresB, sB, idxA, nselA, idxB, nselB, ws=None):
                                      int(sB), idxA.data_ptr(), idxA.numel(), nselA.data_ptr(),
                                      idxB.data_ptr(), idxB.numel(), nselB.data_ptr(),
                                      buf.data_ptr(), nbytes, _stream()))
+
+
+BATCH_MODES = {"prohd": 0, "exact": 1}
+BATCH_EAGER = 1 << 5
+
+
+class BatchPlan:
+    """Plan for many independent pairs (prohd_batch_*).  ``nA``, ``nB``, ``D``
+    are per-pair sizes; the point sets are passed packed (``pack``)."""
+
+    def __init__(self, nA, nB, D, alpha=0.01):
+        self.nA = np.ascontiguousarray(nA, dtype=np.int64)
+        self.nB = np.ascontiguousarray(nB, dtype=np.int64)
+        self.D = np.ascontiguousarray(D, dtype=np.int32)
+        if not (self.nA.size == self.nB.size == self.D.size):
+            raise ValueError("nA, nB and D need one entry per pair")
+        self.P = int(self.nA.size)
+        self.alpha = float(alpha)
+        h = C.c_void_p()
+        _check(lib().prohd_batch_create(self.P, self.nA.ctypes.data, self.nB.ctypes.data,
+                                        self.D.ctypes.data, self.alpha, C.byref(h)))
+        self._h = h
+        sizes_a = self.nA * self.D
+        sizes_b = self.nB * self.D
+        self.offA = np.concatenate([[0], np.cumsum(sizes_a)]).astype(np.int64)
+        self.offB = np.concatenate([[0], np.cumsum(sizes_b)]).astype(np.int64)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().prohd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, mode="prohd"):
+        return int(lib().prohd_batch_workspace_size(self._h, BATCH_MODES[mode]))
+
+    def pack(self, As, Bs, device="cuda"):
+        """Packed float32 device buffers from per-pair arrays (host numpy)."""
+        torch = _torch()
+        hA = np.empty(int(self.offA[-1]), dtype=np.float32)
+        hB = np.empty(int(self.offB[-1]), dtype=np.float32)
+        for i, (a, b) in enumerate(zip(As, Bs)):
+            hA[self.offA[i]:self.offA[i + 1]] = np.ascontiguousarray(a, dtype=np.float32).ravel()
+            hB[self.offB[i]:self.offB[i + 1]] = np.ascontiguousarray(b, dtype=np.float32).ravel()
+        return torch.from_numpy(hA).to(device), torch.from_numpy(hB).to(device)
+
+    def _args(self, A, B, out, ws, mode):
+        torch = _torch()
+        if A.dtype != torch.float32 or B.dtype != torch.float32 or not A.is_cuda or not B.is_cuda:
+            raise TypeError("A and B must be packed float32 CUDA (HIP) tensors")
+        if A.numel() != int(self.offA[-1]) or B.numel() != int(self.offB[-1]):
+            raise ValueError("packed sets do not match the plan's sizes")
+        if out is None:
+            out = torch.zeros((self.P, RESULT_BYTES), dtype=torch.uint8, device=A.device)
+        buf, nbytes = _ws(ws, self.workspace_size(mode))
+        return out, buf, nbytes
+
+    def run(self, A, B, mode="prohd", out=None, ws=None, eager=False, sync=False):
+        """Runs the batch (graph launch unless ``eager``); returns the device
+        result array (P x 80 bytes)."""
+        out, buf, nbytes = self._args(A, B, out, ws, mode)
+        flags = (BATCH_EAGER if eager else 0) | (SYNC if sync else 0)
+        _check(lib().prohd_batch_run(self._h, BATCH_MODES[mode], A.data_ptr(), B.data_ptr(),
+                                     out.data_ptr(), buf.data_ptr(), nbytes, flags, _stream()))
+        return out
+
+    def tune(self, A, B, mode="prohd", out=None, ws=None, json_path=None):
+        out, buf, nbytes = self._args(A, B, out, ws, mode)
+        _check(lib().prohd_batch_tune(self._h, BATCH_MODES[mode], A.data_ptr(), B.data_ptr(),
+                                      out.data_ptr(), buf.data_ptr(), nbytes, _stream(),
+                                      json_path.encode() if json_path else None))
+
+    def load_tuning(self, path):
+        _check(lib().prohd_batch_load_tuning(self._h, path.encode()))
+
+    @staticmethod
+    def results(out):
+        """Device result array -> list of dicts (synchronises)."""
+        arr = np.frombuffer(out.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)
+        return [{k: a[k].item() for k in RESULT_DTYPE.names} for a in arr]
 
 
 def profile_enable(on: bool = True):

@@ -58,6 +58,7 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_pool;
 thread_local int g_open = -1;
+thread_local bool g_capturing = false;
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -71,7 +72,9 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool profiling() { return g_prof_on; }
+bool profiling() { return g_prof_on && !g_capturing; }
+
+void set_capturing(bool on) { g_capturing = on; }
 
 void profile_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -26,6 +26,9 @@ prohd_status fail(prohd_status code, const std::string& msg);
 
 // ------------------------------------------------------------ kernel timing
 bool profiling();
+// While a launch sequence is being captured into a graph, kernel timing is
+// suspended (events of a capture are graph nodes, not timestamps).
+void set_capturing(bool on);
 void profile_begin(const char* name, hipStream_t s);
 void profile_end(hipStream_t s);
 

@@ -18,6 +18,7 @@
 // diagonal and zeros elsewhere, so they stay decoupled and below every real
 // (non-negative) eigenvalue.
 
+#include "batch.h"
 #include "common.h"
 
 namespace prohd {
@@ -72,7 +73,7 @@ __device__ __forceinline__ double start_value(int k, int c) {
 }
 
 template <int DP>
-__global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
+__device__ __forceinline__ void eig_body(
     double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
     const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
     const int32_t* __restrict__ status) {
@@ -410,6 +411,25 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
 }
 
 template <int DP>
+__global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
+    double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
+    const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
+    const int32_t* __restrict__ status) {
+  eig_body<DP>(Mg, D, m, Vg, Yg, u0, dirs, evals, status);
+}
+
+// One work-group per job (pair).
+template <int DP>
+__global__ __launch_bounds__(EigShape<DP>::NT) void eig_batch(const EigJob* __restrict__ jobs, int D,
+                                                              int njobs) {
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const EigJob j = jobs[it];
+    __syncthreads();
+    eig_body<DP>(j.C, D, j.m, j.V, j.Y, j.u0, j.dirs, nullptr, j.status);
+  }
+}
+
+template <int DP>
 prohd_status eig_dp(double* C, int32_t D, int32_t m, const double* u0, float* dirs, double* evals,
                     const int32_t* status, void* ws, size_t ws_bytes, hipStream_t s) {
   Arena ar(ws);
@@ -442,6 +462,22 @@ prohd_status eig_run(double* C, int32_t D, int32_t m, const double* u0, float* d
     case 256: return eig_dp<256>(C, D, m, u0, dirs, evals, status, ws, ws_bytes, s);
     default: return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM");
   }
+}
+
+size_t eig_job_doubles(int DP) { return (size_t)DP * DP + (size_t)PROHD_MAX_DIRS * DP; }
+
+prohd_status batch_eig(int DP, int D, const EigJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 2 * cu_count());
+  switch (DP) {
+    case 16: PROHD_LAUNCH("batch_eig", eig_batch<16>, dim3(grid), dim3(EigShape<16>::NT), 0, s, jobs, D, njobs); break;
+    case 32: PROHD_LAUNCH("batch_eig", eig_batch<32>, dim3(grid), dim3(EigShape<32>::NT), 0, s, jobs, D, njobs); break;
+    case 64: PROHD_LAUNCH("batch_eig", eig_batch<64>, dim3(grid), dim3(EigShape<64>::NT), 0, s, jobs, D, njobs); break;
+    case 128: PROHD_LAUNCH("batch_eig", eig_batch<128>, dim3(grid), dim3(EigShape<128>::NT), 0, s, jobs, D, njobs); break;
+    case 256: PROHD_LAUNCH("batch_eig", eig_batch<256>, dim3(grid), dim3(EigShape<256>::NT), 0, s, jobs, D, njobs); break;
+    default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
+  }
+  return PROHD_OK;
 }
 
 }  // namespace prohd

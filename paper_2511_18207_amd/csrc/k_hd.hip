@@ -30,6 +30,7 @@
 //   finalize the largest refined minimum per direction gives the witness pair,
 //            whose distance is recomputed in float64 from the original rows.
 
+#include "batch.h"
 #include "common.h"
 
 namespace prohd {
@@ -58,15 +59,15 @@ __device__ __forceinline__ int64_t dev_or(const int64_t* p, int64_t v) {
 // host count).  src(i) = idx ? idx[i] : i.  s = X0[shift_idx ? *shift_idx : 0]
 // taken from the FIRST set so both sets share it.  One wave per row.
 template <int DP>
-__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int D,
-                                                 const int32_t* __restrict__ idx,
-                                                 const int64_t* __restrict__ dn, int64_t hn,
-                                                 const float* __restrict__ S,
-                                                 const int32_t* __restrict__ sidx,
-                                                 const int64_t* __restrict__ sdn,
-                                                 float* __restrict__ Xp, float* __restrict__ xn,
-                                                 int32_t* __restrict__ status,
-                                                 uint32_t* __restrict__ maxabs) {
+__device__ __forceinline__ void prep_body(const float* __restrict__ X, int D,
+                                          const int32_t* __restrict__ idx,
+                                          const int64_t* __restrict__ dn, int64_t hn,
+                                          const float* __restrict__ S,
+                                          const int32_t* __restrict__ sidx,
+                                          const int64_t* __restrict__ sdn,
+                                          float* __restrict__ Xp, float* __restrict__ xn,
+                                          int32_t* __restrict__ status,
+                                          uint32_t* __restrict__ maxabs, int bx, int nbx) {
   const int64_t n = dev_or(dn, hn);
   if (n <= 0) return;
   const int lane = threadIdx.x & 63;
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
   }
   bool bad = false;
   float amax = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+  for (int64_t i = (int64_t)bx * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)nbx * 4) {
     const int64_t src = idx ? (int64_t)idx[i] : i;
     const float* xr = X + src * D;
     float acc = 0.f;
@@ -113,6 +114,19 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
   }
 }
 
+template <int DP>
+__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int D,
+                                                 const int32_t* __restrict__ idx,
+                                                 const int64_t* __restrict__ dn, int64_t hn,
+                                                 const float* __restrict__ S,
+                                                 const int32_t* __restrict__ sidx,
+                                                 const int64_t* __restrict__ sdn,
+                                                 float* __restrict__ Xp, float* __restrict__ xn,
+                                                 int32_t* __restrict__ status,
+                                                 uint32_t* __restrict__ maxabs) {
+  prep_body<DP>(X, D, idx, dn, hn, S, sidx, sdn, Xp, xn, status, maxabs, blockIdx.x, gridDim.x);
+}
+
 __global__ void fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -128,14 +142,14 @@ constexpr int kTileRows = 256;  // rows of X per work-group (8 waves x 32)
 constexpr int kBN = 32;         // rows of Y per LDS block
 
 template <int DP, bool COLMIN>
-__global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
-                                                 const float* __restrict__ xn,
-                                                 const int64_t* __restrict__ dnX, int64_t hnX,
-                                                 const float* __restrict__ Yp,
-                                                 const float* __restrict__ yn,
-                                                 const int64_t* __restrict__ dnY, int64_t hnY,
-                                                 int ysplit, uint32_t* __restrict__ rowmin,
-                                                 uint32_t* __restrict__ colmin) {
+__device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
+                                               const float* __restrict__ xn,
+                                               const int64_t* __restrict__ dnX, int64_t hnX,
+                                               const float* __restrict__ Yp,
+                                               const float* __restrict__ yn,
+                                               const int64_t* __restrict__ dnY, int64_t hnY,
+                                               int ysplit, uint32_t* __restrict__ rowmin,
+                                               uint32_t* __restrict__ colmin, int bx) {
   constexpr int KH = DP / 2;       // k values per half-wave
   constexpr int ST = DP + 4;       // LDS row stride (floats): conflict-free b128 reads
   constexpr int NV4 = kBN * DP / 4;             // float4s per Y block
@@ -146,8 +160,8 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
 
   const int64_t nX = dev_or(dnX, hnX);
   const int64_t nY = dev_or(dnY, hnY);
-  const int xblk = blockIdx.x / ysplit;
-  const int ysi = blockIdx.x - xblk * ysplit;
+  const int xblk = bx / ysplit;
+  const int ysi = bx - xblk * ysplit;
   const int64_t x0 = (int64_t)xblk * kTileRows;
   if (x0 >= nX) return;
   const int64_t chunk = ((nY + ysplit - 1) / ysplit + kBN - 1) / kBN * kBN;
@@ -277,6 +291,18 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
     const int64_t r = x0 + 32 * wave + 8 * (c >> 2) + 4 * g + (c & 3);
     if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
   }
+}
+
+template <int DP, bool COLMIN>
+__global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
+                                                 const float* __restrict__ xn,
+                                                 const int64_t* __restrict__ dnX, int64_t hnX,
+                                                 const float* __restrict__ Yp,
+                                                 const float* __restrict__ yn,
+                                                 const int64_t* __restrict__ dnY, int64_t hnY,
+                                                 int ysplit, uint32_t* __restrict__ rowmin,
+                                                 uint32_t* __restrict__ colmin) {
+  dist_tile_body<DP, COLMIN>(Xp, xn, dnX, hnX, Yp, yn, dnY, hnY, ysplit, rowmin, colmin, blockIdx.x);
 }
 
 // ------------------------------------------------- low-precision copies
@@ -541,13 +567,13 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int DP>
-__global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
-                                                   const int32_t* __restrict__ cand,
-                                                   const int64_t* __restrict__ dR,
-                                                   const float* __restrict__ Yp,
-                                                   const int64_t* __restrict__ dnY, int64_t hnY,
-                                                   int ysplit,
-                                                   unsigned long long* __restrict__ best) {
+__device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
+                                            const int32_t* __restrict__ cand,
+                                            const int64_t* __restrict__ dR,
+                                            const float* __restrict__ Yp,
+                                            const int64_t* __restrict__ dnY, int64_t hnY,
+                                            int ysplit,
+                                            unsigned long long* __restrict__ best, int bx) {
   constexpr int KS = DP / 4;        // k steps of the 16x16x4 op
   constexpr int BNY = 32;           // Y rows per LDS block
   constexpr int STY = DP + 4;       // LDS row stride (doubles)
@@ -555,8 +581,8 @@ __global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
   __shared__ double yq[BNY];
   const int64_t R = *dR;
   const int64_t nY = dev_or(dnY, hnY);
-  const int cb = blockIdx.x / ysplit;
-  const int ysi = blockIdx.x - cb * ysplit;
+  const int cb = bx / ysplit;
+  const int ysi = bx - cb * ysplit;
   if ((int64_t)cb * 64 >= R) return;
   const int64_t chunk = ((nY + ysplit - 1) / ysplit + BNY - 1) / BNY * BNY;
   const int64_t yb = (int64_t)ysi * chunk;
@@ -646,6 +672,17 @@ __global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
   }
 }
 
+template <int DP>
+__global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
+                                                   const int32_t* __restrict__ cand,
+                                                   const int64_t* __restrict__ dR,
+                                                   const float* __restrict__ Yp,
+                                                   const int64_t* __restrict__ dnY, int64_t hnY,
+                                                   int ysplit,
+                                                   unsigned long long* __restrict__ best) {
+  refine_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x);
+}
+
 // -------------------------------------------------------------- finalize
 struct DirIn {
   const unsigned long long* best;  // refined minima
@@ -675,11 +712,11 @@ __device__ double pair_dist64(const float* __restrict__ X, int64_t i, const floa
   return r;
 }
 
-__global__ __launch_bounds__(256) void finalize(DirIn ab, DirIn ba, int D,
-                                                const int64_t* __restrict__ dnA, int64_t hnA,
-                                                const int64_t* __restrict__ dnB, int64_t hnB,
-                                                const int32_t* __restrict__ status,
-                                                prohd_result* __restrict__ out) {
+__device__ __forceinline__ void finalize_body(const DirIn& ab, const DirIn& ba, int D,
+                                              const int64_t* __restrict__ dnA, int64_t hnA,
+                                              const int64_t* __restrict__ dnB, int64_t hnB,
+                                              const int32_t* __restrict__ status,
+                                              prohd_result* __restrict__ out) {
   __shared__ double red[256];
   __shared__ unsigned long long bestp[256];
   int64_t wx[2], wy[2];
@@ -733,8 +770,68 @@ __global__ __launch_bounds__(256) void finalize(DirIn ab, DirIn ba, int D,
   }
 }
 
+__global__ __launch_bounds__(256) void finalize(DirIn ab, DirIn ba, int D,
+                                                const int64_t* __restrict__ dnA, int64_t hnA,
+                                                const int64_t* __restrict__ dnB, int64_t hnB,
+                                                const int32_t* __restrict__ status,
+                                                prohd_result* __restrict__ out) {
+  finalize_body(ab, ba, D, dnA, hnA, dnB, hnB, status, out);
+}
+
 __global__ void store_refined(prohd_result* out, const int64_t* dR1, const int64_t* dR2) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out->refined = (int32_t)max(*dR1, *dR2);
+}
+
+// ------------------------------------------------------------ batched
+// Persistent versions: each work-group walks the item table and runs the
+// single-pair body of its job with the item's block index.
+template <int DP>
+__global__ __launch_bounds__(256) void prep_batch(const PrepJob* __restrict__ jobs, int D,
+                                                  const BItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const PrepJob j = jobs[w.job];
+    prep_body<DP>(j.X, D, j.idx, j.dn, j.hn, j.S, j.sidx, j.sdn, j.Xp, j.xn, j.status, nullptr, w.bx,
+                  j.nbx);
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(512) void tile_batch(const TileJob* __restrict__ jobs,
+                                                  const BItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const TileJob j = jobs[w.job];
+    __syncthreads();  // LDS of the previous item is no longer read
+    dist_tile_body<DP, true>(j.Xp, j.xn, j.dnX, j.hnX, j.Yp, j.yn, j.dnY, j.hnY, j.ysplit, j.rowmin,
+                             j.colmin, w.bx);
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void refine_batch(const RefineJob* __restrict__ jobs,
+                                                    const BItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const RefineJob j = jobs[w.job];
+    __syncthreads();
+    refine_body<DP>(j.Xp, j.cand, j.dR, j.Yp, j.dnY, j.hnY, j.ysplit, j.best, w.bx);
+  }
+}
+
+__global__ __launch_bounds__(256) void finalize_batch(const FinalJob* __restrict__ jobs, int njobs) {
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const FinalJob j = jobs[it];
+    const DirIn ab{j.ab.best, j.ab.cand, j.ab.dR, j.ab.mapX, j.ab.mapY, j.ab.Xo, j.ab.Yo};
+    const DirIn ba{j.ba.best, j.ba.cand, j.ba.dR, j.ba.mapX, j.ba.mapY, j.ba.Xo, j.ba.Yo};
+    __syncthreads();
+    finalize_body(ab, ba, j.D, j.dnA, j.hnA, j.dnB, j.hnB, j.status, j.out);
+    __syncthreads();
+    if (threadIdx.x == 0) j.out->refined = (int32_t)max(*j.ab.dR, *j.ba.dR);
+  }
 }
 
 // ------------------------------------------------------------ host side
@@ -1033,6 +1130,69 @@ prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, in
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, nullptr, nullptr, nA, nullptr, nullptr, nB,
                                        false, fmt, out, nn2A, nn2B, ws, ws_bytes, s);
   });
+}
+
+template <class F>
+prohd_status by_dp_batch(int DP, F&& f) {
+  switch (DP) {
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
+  }
+}
+
+prohd_status batch_prep(int DP, int D, const PrepJob* jobs, const BItem* items, int nitems, int grid,
+                        hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  return by_dp_batch(DP, [&](auto dp) {
+    PROHD_LAUNCH("batch_prep", prep_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0, s, jobs, D,
+                 items, nitems);
+    return PROHD_OK;
+  });
+}
+
+prohd_status batch_tile(int DP, const TileJob* jobs, const BItem* items, int nitems, int grid,
+                        hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  return by_dp_batch(DP, [&](auto dp) {
+    PROHD_LAUNCH("batch_tile", tile_batch<decltype(dp)::value>, dim3(grid), dim3(512), 0, s, jobs,
+                 items, nitems);
+    return PROHD_OK;
+  });
+}
+
+prohd_status batch_refine(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
+                          hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  return by_dp_batch(DP, [&](auto dp) {
+    PROHD_LAUNCH("batch_refine", refine_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0, s, jobs,
+                 items, nitems);
+    return PROHD_OK;
+  });
+}
+
+prohd_status batch_finalize(const FinalJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 4 * cu_count());
+  PROHD_LAUNCH("batch_finalize", finalize_batch, dim3(grid), dim3(256), 0, s, jobs, njobs);
+  return PROHD_OK;
+}
+
+prohd_status batch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return PROHD_OK;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 4096));
+  PROHD_LAUNCH("batch_fill", fill_u32, dim3(grid), dim3(256), 0, s, p, n, v);
+  return PROHD_OK;
+}
+
+prohd_status batch_fill64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return PROHD_OK;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 4096));
+  PROHD_LAUNCH("batch_fill", fill_u64, dim3(grid), dim3(256), 0, s, p, n, v);
+  return PROHD_OK;
 }
 
 }  // namespace prohd

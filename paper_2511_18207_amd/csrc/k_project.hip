@@ -14,6 +14,7 @@
 // This pass is bound by HBM bandwidth: 4 D bytes read and 4 (m+1) bytes
 // written per row.
 
+#include "batch.h"
 #include "common.h"
 
 namespace prohd {
@@ -151,6 +152,105 @@ __global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict
   }
 }
 
+// Batched: one item = one 512-row tile of one set of one pair (directions
+// of that pair, at most 32, in Ut as above).  Same per-row arithmetic as
+// project_rows; the next chunk of the tile is prefetched in registers.
+template <int DP, int NG, bool VEC>
+__global__ __launch_bounds__(kThreads) void project_batch(const ProjJob* __restrict__ jobs, int njobs,
+                                                          int D) {
+  constexpr int KC = DP < 32 ? DP : 32;
+  constexpr int NCH = DP / KC;
+  constexpr int ST = KC + 4;
+  constexpr int ND = 8 * NG;
+  constexpr int F4R = KC / 4;
+  constexpr int NF = kTileRows * F4R / kThreads;
+  __shared__ __attribute__((aligned(16))) float xt[kTileRows * ST];
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const ProjJob j = jobs[it];
+    const int rows = (int)min<int64_t>(kTileRows, j.n - j.r0);
+    float4 buf[NF];
+    auto load = [&](int c) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const int f = tid + kThreads * i;
+        const int r = f / F4R, q = f - r * F4R;
+        const int k = c * KC + 4 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < rows) {
+          const float* src = j.X + (j.r0 + r) * D + k;
+          if (VEC) {
+            if (k < D) v = *reinterpret_cast<const float4*>(src);
+          } else {
+            if (k + 0 < D) v.x = src[0];
+            if (k + 1 < D) v.y = src[1];
+            if (k + 2 < D) v.z = src[2];
+            if (k + 3 < D) v.w = src[3];
+          }
+        }
+        buf[i] = v;
+      }
+    };
+    float acc[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = 0.f;
+    load(0);
+    for (int c = 0; c < NCH; ++c) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const int f = tid + kThreads * i;
+        const int r = f / F4R, q = f - r * F4R;
+        *reinterpret_cast<float4*>(&xt[r * ST + 4 * q]) = buf[i];
+      }
+      __syncthreads();
+      if (c + 1 < NCH) load(c + 1);
+      const float* xr = &xt[tid * ST];
+      const float* uc = j.Ut + (size_t)(c * KC) * ND;
+#pragma unroll 2
+      for (int k4 = 0; k4 < KC / 4; ++k4) {
+        const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
+        const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const float* uk = uc + (4 * k4 + kk) * ND;
+#pragma unroll
+          for (int d4 = 0; d4 < ND / 4; ++d4) {
+            const float4 u = *reinterpret_cast<const float4*>(uk + 4 * d4);
+            acc[4 * d4 + 0] = fmaf(xs[kk], u.x, acc[4 * d4 + 0]);
+            acc[4 * d4 + 1] = fmaf(xs[kk], u.y, acc[4 * d4 + 1]);
+            acc[4 * d4 + 2] = fmaf(xs[kk], u.z, acc[4 * d4 + 2]);
+            acc[4 * d4 + 3] = fmaf(xs[kk], u.w, acc[4 * d4 + 3]);
+          }
+        }
+      }
+    }
+    const int64_t row = j.r0 + tid;
+    if (tid < rows) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        if (d < j.ndirs) j.P[(size_t)d * j.n + row] = acc[d];
+    }
+  }
+}
+
+// Batched transpose: one work-group per job.
+__global__ void transpose_batch(const TransJob* __restrict__ jobs, int njobs, int D, int DP) {
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const TransJob j = jobs[it];
+    const int nblk = (j.ndirs + 31) / 32;
+    for (int e = threadIdx.x; e < nblk * 32 * DP; e += blockDim.x) {
+      const int b = e / (32 * DP);
+      const int r = e - b * 32 * DP;
+      const int nd = min(32, j.ndirs - 32 * b);
+      const int nd8 = 8 * ((nd + 7) / 8);
+      const int k = r / nd8, q = r - k * nd8;
+      if (k >= DP) continue;
+      j.Ut[(size_t)b * 32 * DP + r] = (q < nd && k < D) ? j.dirs[(size_t)(32 * b + q) * D + k] : 0.f;
+    }
+  }
+}
+
 struct ProjLayout {
   int32_t* status;
   double* C;
@@ -249,6 +349,51 @@ prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB,
     case 256: return launch_project<256>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
     default: return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM");
   }
+}
+
+template <int DP, int NG>
+prohd_status batch_project_ng(int D, bool vec, const ProjJob* jobs, int njobs, int grid, hipStream_t s) {
+  if (vec) {
+    PROHD_LAUNCH("batch_project", (project_batch<DP, NG, true>), dim3(grid), dim3(kThreads), 0, s, jobs,
+                 njobs, D);
+  } else {
+    PROHD_LAUNCH("batch_project", (project_batch<DP, NG, false>), dim3(grid), dim3(kThreads), 0, s, jobs,
+                 njobs, D);
+  }
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status batch_project_dp(int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
+                              hipStream_t s) {
+  switch ((ndirs + 7) / 8) {
+    case 1: return batch_project_ng<DP, 1>(D, vec, jobs, njobs, grid, s);
+    case 2: return batch_project_ng<DP, 2>(D, vec, jobs, njobs, grid, s);
+    case 3: return batch_project_ng<DP, 3>(D, vec, jobs, njobs, grid, s);
+    case 4: return batch_project_ng<DP, 4>(D, vec, jobs, njobs, grid, s);
+    default: return fail(PROHD_EUNSUPPORTED, "batched projection: more than 32 directions");
+  }
+}
+
+prohd_status batch_project(int DP, int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
+                           hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  vec = vec && D % 4 == 0;
+  switch (DP) {
+    case 16: return batch_project_dp<16>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 32: return batch_project_dp<32>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 64: return batch_project_dp<64>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 128: return batch_project_dp<128>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 256: return batch_project_dp<256>(D, ndirs, vec, jobs, njobs, grid, s);
+    default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
+  }
+}
+
+prohd_status batch_transpose(int D, int DP, const TransJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 8 * cu_count());
+  PROHD_LAUNCH("batch_transpose", transpose_batch, dim3(grid), dim3(256), 0, s, jobs, njobs, D, DP);
+  return PROHD_OK;
 }
 
 }  // namespace prohd

@@ -15,6 +15,7 @@
 // Every launch reads its array lengths from device memory when asked to, so
 // a whole chain runs without a host synchronisation.
 
+#include "batch.h"
 #include "common.h"
 
 namespace prohd {
@@ -329,6 +330,166 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, size_t words, uint8_t* __r
   if (blockIdx.x == 0 && threadIdx.x < tail_bytes) tail[threadIdx.x] = 0;
 }
 
+// ------------------------------------------------ batched (one WG / segment)
+// For many short segments (up to a few 10^5 values each) one work-group per
+// segment does the whole selection with LDS histograms: three digit passes
+// (11/11/10 bits) fix the k-th key from each end (the high end uses the
+// complemented key, so equal values still rank by index), then one pass
+// marks.  Entries equal to the k-th key are all taken when they fit; only
+// otherwise a second, index-ordered pass ranks them (ties to the smaller
+// index, as in the multi-launch selection).
+constexpr int kSegT = 256;
+constexpr int kSegBins = 2048;
+
+// Exclusive prefix over the work-group (256 threads); *total gets the sum.
+__device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSegT / 64; ++w) {
+    const uint32_t t = lds[w];
+    base += (w < wave) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(kSegT) void select_seg(const SegJob* __restrict__ jobs, int njobs) {
+  __shared__ uint32_t hist[2][kSegBins];
+  __shared__ uint32_t scan_lds[kSegT / 64];
+  __shared__ uint32_t s_bin[2], s_before[2];
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const SegJob j = jobs[it];
+    int64_t n = j.dn ? *j.dn : j.n;
+    n = n < j.n ? (n > 0 ? n : 0) : j.n;
+    const uint32_t k[2] = {(uint32_t)min<int64_t>(j.lo, n), (uint32_t)min<int64_t>(j.hi, n)};
+    if (n == 0 || (k[0] == 0 && k[1] == 0)) continue;
+    uint32_t pre[2] = {0u, 0u}, rem[2] = {k[0], k[1]}, eq[2] = {0u, 0u};
+    const int shifts[3] = {21, 10, 0};
+    const uint32_t masks[3] = {0x7FFu, 0x7FFu, 0x3FFu};
+    const uint32_t pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
+    for (int p = 0; p < 3; ++p) {
+      __syncthreads();
+      for (int b = tid; b < 2 * kSegBins; b += kSegT) (&hist[0][0])[b] = 0u;
+      __syncthreads();
+      for (int64_t i = tid; i < n; i += kSegT) {
+        const uint32_t key = fkey(j.vals[i]);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const uint32_t ke = e ? ~key : key;
+          if (k[e] && (ke & pmasks[p]) == pre[e]) atomicAdd(&hist[e][(ke >> shifts[p]) & masks[p]], 1u);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (!k[e]) continue;   // uniform
+        uint32_t loc = 0;
+#pragma unroll
+        for (int b = 0; b < kSegBins / kSegT; ++b) loc += hist[e][tid * (kSegBins / kSegT) + b];
+        uint32_t tot;
+        const uint32_t ex = wg_excl_scan(loc, scan_lds, &tot);
+        if (ex < rem[e] && rem[e] <= ex + loc) {
+          uint32_t acc = ex;
+          for (int b = 0; b < kSegBins / kSegT; ++b) {
+            const int bin = tid * (kSegBins / kSegT) + b;
+            const uint32_t h = hist[e][bin];
+            if (acc + h >= rem[e]) {
+              s_bin[e] = (uint32_t)bin;
+              s_before[e] = acc;
+              break;
+            }
+            acc += h;
+          }
+        }
+        __syncthreads();
+        pre[e] |= s_bin[e] << shifts[p];
+        rem[e] -= s_before[e];
+        if (p == 2) eq[e] = hist[e][s_bin[e]];
+        __syncthreads();
+      }
+    }
+    // mark: below the k-th key, and ties when all of them fit
+    bool ordered[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) ordered[e] = k[e] && rem[e] < eq[e];
+    for (int64_t i = tid; i < n; i += kSegT) {
+      const uint32_t key = fkey(j.vals[i]);
+      bool f = false;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const uint32_t ke = e ? ~key : key;
+        if (k[e]) f |= ke < pre[e] || (ke == pre[e] && !ordered[e]);
+      }
+      if (f) j.flags[i] = 1;
+    }
+    // ties that do not all fit: rank them in index order
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (!ordered[e]) continue;   // uniform
+      uint32_t taken = 0;
+      for (int64_t c0 = 0; c0 < n; c0 += kSegT) {
+        const int64_t i = c0 + tid;
+        bool tie = false;
+        if (i < n) {
+          const uint32_t key = fkey(j.vals[i]);
+          tie = (e ? ~key : key) == pre[e];
+        }
+        uint32_t tot;
+        const uint32_t ex = wg_excl_scan(tie ? 1u : 0u, scan_lds, &tot);
+        if (tie && taken + ex < rem[e]) j.flags[i] = 1;
+        taken += tot;
+        if (taken >= rem[e]) break;   // uniform
+      }
+    }
+  }
+}
+
+// Compaction of one flag array into ascending indices (at most cap) and its
+// count; one work-group per job.
+__global__ __launch_bounds__(kSegT) void compact_seg(const CompactJob* __restrict__ jobs, int njobs) {
+  __shared__ uint32_t scan_lds[kSegT / 64];
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const CompactJob j = jobs[it];
+    int64_t n = j.dn ? *j.dn : j.n;
+    n = n < j.n ? (n > 0 ? n : 0) : j.n;
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 4 * kSegT) {
+      uint32_t f[4], cnt = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = c0 + 4 * tid + q;
+        f[q] = (i < n && j.flags[i]) ? 1u : 0u;
+        cnt += f[q];
+      }
+      uint32_t tot;
+      uint32_t pos = wg_excl_scan(cnt, scan_lds, &tot);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (f[q]) {
+          const int64_t o = base + pos;
+          if (o < j.cap) j.idx[o] = (int32_t)(c0 + 4 * tid + q);
+          ++pos;
+        }
+      }
+      base += tot;
+    }
+    if (tid == 0) *j.count = base < j.cap ? base : j.cap;
+  }
+}
+
 struct SelLayout {
   EndState* st;
   uint32_t* hist;
@@ -433,6 +594,20 @@ prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s) {
   const int grid = (int)std::min<size_t>(4096, std::max<size_t>(1, cdiv((int64_t)words, 256 * 4)));
   PROHD_LAUNCH("zero", zero_kernel, dim3(grid), dim3(256), 0, s, (uint32_t*)p, words,
                (uint8_t*)p + words * 4, tail);
+  return PROHD_OK;
+}
+
+prohd_status batch_select(const SegJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 16 * cu_count());
+  PROHD_LAUNCH("batch_select", select_seg, dim3(grid), dim3(kSegT), 0, s, jobs, njobs);
+  return PROHD_OK;
+}
+
+prohd_status batch_compact(const CompactJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 16 * cu_count());
+  PROHD_LAUNCH("batch_compact", compact_seg, dim3(grid), dim3(kSegT), 0, s, jobs, njobs);
   return PROHD_OK;
 }
 

@@ -22,6 +22,7 @@
 
 #include <utility>
 
+#include "batch.h"
 #include "common.h"
 
 namespace prohd {
@@ -88,13 +89,13 @@ __device__ __forceinline__ void block_ij(int t, int nb, int& I, int& J) {
   J = i + rem;
 }
 
+// Gram partial of rows [r_begin, r_end) of X, shifted by the row `shift`;
+// super-block share ts of TSPLIT; writes gp (T x 256) and sp (2 DP sums).
 template <int DP>
-__global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const float* __restrict__ A, int64_t nA,
-                                                    const float* __restrict__ B, int64_t nB,
-                                                    int D, int64_t rows_per_wg, int nslices,
-                                                    double* __restrict__ gpart,
-                                                    double* __restrict__ spart,
-                                                    int32_t* __restrict__ status) {
+__device__ __forceinline__ void gram_body(const float* __restrict__ shift, const float* __restrict__ X,
+                                          int64_t r_begin, int64_t r_end, int D, int ts, bool setA,
+                                          double* __restrict__ gp, double* __restrict__ spo,
+                                          int32_t* __restrict__ status) {
   using S = GramShape<DP>;
   constexpr int NT = S::THREADS;
   constexpr int RC = S::RC;
@@ -108,26 +109,13 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int col = lane & 15;   // column within a 16-block
   const int rsub = lane >> 4;  // row within a group of four
-  // row slices [0, wgA) of A, then of B; TSPLIT work-groups per slice share
-  // its super-blocks and get ids congruent mod 8 (one XCD, one L2)
-  const int xcd = blockIdx.x & 7;
-  const int q8 = blockIdx.x >> 3;
-  const int ts = q8 % S::TSPLIT;
-  const int slice = (q8 / S::TSPLIT) * 8 + xcd;
-  if (slice >= nslices) return;
-  const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
-  const bool setA = (int64_t)slice < wgA;
-  const float* X = setA ? A : B;
-  const int64_t nX = setA ? nA : nB;
-  const int64_t r_begin = (setA ? (int64_t)slice : (int64_t)slice - wgA) * rows_per_wg;
-  const int64_t r_end = min(nX, r_begin + rows_per_wg);
 
   // staging: thread tid handles elements e = tid + NT i of a chunk, i.e.
   // row tid/DP + (NT/DP) i and the fixed column tid % DP (DP divides NT).
   const int mycol = tid % DP;
   const int myrow = tid / DP;
   constexpr int RSTEP = NT / DP;
-  const double sh = (mycol < D) ? (double)A[mycol] : 0.0;   // shift s = A[0]
+  const double sh = (mycol < D) ? (double)shift[mycol] : 0.0;   // shift s = A[0]
   double sum = 0.0;
   bool bad = false;
   float raw[PER];
@@ -210,7 +198,6 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
 
   // live blocks: element v of lane l of the 16x16x4 f64 result is row
   // l/16 + 4 v, column l%16
-  double* gp = gpart + (size_t)slice * S::T * 256;
 #pragma unroll
   for (int u = 0; u < S::SPW; ++u) {
     if (sp[u] >= 0) {
@@ -235,18 +222,60 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
   if (tid < DP && ts == 0) {
     double a = 0.0;
     for (int t = tid; t < NT; t += DP) a += sred[t];
-    double* sp = spart + (size_t)slice * 2 * DP;
-    sp[setA ? tid : DP + tid] = a;
-    sp[setA ? DP + tid : tid] = 0.0;
+    spo[setA ? tid : DP + tid] = a;
+    spo[setA ? DP + tid : tid] = 0.0;
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const float* __restrict__ A, int64_t nA,
+                                                    const float* __restrict__ B, int64_t nB,
+                                                    int D, int64_t rows_per_wg, int nslices,
+                                                    double* __restrict__ gpart,
+                                                    double* __restrict__ spart,
+                                                    int32_t* __restrict__ status) {
+  using S = GramShape<DP>;
+  // row slices [0, wgA) of A, then of B; TSPLIT work-groups per slice share
+  // its super-blocks and get ids congruent mod 8 (one XCD, one L2)
+  const int xcd = blockIdx.x & 7;
+  const int q8 = blockIdx.x >> 3;
+  const int ts = q8 % S::TSPLIT;
+  const int slice = (q8 / S::TSPLIT) * 8 + xcd;
+  if (slice >= nslices) return;
+  const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
+  const bool setA = (int64_t)slice < wgA;
+  const float* X = setA ? A : B;
+  const int64_t nX = setA ? nA : nB;
+  const int64_t r_begin = (setA ? (int64_t)slice : (int64_t)slice - wgA) * rows_per_wg;
+  const int64_t r_end = min(nX, r_begin + rows_per_wg);
+  gram_body<DP>(A, X, r_begin, r_end, D, ts, setA, gpart + (size_t)slice * S::T * 256,
+                spart + (size_t)slice * 2 * DP, status);
+}
+
+// Batched: item (slice job, ts); the host orders items so that the TSPLIT
+// shares of a slice are congruent modulo 8 (same XCD) for a grid that is a
+// multiple of 8.
+template <int DP>
+__global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_batch(const GramJob* __restrict__ jobs,
+                                                                    int D,
+                                                                    const BItem* __restrict__ items,
+                                                                    int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const GramJob j = jobs[w.job];
+    __syncthreads();
+    gram_body<DP>(j.shift, j.X, j.r_begin, j.r_end, D, w.bx, j.setA != 0, j.gp, j.sp, j.status);
   }
 }
 
 // Sums the partials (fixed order), forms the covariance and the centroid axis.
 template <int DP>
-__global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gpart,
-                                                   const double* __restrict__ spart, int nwg,
-                                                   int64_t nA, int64_t nB, int D,
-                                                   double* __restrict__ C, double* __restrict__ u0) {
+__device__ __forceinline__ void gram_reduce_body(const double* __restrict__ gpart,
+                                                 const double* __restrict__ spart, int nwg,
+                                                 int64_t nA, int64_t nB, int D,
+                                                 double* __restrict__ C, double* __restrict__ u0,
+                                                 int bx, int nbx) {
   using S = GramShape<DP>;
   constexpr int NB = S::NB;
   __shared__ double sA[DP], sB[DP];
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gp
   const double N = (double)(nA + nB);
   const double inv = 1.0 / (double)((nA + nB) > 1 ? (nA + nB - 1) : 1);
   // covariance entries, one Gram element per thread iteration
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < S::T * 256; e += gridDim.x * blockDim.x) {
+  for (int e = bx * blockDim.x + threadIdx.x; e < S::T * 256; e += nbx * blockDim.x) {
     const int t = e >> 8;
     const int i = (e >> 4) & 15;
     const int j = e & 15;
@@ -283,7 +312,7 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gp
     C[(size_t)r * DP + c] = v;
     C[(size_t)c * DP + r] = v;
   }
-  if (blockIdx.x != 0) return;
+  if (bx != 0) return;
   // centroid axis: mean(B) - mean(A) = sB/nB - sA/nA (the shift cancels)
   double nrm2 = 0.0;
   for (int k = threadIdx.x; k < D; k += blockDim.x) {
@@ -300,6 +329,24 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gp
   for (int k = threadIdx.x; k < D; k += blockDim.x) {
     const double d = sB[k] / (double)nB - sA[k] / (double)nA;
     u0[k] = (nrm < 1e-9) ? (k == 0 ? 1.0 : 0.0) : d / nrm;
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ gpart,
+                                                   const double* __restrict__ spart, int nwg,
+                                                   int64_t nA, int64_t nB, int D,
+                                                   double* __restrict__ C, double* __restrict__ u0) {
+  gram_reduce_body<DP>(gpart, spart, nwg, nA, nB, D, C, u0, blockIdx.x, gridDim.x);
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void gram_reduce_batch(const GramRedJob* __restrict__ jobs, int D,
+                                                         int njobs, int per_job) {
+  for (int it = blockIdx.x; it < njobs * per_job; it += gridDim.x) {
+    const GramRedJob j = jobs[it / per_job];
+    __syncthreads();
+    gram_reduce_body<DP>(j.gpart, j.spart, j.nwg, j.nA, j.nB, D, j.C, j.u0, it % per_job, per_job);
   }
 }
 
@@ -364,6 +411,58 @@ prohd_status stats_run(const float* A, int64_t nA, const float* B, int64_t nB, i
     case 256: return stats_dp<256>(A, nA, B, nB, D, C, u0, status, ws, ws_bytes, s);
     default: return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM");
   }
+}
+
+template <class F>
+prohd_status by_dp_stats(int DP, F&& f) {
+  switch (DP) {
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
+  }
+}
+
+int gram_tsplit(int DP) {
+  int v = 1;
+  by_dp_stats(DP, [&](auto dp) { v = GramShape<decltype(dp)::value>::TSPLIT; return PROHD_OK; });
+  return v;
+}
+
+int gram_rows_quantum(int DP) {
+  int v = 32;
+  by_dp_stats(DP, [&](auto dp) { v = GramShape<decltype(dp)::value>::RC; return PROHD_OK; });
+  return v;
+}
+
+size_t gram_partial_doubles(int DP) {
+  size_t v = 0;
+  by_dp_stats(DP, [&](auto dp) { v = (size_t)GramShape<decltype(dp)::value>::T * 256; return PROHD_OK; });
+  return v;
+}
+
+prohd_status batch_gram(int DP, int D, const GramJob* jobs, const BItem* items, int nitems, int grid,
+                        hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  return by_dp_stats(DP, [&](auto dp) {
+    constexpr int V = decltype(dp)::value;
+    PROHD_LAUNCH("batch_gram", gram_batch<V>, dim3(grid), dim3(GramShape<V>::THREADS), 0, s, jobs, D,
+                 items, nitems);
+    return PROHD_OK;
+  });
+}
+
+prohd_status batch_gram_reduce(int DP, int D, const GramRedJob* jobs, int njobs, int per_job,
+                               hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = (int)std::min<int64_t>((int64_t)njobs * per_job, 8 * cu_count());
+  return by_dp_stats(DP, [&](auto dp) {
+    PROHD_LAUNCH("batch_gram_reduce", gram_reduce_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0,
+                 s, jobs, D, njobs, per_job);
+    return PROHD_OK;
+  });
 }
 
 }  // namespace prohd

@@ -126,6 +126,28 @@ def test_mlp_and_scored_validation():
                                  1 << 30, None) == 1
 
 
+def test_batch_plan_validation():
+    L = ph.lib()
+    h = C.c_void_p()
+    nA = (C.c_int64 * 2)(10, 0)
+    nB = (C.c_int64 * 2)(10, 10)
+    D = (C.c_int32 * 2)(8, 8)
+    assert L.prohd_batch_create(2, nA, nB, D, 0.01, C.byref(h)) == 1
+    assert "sizes" in L.prohd_last_error().decode()
+    D2 = (C.c_int32 * 2)(8, 300)
+    nA2 = (C.c_int64 * 2)(10, 10)
+    assert L.prohd_batch_create(2, nA2, nB, D2, 0.01, C.byref(h)) == 5
+    assert L.prohd_batch_create(2, nA2, nB, D, 0.0, C.byref(h)) == 1
+    assert L.prohd_batch_create(0, nA2, nB, D, 0.01, C.byref(h)) == 1
+    plan = ph.BatchPlan([100, 2000, 1], [50, 3000, 2], [16, 256, 3])
+    assert plan.workspace_size("prohd") > 0 and plan.workspace_size("exact") > 0
+    assert list(plan.offA) == [0, 1600, 1600 + 512000, 1600 + 512000 + 3]
+    assert L.prohd_batch_run(plan._h, 7, FAKE, FAKE, FAKE, FAKE, 1 << 20, 0, None) == 1
+    assert L.prohd_batch_run(plan._h, 0, None, FAKE, FAKE, FAKE, 1 << 20, 0, None) == 1
+    assert L.prohd_batch_run(plan._h, 0, FAKE, FAKE, FAKE, FAKE, 1 << 20, 1 << 9, None) == 1
+    plan.close()
+
+
 def test_k_rule_matches_oracle():
     import oracle
     for a, n in [(0.01, 2_000_000), (0.01 / 16, 2_000_000), (0.29, 100), (0.5, 3), (0.001, 10)]:
