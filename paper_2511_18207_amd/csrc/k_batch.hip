@@ -43,6 +43,7 @@ struct Tuning {
   int tile_yc = 8192;     // Y rows per distance item
   int tile_mult = 2;      // distance work-groups per compute unit
   int refine_yc = 8192;   // Y rows per refinement item
+  int eig_narrow = 0;     // eigensolver work-group: 1 narrow (256 threads), 0 wide (512)
 };
 
 struct Pair {
@@ -243,6 +244,7 @@ prohd_status build(prohd_batch* b) {
   };
   std::vector<Rec> recs;
   const bool prohd = mode == PROHD_BATCH_PROHD;
+  const float* ubase = static_cast<const float*>(b->ws);   // 256-byte aligned workspace base
   for (int D : b->dims) {
     const std::vector<int> g = group(b, D);
     Rec r{};
@@ -279,7 +281,7 @@ prohd_status build(prohd_batch* b) {
         for (int s = 0; s < 2; ++s) {
           const int64_t n = s ? q.nB : q.nA;
           for (int64_t r0 = 0; r0 < n; r0 += 512)
-            pj.push_back(ProjJob{s ? Bp : Ap, n, r0, w.Ut, w.proj[s], q.m + 1});
+            pj.push_back(ProjJob{s ? Bp : Ap, n, r0, (int64_t)(w.Ut - ubase), w.proj[s], q.m + 1});
           for (int d = 0; d <= q.m; ++d) {
             const int32_t k = s ? q.kB[d] : q.kA[d];
             sj.push_back(SegJob{w.proj[s] + (size_t)d * n, n, nullptr, k, k, w.flags[s]});
@@ -424,13 +426,16 @@ prohd_status build(prohd_batch* b) {
     Ls.push_back([=](hipStream_t s) {
       return batch_gram_reduce(r.DP, r.D, (const GramRedJob*)at(r.red_jobs), r.n_red, 4, s);
     });
-    Ls.push_back([=](hipStream_t s) { return batch_eig(r.DP, r.D, (const EigJob*)at(r.eig_jobs), r.n_eig, s); });
+    const bool narrow = t.eig_narrow != 0 && r.m < 32;
+    Ls.push_back([=](hipStream_t s) {
+      return batch_eig(r.DP, r.D, (const EigJob*)at(r.eig_jobs), r.n_eig, narrow, s);
+    });
     Ls.push_back([=](hipStream_t s) { return batch_transpose(r.D, r.DP, (const TransJob*)at(r.tr_jobs), r.n_tr, s); });
     const int pgrid = persist(r.n_proj, t.proj_mult);
     const bool vec = ((uintptr_t)b->A % 16 == 0) && ((uintptr_t)b->B % 16 == 0);
     Ls.push_back([=](hipStream_t s) {
-      return batch_project(r.DP, r.D, r.m + 1, vec, (const ProjJob*)at(r.proj_jobs), r.n_proj, pgrid,
-                           s);
+      return batch_project(r.DP, r.D, r.m + 1, vec, ubase, (const ProjJob*)at(r.proj_jobs), r.n_proj,
+                           pgrid, s);
     });
     Ls.push_back([=](hipStream_t s) { return batch_select((const SegJob*)at(r.seg_jobs), r.n_seg, s); });
     Ls.push_back([=](hipStream_t s) { return batch_compact((const CompactJob*)at(r.cmp_jobs), r.n_cmp, s); });
@@ -647,14 +652,15 @@ prohd_status prohd_batch_tune(prohd_batch* plan, uint32_t mode, const float* A, 
   };
   std::vector<Knob> knobs;
   if (mode == PROHD_BATCH_PROHD) {
+    knobs.push_back({"eig_narrow", &Tuning::eig_narrow, {0, 1}, "batch_eig"});
     knobs.push_back({"gram_rows", &Tuning::gram_rows, {3072, 6144, 12288, 24576}, "batch_gram"});
     knobs.push_back({"gram_mult", &Tuning::gram_mult, {1, 2, 3}, "batch_gram"});
     knobs.push_back({"proj_mult", &Tuning::proj_mult, {2, 4, 8}, "batch_project"});
     knobs.push_back({"tile_yc", &Tuning::tile_yc, {1024, 4096, 16384}, "batch_tile"});
   } else {
-    knobs.push_back({"tile_yc", &Tuning::tile_yc, {2048, 4096, 8192, 16384}, "batch_tile"});
-    knobs.push_back({"tile_mult", &Tuning::tile_mult, {1, 2, 3}, "batch_tile"});
-    knobs.push_back({"refine_yc", &Tuning::refine_yc, {2048, 8192, 32768}, "batch_refine"});
+    knobs.push_back({"tile_yc", &Tuning::tile_yc, {4096, 8192, 16384}, "batch_tile"});
+    knobs.push_back({"tile_mult", &Tuning::tile_mult, {1, 2}, "batch_tile"});
+    knobs.push_back({"refine_yc", &Tuning::refine_yc, {8192, 32768}, "batch_refine"});
   }
   std::string trials;
   for (const Knob& k : knobs) {
@@ -697,9 +703,10 @@ prohd_status prohd_batch_tune(prohd_batch* plan, uint32_t mode, const float* A, 
     std::fprintf(f,
                  "{\"mode\": \"%s\", \"pairs\": %d, \"cus\": %d, \"knobs\": {\"gram_rows\": %d, "
                  "\"gram_mult\": %d, \"proj_mult\": %d, \"tile_yc\": %d, \"tile_mult\": %d, "
-                 "\"refine_yc\": %d}, \"trials\": [%s]}\n",
+                 "\"refine_yc\": %d, \"eig_narrow\": %d}, \"trials\": [%s]}\n",
                  mode == PROHD_BATCH_PROHD ? "prohd" : "exact", plan->P, cu_count(), t.gram_rows,
-                 t.gram_mult, t.proj_mult, t.tile_yc, t.tile_mult, t.refine_yc, trials.c_str());
+                 t.gram_mult, t.proj_mult, t.tile_yc, t.tile_mult, t.refine_yc, t.eig_narrow,
+                 trials.c_str());
     std::fclose(f);
   }
   return PROHD_OK;
@@ -724,6 +731,12 @@ prohd_status prohd_batch_load_tuning(prohd_batch* plan, const char* json_path) {
   json_int(knobs, "tile_yc", &t.tile_yc);
   json_int(knobs, "tile_mult", &t.tile_mult);
   json_int(knobs, "refine_yc", &t.refine_yc);
+  int en = 0;
+  if (knobs.find("\"eig_narrow\"") != std::string::npos) {
+    const size_t c = knobs.find(':', knobs.find("\"eig_narrow\""));
+    en = c != std::string::npos ? std::atoi(knobs.c_str() + c + 1) : 1;
+    t.eig_narrow = en != 0;
+  }
   plan->tune = t;
   plan->bound = false;
   release_graph(plan);

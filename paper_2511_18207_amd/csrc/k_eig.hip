@@ -18,6 +18,8 @@
 // diagonal and zeros elsewhere, so they stay decoupled and below every real
 // (non-negative) eigenvalue.
 
+#include <type_traits>
+
 #include "batch.h"
 #include "common.h"
 
@@ -29,19 +31,32 @@ prohd_status eig_run(double* C, int32_t D, int32_t m, const double* u0, float* d
 
 namespace {
 
-constexpr int kSlots = 16;   // concurrent inverse-iteration workers
-
-template <int DP>
+// Work-group shape.  The single-pair solve is latency bound and uses a wide
+// work-group (512 threads with 256 registers each, the matrix held in
+// registers, 8-16 inverse-iteration slots); the batched solve may instead
+// use a narrow one (256 threads, 4 slots, matrix in LDS up to D = 64 and in
+// global memory above) so that several problems share a compute unit.
+// With the wide work-group and DP >= 64 the matrix is held in registers during
+// the tridiagonalisation (REG); LDS then only holds vectors and, later, the
+// inverse-iteration slots and reflector chunks.
+template <int DP, int NT_ = (DP >= 64 ? 512 : 256), int SLOTS_ = 16,
+          bool LDSMAT = (DP <= 32), int MAXD_ = PROHD_MAX_DIRS>
 struct EigShape {
-  static constexpr int NT = DP >= 64 ? 1024 : 256;     // threads
+  static constexpr int NT = NT_;                        // threads
+  static constexpr int SLOTS = SLOTS_;                  // concurrent inverse-iteration workers
+  static constexpr int MAXD = MAXD_;                    // largest m + 1 handled
   static constexpr int NQ = NT / DP;                    // threads per column
   static constexpr int QS = DP / NQ > 0 ? DP / NQ : 1;  // rows per thread
-  static constexpr bool IN_LDS = DP <= 128;             // matrix in LDS
-  // LDS region reused: matrix (n <= 128), then LU slots, then reflector chunks
-  static constexpr int BIG = IN_LDS ? (DP * DP > 4 * kSlots * DP ? DP * DP : 4 * kSlots * DP)
-                                    : 4 * kSlots * DP;
+  static constexpr bool REG = NT == 512 && DP >= 64;    // register-resident matrix
+  static constexpr bool IN_LDS = LDSMAT && !REG;        // matrix in LDS
+  // LDS region reused: matrix (when in LDS), then LU slots, then reflector chunks
+  static constexpr int BIG = IN_LDS ? (DP * DP > 4 * SLOTS * DP ? DP * DP : 4 * SLOTS * DP)
+                                    : 4 * SLOTS * DP;
   static constexpr int VROWS = BIG / DP;                // reflector rows per chunk
 };
+
+template <int DP>
+using EigNarrow = EigShape<DP, 256, 4, (DP <= 64), 32>;
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -63,6 +78,231 @@ __device__ double block_sum(double x, double* red) {
   return t;
 }
 
+// Lane permutations through DPP (no LDS round trip), on both halves of a
+// double.  CTRL: 0xB1 quad_perm [1,0,3,2] (xor 1), 0x4E quad_perm [2,3,0,1]
+// (xor 2), 0x141 row_half_mirror (lane i of 8 <- 7 - i), 0x128 row_ror 8
+// (xor 8 within 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over the 8 consecutive lanes of each group of 8; every lane of the
+// group gets the same bits.
+__device__ __forceinline__ double sum8(double x) {
+  x += dpp_d<0xB1>(x);
+  x += dpp_d<0x4E>(x);
+  x += dpp_d<0x141>(x);
+  return x;
+}
+
+// Sum over the whole wave (all lanes active), returned wave-uniform: DPP
+// within rows of 16 lanes, then the four row sums read from lanes 0, 16, 32
+// and 48 in a fixed order.
+__device__ __forceinline__ double wave_sum_dpp(double x) {
+  x = sum8(x);
+  x += dpp_d<0x128>(x);
+  auto rl = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+  };
+  return (rl(0) + rl(16)) + (rl(32) + rl(48));
+}
+
+// Sum over lanes congruent modulo 8 (the 8 lanes l % 8 == r).
+__device__ __forceinline__ double sum_mod8(double x) {
+  x += dpp_d<0x128>(x);
+  x += __shfl_xor(x, 16);
+  x += __shfl_xor(x, 32);
+  return x;
+}
+
+// Householder tridiagonalisation with the symmetric matrix in registers.
+// The lower triangle is cut into 16 x 16 tiles (I >= J; diagonal tiles hold
+// both triangles).  Wave w owns the tile rows w and NB-1-w (NB + 1 tiles per
+// wave); lane l holds the 2 x 2 block at tile rows 2 (l % 8).. and columns
+// 2 (l / 8)..  Per step j: the owners of column j publish it in LDS; every
+// wave forms the reflector v (Householder vector of the column below the
+// subdiagonal) from it; the trailing matvec p = tau A v is summed per wave
+// (row sums accumulated over a tile row before one cross-lane reduction,
+// column sums reduced within groups of 8 lanes per tile) into a private LDS
+// row, then across waves in a fixed order; every wave forms K = (tau/2) p.v
+// and the tiles take the rank-2 update A -= v w^T + w v^T, w = p - K v, in
+// registers.  Writes d, e, tau and the reflectors (Vg rows) as the LDS /
+// global variant does.
+template <int DP, int NT>
+__device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, double* __restrict__ Vg,
+                                            double* col, double* pbuf, double* pw, double* red,
+                                            double* dd, double* ee, double* tau) {
+  constexpr int W = NT / 64;
+  constexpr int NB = DP / 16;
+  constexpr int TPW = NB + 1;          // tiles of tile rows RA and RB
+  static_assert(NB / 2 <= W, "one pair of tile rows per wave");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool owner = wave < NB / 2;
+  const int RA = wave, RB = NB - 1 - wave;
+  const int rb = lane & 7, cb = lane >> 3;
+  double a[TPW][2][2];
+  // tile u: row RA for u <= RA (J = u), else row RB (J = u - RA - 1)
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int I = u <= RA ? RA : RB, J = u <= RA ? u : u - RA - 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        a[u][i][q] = owner ? Mg[(size_t)(16 * I + 2 * rb + i) * DP + 16 * J + 2 * cb + q] : 0.0;
+  }
+  double* mypw = pw + (size_t)wave * DP;
+  // one step; QJ = j % 2 is a compile-time constant so that the column
+  // element is picked without indexing the register array
+  auto step = [&](const int j, auto QJ) {
+    __syncthreads();   // readers of col / pbuf / pw of the previous step are done
+    // per-lane offsets made opaque at every step, so that the compiler
+    // recomputes the (cheap) addresses instead of keeping a tile row's worth
+    // of loop-invariant addresses live in registers
+    int rb2 = 2 * rb, cb2 = 2 * cb;
+    asm volatile("" : "+v"(rb2), "+v"(cb2));
+    const int Jj = j >> 4, cj = (j & 15) >> 1;
+    if (owner && cb == cj) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int I = u <= RA ? RA : RB, J = u <= RA ? u : u - RA - 1;
+        if (J == Jj) {
+          col[16 * I + rb2] = a[u][0][decltype(QJ)::value];
+          col[16 * I + rb2 + 1] = a[u][1][decltype(QJ)::value];
+        }
+      }
+    }
+    for (int k = lane; k < DP; k += 64) mypw[k] = 0.0;
+    __syncthreads();
+    // reflector (every wave computes the same values in the same order)
+    const double alpha = col[j + 1];
+    double s2 = 0.0;
+    for (int k = lane; k < DP; k += 64) s2 += (k > j + 1) ? col[k] * col[k] : 0.0;
+    const double sigma = wave_sum_dpp(s2);
+    double tj = 0.0, beta = alpha, scale = 0.0;
+    if (sigma > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tj = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    auto vof = [&](int k) { return k == j + 1 ? 1.0 : (k > j + 1 ? col[k] * scale : 0.0); };
+    if (tid == 0) {
+      ee[j] = beta;
+      tau[j] = tj;
+      dd[j] = col[j];
+    }
+    if (wave == 0)
+      for (int k = lane; k < DP; k += 64) Vg[(size_t)j * DP + k] = vof(k);
+    if (tj == 0.0) return;   // uniform: nothing below the subdiagonal
+    // p = A v over the trailing block, per wave
+    if (owner) {
+      double pa0 = 0.0, pa1 = 0.0, pb0 = 0.0, pb1 = 0.0;
+      const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
+      const double vb0 = vof(16 * RB + rb2), vb1 = vof(16 * RB + rb2 + 1);
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const bool rowA = u <= RA;
+        const int I = rowA ? RA : RB, J = rowA ? u : u - RA - 1;
+        if (16 * J + 15 > j) {   // uniform per wave
+          const int c0 = 16 * J + cb2;
+          const double vc0 = vof(c0), vc1 = vof(c0 + 1);
+          const double vr0 = rowA ? va0 : vb0, vr1 = rowA ? va1 : vb1;
+          const double r0s = a[u][0][0] * vc0 + a[u][0][1] * vc1;
+          const double r1s = a[u][1][0] * vc0 + a[u][1][1] * vc1;
+          if (rowA) {
+            pa0 += r0s;
+            pa1 += r1s;
+          } else {
+            pb0 += r0s;
+            pb1 += r1s;
+          }
+          if (I > J) {
+            // column sums over the 8 row-pair lanes; LDS adds in program
+            // order (one lane per address per instruction: deterministic)
+            const double pc0 = sum8(a[u][0][0] * vr0 + a[u][1][0] * vr1);
+            const double pc1 = sum8(a[u][0][1] * vr0 + a[u][1][1] * vr1);
+            if (rb == 0) {
+              atomicAdd(&mypw[c0], pc0);
+              atomicAdd(&mypw[c0 + 1], pc1);
+            }
+          }
+        }
+      }
+      pa0 = sum_mod8(pa0);
+      pa1 = sum_mod8(pa1);
+      pb0 = sum_mod8(pb0);
+      pb1 = sum_mod8(pb1);
+      if (cb == 0) {
+        atomicAdd(&mypw[16 * RA + rb2], pa0);
+        atomicAdd(&mypw[16 * RA + rb2 + 1], pa1);
+        atomicAdd(&mypw[16 * RB + rb2], pb0);
+        atomicAdd(&mypw[16 * RB + rb2 + 1], pb1);
+      }
+    }
+    __syncthreads();
+    // p in a fixed order over waves
+    if (tid < DP) {
+      double p = 0.0;
+      if (tid > j) {
+#pragma unroll
+        for (int w = 0; w < NB / 2; ++w) p += pw[(size_t)w * DP + tid];
+        p *= tj;
+      }
+      pbuf[tid] = p;
+    }
+    __syncthreads();
+    // K = (tau / 2) p.v (each wave, same order); w_k = p_k - K v_k
+    double kd = 0.0;
+    for (int k = lane; k < DP; k += 64) kd += pbuf[k] * vof(k);
+    const double K = 0.5 * tj * wave_sum_dpp(kd);
+    if (!owner) return;
+    auto wof = [&](int k) { return k > j ? pbuf[k] - K * vof(k) : 0.0; };
+    const double wa0 = wof(16 * RA + rb2), wa1 = wof(16 * RA + rb2 + 1);
+    const double wb0 = wof(16 * RB + rb2), wb1 = wof(16 * RB + rb2 + 1);
+    const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
+    const double vb0 = vof(16 * RB + rb2), vb1 = vof(16 * RB + rb2 + 1);
+    // A -= v w^T + w v^T
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const bool rowA = u <= RA;
+      const int J = rowA ? u : u - RA - 1;
+      if (16 * J + 15 > j) {
+        const int c0 = 16 * J + cb2;
+        const double vc0 = vof(c0), vc1 = vof(c0 + 1), wc0 = wof(c0), wc1 = wof(c0 + 1);
+        const double vr0 = rowA ? va0 : vb0, vr1 = rowA ? va1 : vb1;
+        const double wr0 = rowA ? wa0 : wb0, wr1 = rowA ? wa1 : wb1;
+        a[u][0][0] -= vr0 * wc0 + wr0 * vc0;
+        a[u][0][1] -= vr0 * wc1 + wr0 * vc1;
+        a[u][1][0] -= vr1 * wc0 + wr1 * vc0;
+        a[u][1][1] -= vr1 * wc1 + wr1 * vc1;
+      }
+    }
+  };
+  for (int j = 0; j < DP - 2; j += 2) {   // DP - 2 is even
+    step(j, std::integral_constant<int, 0>{});
+    step(j + 1, std::integral_constant<int, 1>{});
+  }
+  // trailing 2 x 2 block: rows / columns DP-2, DP-1 (diagonal tile NB-1 is
+  // tile u = NB of wave 0, whose row RB = NB-1; lane 63 holds rows 14-15)
+  if (wave == 0 && lane == 63) {
+    dd[DP - 2] = a[TPW - 1][0][0];
+    dd[DP - 1] = a[TPW - 1][1][1];
+    ee[DP - 2] = a[TPW - 1][1][0];
+  }
+  if (tid == 0) {
+    ee[DP - 1] = 0.0;
+    tau[DP - 2] = tau[DP - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ double start_value(int k, int c) {
   // deterministic pseudo-random start vector entry in (-1, 1)
   uint32_t h = (uint32_t)k * 0x9E3779B1u ^ ((uint32_t)c + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -72,18 +312,17 @@ __device__ __forceinline__ double start_value(int k, int c) {
   return ((double)(h & 0xFFFFFFu) / 8388608.0) - 1.0 + 1.0 / 16777216.0;
 }
 
-template <int DP>
+template <int DP, class S>
 __device__ __forceinline__ void eig_body(
     double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
     const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
     const int32_t* __restrict__ status) {
-  using S = EigShape<DP>;
   constexpr int NT = S::NT;
   __shared__ double big[S::BIG];
   __shared__ double vs[DP], wv[DP], part[S::NQ][DP];
   __shared__ double dd[DP], ee[DP], e2[DP], tau[DP], lam[DP];
   __shared__ double red[NT / 64];
-  __shared__ uint8_t piv[kSlots][DP];
+  __shared__ uint8_t piv[S::SLOTS][DP];
   __shared__ int lead_of[64];
 
   const int t = threadIdx.x;
@@ -96,85 +335,89 @@ __device__ __forceinline__ void eig_body(
   __syncthreads();
 
   // ---------------------------------------------------- 1. tridiagonalise
-  const int ci = t % DP;        // column owned in the matvec / update
-  const int cq = t / DP;        // row block of that column
-  const int k0 = cq * S::QS;
-  const int k1 = k0 + S::QS;
-  __shared__ double sq[S::NQ];
-  // sigma of column 0 below the subdiagonal
-  double sigma = block_sum<NT>((t > 1 && t < DP) ? M[(size_t)t * DP] * M[(size_t)t * DP] : 0.0, red);
-  for (int j = 0; j < DP - 2; ++j) {
-    const double xk = (t > j + 1 && t < DP) ? M[(size_t)t * DP + j] : 0.0;
-    const double alpha = M[(size_t)(j + 1) * DP + j];
-    double tj = 0.0, beta = alpha, scale = 0.0;
-    if (sigma > 0.0) {
-      const double nrm = sqrt(alpha * alpha + sigma);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tj = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    if (t < DP) {
-      const double v = (t == j + 1) ? 1.0 : (t > j + 1 ? xk * scale : 0.0);
-      vs[t] = v;
-      Vg[(size_t)j * DP + t] = v;
+  if constexpr (S::REG) {
+    tridiag_reg<DP, NT>(Mg, Vg, vs, wv, big, red, dd, ee, tau);   // col = vs, p = wv
+  } else {
+    const int ci = t % DP;        // column owned in the matvec / update
+    const int cq = t / DP;        // row block of that column
+    const int k0 = cq * S::QS;
+    const int k1 = k0 + S::QS;
+    __shared__ double sq[S::NQ];
+    // sigma of column 0 below the subdiagonal
+    double sigma = block_sum<NT>((t > 1 && t < DP) ? M[(size_t)t * DP] * M[(size_t)t * DP] : 0.0, red);
+    for (int j = 0; j < DP - 2; ++j) {
+      const double xk = (t > j + 1 && t < DP) ? M[(size_t)t * DP + j] : 0.0;
+      const double alpha = M[(size_t)(j + 1) * DP + j];
+      double tj = 0.0, beta = alpha, scale = 0.0;
+      if (sigma > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (t < DP) {
+        const double v = (t == j + 1) ? 1.0 : (t > j + 1 ? xk * scale : 0.0);
+        vs[t] = v;
+        Vg[(size_t)j * DP + t] = v;
+      }
+      if (t == 0) {
+        ee[j] = beta;
+        tau[j] = tj;
+        dd[j] = M[(size_t)j * DP + j];
+      }
+      __syncthreads();
+      if (tj != 0.0) {  // uniform
+        // p = tau * M v over the trailing block (rows k > j, columns > j)
+        if (ci > j) {
+          double acc = 0.0;
+          const int kb = k0 > j + 1 ? k0 : j + 1;
+  #pragma unroll 8
+          for (int k = kb; k < k1; ++k) acc += M[(size_t)k * DP + ci] * vs[k];
+          part[cq][ci] = acc;
+        }
+        __syncthreads();
+        double p = 0.0, v = 0.0;
+        if (t < DP && t > j) {
+  #pragma unroll
+          for (int q = 0; q < S::NQ; ++q) p += part[q][t];
+          p *= tj;
+          v = vs[t];
+        }
+        const double K = 0.5 * tj * block_sum<NT>(p * v, red);
+        if (t < DP) wv[t] = (t > j) ? p - K * v : 0.0;
+        __syncthreads();
+        // M -= v w^T + w v^T on the trailing block; the owners of column j+1
+        // also sum its squares below the next subdiagonal (next step's sigma)
+        double s2 = 0.0;
+        if (ci > j) {
+          const double vi = vs[ci], wi = wv[ci];
+          const int kb = k0 > j + 1 ? k0 : j + 1;
+  #pragma unroll 8
+          for (int k = kb; k < k1; ++k) {
+            const double nv = M[(size_t)k * DP + ci] - (vs[k] * wi + wv[k] * vi);
+            M[(size_t)k * DP + ci] = nv;
+            s2 += (k > j + 2) ? nv * nv : 0.0;
+          }
+        }
+        if (ci == j + 1) sq[cq] = s2;
+        __syncthreads();
+        sigma = 0.0;
+  #pragma unroll
+        for (int q = 0; q < S::NQ; ++q) sigma += sq[q];
+      } else {
+        const double nx = (t > j + 2 && t < DP) ? M[(size_t)t * DP + j + 1] : 0.0;
+        sigma = block_sum<NT>(nx * nx, red);
+      }
     }
     if (t == 0) {
-      ee[j] = beta;
-      tau[j] = tj;
-      dd[j] = M[(size_t)j * DP + j];
+      dd[DP - 2] = M[(size_t)(DP - 2) * DP + DP - 2];
+      dd[DP - 1] = M[(size_t)(DP - 1) * DP + DP - 1];
+      ee[DP - 2] = M[(size_t)(DP - 1) * DP + DP - 2];
+      ee[DP - 1] = 0.0;
+      tau[DP - 2] = tau[DP - 1] = 0.0;
     }
     __syncthreads();
-    if (tj != 0.0) {  // uniform
-      // p = tau * M v over the trailing block (rows k > j, columns > j)
-      if (ci > j) {
-        double acc = 0.0;
-        const int kb = k0 > j + 1 ? k0 : j + 1;
-#pragma unroll 8
-        for (int k = kb; k < k1; ++k) acc += M[(size_t)k * DP + ci] * vs[k];
-        part[cq][ci] = acc;
-      }
-      __syncthreads();
-      double p = 0.0, v = 0.0;
-      if (t < DP && t > j) {
-#pragma unroll
-        for (int q = 0; q < S::NQ; ++q) p += part[q][t];
-        p *= tj;
-        v = vs[t];
-      }
-      const double K = 0.5 * tj * block_sum<NT>(p * v, red);
-      if (t < DP) wv[t] = (t > j) ? p - K * v : 0.0;
-      __syncthreads();
-      // M -= v w^T + w v^T on the trailing block; the owners of column j+1
-      // also sum its squares below the next subdiagonal (next step's sigma)
-      double s2 = 0.0;
-      if (ci > j) {
-        const double vi = vs[ci], wi = wv[ci];
-        const int kb = k0 > j + 1 ? k0 : j + 1;
-#pragma unroll 8
-        for (int k = kb; k < k1; ++k) {
-          const double nv = M[(size_t)k * DP + ci] - (vs[k] * wi + wv[k] * vi);
-          M[(size_t)k * DP + ci] = nv;
-          s2 += (k > j + 2) ? nv * nv : 0.0;
-        }
-      }
-      if (ci == j + 1) sq[cq] = s2;
-      __syncthreads();
-      sigma = 0.0;
-#pragma unroll
-      for (int q = 0; q < S::NQ; ++q) sigma += sq[q];
-    } else {
-      const double nx = (t > j + 2 && t < DP) ? M[(size_t)t * DP + j + 1] : 0.0;
-      sigma = block_sum<NT>(nx * nx, red);
-    }
   }
-  if (t == 0) {
-    dd[DP - 2] = M[(size_t)(DP - 2) * DP + DP - 2];
-    dd[DP - 1] = M[(size_t)(DP - 1) * DP + DP - 1];
-    ee[DP - 2] = M[(size_t)(DP - 1) * DP + DP - 2];
-    ee[DP - 1] = 0.0;
-    tau[DP - 2] = tau[DP - 1] = 0.0;
-  }
-  __syncthreads();
 
   // ------------------------------------------------------- 2. bisection
   if (t < DP) e2[t] = ee[t] * ee[t];
@@ -188,25 +431,55 @@ __device__ __forceinline__ void eig_body(
   }
   const double tnorm = fmax(fabs(gl), fabs(gu));
   const double pivmin = 1e-290 * fmax(1.0, emax);
-  if (t < DP) {
+  // count(x) = number of eigenvalues below x (Sturm sequence of T - x I)
+  auto sturm = [&](double x) {
+    int cnt = 0;
+    double q = dd[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = 1; i < DP; ++i) {
+      double r = __builtin_amdgcn_rcp(q);   // 1/q, refined by one Newton step
+      r = fma(r, fma(-q, r, 1.0), r);
+      q = dd[i] - x - e2[i - 1] * r;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    return cnt;
+  };
+  if (evals == nullptr && NT >= 512) {
+    // only the m + 1 largest and the smallest real eigenvalue are used:
+    // 16-way multisection, one group of 16 lanes per eigenvalue
+    constexpr int G = 16;
+    const int grp = t / G, gi = t % G;
+    const int ne = m + 2;
+    for (int base = 0; base < ne; base += NT / G) {
+      const int e = base + grp;
+      if (e < ne) {   // uniform per group of 16 lanes
+        const int idx = e <= m ? DP - 1 - e : DP - D;
+        double lo = gl - 1e-14 * tnorm - pivmin, hi = gu + 1e-14 * tnorm + pivmin;
+        for (int it = 0; it < 40; ++it) {
+          const double w = hi - lo;
+          if (!(w > 2.2e-16 * (fmax(fabs(lo), fabs(hi)) + tnorm) + pivmin)) break;
+          const double x = lo + w * (double)(gi + 1) / (double)(G + 1);
+          const unsigned long long bal = __ballot(sturm(x) <= idx);
+          const int k = __popcll((bal >> (t & 63 & ~(G - 1))) & 0xFFFFull);
+          const double nlo = k > 0 ? lo + w * (double)k / (double)(G + 1) : lo;
+          const double nhi = k < G ? lo + w * (double)(k + 1) / (double)(G + 1) : hi;
+          if (!(nlo >= lo && nhi <= hi && nlo < nhi)) break;
+          lo = nlo;
+          hi = nhi;
+        }
+        if (gi == 0) lam[idx] = 0.5 * (lo + hi);
+      }
+    }
+  } else if (t < DP) {
     // lam[t] = (t+1)-th smallest eigenvalue: count(x) = #eigenvalues < x
     double lo = gl - 1e-14 * tnorm - pivmin, hi = gu + 1e-14 * tnorm + pivmin;
     for (int it = 0; it < 200; ++it) {
       const double mid = 0.5 * (lo + hi);
       if (!(mid > lo && mid < hi)) break;
       if (hi - lo <= 2.2e-16 * (fmax(fabs(lo), fabs(hi)) + tnorm) + pivmin) break;
-      int cnt = 0;
-      double q = dd[0] - mid;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      for (int i = 1; i < DP; ++i) {
-        double r = __builtin_amdgcn_rcp(q);   // 1/q, refined by one Newton step
-        r = fma(r, fma(-q, r, 1.0), r);
-        q = dd[i] - mid - e2[i - 1] * r;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-      }
-      if (cnt >= t + 1) hi = mid; else lo = mid;
+      if (sturm(mid) >= t + 1) hi = mid; else lo = mid;
     }
     lam[t] = 0.5 * (lo + hi);
   }
@@ -225,12 +498,12 @@ __device__ __forceinline__ void eig_body(
     }
   }
   __syncthreads();
-  double* slot_base = big;  // kSlots x 4 x DP doubles: U0 inverse, U1, L, x
-  // leaders take slots in rounds of kSlots
-  for (int round = 0; round * kSlots < m; ++round) {
+  double* slot_base = big;  // SLOTS x 4 x DP doubles: U0 inverse, U1, L, x
+  // leaders take slots in rounds of SLOTS
+  for (int round = 0; round * S::SLOTS < m; ++round) {
     const int c0 = t;  // candidate leader index handled by this thread
-    const int leader = round * kSlots + c0;
-    if (c0 < kSlots && leader < m && lead_of[leader] == leader && ok) {
+    const int leader = round * S::SLOTS + c0;
+    if (c0 < S::SLOTS && leader < m && lead_of[leader] == leader && ok) {
       double* U0 = slot_base + (size_t)c0 * 4 * DP;
       double* U1 = U0 + DP;
       double* Lm = U0 + 2 * DP;
@@ -323,7 +596,7 @@ __device__ __forceinline__ void eig_body(
   // k = lane + 64 r.
   constexpr int PR = (DP + 63) / 64;
   constexpr int NW = NT / 64;
-  constexpr int VPW = (PROHD_MAX_DIRS - 1 + NW - 1) / NW;
+  constexpr int VPW = (S::MAXD - 1 + NW - 1) / NW;
   const int lane = t & 63, wave = t >> 6;
   double z[VPW][PR];
 #pragma unroll
@@ -415,17 +688,16 @@ __global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
     double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
     const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
     const int32_t* __restrict__ status) {
-  eig_body<DP>(Mg, D, m, Vg, Yg, u0, dirs, evals, status);
+  eig_body<DP, EigShape<DP>>(Mg, D, m, Vg, Yg, u0, dirs, evals, status);
 }
 
 // One work-group per job (pair).
-template <int DP>
-__global__ __launch_bounds__(EigShape<DP>::NT) void eig_batch(const EigJob* __restrict__ jobs, int D,
-                                                              int njobs) {
+template <int DP, class S>
+__global__ __launch_bounds__(S::NT) void eig_batch(const EigJob* __restrict__ jobs, int D, int njobs) {
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const EigJob j = jobs[it];
     __syncthreads();
-    eig_body<DP>(j.C, D, j.m, j.V, j.Y, j.u0, j.dirs, nullptr, j.status);
+    eig_body<DP, S>(j.C, D, j.m, j.V, j.Y, j.u0, j.dirs, nullptr, j.status);
   }
 }
 
@@ -466,18 +738,29 @@ prohd_status eig_run(double* C, int32_t D, int32_t m, const double* u0, float* d
 
 size_t eig_job_doubles(int DP) { return (size_t)DP * DP + (size_t)PROHD_MAX_DIRS * DP; }
 
-prohd_status batch_eig(int DP, int D, const EigJob* jobs, int njobs, hipStream_t s) {
+template <int DP, class S>
+prohd_status batch_eig_shape(int D, const EigJob* jobs, int njobs, int per_cu, hipStream_t s) {
+  const int grid = std::min(njobs, per_cu * cu_count());
+  PROHD_LAUNCH("batch_eig", (eig_batch<DP, S>), dim3(grid), dim3(S::NT), 0, s, jobs, D, njobs);
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status batch_eig_dp(int D, const EigJob* jobs, int njobs, bool narrow, hipStream_t s) {
+  if (narrow) return batch_eig_shape<DP, EigNarrow<DP>>(D, jobs, njobs, 4, s);
+  return batch_eig_shape<DP, EigShape<DP>>(D, jobs, njobs, 2, s);
+}
+
+prohd_status batch_eig(int DP, int D, const EigJob* jobs, int njobs, bool narrow, hipStream_t s) {
   if (njobs <= 0) return PROHD_OK;
-  const int grid = std::min(njobs, 2 * cu_count());
   switch (DP) {
-    case 16: PROHD_LAUNCH("batch_eig", eig_batch<16>, dim3(grid), dim3(EigShape<16>::NT), 0, s, jobs, D, njobs); break;
-    case 32: PROHD_LAUNCH("batch_eig", eig_batch<32>, dim3(grid), dim3(EigShape<32>::NT), 0, s, jobs, D, njobs); break;
-    case 64: PROHD_LAUNCH("batch_eig", eig_batch<64>, dim3(grid), dim3(EigShape<64>::NT), 0, s, jobs, D, njobs); break;
-    case 128: PROHD_LAUNCH("batch_eig", eig_batch<128>, dim3(grid), dim3(EigShape<128>::NT), 0, s, jobs, D, njobs); break;
-    case 256: PROHD_LAUNCH("batch_eig", eig_batch<256>, dim3(grid), dim3(EigShape<256>::NT), 0, s, jobs, D, njobs); break;
+    case 16: return batch_eig_dp<16>(D, jobs, njobs, narrow, s);
+    case 32: return batch_eig_dp<32>(D, jobs, njobs, narrow, s);
+    case 64: return batch_eig_dp<64>(D, jobs, njobs, narrow, s);
+    case 128: return batch_eig_dp<128>(D, jobs, njobs, narrow, s);
+    case 256: return batch_eig_dp<256>(D, jobs, njobs, narrow, s);
     default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
   }
-  return PROHD_OK;
 }
 
 }  // namespace prohd

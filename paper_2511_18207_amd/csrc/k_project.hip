@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict
 // project_rows; the next chunk of the tile is prefetched in registers.
 template <int DP, int NG, bool VEC>
 __global__ __launch_bounds__(kThreads) void project_batch(const ProjJob* __restrict__ jobs, int njobs,
-                                                          int D) {
+                                                          int D, const float* __restrict__ Ubase) {
   constexpr int KC = DP < 32 ? DP : 32;
   constexpr int NCH = DP / KC;
   constexpr int ST = KC + 4;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void project_batch(const ProjJob* __restr
       __syncthreads();
       if (c + 1 < NCH) load(c + 1);
       const float* xr = &xt[tid * ST];
-      const float* uc = j.Ut + (size_t)(c * KC) * ND;
+      const float* uc = Ubase + j.ut_off + (size_t)(c * KC) * ND;
 #pragma unroll 2
       for (int k4 = 0; k4 < KC / 4; ++k4) {
         const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
@@ -352,39 +352,40 @@ prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB,
 }
 
 template <int DP, int NG>
-prohd_status batch_project_ng(int D, bool vec, const ProjJob* jobs, int njobs, int grid, hipStream_t s) {
+prohd_status batch_project_ng(int D, bool vec, const float* U, const ProjJob* jobs, int njobs, int grid,
+                              hipStream_t s) {
   if (vec) {
     PROHD_LAUNCH("batch_project", (project_batch<DP, NG, true>), dim3(grid), dim3(kThreads), 0, s, jobs,
-                 njobs, D);
+                 njobs, D, U);
   } else {
     PROHD_LAUNCH("batch_project", (project_batch<DP, NG, false>), dim3(grid), dim3(kThreads), 0, s, jobs,
-                 njobs, D);
+                 njobs, D, U);
   }
   return PROHD_OK;
 }
 
 template <int DP>
-prohd_status batch_project_dp(int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
-                              hipStream_t s) {
+prohd_status batch_project_dp(int D, int ndirs, bool vec, const float* U, const ProjJob* jobs, int njobs,
+                              int grid, hipStream_t s) {
   switch ((ndirs + 7) / 8) {
-    case 1: return batch_project_ng<DP, 1>(D, vec, jobs, njobs, grid, s);
-    case 2: return batch_project_ng<DP, 2>(D, vec, jobs, njobs, grid, s);
-    case 3: return batch_project_ng<DP, 3>(D, vec, jobs, njobs, grid, s);
-    case 4: return batch_project_ng<DP, 4>(D, vec, jobs, njobs, grid, s);
+    case 1: return batch_project_ng<DP, 1>(D, vec, U, jobs, njobs, grid, s);
+    case 2: return batch_project_ng<DP, 2>(D, vec, U, jobs, njobs, grid, s);
+    case 3: return batch_project_ng<DP, 3>(D, vec, U, jobs, njobs, grid, s);
+    case 4: return batch_project_ng<DP, 4>(D, vec, U, jobs, njobs, grid, s);
     default: return fail(PROHD_EUNSUPPORTED, "batched projection: more than 32 directions");
   }
 }
 
-prohd_status batch_project(int DP, int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
-                           hipStream_t s) {
+prohd_status batch_project(int DP, int D, int ndirs, bool vec, const float* U, const ProjJob* jobs,
+                           int njobs, int grid, hipStream_t s) {
   if (njobs <= 0) return PROHD_OK;
   vec = vec && D % 4 == 0;
   switch (DP) {
-    case 16: return batch_project_dp<16>(D, ndirs, vec, jobs, njobs, grid, s);
-    case 32: return batch_project_dp<32>(D, ndirs, vec, jobs, njobs, grid, s);
-    case 64: return batch_project_dp<64>(D, ndirs, vec, jobs, njobs, grid, s);
-    case 128: return batch_project_dp<128>(D, ndirs, vec, jobs, njobs, grid, s);
-    case 256: return batch_project_dp<256>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 16: return batch_project_dp<16>(D, ndirs, vec, U, jobs, njobs, grid, s);
+    case 32: return batch_project_dp<32>(D, ndirs, vec, U, jobs, njobs, grid, s);
+    case 64: return batch_project_dp<64>(D, ndirs, vec, U, jobs, njobs, grid, s);
+    case 128: return batch_project_dp<128>(D, ndirs, vec, U, jobs, njobs, grid, s);
+    case 256: return batch_project_dp<256>(D, ndirs, vec, U, jobs, njobs, grid, s);
     default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
   }
 }

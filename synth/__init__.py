@@ -37,7 +37,7 @@ CHUNK = 16384
 
 __all__ = [
     "CHUNK", "rng", "gauss_outliers", "mixture", "t_mixture", "shells",
-    "uniform_clouds", "batch_sizes", "workload",
+    "uniform_clouds", "batch_sizes", "batch_pair", "workload",
 ]
 
 
@@ -183,6 +183,12 @@ def batch_sizes(P: int, seed: int, lo: int = 256, hi: int = 65536,
     nB = np.floor(np.exp(g.uniform(math.log(lo), math.log(hi), size=P))).astype(np.int64)
     D = np.asarray(dims)[g.integers(0, len(dims), size=P)].astype(np.int64)
     return np.clip(nA, lo, hi), np.clip(nB, lo, hi), D
+
+
+def batch_pair(seed: int, i: int, nA: int, nB: int, D: int):
+    """Pair i of a batch drawn with ``batch_sizes(P, seed)``: the
+    ``gauss_outliers`` law at that pair's sizes, seed ``seed * 2^20 + i``."""
+    return gauss_outliers(int(nA), int(nB), int(D), seed=(int(seed) << 20) + int(i))
 
 
 def workload(name: str, seed: int = 0):
