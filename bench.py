@@ -450,6 +450,32 @@ def main():
             "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
             "per_launch": {"algorithmic_flops": flops, "avg_ms": tile_avg, "launches": tile_n}}
 
+    # error certificate (Sec. II-E bounds) of this step's directions and
+    # projections, with the inner-minimum-over-the-full-set value as the
+    # lower bound
+    dirs_c, pA_c, pB_c, _, _ = ph.prohd_project(dA, dB, m, ws=ws, evals=False)
+    iA_c, cA_c, iB_c, cB_c = ph.prohd_select(pA_c, pB_c, kA, kB, capA=capA, capB=capB, ws=ws)
+    full_out = ph.prohd_hd(dA, dB, iA_c, cA_c, iB_c, cB_c, capA=capA, capB=capB, ws=ws, inner_full=True)
+    cws = ph.Workspace(dev)
+    ph.certificate(dA, dB, dirs_c, pA_c, pB_c, lower=full_out, ws=cws)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    cert = ph.certificate(dA, dB, dirs_c, pA_c, pB_c, lower=full_out, ws=cws)
+    c1.record()
+    torch.cuda.synchronize()
+    cert["ms"] = c0.elapsed_time(c1)
+    ph.profile_reset()
+    ph.profile_enable(True)
+    ph.certificate(dA, dB, dirs_c, pA_c, pB_c, lower=full_out, ws=cws)
+    torch.cuda.synchronize()
+    ph.profile_enable(False)
+    cert["kernels_ms"] = {k: ph.profile_read(k)[1] for k in ("cert_rows", "cert_bins", "cert_scan",
+                                                              "cert_query", "centroid", "cert_init")}
+    ph.profile_reset()
+    cert["inner_full_H"] = ph.decode_result(full_out)["H"]
+    del cws
+    log(f"certificate [{cert['lb']:.6f}, {cert['ub']:.6f}] in {cert['ms']:.3f} ms")
+
     def time_prohd(prec, kA_, kB_, reps):
         capA_ = int(min(nA, 2 * sum(min(k, nA) for k in kA_)))
         capB_ = int(min(nB, 2 * sum(min(k, nB) for k in kB_)))
@@ -508,6 +534,7 @@ def main():
         for prec in ("bf16", "fp8"):
             exact[prec]["rel_err_vs_fp32_exact"] = abs(exact[prec]["H"] - Hx) / Hx
         exact["prohd_fp32_rel_err_vs_exact"] = abs(res["H"] - Hx) / Hx
+        exact["certificate_contains_exact"] = bool(cert["lb"] <= Hx <= cert["ub"])
         # precision form: ProHD with low-precision tiles, at the same budget and
         # at a 4x larger alpha (about the same time as the float32 path)
         forms = []
@@ -565,6 +592,7 @@ def main():
         "result": {"H": res["H"], "hAB": res["hAB"], "hBA": res["hBA"], "nA_sel": res["nA_sel"],
                    "nB_sel": res["nB_sel"], "status": res["status"]},
         "check": check,
+        "certificate": cert,
         "roofline": roof,
         "exact": exact,
         "kernels": kernels,

@@ -305,6 +305,40 @@ prohd_status prohd_batch_tune(prohd_batch* plan, uint32_t mode, const float* A, 
                               const char* json_path);
 prohd_status prohd_batch_load_tuning(prohd_batch* plan, const char* json_path);
 
+/*
+ * prohd_certificate -- a certified interval for the true distance H(A,B)
+ * from the projections ProHD already made (Sec. II-E: H_u <= H <= H_u +
+ * 2 delta(u) for every direction u, delta measured from the line through
+ * the centroid of A u B, which the bound allows since H and H_u are
+ * translation invariant).
+ *
+ *   dirs, projA, projB  the outputs of prohd_project (ndirs = m + 1 rows).
+ *   lower   device prohd_result whose H is known to be <= H(A,B) -- the
+ *           result of prohd_hd with PROHD_INNER_FULL -- or NULL.
+ *   out     device prohd_cert: lb <= H(A,B) <= ub, with lb = max(max_u lower
+ *           bound of H_u, lower->H) and ub = min_u (upper bound of H_u +
+ *           2 delta(u)); hu_lo / hu_hi bound H_U = max_u H_u; delta_min =
+ *           min_u delta(u); proj_err = bound of the float32 projection
+ *           error used to widen the H_u bounds; best_dir = the u giving ub.
+ * The bounds account for float32 rounding of the projections (rigorous for
+ * finite inputs).  Workspace: prohd_certificate_workspace_size(D, ndirs).
+ * Errors: EINVAL, EUNSUPPORTED (D > 256 or ndirs > 64), EWORKSPACE.
+ */
+typedef struct {
+  double lb, ub;
+  double hu_lo, hu_hi;
+  double delta_min;
+  double proj_err;
+  int32_t best_dir;
+  int32_t status;
+} prohd_cert;
+
+size_t prohd_certificate_workspace_size(int32_t D, int32_t ndirs);
+prohd_status prohd_certificate(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                               const float* dirs, int32_t ndirs, const float* projA,
+                               const float* projB, const prohd_result* lower, prohd_cert* out,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* Message of the last non-OK return on this host thread ("" if none). */
 const char* prohd_last_error(void);
 

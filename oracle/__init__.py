@@ -35,6 +35,7 @@ from .hausdorff import (  # noqa: F401
     hd_1d,
     hd_directions,
     delta,
+    certificate,
 )
 from .prohd import (  # noqa: F401
     k_rule,

@@ -32,6 +32,7 @@ __all__ = [
     "hd_1d",
     "hd_directions",
     "delta",
+    "certificate",
 ]
 
 
@@ -173,14 +174,32 @@ def hd_directions(A, B, U) -> float:
     return max(hd_1d(A @ u, B @ u) for u in U)
 
 
-def delta(A, B, u) -> float:
+def delta(A, B, u, c=None) -> float:
     """delta(u) of Eq. (2): max over A u B of the distance to the line R*u.
 
     ``u`` must be a unit vector; the line passes through the origin (the
-    definition is not translation invariant).  Computed as the norm of the
-    direct residual ``p - (p^T u) u``.
+    definition is not translation invariant), or through ``c`` when given:
+    the bound H <= H_u + 2 delta(u) of Sec. II-E then still holds, because
+    H and H_u do not change when both sets are translated by -c.
+    Computed as the norm of the direct residual ``p - (p^T u) u``.
     """
     u = np.asarray(u, dtype=np.float64).ravel()
     P = np.vstack([_f64(A), _f64(B)])
+    if c is not None:
+        P = P - np.asarray(c, dtype=np.float64)[None, :]
     res = P - np.outer(P @ u, u)
     return float(np.sqrt(np.einsum("ij,ij->i", res, res)).max())
+
+
+def certificate(A, B, U, c=None):
+    """Interval [lb, ub] around H(A,B) from directions U (Sec. II-E):
+    lb = max_u H_u, ub = min_u (H_u + 2 delta(u)) with delta measured from
+    the line through ``c`` (origin when None).  Rows of U are normalised.
+    Returns a dict with lb, ub, the per-direction H_u and delta."""
+    A = _f64(A)
+    B = _f64(B)
+    U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+    U = U / np.linalg.norm(U, axis=1, keepdims=True)
+    hu = np.array([hd_1d(A @ u, B @ u) for u in U])
+    de = np.array([delta(A, B, u, c) for u in U])
+    return {"lb": float(hu.max()), "ub": float((hu + 2 * de).min()), "hu": hu, "delta": de}

@@ -30,6 +30,7 @@ from ._lib import (  # noqa: F401
     centroid,
     select_scored,
     BatchPlan,
+    certificate,
     profile_enable,
     profile_reset,
     profile_read,

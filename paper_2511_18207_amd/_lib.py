@@ -24,6 +24,12 @@ PREC = {"fp32": 0, "bf16": PREC_BF16, "fp8": PREC_FP8}
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENONFINITE", 3: "EWORKSPACE", 4: "EDEVICE", 5: "EUNSUPPORTED"}
 
+# prohd_cert, as laid out by the C struct
+CERT_DTYPE = np.dtype([
+    ("lb", "<f8"), ("ub", "<f8"), ("hu_lo", "<f8"), ("hu_hi", "<f8"),
+    ("delta_min", "<f8"), ("proj_err", "<f8"), ("best_dir", "<i4"), ("status", "<i4"),
+])
+
 # prohd_result, as laid out by the C struct
 RESULT_DTYPE = np.dtype([
     ("H", "<f8"), ("hAB", "<f8"), ("hBA", "<f8"),
@@ -84,6 +90,10 @@ def lib() -> C.CDLL:
                                        vp, sz, vp]
     L.prohd_centroid.restype = C.c_int
     L.prohd_centroid.argtypes = [vp, i64, i32, vp, vp, sz, vp]
+    L.prohd_certificate_workspace_size.restype = sz
+    L.prohd_certificate_workspace_size.argtypes = [i32, i32]
+    L.prohd_certificate.restype = C.c_int
+    L.prohd_certificate.argtypes = [vp, i64, vp, i64, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]
     L.prohd_select_scored.restype = C.c_int
     L.prohd_select_scored.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp, vp, i64, vp, vp, sz,
                                       vp]
@@ -423,6 +433,25 @@ def centroid(X, out=None, ws=None):
     _check(lib().prohd_centroid(X.data_ptr(), n, D, out.data_ptr(), buf.data_ptr(), nbytes,
                                 _stream()))
     return out
+
+
+def certificate(A, B, dirs, projA, projB, lower=None, ws=None):
+    """Certified interval [lb, ub] around H(A,B) from ProHD's directions and
+    projections (prohd_certificate).  ``lower``: device result of prohd_hd
+    with inner_full=True (a lower bound of H), or None.  Returns a dict."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[0]
+    ndirs = dirs.shape[0]
+    out = torch.zeros(CERT_DTYPE.itemsize, dtype=torch.uint8, device=A.device)
+    buf, nbytes = _ws(ws, int(lib().prohd_certificate_workspace_size(D, ndirs)))
+    _check(lib().prohd_certificate(A.data_ptr(), nA, B.data_ptr(), nB, D, dirs.data_ptr(), ndirs,
+                                   projA.data_ptr(), projB.data_ptr(), _ptr(lower), out.data_ptr(),
+                                   buf.data_ptr(), nbytes, _stream()))
+    arr = np.frombuffer(out.cpu().numpy().tobytes(), dtype=CERT_DTYPE)[0]
+    return {k: arr[k].item() for k in CERT_DTYPE.names}
 
 
 def select_scored(scoresA, sA, scoresB, sB, idxA, nselA, idxB, nselB, ws=None):

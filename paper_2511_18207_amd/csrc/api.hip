@@ -335,6 +335,26 @@ prohd_status prohd_centroid(const float* X, int64_t n, int32_t D, float* mean, v
   return centroid_run(X, n, D, mean, ws, ws_bytes, (hipStream_t)stream);
 }
 
+size_t prohd_certificate_workspace_size(int32_t D, int32_t ndirs) {
+  if (D < 1 || D > PROHD_MAX_DIM || ndirs < 1 || ndirs > PROHD_MAX_DIRS) return 0;
+  return cert_ws_bytes(D, ndirs);
+}
+
+prohd_status prohd_certificate(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                               const float* dirs, int32_t ndirs, const float* projA,
+                               const float* projB, const prohd_result* lower, prohd_cert* out,
+                               void* ws, size_t ws_bytes, void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (bad_ptr(dirs) || bad_ptr(projA) || bad_ptr(projB) || bad_ptr(out) || bad_ptr(ws))
+    return fail(PROHD_EINVAL, "dirs, projA, projB, out and ws must be non-null");
+  if (ndirs < 1) return fail(PROHD_EINVAL, "ndirs must be >= 1");
+  if (ndirs > PROHD_MAX_DIRS) return fail(PROHD_EUNSUPPORTED, "ndirs exceeds PROHD_MAX_DIRS (64)");
+  if (ws_bytes < cert_ws_bytes(D, ndirs)) return fail(PROHD_EWORKSPACE, "workspace too small");
+  return cert_run(A, nA, B, nB, D, dirs, ndirs, projA, projB, lower, out, ws, ws_bytes,
+                  (hipStream_t)stream);
+}
+
 prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
                                  const float* scoresB, int64_t nB, int32_t sB,
                                  int32_t* idxA, int64_t capA, int64_t* nselA,

@@ -116,6 +116,13 @@ size_t centroid_ws_bytes(int32_t D);
 prohd_status centroid_run(const float* X, int64_t n, int32_t D, float* mean, void* ws,
                           size_t ws_bytes, hipStream_t s);
 
+// Error certificate (k_cert.hip).
+size_t cert_ws_bytes(int32_t D, int32_t ndirs);
+prohd_status cert_run(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      const float* dirs, int32_t ndirs, const float* PA, const float* PB,
+                      const prohd_result* lower, prohd_cert* out, void* ws, size_t ws_bytes,
+                      hipStream_t s);
+
 // Learned proposal scorer (k_mlp.hip).
 size_t mlp_param_count(int32_t D);
 size_t mlp_ws_bytes(int64_t rows, int32_t D);

@@ -25,9 +25,19 @@ __global__ __launch_bounds__(kThreads) void colsum_part(const float* __restrict_
   const int64_t r1 = r0 + rows < n ? r0 + rows : n;
   for (int c0 = 0; c0 < D; c0 += kThreads) {
     const int c = c0 + (int)(threadIdx.x % (unsigned)(D >= kThreads ? kThreads : D));
-    double acc = 0.0;
-    if (g < groups && c < D)
-      for (int64_t r = r0 + g; r < r1; r += groups) acc += (double)X[r * D + c];
+    // four independent partial sums (fixed order), added at the end
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (g < groups && c < D) {
+      int64_t r = r0 + g;
+      for (; r + 3 * groups < r1; r += 4 * groups) {
+        a0 += (double)X[r * D + c];
+        a1 += (double)X[(r + groups) * D + c];
+        a2 += (double)X[(r + 2 * groups) * D + c];
+        a3 += (double)X[(r + 3 * groups) * D + c];
+      }
+      for (; r < r1; r += groups) a0 += (double)X[r * D + c];
+    }
+    const double acc = (a0 + a1) + (a2 + a3);
     red[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < (unsigned)(D >= kThreads ? kThreads : D) && c < D) {

@@ -274,6 +274,31 @@ def test_bounds_theorems_random():
             prev = f
 
 
+def test_delta_through_a_point_and_certificate():
+    # delta about a line through c equals delta about the origin after
+    # translating both sets by -c (hand values), and the certificate's
+    # interval contains the exact distance for lines through any point
+    A = np.array([[1.0, 0.0], [2.0, 0.0]])
+    B = np.array([[0.0, 1.0], [3.0, -2.0]])
+    c = np.array([0.5, -1.0])
+    assert oracle.delta(A, B, [1.0, 0.0], c) == pytest.approx(2.0)     # |y - (-1)| max: B[0]
+    assert oracle.delta(A, B, [0.0, 1.0], c) == pytest.approx(2.5)     # |x - 0.5| max: B[1]
+    assert oracle.delta(A + 7.0, B + 7.0, [1.0, 0.0], c + 7.0) == pytest.approx(2.0)
+    g = np.random.default_rng(19)
+    for trial in range(5):
+        D = [2, 3, 6, 10, 4][trial]
+        A = g.standard_normal((200, D)) * g.uniform(0.3, 2, D) + 5.0
+        B = g.standard_normal((180, D)) * g.uniform(0.3, 2, D) + 5.0 + g.standard_normal(D)
+        H = oracle.exact_hd(A, B)["H"]
+        U = g.standard_normal((4, D))
+        for cc in (None, np.vstack([A, B]).mean(0), g.standard_normal(D) * 3):
+            cert = oracle.certificate(A, B, U, cc)
+            assert cert["lb"] <= H + 1e-12 <= cert["ub"] + 2e-12
+        # the centroid line is at least as tight as the origin line here
+        assert oracle.certificate(A, B, U, np.vstack([A, B]).mean(0))["ub"] <= \
+            oracle.certificate(A, B, U)["ub"] + 1e-12
+
+
 # ------------------------------------------------ learned-proposal scorer
 def test_mlp_finite_differences():
     # the manual backward of the FP64 scorer against central differences
