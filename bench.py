@@ -343,6 +343,7 @@ def main():
     ap.add_argument("--learned-n", type=int, default=500_000)
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--batched-pairs", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (HBM-counter calibration)")
@@ -552,6 +553,29 @@ def main():
             log(f"prohd[{prec}, alpha x{mult}] {ms_:.2f} ms H={r_['H']:.6f} err={forms[-1]['rel_err_vs_exact']:.2e}")
         exact["precision_form"] = forms
 
+    # sampling baselines at ProHD's budget and an alpha sweep on random clouds
+    base = None
+    if not args.no_baselines:
+        from paper_2511_18207_amd import evaluate as EV
+        base = {}
+        for name in ("gauss5k", "mix200k"):
+            A2, B2, p2 = synth.workload(name, seed=args.seed)
+            a2, b2 = torch.from_numpy(A2).to(dev), torch.from_numpy(B2).to(dev)
+            H2 = ph.decode_result(ph.exact_hd(a2, b2, ws=ws))["H"]
+            base[name] = EV.baselines(a2, b2, H2, m=p2["m"], k=p2["k"], ws=ws)
+            del a2, b2
+        if exact is not None:
+            base["heavy2m"] = EV.baselines(dA, dB, exact["fp32"]["H"], alpha=alpha, m=m, ws=ws,
+                                           seeds=(0,))
+        for name, b_ in base.items():
+            c_ = b_["candidates"]
+            log(f"baselines {name}: prohd {c_['prohd_err']:.3e} random {c_['random_err_mean']:.3e} "
+                f"systematic {c_['systematic_err_mean']:.3e} (budget {c_['budget']})")
+        sweep = EV.alpha_sweep(lambda D_: synth.uniform_clouds(100_000, 100_000, D_, seed=7),
+                               (2, 4, 8, 16, 32, 64, 128), (0.001, 0.005, 0.01, 0.02, 0.05, 0.1), ws=ws)
+        base["alpha_sweep_uniform_clouds"] = sweep
+        log(f"alpha sweep: {len(sweep)} points")
+
     learned = None
     if not args.no_learned:
         del ws
@@ -596,6 +620,7 @@ def main():
         "roofline": roof,
         "exact": exact,
         "kernels": kernels,
+        "baselines": base,
         "learned": learned,
         "batched": batched,
         "cpu_baseline": cpu,
