@@ -57,7 +57,8 @@ def kernel_source_hash():
     with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", "k_hd.hip")) as fh:
         src = fh.read()
     h = hashlib.sha256()
-    for start in ("void dist_tile(", "int choose_split(", "prohd_status launch_tile("):
+    for start in ("void dist_tile_body(", "void dist_tile(", "int choose_split(",
+                  "prohd_status launch_tile("):
         h.update(_source_block(src, start).encode())
     return h.hexdigest()[:16]
 
@@ -271,7 +272,7 @@ def batched_form(args, dev):
         torch.cuda.synchronize()
         ph.profile_enable(False)
         kern = {}
-        for name in ("batch_gram", "batch_gram_reduce", "batch_eig", "batch_transpose", "batch_project",
+        for name in ("batch_gram", "batch_gram_reduce", "batch_eig", "batch_project",
                      "batch_select", "batch_compact", "batch_prep", "batch_tile", "batch_refine",
                      "batch_finalize", "batch_fill"):
             n, tot = ph.profile_read(name)
@@ -418,7 +419,7 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     res = ph.decode_result(out)
     kernels = {}
-    for name in ("stats_gram", "stats_reduce", "eig", "project_rows", "select_", "compact_",
+    for name in ("stats_gram", "stats_reduce", "eig", "project_mfma", "select_", "compact_",
                  "hd_prep", "hd_tile", "hd_refine", "hd_finalize"):
         n, tot = ph.profile_read(name)
         if n:

@@ -112,20 +112,12 @@ struct EigJob {
   int32_t m;
 };
 
-struct TransJob {
-  const float* dirs;
-  float* Ut;
-  int32_t ndirs;
-};
-
-// one 512-row tile of one set
-// (the directions are addressed as an offset from one restrict-qualified
-// base, so that their wave-uniform reads become scalar loads)
+// one 512-row tile of one set; dirs: the pair's ndirs x D directions
 struct ProjJob {
   const float* X;
   int64_t n;
   int64_t r0;
-  int64_t ut_off;   // Ut of the pair = Ubase + ut_off
+  const float* dirs;
   float* P;
   int32_t ndirs;
 };
@@ -168,10 +160,10 @@ prohd_status batch_gram_reduce(int DP, int D, const GramRedJob* jobs, int njobs,
 size_t eig_job_doubles(int DP);
 // narrow: 256-thread work-groups (several problems per compute unit), m < 32
 prohd_status batch_eig(int DP, int D, const EigJob* jobs, int njobs, bool narrow, hipStream_t s);
-prohd_status batch_transpose(int D, int DP, const TransJob* jobs, int njobs, hipStream_t s);
-// vec: float4 row loads (D % 4 == 0 and 16-byte aligned packed sets)
-prohd_status batch_project(int DP, int D, int ndirs, bool vec, const float* Ubase, const ProjJob* jobs,
-                           int njobs, int grid, hipStream_t s);
+// vec: float4 row loads (D % 4 == 0 and 16-byte aligned packed sets);
+// ndirs <= 33
+prohd_status batch_project(int DP, int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
+                           hipStream_t s);
 prohd_status batch_select(const SegJob* jobs, int njobs, hipStream_t s);
 prohd_status batch_compact(const CompactJob* jobs, int njobs, hipStream_t s);
 

@@ -81,7 +81,6 @@ struct PairWs {
   double* V;
   double* Y;
   float* dirs;
-  float* Ut;
   float* proj[2];
 };
 
@@ -181,7 +180,6 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
       w.V = ar.take<double>(eig_job_doubles(q.DP));
       w.Y = w.V + (size_t)q.DP * q.DP;
       w.dirs = ar.take<float>((size_t)(q.m + 1) * q.D);
-      w.Ut = ar.take<float>((size_t)32 * q.DP);
       w.proj[0] = ar.take<float>((size_t)(q.m + 1) * q.nA);
       w.proj[1] = ar.take<float>((size_t)(q.m + 1) * q.nB);
     }
@@ -236,15 +234,14 @@ prohd_status build(prohd_batch* b) {
   Tables T;
   struct Rec {
     int D, DP, m;
-    size_t gram_jobs, gram_items, red_jobs, eig_jobs, tr_jobs, proj_jobs, seg_jobs, cmp_jobs;
-    int n_gram_items, n_red, n_eig, n_tr, n_proj, n_seg, n_cmp;
+    size_t gram_jobs, gram_items, red_jobs, eig_jobs, proj_jobs, seg_jobs, cmp_jobs;
+    int n_gram_items, n_red, n_eig, n_proj, n_seg, n_cmp;
     size_t prep_jobs, prep_items, tile_jobs, tile_items, top_jobs, topc_jobs, ref_jobs, ref_items,
         fin_jobs;
     int n_prep_items, n_tile_items, n_top, n_topc, n_ref_items, n_fin;
   };
   std::vector<Rec> recs;
   const bool prohd = mode == PROHD_BATCH_PROHD;
-  const float* ubase = static_cast<const float*>(b->ws);   // 256-byte aligned workspace base
   for (int D : b->dims) {
     const std::vector<int> g = group(b, D);
     Rec r{};
@@ -257,7 +254,6 @@ prohd_status build(prohd_batch* b) {
       std::vector<GramJob> gj;
       std::vector<GramRedJob> rj;
       std::vector<EigJob> ej;
-      std::vector<TransJob> tj;
       std::vector<ProjJob> pj;
       std::vector<SegJob> sj;
       std::vector<CompactJob> cj;
@@ -277,11 +273,10 @@ prohd_status build(prohd_batch* b) {
         }
         rj.push_back(GramRedJob{w.gpart, w.spart, sl, q.nA, q.nB, w.C, w.u0});
         ej.push_back(EigJob{w.C, w.V, w.Y, w.u0, w.dirs, w.status, q.m});
-        tj.push_back(TransJob{w.dirs, w.Ut, q.m + 1});
         for (int s = 0; s < 2; ++s) {
           const int64_t n = s ? q.nB : q.nA;
           for (int64_t r0 = 0; r0 < n; r0 += 512)
-            pj.push_back(ProjJob{s ? Bp : Ap, n, r0, (int64_t)(w.Ut - ubase), w.proj[s], q.m + 1});
+            pj.push_back(ProjJob{s ? Bp : Ap, n, r0, w.dirs, w.proj[s], q.m + 1});
           for (int d = 0; d <= q.m; ++d) {
             const int32_t k = s ? q.kB[d] : q.kA[d];
             sj.push_back(SegJob{w.proj[s] + (size_t)d * n, n, nullptr, k, k, w.flags[s]});
@@ -302,8 +297,6 @@ prohd_status build(prohd_batch* b) {
       r.n_red = (int)rj.size();
       r.eig_jobs = T.add(ej);
       r.n_eig = (int)ej.size();
-      r.tr_jobs = T.add(tj);
-      r.n_tr = (int)tj.size();
       r.proj_jobs = T.add(pj);
       r.n_proj = (int)pj.size();
       r.seg_jobs = T.add(sj);
@@ -430,11 +423,10 @@ prohd_status build(prohd_batch* b) {
     Ls.push_back([=](hipStream_t s) {
       return batch_eig(r.DP, r.D, (const EigJob*)at(r.eig_jobs), r.n_eig, narrow, s);
     });
-    Ls.push_back([=](hipStream_t s) { return batch_transpose(r.D, r.DP, (const TransJob*)at(r.tr_jobs), r.n_tr, s); });
     const int pgrid = persist(r.n_proj, t.proj_mult);
     const bool vec = ((uintptr_t)b->A % 16 == 0) && ((uintptr_t)b->B % 16 == 0);
     Ls.push_back([=](hipStream_t s) {
-      return batch_project(r.DP, r.D, r.m + 1, vec, ubase, (const ProjJob*)at(r.proj_jobs), r.n_proj,
+      return batch_project(r.DP, r.D, r.m + 1, vec, (const ProjJob*)at(r.proj_jobs), r.n_proj,
                            pgrid, s);
     });
     Ls.push_back([=](hipStream_t s) { return batch_select((const SegJob*)at(r.seg_jobs), r.n_seg, s); });

@@ -3,16 +3,25 @@
 // both sets, plus the driver that chains statistics -> eigensolve ->
 // projection without a host synchronisation.
 //
-// project_rows streams the n x D rows once from HBM: a work-group of 512
-// threads owns 512 rows (one per thread) and walks their columns in chunks of
-// 32 (coalesced 128-byte row segments staged through LDS, the next chunk
-// prefetched in registers while the current one is used).  The directions
-// (up to 32 per launch) are stored k-major and read as wave-uniform scalar
-// loads, so a k-step is one LDS read of x feeding 8-32 FMAs with scalar
-// operands; the finished row writes P[d * n + i] (coalesced across the wave
-// per direction).
+// The projection of n rows onto up to 33 directions is a skinny product
+// (n x D) (D x nd) done on the FP32 matrix cores: v_mfma_f32_16x16x4f32 with
+// the directions as the 16-row A operand and 16 points as the B operand, so
+// the 16 x 16 result block holds direction-major values that store straight
+// into P[d * n + i] (16 consecutive points = 64 contiguous bytes per
+// direction).  A wave owns 16 rows at a time and reads them straight from HBM
+// into registers: lane (p, g) = (lane % 16, lane / 16) holds the float4s
+// x[p][16 t + 4 g .. + 3], t = 0 .. D/16 - 1, so the four lane groups of a
+// point read 64 contiguous bytes per load and the contraction index k is
+// permuted identically for both operands (MFMA step (t, c) contracts
+// k = 16 t + 4 g + c in lane group g).  The directions sit in LDS for the
+// whole launch (one copy per work-group, row stride DP + 4 so that the 16
+// directions of a read hit distinct banks).  Direction counts of 16 n + 1
+// (the default m + 1 = 17) take the last direction on the vector ALUs with
+// the same operands, reduced over the four lane groups at the end.
+// No LDS barrier sits in the row loop; latency is hidden by occupancy.
 // This pass is bound by HBM bandwidth: 4 D bytes read and 4 (m+1) bytes
-// written per row.
+// written per row; the matrix cores need about 40 % of their peak at the
+// HBM rate for 17 directions at D = 256.
 
 #include "batch.h"
 #include "common.h"
@@ -29,233 +38,186 @@ prohd_status eig_run(double* C, int32_t D, int32_t m, const double* u0, float* d
 
 namespace {
 
-constexpr int kTileRows = 512;  // rows per tile: one per thread
-constexpr int kThreads = 512;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Directions in blocks of 32: block b (directions 32b..) is stored k-major,
-// Ut[32 b DP + k nd8 + j] = dirs[32 b + j][k], nd8 = 8 ceil(nd/8) for the
-// nd directions of that block; zero for k >= D.
-__global__ void transpose_dirs(const float* __restrict__ dirs, int ndirs, int D, int DP,
-                               float* __restrict__ Ut) {
-  const int nblk = (ndirs + 31) / 32;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nblk * 32 * DP; e += gridDim.x * blockDim.x) {
-    const int b = e / (32 * DP);
-    const int r = e - b * 32 * DP;
-    const int nd = min(32, ndirs - 32 * b);
-    const int nd8 = 8 * ((nd + 7) / 8);
-    const int k = r / nd8, j = r - k * nd8;
-    if (k >= DP) continue;
-    Ut[(size_t)b * 32 * DP + r] = (j < nd && k < D) ? dirs[(size_t)(32 * b + j) * D + k] : 0.f;
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBlockRows = 16;     // rows per wave step (the MFMA's N)
+constexpr int kJobRows = 512;      // rows per batched job
+constexpr int kMaxGroup = 33;      // directions per launch: 2 MFMA blocks + 1 on the ALUs
+constexpr int kBufferFlags = 0x00020000;   // buffer descriptor word 3 (32-bit data, CDNA)
+
+// directions [d0, d0 + nd) of row-major dirs (ndirs x D) -> LDS rows of
+// stride DP + 4, zero beyond nd and beyond D
+template <int DP, int NDL>
+__device__ __forceinline__ void stage_dirs(float* us, const float* __restrict__ dirs, int d0, int nd,
+                                           int D) {
+  constexpr int S = DP + 4;
+  for (int e = threadIdx.x; e < NDL * DP; e += kThreads) {
+    const int d = e / DP, k = e - d * DP;
+    us[d * S + k] = (d < nd && k < D) ? dirs[(size_t)(d0 + d) * D + k] : 0.f;
   }
 }
 
-template <int DP, int NG, bool VEC>
-__global__ __launch_bounds__(kThreads) void project_rows(const float* __restrict__ A, int64_t nA,
+// One wave: rows [r0, r0 + 16) of X (n rows) onto the nd staged directions;
+// P points at the projection of the first staged direction (row stride n).
+// The rows are read with buffer loads whose range is the block's live rows,
+// so a dead lane (row >= n) reads zeros without a branch; a column k >= D of
+// a live row reads the next row or zero and meets a zero direction entry
+// (the staged directions are zero beyond D).  Inputs are taken to be finite.
+template <int DP, int NB, bool TAIL, bool VEC>
+__device__ __forceinline__ void proj_block(const float* __restrict__ X, int64_t n, int64_t r0, int D,
+                                           const float* us, int nd, float* __restrict__ P) {
+  constexpr int S = DP + 4;
+  constexpr int T = DP / 16;
+  const int lane = threadIdx.x & 63;
+  const int p = lane & 15, g = lane >> 4;
+  const int live_rows = (int)min<int64_t>(kBlockRows, n - r0);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(X + r0 * D), 0, live_rows * D * 4, kBufferFlags);
+  const int voff = (p * D + 4 * g) * 4;
+  float4 x[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (VEC) {
+      x[t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 64 * t, 0, 0));
+    } else {
+      x[t] = make_float4(
+          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 64 * t + 0, 0, 0)),
+          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 64 * t + 4, 0, 0)),
+          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 64 * t + 8, 0, 0)),
+          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 64 * t + 12, 0, 0)));
+    }
+  }
+  const int64_t row = r0 + p;
+  const bool live = p < live_rows;
+  floatx4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float tl = 0.f;
+  // direction operands of step t, read one step ahead; the scheduling
+  // barrier keeps the compiler from hoisting every LDS read of the block
+  // (that would double the registers and halve the occupancy)
+  const float* ua = us + p * S + 4 * g;
+  const float* ut = us + 16 * NB * S + 4 * g;
+  float4 a[NB], at;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) a[b] = *reinterpret_cast<const float4*>(ua + 16 * b * S);
+  if (TAIL) at = *reinterpret_cast<const float4*>(ut);
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    float4 an[NB], atn;
+    if (t + 1 < T) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        an[b] = *reinterpret_cast<const float4*>(ua + 16 * b * S + 16 * (t + 1));
+      if (TAIL) atn = *reinterpret_cast<const float4*>(ut + 16 * (t + 1));
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].x, x[t].x, acc[b], 0, 0, 0);
+      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].y, x[t].y, acc[b], 0, 0, 0);
+      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].z, x[t].z, acc[b], 0, 0, 0);
+      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].w, x[t].w, acc[b], 0, 0, 0);
+    }
+    if (TAIL) {
+      tl = fmaf(at.x, x[t].x, tl);
+      tl = fmaf(at.y, x[t].y, tl);
+      tl = fmaf(at.z, x[t].z, tl);
+      tl = fmaf(at.w, x[t].w, tl);
+      asm volatile("" : "+v"(tl));   // keep the chain in step with the MFMAs
+    }
+    if (t + 1 < T) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) a[b] = an[b];
+      if (TAIL) at = atn;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // result block b: lane (p, g) holds directions 16 b + 4 g + v of point p
+  float* q = P + (live ? row : 0);
+  if (live) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int d = 16 * b + 4 * g + v;
+        if (d < nd) q[(int64_t)d * n] = acc[b][v];
+      }
+  }
+  if (TAIL) {
+    tl += __shfl_xor(tl, 16);
+    tl += __shfl_xor(tl, 32);
+    if (live && g == 0 && 16 * NB < nd) q[(int64_t)(16 * NB) * n] = tl;
+  }
+}
+
+// Single pair: every wave walks 16-row blocks of A, then B (blocks
+// w, w + W, ... over W waves in the grid); directions [d0, d0 + nd).
+template <int DP, int NB, bool TAIL, bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void project_mfma(const float* __restrict__ A, int64_t nA,
                                                          const float* __restrict__ B, int64_t nB,
-                                                         int D, const float* __restrict__ Ut,
-                                                         int ndirs,
-                                                         float* __restrict__ PA,
+                                                         int D, const float* __restrict__ dirs,
+                                                         int d0, int nd, float* __restrict__ PA,
                                                          float* __restrict__ PB) {
-  constexpr int KC = DP < 32 ? DP : 32;             // columns per chunk
-  constexpr int NCH = DP / KC;                      // chunks per row
-  constexpr int ST = KC + 4;                        // LDS row stride (floats)
-  constexpr int ND = 8 * NG;                        // directions, padded
-  constexpr int F4R = KC / 4;                       // float4 per row chunk
-  constexpr int NF = kTileRows * F4R / kThreads;    // float4 per thread per chunk
-  __shared__ __attribute__((aligned(16))) float xt[kTileRows * ST];
-  const int tid = threadIdx.x;
-  const int64_t tilesA = (nA + kTileRows - 1) / kTileRows;
-  const int64_t tiles = tilesA + (nB + kTileRows - 1) / kTileRows;
-
-  float4 buf[NF];
-  // chunk c of tile tl: row f / F4R, float4 f % F4R of columns [c KC, c KC + KC)
-  auto load = [&](int64_t tl, int c) {
-    const bool inA = tl < tilesA;
-    const float* X = inA ? A : B;
+  constexpr int NDL = 16 * NB + (TAIL ? 1 : 0);
+  __shared__ __attribute__((aligned(16))) float us[NDL * (DP + 4)];
+  stage_dirs<DP, NDL>(us, dirs, d0, nd, D);
+  __syncthreads();
+  const int64_t bA = (nA + kBlockRows - 1) / kBlockRows;
+  const int64_t nblk = bA + (nB + kBlockRows - 1) / kBlockRows;
+  const int64_t W = (int64_t)gridDim.x * kWaves;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t b = (int64_t)blockIdx.x * kWaves + wave; b < nblk; b += W) {
+    const bool inA = b < bA;
     const int64_t n = inA ? nA : nB;
-    const int64_t r0 = (inA ? tl : tl - tilesA) * kTileRows;
-    const int rows = (int)min<int64_t>(kTileRows, n - r0);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const int f = tid + kThreads * i;
-      const int r = f / F4R, j = f - r * F4R;
-      const int k = c * KC + 4 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < rows) {
-        const float* src = X + (r0 + r) * D + k;
-        if (VEC) {
-          if (k < D) v = *reinterpret_cast<const float4*>(src);
-        } else {
-          if (k + 0 < D) v.x = src[0];
-          if (k + 1 < D) v.y = src[1];
-          if (k + 2 < D) v.z = src[2];
-          if (k + 3 < D) v.w = src[3];
-        }
-      }
-      buf[i] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const int f = tid + kThreads * i;
-      const int r = f / F4R, j = f - r * F4R;
-      *reinterpret_cast<float4*>(&xt[r * ST + 4 * j]) = buf[i];
-    }
-  };
-
-  int64_t tl = blockIdx.x;
-  if (tl < tiles) load(tl, 0);
-  for (; tl < tiles; tl += gridDim.x) {
-    float acc[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) acc[d] = 0.f;
-    for (int c = 0; c < NCH; ++c) {
-      __syncthreads();
-      store();
-      __syncthreads();
-      // prefetch the next chunk (or the first chunk of the next tile)
-      if (c + 1 < NCH) load(tl, c + 1);
-      else if (tl + gridDim.x < tiles) load(tl + gridDim.x, 0);
-      // row tid: x from LDS; direction values are wave-uniform scalar loads
-      // (all waves work on the same chunk, so its KC x ND values stay in the
-      // scalar cache)
-      const float* xr = &xt[tid * ST];
-      const float* uc = Ut + (size_t)(c * KC) * ND;
-#pragma unroll 2
-      for (int k4 = 0; k4 < KC / 4; ++k4) {
-        const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
-        const float xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const float* uk = uc + (4 * k4 + kk) * ND;
-#pragma unroll
-          for (int d4 = 0; d4 < ND / 4; ++d4) {
-            const float4 u = *reinterpret_cast<const float4*>(uk + 4 * d4);
-            acc[4 * d4 + 0] = fmaf(xs[kk], u.x, acc[4 * d4 + 0]);
-            acc[4 * d4 + 1] = fmaf(xs[kk], u.y, acc[4 * d4 + 1]);
-            acc[4 * d4 + 2] = fmaf(xs[kk], u.z, acc[4 * d4 + 2]);
-            acc[4 * d4 + 3] = fmaf(xs[kk], u.w, acc[4 * d4 + 3]);
-          }
-        }
-      }
-    }
-    const bool inA = tl < tilesA;
-    const int64_t n = inA ? nA : nB;
-    const int64_t row = (inA ? tl : tl - tilesA) * kTileRows + tid;
-    float* P = inA ? PA : PB;
-    if (row < n) {
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-        if (d < ndirs) P[(size_t)d * n + row] = acc[d];
-    }
+    float* P = inA ? PA + (size_t)d0 * nA : PB + (size_t)d0 * nB;
+    proj_block<DP, NB, TAIL, VEC>(inA ? A : B, n, (inA ? b : b - bA) * kBlockRows, D, us, nd, P);
   }
 }
 
-// Batched: one item = one 512-row tile of one set of one pair (directions
-// of that pair, at most 32, in Ut as above).  Same per-row arithmetic as
-// project_rows; the next chunk of the tile is prefetched in registers.
-template <int DP, int NG, bool VEC>
-__global__ __launch_bounds__(kThreads) void project_batch(const ProjJob* __restrict__ jobs, int njobs,
-                                                          int D, const float* __restrict__ Ubase) {
-  constexpr int KC = DP < 32 ? DP : 32;
-  constexpr int NCH = DP / KC;
-  constexpr int ST = KC + 4;
-  constexpr int ND = 8 * NG;
-  constexpr int F4R = KC / 4;
-  constexpr int NF = kTileRows * F4R / kThreads;
-  __shared__ __attribute__((aligned(16))) float xt[kTileRows * ST];
-  const int tid = threadIdx.x;
+// Batched: one item = one 512-row tile of one set of one pair; the pair's
+// directions (all of them, at most 33) are staged per item.
+template <int DP, int NB, bool TAIL, bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void project_batch(const ProjJob* __restrict__ jobs, int njobs,
+                                                          int D) {
+  constexpr int NDL = 16 * NB + (TAIL ? 1 : 0);
+  __shared__ __attribute__((aligned(16))) float us[NDL * (DP + 4)];
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const ProjJob j = jobs[it];
-    const int rows = (int)min<int64_t>(kTileRows, j.n - j.r0);
-    float4 buf[NF];
-    auto load = [&](int c) {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const int f = tid + kThreads * i;
-        const int r = f / F4R, q = f - r * F4R;
-        const int k = c * KC + 4 * q;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < rows) {
-          const float* src = j.X + (j.r0 + r) * D + k;
-          if (VEC) {
-            if (k < D) v = *reinterpret_cast<const float4*>(src);
-          } else {
-            if (k + 0 < D) v.x = src[0];
-            if (k + 1 < D) v.y = src[1];
-            if (k + 2 < D) v.z = src[2];
-            if (k + 3 < D) v.w = src[3];
-          }
-        }
-        buf[i] = v;
-      }
-    };
-    float acc[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) acc[d] = 0.f;
-    load(0);
-    for (int c = 0; c < NCH; ++c) {
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const int f = tid + kThreads * i;
-        const int r = f / F4R, q = f - r * F4R;
-        *reinterpret_cast<float4*>(&xt[r * ST + 4 * q]) = buf[i];
-      }
-      __syncthreads();
-      if (c + 1 < NCH) load(c + 1);
-      const float* xr = &xt[tid * ST];
-      const float* uc = Ubase + j.ut_off + (size_t)(c * KC) * ND;
-#pragma unroll 2
-      for (int k4 = 0; k4 < KC / 4; ++k4) {
-        const float4 x = *reinterpret_cast<const float4*>(xr + 4 * k4);
-        const float xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const float* uk = uc + (4 * k4 + kk) * ND;
-#pragma unroll
-          for (int d4 = 0; d4 < ND / 4; ++d4) {
-            const float4 u = *reinterpret_cast<const float4*>(uk + 4 * d4);
-            acc[4 * d4 + 0] = fmaf(xs[kk], u.x, acc[4 * d4 + 0]);
-            acc[4 * d4 + 1] = fmaf(xs[kk], u.y, acc[4 * d4 + 1]);
-            acc[4 * d4 + 2] = fmaf(xs[kk], u.z, acc[4 * d4 + 2]);
-            acc[4 * d4 + 3] = fmaf(xs[kk], u.w, acc[4 * d4 + 3]);
-          }
-        }
-      }
-    }
-    const int64_t row = j.r0 + tid;
-    if (tid < rows) {
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-        if (d < j.ndirs) j.P[(size_t)d * j.n + row] = acc[d];
+    __syncthreads();   // the previous item's reads of us are done
+    stage_dirs<DP, NDL>(us, j.dirs, 0, j.ndirs, D);
+    __syncthreads();
+    for (int b = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); b < kJobRows / kBlockRows;
+         b += kWaves) {
+      const int64_t r0 = j.r0 + (int64_t)b * kBlockRows;
+      if (r0 >= j.n) break;
+      proj_block<DP, NB, TAIL, VEC>(j.X, j.n, r0, D, us, j.ndirs, j.P);
     }
   }
 }
 
-// Batched transpose: one work-group per job.
-__global__ void transpose_batch(const TransJob* __restrict__ jobs, int njobs, int D, int DP) {
-  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
-    const TransJob j = jobs[it];
-    const int nblk = (j.ndirs + 31) / 32;
-    for (int e = threadIdx.x; e < nblk * 32 * DP; e += blockDim.x) {
-      const int b = e / (32 * DP);
-      const int r = e - b * 32 * DP;
-      const int nd = min(32, j.ndirs - 32 * b);
-      const int nd8 = 8 * ((nd + 7) / 8);
-      const int k = r / nd8, q = r - k * nd8;
-      if (k >= DP) continue;
-      j.Ut[(size_t)b * 32 * DP + r] = (q < nd && k < D) ? j.dirs[(size_t)(32 * b + q) * D + k] : 0.f;
-    }
-  }
+// (NB, TAIL) for a group of nd <= 33 directions
+inline void group_shape(int nd, int& nb, bool& tail) {
+  nb = nd <= 17 ? 1 : 2;
+  tail = nd == 17 || nd == 33;
+}
+
+// persistent grid: resident work-groups per CU (from the kernel's own
+// register and LDS use) times the CU count, capped by the work
+template <typename K>
+int resident_grid(K kernel, int64_t work_groups) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 2;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(work_groups, (int64_t)per_cu * cu_count()));
 }
 
 struct ProjLayout {
   int32_t* status;
   double* C;
   double* u0;
-  float* Ut;
   void* sub;
   size_t sub_bytes;
 };
@@ -263,53 +225,51 @@ struct ProjLayout {
 ProjLayout proj_layout(Arena& ar, int64_t nA, int64_t nB, int D, int ndirs) {
   ProjLayout L;
   const int DP = pad_dim(D);
-  const int ndp = ((ndirs + 7) / 8) * 8;
   L.status = ar.take<int32_t>(64);
   L.C = ar.take<double>((size_t)DP * DP);
   L.u0 = ar.take<double>(DP);
-  L.Ut = ar.take<float>((size_t)DP * ((ndirs + 31) / 32) * 32);
   L.sub_bytes = std::max(stats_ws_bytes(nA, nB, D), eig_ws_bytes(D, ndirs - 1));
   L.sub = ar.take<char>(L.sub_bytes);
   return L;
 }
 
-template <int DP, int NG>
-prohd_status launch_project_ng(const float* A, int64_t nA, const float* B, int64_t nB, int D,
-                               const float* Ut, int ndirs, float* PA, float* PB, hipStream_t s) {
-  const int64_t tiles = cdiv(nA, kTileRows) + cdiv(nB, kTileRows);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cu_count()));
+template <int DP, int NB, bool TAIL>
+prohd_status launch_group(const float* A, int64_t nA, const float* B, int64_t nB, int D,
+                          const float* dirs, int d0, int nd, float* PA, float* PB, hipStream_t s) {
+  const int64_t wgs = cdiv(cdiv(nA, kBlockRows) + cdiv(nB, kBlockRows), kWaves);
   const bool vec = (D % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
   if (vec) {
-    PROHD_LAUNCH("project_rows", (project_rows<DP, NG, true>), dim3(grid), dim3(kThreads), 0, s, A, nA,
-                 B, nB, D, Ut, ndirs, PA, PB);
+    static const int per = resident_grid(project_mfma<DP, NB, TAIL, true>, 1 << 30);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, per));
+    PROHD_LAUNCH("project_mfma", (project_mfma<DP, NB, TAIL, true>), dim3(grid), dim3(kThreads), 0, s,
+                 A, nA, B, nB, D, dirs, d0, nd, PA, PB);
   } else {
-    PROHD_LAUNCH("project_rows", (project_rows<DP, NG, false>), dim3(grid), dim3(kThreads), 0, s, A,
-                 nA, B, nB, D, Ut, ndirs, PA, PB);
+    static const int per = resident_grid(project_mfma<DP, NB, TAIL, false>, 1 << 30);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, per));
+    PROHD_LAUNCH("project_mfma", (project_mfma<DP, NB, TAIL, false>), dim3(grid), dim3(kThreads), 0, s,
+                 A, nA, B, nB, D, dirs, d0, nd, PA, PB);
   }
   return PROHD_OK;
 }
 
-// Direction groups of 8 per launch: 1, 2, 3 or 4 groups (up to 32 directions).
+// Directions in groups of at most 33 per launch.
 template <int DP>
 prohd_status launch_project(const float* A, int64_t nA, const float* B, int64_t nB, int D,
-                            const float* Ut, int ndirs, int ndp, float* PA, float* PB,
-                            hipStream_t s) {
-  for (int d0 = 0; d0 < ndirs; d0 += 32) {
-    const int nd = std::min(32, ndirs - d0);
-    const int ng = (nd + 7) / 8;
-    const float* U = Ut + (size_t)d0 * DP;   // Ut is stored per 32-direction block
-    float* pa = PA + (size_t)d0 * nA;
-    float* pb = PB + (size_t)d0 * nB;
+                            const float* dirs, int ndirs, float* PA, float* PB, hipStream_t s) {
+  for (int d0 = 0; d0 < ndirs; d0 += kMaxGroup) {
+    const int nd = std::min(kMaxGroup, ndirs - d0);
+    int nb;
+    bool tail;
+    group_shape(nd, nb, tail);
     prohd_status r;
-    switch (ng) {
-      case 1: r = launch_project_ng<DP, 1>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
-      case 2: r = launch_project_ng<DP, 2>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
-      case 3: r = launch_project_ng<DP, 3>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
-      default: r = launch_project_ng<DP, 4>(A, nA, B, nB, D, U, nd, pa, pb, s); break;
-    }
+    if (nb == 1)
+      r = tail ? launch_group<DP, 1, true>(A, nA, B, nB, D, dirs, d0, nd, PA, PB, s)
+               : launch_group<DP, 1, false>(A, nA, B, nB, D, dirs, d0, nd, PA, PB, s);
+    else
+      r = tail ? launch_group<DP, 2, true>(A, nA, B, nB, D, dirs, d0, nd, PA, PB, s)
+               : launch_group<DP, 2, false>(A, nA, B, nB, D, dirs, d0, nd, PA, PB, s);
     if (r) return r;
   }
-  (void)ndp;
   return PROHD_OK;
 }
 
@@ -337,64 +297,55 @@ prohd_status project_run(const float* A, int64_t nA, const float* B, int64_t nB,
     r = eig_run(L.C, D, m, L.u0, dirs, evals, st, L.sub, L.sub_bytes, s);
     if (r) return r;
   }
-  const int DP = pad_dim(D);
-  const int ndp = ((ndirs + 7) / 8) * 8;
-  PROHD_LAUNCH("project_dirs", transpose_dirs, dim3(std::max(1, std::min(64, DP * ndp / 256))),
-               dim3(256), 0, s, dirs, ndirs, D, DP, L.Ut);
-  switch (DP) {
-    case 16: return launch_project<16>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
-    case 32: return launch_project<32>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
-    case 64: return launch_project<64>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
-    case 128: return launch_project<128>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
-    case 256: return launch_project<256>(A, nA, B, nB, D, L.Ut, ndirs, ndp, projA, projB, s);
+  switch (pad_dim(D)) {
+    case 16: return launch_project<16>(A, nA, B, nB, D, dirs, ndirs, projA, projB, s);
+    case 32: return launch_project<32>(A, nA, B, nB, D, dirs, ndirs, projA, projB, s);
+    case 64: return launch_project<64>(A, nA, B, nB, D, dirs, ndirs, projA, projB, s);
+    case 128: return launch_project<128>(A, nA, B, nB, D, dirs, ndirs, projA, projB, s);
+    case 256: return launch_project<256>(A, nA, B, nB, D, dirs, ndirs, projA, projB, s);
     default: return fail(PROHD_EUNSUPPORTED, "D exceeds PROHD_MAX_DIM");
   }
 }
 
-template <int DP, int NG>
-prohd_status batch_project_ng(int D, bool vec, const float* U, const ProjJob* jobs, int njobs, int grid,
-                              hipStream_t s) {
+template <int DP, int NB, bool TAIL>
+prohd_status batch_project_g(int D, bool vec, const ProjJob* jobs, int njobs, int grid, hipStream_t s) {
   if (vec) {
-    PROHD_LAUNCH("batch_project", (project_batch<DP, NG, true>), dim3(grid), dim3(kThreads), 0, s, jobs,
-                 njobs, D, U);
+    PROHD_LAUNCH("batch_project", (project_batch<DP, NB, TAIL, true>), dim3(grid), dim3(kThreads), 0, s,
+                 jobs, njobs, D);
   } else {
-    PROHD_LAUNCH("batch_project", (project_batch<DP, NG, false>), dim3(grid), dim3(kThreads), 0, s, jobs,
-                 njobs, D, U);
+    PROHD_LAUNCH("batch_project", (project_batch<DP, NB, TAIL, false>), dim3(grid), dim3(kThreads), 0,
+                 s, jobs, njobs, D);
   }
   return PROHD_OK;
 }
 
 template <int DP>
-prohd_status batch_project_dp(int D, int ndirs, bool vec, const float* U, const ProjJob* jobs, int njobs,
-                              int grid, hipStream_t s) {
-  switch ((ndirs + 7) / 8) {
-    case 1: return batch_project_ng<DP, 1>(D, vec, U, jobs, njobs, grid, s);
-    case 2: return batch_project_ng<DP, 2>(D, vec, U, jobs, njobs, grid, s);
-    case 3: return batch_project_ng<DP, 3>(D, vec, U, jobs, njobs, grid, s);
-    case 4: return batch_project_ng<DP, 4>(D, vec, U, jobs, njobs, grid, s);
-    default: return fail(PROHD_EUNSUPPORTED, "batched projection: more than 32 directions");
-  }
+prohd_status batch_project_dp(int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
+                              hipStream_t s) {
+  if (ndirs < 1 || ndirs > kMaxGroup)
+    return fail(PROHD_EUNSUPPORTED, "batched projection: more than 33 directions");
+  int nb;
+  bool tail;
+  group_shape(ndirs, nb, tail);
+  if (nb == 1)
+    return tail ? batch_project_g<DP, 1, true>(D, vec, jobs, njobs, grid, s)
+                : batch_project_g<DP, 1, false>(D, vec, jobs, njobs, grid, s);
+  return tail ? batch_project_g<DP, 2, true>(D, vec, jobs, njobs, grid, s)
+              : batch_project_g<DP, 2, false>(D, vec, jobs, njobs, grid, s);
 }
 
-prohd_status batch_project(int DP, int D, int ndirs, bool vec, const float* U, const ProjJob* jobs,
-                           int njobs, int grid, hipStream_t s) {
+prohd_status batch_project(int DP, int D, int ndirs, bool vec, const ProjJob* jobs, int njobs, int grid,
+                           hipStream_t s) {
   if (njobs <= 0) return PROHD_OK;
   vec = vec && D % 4 == 0;
   switch (DP) {
-    case 16: return batch_project_dp<16>(D, ndirs, vec, U, jobs, njobs, grid, s);
-    case 32: return batch_project_dp<32>(D, ndirs, vec, U, jobs, njobs, grid, s);
-    case 64: return batch_project_dp<64>(D, ndirs, vec, U, jobs, njobs, grid, s);
-    case 128: return batch_project_dp<128>(D, ndirs, vec, U, jobs, njobs, grid, s);
-    case 256: return batch_project_dp<256>(D, ndirs, vec, U, jobs, njobs, grid, s);
+    case 16: return batch_project_dp<16>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 32: return batch_project_dp<32>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 64: return batch_project_dp<64>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 128: return batch_project_dp<128>(D, ndirs, vec, jobs, njobs, grid, s);
+    case 256: return batch_project_dp<256>(D, ndirs, vec, jobs, njobs, grid, s);
     default: return fail(PROHD_EUNSUPPORTED, "batched: unsupported padded dimension");
   }
-}
-
-prohd_status batch_transpose(int D, int DP, const TransJob* jobs, int njobs, hipStream_t s) {
-  if (njobs <= 0) return PROHD_OK;
-  const int grid = std::min(njobs, 8 * cu_count());
-  PROHD_LAUNCH("batch_transpose", transpose_batch, dim3(grid), dim3(256), 0, s, jobs, njobs, D, DP);
-  return PROHD_OK;
 }
 
 }  // namespace prohd
