@@ -9,16 +9,24 @@
 // covariance is then C = (G - N mu_w mu_w^T) / (N - 1) with mu_w the mean of
 // the shifted rows.
 //
-// gram_partial: one work-group per slice of rows of one set (12 waves at
-// D >= 128, else 8).  For every group
-// of four rows, lane l holds w[row l/16][16*I + l%16] for each 16-column block
-// I; the 16x16 Gram block (I, J) gains one v_mfma_f64_16x16x4_f64 with A
-// operand = block I and B operand = block J (the four rows are the k index).
-// Only blocks with I <= J are formed.  The work-group writes its partial
-// blocks and per-set column sums; gram_reduce adds the partials in a fixed
-// order (deterministic) and writes C (padded to DP x DP: rows/columns >= D
-// hold -1 on the diagonal, which keeps those padding directions below every
-// real eigenvalue), the centroid axis (dirs row 0) and the status word.
+// gram_partial: TSPLIT work-groups per slice of rows of one set, each owning
+// a share of the upper-triangle super-blocks (SB x SB blocks of 16 x 16),
+// one super-block per wave.  Rows arrive in chunks of RC rows copied
+// straight from HBM into LDS as float32 (buffer loads into LDS, no
+// registers), double-buffered so that the next chunk streams in while the
+// matrix cores work on the current one; one barrier per chunk.  For every
+// group of four rows, lane l reads w[row l/16][16*I + l%16] for its blocks,
+// converts to float64 and subtracts the shift (exact), and the 16x16 Gram
+// block (I, J) gains one v_mfma_f64_16x16x4_f64 with A operand = block I and
+// B operand = block J (the four rows are the k index).  Only blocks with
+// I <= J are formed.  The waves that own a diagonal super-block also add the
+// shifted values into the per-set column sums (each column has exactly one
+// diagonal super-block) and check them for non-finite input.  The
+// work-group writes its partial blocks and its columns' sums; gram_reduce
+// adds the partials in a fixed order (deterministic) and writes C (padded
+// to DP x DP: rows/columns >= D hold -1 on the diagonal, which keeps those
+// padding directions below every real eigenvalue), the centroid axis (dirs
+// row 0) and the status word.
 
 #include <utility>
 
@@ -38,18 +46,17 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int DP>
 struct GramShape {
-  static constexpr int WAVES = DP >= 128 ? 12 : 8;      // waves per work-group
-  static constexpr int THREADS = 64 * WAVES;
-  static constexpr int RC = DP >= 128 ? 48 : 32;        // rows staged per chunk
   static constexpr int NB = DP / 16;                    // 16-column blocks
   static constexpr int T = NB * (NB + 1) / 2;           // blocks with I <= J
-  static constexpr int SB = NB >= 2 ? 2 : 1;            // super-block edge (blocks)
+  static constexpr int SB = DP >= 128 ? 2 : 1;          // super-block edge (blocks)
   static constexpr int NS = NB / SB;                    // super-blocks per edge
   static constexpr int TS = NS * (NS + 1) / 2;          // upper super-blocks
   static constexpr int TSPLIT = DP >= 256 ? 3 : 1;      // work-groups per row slice
   static constexpr int TSW = (TS + TSPLIT - 1) / TSPLIT;  // super-blocks per work-group
-  static constexpr int SPW = (TSW + WAVES - 1) / WAVES;   // super-blocks per wave
-  static constexpr int ST = DP + 16;                    // LDS row stride (doubles)
+  static constexpr int WAVES = TSW > 4 ? TSW : 4;       // one super-block per wave
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int RC = 32;                         // rows per chunk
+  static constexpr int CHUNK = RC * DP;                 // floats per LDS buffer
 };
 
 // Upper-triangle index of block (I, J), I <= J, rows enumerated in order.
@@ -90,140 +97,137 @@ __device__ __forceinline__ void block_ij(int t, int nb, int& I, int& J) {
 }
 
 // Gram partial of rows [r_begin, r_end) of X, shifted by the row `shift`;
-// super-block share ts of TSPLIT; writes gp (T x 256) and sp (2 DP sums).
+// super-block share ts of TSPLIT; writes gp (T x 256) and, for the columns
+// of its diagonal super-blocks, sp (2 DP sums: set A's, then set B's).
 template <int DP>
 __device__ __forceinline__ void gram_body(const float* __restrict__ shift, const float* __restrict__ X,
                                           int64_t r_begin, int64_t r_end, int D, int ts, bool setA,
                                           double* __restrict__ gp, double* __restrict__ spo,
                                           int32_t* __restrict__ status) {
   using S = GramShape<DP>;
-  constexpr int NT = S::THREADS;
   constexpr int RC = S::RC;
-  constexpr int PER = RC * DP / NT;           // staged elements per thread
-  static_assert(NT % DP == 0 && (RC * DP) % NT == 0 && RC % 4 == 0, "staging shape");
-  constexpr int ST = S::ST;
-  __shared__ double wbuf[RC * ST];            // shifted rows, float64
-  __shared__ double sred[NT];
+  constexpr int SB = S::SB;
+  __shared__ __attribute__((aligned(16))) float xs[2][S::CHUNK];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int col = lane & 15;   // column within a 16-block
   const int rsub = lane >> 4;  // row within a group of four
+  const bool vec = (D & 3) == 0;
 
-  // staging: thread tid handles elements e = tid + NT i of a chunk, i.e.
-  // row tid/DP + (NT/DP) i and the fixed column tid % DP (DP divides NT).
-  const int mycol = tid % DP;
-  const int myrow = tid / DP;
-  constexpr int RSTEP = NT / DP;
-  const double sh = (mycol < D) ? (double)shift[mycol] : 0.0;   // shift s = A[0]
-  double sum = 0.0;
-  bool bad = false;
-  float raw[PER];
-  auto fetch = [&](int64_t r0) {
-    // one per-thread base pointer, 32-bit offsets stepping by a uniform stride
-    const float* base = X + r0 * D + mycol;
-    const int lim = (int)min<int64_t>(RC, r_end - r0);
-    const int step = RSTEP * D;
-    int off = myrow * D;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int rr = myrow + RSTEP * i;
-      raw[i] = (rr < lim && mycol < D) ? base[off] : 0.f;
-      off += step;
-    }
-  };
-  auto stage = [&](int64_t r0) {
-    const int lim = (int)min<int64_t>(RC, r_end - r0);
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int rr = myrow + RSTEP * i;
-      const float x = raw[i];
-      bad |= !(x - x == 0.f);
-      const double w = (rr < lim && mycol < D) ? ((double)x - sh) : 0.0;
-      wbuf[(myrow + RSTEP * i) * ST + mycol] = w;
-      sum += w;
-    }
-  };
-
-  // this wave's super-blocks s = wave + WAVES u: block rows P*SB.., columns Q*SB..
-  int sp[S::SPW], sq[S::SPW];
-#pragma unroll
-  for (int u = 0; u < S::SPW; ++u) {
-    const int sl = wave + S::WAVES * u;
-    const int sidx = ts * S::TSW + sl;
-    if (sl < S::TSW && sidx < S::TS) {
-      sb_pq(sidx, S::NS, sp[u], sq[u]);
+  // chunk c: rows [r_begin + c RC, ..) = one contiguous run of floats, copied
+  // to LDS in 1 KiB (vec: 16 bytes per lane) or 256-byte pieces; the buffer
+  // range ends at the slice's last row, so the rest reads as zero
+  const int64_t nch = (r_end - r_begin + RC - 1) / RC;
+  auto copy = [&](int64_t c) {
+    const int64_t r0 = r_begin + c * RC;
+    const int rows = (int)min<int64_t>(RC, r_end - r0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(X + r0 * D), 0, rows * D * 4, 0x00020000);
+    float* dst = xs[c & 1];
+    if (vec) {
+      const int pieces = (RC * D + 255) / 256;
+      for (int i = wave; i < pieces; i += S::WAVES)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(dst + 256 * i), 16, (256 * i + 4 * lane) * 4, 0,
+            0, 0);
     } else {
-      sp[u] = -1;
-      sq[u] = -1;
+      const int pieces = (RC * D + 63) / 64;
+      for (int i = wave; i < pieces; i += S::WAVES)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(dst + 64 * i), 4, (64 * i + lane) * 4, 0, 0, 0);
     }
-  }
-  doublex4 acc[S::SPW][S::SB * S::SB];
-#pragma unroll
-  for (int u = 0; u < S::SPW; ++u)
-#pragma unroll
-    for (int x = 0; x < S::SB * S::SB; ++x) acc[u][x] = doublex4{0.0, 0.0, 0.0, 0.0};
+  };
 
-  if (r_begin < r_end) fetch(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += RC) {
+  // this wave's super-block s = ts TSW + wave: block rows P SB.., columns Q SB..
+  int sp = -1, sq = -1;
+  {
+    const int sidx = ts * S::TSW + wave;
+    if (wave < S::TSW && sidx < S::TS) sb_pq(sidx, S::NS, sp, sq);
+  }
+  const bool diag = sp >= 0 && sp == sq;
+  int ca[SB], cb[SB];          // this lane's column in each block
+  double sha[SB], shb[SB];     // the shift at those columns
+  double sum[SB];
+#pragma unroll
+  for (int x = 0; x < SB; ++x) {
+    ca[x] = 16 * (max(sp, 0) * SB + x) + col;
+    cb[x] = 16 * (max(sq, 0) * SB + x) + col;
+    sha[x] = ca[x] < D ? (double)shift[ca[x]] : 0.0;
+    shb[x] = cb[x] < D ? (double)shift[cb[x]] : 0.0;
+    sum[x] = 0.0;
+  }
+  bool bad = false;
+  doublex4 acc[SB * SB];
+#pragma unroll
+  for (int x = 0; x < SB * SB; ++x) acc[x] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  if (nch > 0) copy(0);
+  for (int64_t c = 0; c < nch; ++c) {
+    // chunk c has landed (every wave waited for its own copies), and every
+    // wave is done with chunk c - 1, whose buffer the next copy overwrites
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    stage(r0);
-    __syncthreads();
-    if (r0 + RC < r_end) fetch(r0 + RC);
-#pragma unroll 1
+    if (c + 1 < nch) copy(c + 1);
+    if (sp < 0) continue;
+    const float* buf = xs[c & 1];
+    const int lim = (int)min<int64_t>(RC, r_end - (r_begin + c * RC));
+#pragma unroll 2
     for (int q = 0; q < RC / 4; ++q) {
-      const double* rowp = &wbuf[(4 * q + rsub) * ST + col];
+      const int row = 4 * q + rsub;
+      const bool live = row < lim;
+      const float* rp = buf + row * D;
+      double a[SB], b[SB];
 #pragma unroll
-      for (int u = 0; u < S::SPW; ++u) {
-        if (sp[u] >= 0) {
-          double a[S::SB], b[S::SB];
-#pragma unroll
-          for (int x = 0; x < S::SB; ++x) {
-            a[x] = rowp[16 * (sp[u] * S::SB + x)];
-            b[x] = rowp[16 * (sq[u] * S::SB + x)];
-          }
-          const bool diag = sp[u] == sq[u];
-#pragma unroll
-          for (int x = 0; x < S::SB; ++x)
-#pragma unroll
-            for (int y = 0; y < S::SB; ++y)
-              if (!diag || x <= y)
-                acc[u][x * S::SB + y] =
-                    __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[u][x * S::SB + y], 0, 0, 0);
+      for (int x = 0; x < SB; ++x) {
+        const bool oka = live && ca[x] < D, okb = live && cb[x] < D;
+        const float fa = rp[ca[x]], fb = rp[cb[x]];
+        a[x] = oka ? (double)fa - sha[x] : 0.0;
+        b[x] = okb ? (double)fb - shb[x] : 0.0;
+        if (diag) {
+          bad |= oka && !(fa - fa == 0.f);
+          sum[x] += a[x];
         }
       }
+#pragma unroll
+      for (int x = 0; x < SB; ++x)
+#pragma unroll
+        for (int y = 0; y < SB; ++y)
+          if (!diag || x <= y)
+            acc[x * SB + y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x * SB + y], 0, 0, 0);
     }
   }
   if (bad) atomicOr(status, ST_NONFINITE);
 
   // live blocks: element v of lane l of the 16x16x4 f64 result is row
   // l/16 + 4 v, column l%16
+  if (sp >= 0) {
 #pragma unroll
-  for (int u = 0; u < S::SPW; ++u) {
-    if (sp[u] >= 0) {
+    for (int x = 0; x < SB; ++x)
 #pragma unroll
-      for (int x = 0; x < S::SB; ++x)
+      for (int y = 0; y < SB; ++y) {
+        const int I = sp * SB + x, J = sq * SB + y;
+        if (I <= J) {
+          const int t = cblock_t(I, J, S::NB);
 #pragma unroll
-        for (int y = 0; y < S::SB; ++y) {
-          const int I = sp[u] * S::SB + x, J = sq[u] * S::SB + y;
-          if (I <= J) {
-            const int t = cblock_t(I, J, S::NB);
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[u][x * S::SB + y][v];
-          }
+          for (int v = 0; v < 4; ++v)
+            gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[x * SB + y][v];
         }
-    }
+      }
   }
-  // partial column sums: the NT/DP threads of each column combine in LDS
-  __syncthreads();
-  sred[tid] = sum;
-  __syncthreads();
-  if (tid < DP && ts == 0) {
-    double a = 0.0;
-    for (int t = tid; t < NT; t += DP) a += sred[t];
-    spo[setA ? tid : DP + tid] = a;
-    spo[setA ? DP + tid : tid] = 0.0;
+  // column sums of the diagonal super-blocks: the four row phases of a
+  // column sit in lanes col, col + 16, col + 32, col + 48
+  if (diag) {
+#pragma unroll
+    for (int x = 0; x < SB; ++x) {
+      double v = sum[x];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (rsub == 0) {
+        spo[setA ? ca[x] : DP + ca[x]] = v;
+        spo[setA ? DP + ca[x] : ca[x]] = 0.0;
+      }
+    }
   }
 }
 
