@@ -76,6 +76,41 @@ def load_traffic(name):
     return d.get("bytes_per_launch")
 
 
+def attainable_peaks(dev):
+    """Rates this GPU reaches on plain library work, as a yardstick beside the
+    datasheet peaks: square float32 and float64 products through torch
+    (hipBLASLt / rocBLAS), a 4 GiB read-only reduction and a 2 GiB copy."""
+    import torch
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    for name, dt, n in (("gemm_fp32_tflops", torch.float32, 8192), ("gemm_fp64_tflops", torch.float64, 8192)):
+        a = torch.randn(n, n, device=dev, dtype=dt)
+        b = torch.randn(n, n, device=dev, dtype=dt)
+        ms = timed(lambda: torch.matmul(a, b), 5)
+        out[name] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        del a, b
+    x = torch.ones(1 << 30, device=dev, dtype=torch.float32)
+    ms = timed(lambda: x.sum(), 10)
+    out["hbm_read_gbs"] = 4.0 * (1 << 30) / (ms * 1e-3) / 1e9
+    y = torch.empty(1 << 29, device=dev, dtype=torch.float32)
+    ms = timed(lambda: y.copy_(x[: 1 << 29]), 10)
+    out["hbm_copy_gbs"] = 2 * 4.0 * (1 << 29) / (ms * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(A, B, m, alpha, n_sample):
     """FP64 oracle on the first n_sample rows of each set, phases timed; the
     linear phases scale with n, the candidate distance with n^2."""
@@ -345,6 +380,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--batched-pairs", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (HBM-counter calibration)")
@@ -451,6 +487,41 @@ def main():
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
             "per_launch": {"algorithmic_flops": flops, "avg_ms": tile_avg, "launches": tile_n}}
+
+    # the other kernels of the step against their own bounds (algorithmic
+    # work: the symmetric half of the union Gram, one read of both sets plus
+    # the projection writes, one read of the projections for selection)
+    def per_step(name):
+        k = kernels.get(name)
+        return k["ms_per_step"] if k else None
+    path_roof = {}
+    g_ms = per_step("stats_gram")
+    if g_ms:
+        gf = float(nA + nB) * D * (D + 1)
+        path_roof["gram"] = {"bound": "mfma_fp64", "algorithmic_flops": gf, "ms": g_ms,
+                             "achieved": gf / (g_ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": gf / (g_ms * 1e-3) / 1e12 / 78.6}
+    p_ms = per_step("project_mfma")
+    if p_ms:
+        pb = float(nA + nB) * 4 * (D + m + 1)
+        path_roof["project"] = {"bound": "hbm", "algorithmic_bytes": pb, "ms": p_ms,
+                                "achieved": pb / (p_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
+                                "frac": pb / (p_ms * 1e-3) / 1e9 / PEAK_HBM}
+    s_ms = per_step("select_")
+    if s_ms:
+        sb = float(nA + nB) * 4 * (m + 1)
+        path_roof["select"] = {"bound": "hbm", "algorithmic_bytes": sb, "ms": s_ms,
+                               "achieved": sb / (s_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
+                               "frac": sb / (s_ms * 1e-3) / 1e9 / PEAK_HBM}
+    peaks = None
+    if not args.no_peaks:
+        peaks = attainable_peaks(dev)
+        log("attainable: " + ", ".join(f"{k} {v:.1f}" for k, v in peaks.items()))
+        if "gram" in path_roof:
+            path_roof["gram"]["frac_of_attainable"] = path_roof["gram"]["achieved"] / peaks["gemm_fp64_tflops"]
+        if "project" in path_roof:
+            path_roof["project"]["frac_of_attainable"] = path_roof["project"]["achieved"] / peaks["hbm_read_gbs"]
+        roof["frac_of_attainable"] = achieved / peaks["gemm_fp32_tflops"]
 
     # error certificate (Sec. II-E bounds) of this step's directions and
     # projections, with the inner-minimum-over-the-full-set value as the
@@ -619,6 +690,8 @@ def main():
         "check": check,
         "certificate": cert,
         "roofline": roof,
+        "path_roofline": path_roof,
+        "attainable": peaks,
         "exact": exact,
         "kernels": kernels,
         "baselines": base,
