@@ -520,7 +520,8 @@ def main():
         if "gram" in path_roof:
             path_roof["gram"]["frac_of_attainable"] = path_roof["gram"]["achieved"] / peaks["gemm_fp64_tflops"]
         if "project" in path_roof:
-            path_roof["project"]["frac_of_attainable"] = path_roof["project"]["achieved"] / peaks["hbm_read_gbs"]
+            hbm = max(peaks["hbm_read_gbs"], peaks["hbm_copy_gbs"])
+            path_roof["project"]["frac_of_attainable"] = path_roof["project"]["achieved"] / hbm
         roof["frac_of_attainable"] = achieved / peaks["gemm_fp32_tflops"]
 
     # error certificate (Sec. II-E bounds) of this step's directions and

@@ -55,7 +55,7 @@ struct GramShape {
   static constexpr int TSW = (TS + TSPLIT - 1) / TSPLIT;  // super-blocks per work-group
   static constexpr int WAVES = TSW > 4 ? TSW : 4;       // one super-block per wave
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr int RC = 32;                         // rows per chunk
+  static constexpr int RC = 64;                         // rows per chunk
   static constexpr int CHUNK = RC * DP;                 // floats per LDS buffer
 };
 
@@ -172,6 +172,49 @@ __device__ __forceinline__ void gram_body(const float* __restrict__ shift, const
     if (sp < 0) continue;
     const float* buf = xs[c & 1];
     const int lim = (int)min<int64_t>(RC, r_end - (r_begin + c * RC));
+    if (lim == RC && D == DP) {
+      // full chunk, no padding columns: no masks; each step reads the next
+      // step's values ahead (the scheduling barrier keeps that order)
+      const float* bq = buf + rsub * DP;
+      float f[SB], g[SB];
+#pragma unroll
+      for (int x = 0; x < SB; ++x) {
+        f[x] = bq[ca[x]];
+        g[x] = bq[cb[x]];
+      }
+#pragma unroll
+      for (int q = 0; q < RC / 4; ++q) {
+        float nf[SB], ng[SB];
+#pragma unroll
+        for (int x = 0; x < SB; ++x) {
+          nf[x] = q + 1 < RC / 4 ? bq[4 * (q + 1) * DP + ca[x]] : 0.f;
+          ng[x] = (q + 1 < RC / 4 && !diag) ? bq[4 * (q + 1) * DP + cb[x]] : 0.f;
+        }
+        double a[SB], b[SB];
+#pragma unroll
+        for (int x = 0; x < SB; ++x) {
+          a[x] = (double)f[x] - sha[x];
+          b[x] = diag ? a[x] : (double)g[x] - shb[x];
+          if (diag) {
+            bad |= !(f[x] - f[x] == 0.f);
+            sum[x] += a[x];
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < SB; ++x)
+#pragma unroll
+          for (int y = 0; y < SB; ++y)
+            if (!diag || x <= y)
+              acc[x * SB + y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x * SB + y], 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < SB; ++x) {
+          f[x] = nf[x];
+          g[x] = ng[x];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      continue;
+    }
 #pragma unroll 2
     for (int q = 0; q < RC / 4; ++q) {
       const int row = 4 * q + rsub;
@@ -357,7 +400,7 @@ __global__ __launch_bounds__(256) void gram_reduce_batch(const GramRedJob* __res
 struct StatsLayout {
   double* gpart;
   double* spart;
-  int64_t rows;  // rows per work-group (multiple of the 32-row chunk)
+  int64_t rows;  // rows per work-group (multiple of the 64-row chunk)
   int nwg;       // work-groups: ceil(nA/rows) over A, then ceil(nB/rows) over B
 };
 
@@ -365,7 +408,7 @@ StatsLayout stats_layout(Arena& ar, int64_t nA, int64_t nB, int DP, int cus) {
   StatsLayout L;
   const int64_t N = nA + nB;
   const int64_t target = std::max<int64_t>(1, std::min<int64_t>(cus, cdiv(N, 1024)));
-  L.rows = cdiv(cdiv(N, target), 32) * 32;
+  L.rows = cdiv(cdiv(N, target), 64) * 64;   // whole chunks
   L.nwg = (int)(cdiv(nA, L.rows) + cdiv(nB, L.rows));
   const int nb = DP / 16;
   const int T = nb * (nb + 1) / 2;
