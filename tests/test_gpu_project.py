@@ -99,6 +99,29 @@ def test_project_given_dirs():
         assert np.max(np.abs(P.cpu().numpy() - want)) <= 1e-5 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("D,m", [(64, 15), (256, 16), (256, 23), (64, 32), (256, 40), (50, 32),
+                                 (50, 50), (256, 63)])
+def test_project_direction_counts(D, m):
+    """Every direction-group shape of the projection kernel: 16 or fewer,
+    17 (one block and the extra direction), 18-32 (two blocks), 33 (two
+    blocks and the extra direction), more than 33 (several launches); D not
+    a multiple of 4 takes the scalar-load path.  Row counts leave ragged
+    16-row blocks."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"prohd_project given directions D={D} ndirs={m + 1}")
+    A, B = synth.gauss_outliers(2053, 1011, D, seed=m)
+    g = np.random.default_rng(m)
+    U = g.standard_normal((m + 1, D)).astype(np.float32)
+    dirs, pA, pB, ev, st = ph.prohd_project(to_dev(torch, A), to_dev(torch, B), m,
+                                            dirs=to_dev(torch, U), sync=True)
+    assert int(st.item()) == 0
+    for X, P in ((A, pA), (B, pB)):
+        want = U.astype(np.float64) @ X.astype(np.float64).T
+        bound = (D + 2) * 2.0 ** -24 * (np.abs(U).astype(np.float64) @ np.abs(X.astype(np.float64)).T)
+        assert np.all(np.abs(P.cpu().numpy() - want) <= bound + 1e-30)
+
+
 def test_project_identical_sets_fallback_axis():
     torch, dev = torch_gpu()
     import paper_2511_18207_amd as ph
