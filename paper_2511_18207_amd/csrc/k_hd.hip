@@ -929,7 +929,11 @@ prohd_status launch_refine(const float* Xp, const int32_t* cand, const int64_t* 
                            const int64_t* dnY, int64_t capY, unsigned long long* best,
                            hipStream_t s) {
   const int64_t cblocks = cdiv(kRefineRows, 64);
-  const int split = choose_split(cblocks, capY, 256);
+  // at least two work-groups per CU, so that one's staging of Y overlaps the
+  // other's matrix work (each SIMD then holds two waves)
+  const int64_t want = cdiv(2 * (int64_t)cu_count(), cblocks);
+  const int split = (int)std::max<int64_t>(choose_split(cblocks, capY, 256),
+                                           std::min<int64_t>(want, std::max<int64_t>(1, capY / 128)));
   PROHD_LAUNCH("hd_refine", refine_rows<DP>, dim3((unsigned)(cblocks * split)), dim3(256), 0, s, Xp,
                cand, dR, Yp, dnY, capY, split, best);
   return PROHD_OK;
