@@ -486,107 +486,133 @@ __device__ __forceinline__ void eig_body(
   __syncthreads();
 
   // ------------------------------------------------ 3. inverse iteration
-  // vectors c = 0..m-1 (descending eigenvalue); clusters by gap < ortol
+  // vectors c = 0..m-1 (descending eigenvalue); clusters by gap < ortol.
+  // Rounds of SLOTS vectors: one thread per vector factors T - lc I
+  // (pivoted LU) and runs the substitutions; after each substitution the
+  // waves orthogonalise every vector against the earlier members of its
+  // cluster (modified Gram-Schmidt in index order, 64 lanes per vector; one
+  // wave per cluster, so members of a cluster stay in order) and scale it to
+  // unit length.  Members of one cluster iterate together, so a large
+  // cluster costs no more substitutions than a separated eigenvalue.
   const double lmax = fmax(fabs(lam[DP - 1]), fabs(lam[DP - D]));
   const double ortol = 1e-3 * lmax;
   const double tol = 2.2e-16 * fmax(tnorm, 1e-300);
+  __shared__ double shift[S::MAXD];
   if (t == 0) {
     int lead = 0;
+    double prev = 0.0;
     for (int c = 0; c < m; ++c) {
       if (c > 0 && lam[DP - c] - lam[DP - 1 - c] >= ortol) lead = c;
       lead_of[c] = lead;
+      // equal eigenvalues inside a cluster get shifts 10 tol apart
+      double lc = lam[DP - 1 - c];
+      if (c > lead && lc > prev - 10.0 * tol) lc = prev - 10.0 * tol;
+      prev = lc;
+      shift[c] = lc;
     }
   }
   __syncthreads();
   double* slot_base = big;  // SLOTS x 4 x DP doubles: U0 inverse, U1, L, x
-  // leaders take slots in rounds of SLOTS
-  for (int round = 0; round * S::SLOTS < m; ++round) {
-    const int c0 = t;  // candidate leader index handled by this thread
-    const int leader = round * S::SLOTS + c0;
-    if (c0 < S::SLOTS && leader < m && lead_of[leader] == leader && ok) {
-      double* U0 = slot_base + (size_t)c0 * 4 * DP;
-      double* U1 = U0 + DP;
-      double* Lm = U0 + 2 * DP;
-      double* x = U0 + 3 * DP;
-      uint8_t* pv = piv[c0];
-      double prev = 0.0;
-      for (int c = leader; c < m && lead_of[c] == leader; ++c) {
-        double lc = lam[DP - 1 - c];
-        if (c > leader && lc > prev - 10.0 * tol) lc = prev - 10.0 * tol;
-        prev = lc;
-        // pivoted LU of T - lc I
-        double dcur = dd[0] - lc, ucur = ee[0];
-        for (int i = 0; i < DP - 1; ++i) {
-          const double sub = ee[i];
-          const double an = dd[i + 1] - lc;
-          const double bn = (i + 1 < DP - 1) ? ee[i + 1] : 0.0;
-          if (fabs(dcur) >= fabs(sub)) {
-            double dpiv = dcur;
-            if (fabs(dpiv) < tol) dpiv = dpiv < 0.0 ? -tol : tol;
-            const double mult = sub / dpiv;
-            U0[i] = 1.0 / dpiv;
-            U1[i] = ucur;
-            Lm[i] = mult;
-            pv[i] = 0;
-            dcur = an - mult * ucur;
-            ucur = bn;
-          } else {
-            const double mult = dcur / sub;
-            U0[i] = 1.0 / sub;
-            U1[i] = an;
-            Lm[i] = mult;
-            pv[i] = 1;
-            dcur = ucur - mult * an;
-            ucur = -mult * bn;
-          }
+  constexpr int NWV = NT / 64;
+  const int lane3 = t & 63, wave3 = t >> 6;
+  for (int r0 = 0; r0 < m; r0 += S::SLOTS) {
+    const int nr = min(S::SLOTS, m - r0);
+    double* U0 = slot_base + (size_t)t * 4 * DP;
+    double* U1 = U0 + DP;
+    double* Lm = U0 + 2 * DP;
+    double* x = U0 + 3 * DP;
+    uint8_t* pv = piv[t < S::SLOTS ? t : 0];
+    if (t < nr && ok) {
+      const int c = r0 + t;
+      const double lc = shift[c];
+      // pivoted LU of T - lc I
+      double dcur = dd[0] - lc, ucur = ee[0];
+      for (int i = 0; i < DP - 1; ++i) {
+        const double sub = ee[i];
+        const double an = dd[i + 1] - lc;
+        const double bn = (i + 1 < DP - 1) ? ee[i + 1] : 0.0;
+        if (fabs(dcur) >= fabs(sub)) {
+          double dpiv = dcur;
+          if (fabs(dpiv) < tol) dpiv = dpiv < 0.0 ? -tol : tol;
+          const double mult = sub / dpiv;
+          U0[i] = 1.0 / dpiv;
+          U1[i] = ucur;
+          Lm[i] = mult;
+          pv[i] = 0;
+          dcur = an - mult * ucur;
+          ucur = bn;
+        } else {
+          const double mult = dcur / sub;
+          U0[i] = 1.0 / sub;
+          U1[i] = an;
+          Lm[i] = mult;
+          pv[i] = 1;
+          dcur = ucur - mult * an;
+          ucur = -mult * bn;
         }
-        if (fabs(dcur) < tol) dcur = dcur < 0.0 ? -tol : tol;
-        U0[DP - 1] = 1.0 / dcur;
-        // start vector (zero on padding rows keeps them exactly zero)
-        for (int k = 0; k < DP; ++k) x[k] = (k < D) ? start_value(k, c) : 0.0;
-        for (int it = 0; it < 5; ++it) {
-          // forward: apply the row interchanges and multipliers
-          for (int i = 0; i < DP - 1; ++i) {
-            double bi = x[i], bn = x[i + 1];
-            if (pv[i]) {
-              const double tmp = bi;
-              bi = bn;
-              bn = tmp;
-            }
-            x[i] = bi;
-            x[i + 1] = bn - Lm[i] * bi;
+      }
+      if (fabs(dcur) < tol) dcur = dcur < 0.0 ? -tol : tol;
+      U0[DP - 1] = 1.0 / dcur;
+      // start vector (zero on padding rows keeps them exactly zero)
+      for (int k = 0; k < DP; ++k) x[k] = (k < D) ? start_value(k, c) : 0.0;
+    }
+    for (int it = 0; it < 5; ++it) {
+      if (t < nr && ok) {
+        // forward: apply the row interchanges and multipliers
+        for (int i = 0; i < DP - 1; ++i) {
+          double bi = x[i], bn = x[i + 1];
+          if (pv[i]) {
+            const double tmp = bi;
+            bi = bn;
+            bn = tmp;
           }
-          // backward: U has diagonal, first and (when pivoted) second superdiagonal
-          double x2 = 0.0, x1 = x[DP - 1] * U0[DP - 1];
-          x[DP - 1] = x1;
-          for (int i = DP - 2; i >= 0; --i) {
-            const double u2 = (pv[i] && i + 2 < DP) ? ee[i + 1] : 0.0;
-            const double xi = (x[i] - U1[i] * x1 - u2 * x2) * U0[i];
-            x[i] = xi;
-            x2 = x1;
-            x1 = xi;
-          }
-          // orthogonalise against the earlier members of the cluster
-          for (int p = leader; p < c; ++p) {
-            const double* yp = Yg + (size_t)p * DP;
+          x[i] = bi;
+          x[i + 1] = bn - Lm[i] * bi;
+        }
+        // backward: U has diagonal, first and (when pivoted) second superdiagonal
+        double x2 = 0.0, x1 = x[DP - 1] * U0[DP - 1];
+        x[DP - 1] = x1;
+        for (int i = DP - 2; i >= 0; --i) {
+          const double u2 = (pv[i] && i + 2 < DP) ? ee[i + 1] : 0.0;
+          const double xi = (x[i] - U1[i] * x1 - u2 * x2) * U0[i];
+          x[i] = xi;
+          x2 = x1;
+          x1 = xi;
+        }
+      }
+      __syncthreads();
+      if (ok) {
+        for (int v = 0; v < nr; ++v) {
+          const int c = r0 + v;
+          if (lead_of[c] % NWV != wave3) continue;   // wave-uniform
+          double* xv = slot_base + (size_t)v * 4 * DP + 3 * DP;
+          for (int p = lead_of[c]; p < c; ++p) {
+            const double* yp = p < r0 ? Yg + (size_t)p * DP : slot_base + (size_t)(p - r0) * 4 * DP + 3 * DP;
             double d = 0.0;
-            for (int k = 0; k < DP; ++k) d += x[k] * yp[k];
-            for (int k = 0; k < DP; ++k) x[k] -= d * yp[k];
+            for (int k = lane3; k < DP; k += 64) d += xv[k] * yp[k];
+            d = wave_sum_dpp(d);
+            for (int k = lane3; k < DP; k += 64) xv[k] -= d * yp[k];
           }
           double mx = 0.0;
-          for (int k = 0; k < DP; ++k) mx = fmax(mx, fabs(x[k]));
+          for (int k = lane3; k < DP; k += 64) mx = fmax(mx, fabs(xv[k]));
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
           if (!(mx > 0.0)) mx = 1.0;
           double s2 = 0.0;
-          for (int k = 0; k < DP; ++k) {
-            x[k] /= mx;
-            s2 += x[k] * x[k];
+          for (int k = lane3; k < DP; k += 64) {
+            const double xs = xv[k] / mx;
+            xv[k] = xs;
+            s2 += xs * xs;
           }
-          const double inv = 1.0 / sqrt(s2);
-          for (int k = 0; k < DP; ++k) x[k] *= inv;
+          const double inv = 1.0 / sqrt(wave_sum_dpp(s2));
+          for (int k = lane3; k < DP; k += 64) xv[k] *= inv;
         }
-        double* yc = Yg + (size_t)c * DP;
-        for (int k = 0; k < DP; ++k) yc[k] = x[k];
       }
+      __syncthreads();
+    }
+    for (int e = t; e < nr * DP; e += NT) {
+      const int v = e / DP, k = e - v * DP;
+      Yg[(size_t)(r0 + v) * DP + k] = slot_base[(size_t)v * 4 * DP + 3 * DP + k];
     }
     __syncthreads();
   }
