@@ -989,20 +989,28 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
     L.w[d].best = ar.take<unsigned long long>(kRefineRows);
   }
   const int64_t mx = std::max(capA, capB);
-  L.sel_bytes = std::max(select_ws_bytes(1, mx), compact_ws_bytes(mx));
+  L.sel_bytes = std::max(select_ws_bytes(2, mx), compact_ws_bytes(mx));
   L.sel_ws = ar.take<char>(L.sel_bytes);
   return L;
 }
 
-// Top-R rows of `mins` (device length dn / host n) -> w.cand / w.count.
-prohd_status top_rows(const uint32_t* mins, int64_t n, const int64_t* dn, DirWork& w, void* sel_ws,
-                      size_t sel_bytes, hipStream_t s) {
-  prohd_status st = zero_bytes(w.flags, (size_t)n, s);
+// Top-R rows of both directions' minima (`mins[d]`, device length dn[d] /
+// host n[d]) -> w[d].cand / w[d].count; one selection launch chain for both.
+prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const int64_t* const dn[2],
+                       DirWork* w, void* sel_ws, size_t sel_bytes, hipStream_t s) {
+  SelSegment seg[2];
+  for (int d = 0; d < 2; ++d) {
+    prohd_status st = zero_bytes(w[d].flags, (size_t)n[d], s);
+    if (st) return st;
+    seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, kRefineRows, w[d].flags};
+  }
+  prohd_status st = select_mark(seg, 2, sel_ws, sel_bytes, s);
   if (st) return st;
-  SelSegment seg{reinterpret_cast<const float*>(mins), n, dn, 0, kRefineRows, w.flags};
-  st = select_mark(&seg, 1, sel_ws, sel_bytes, s);
-  if (st) return st;
-  return compact_flags(w.flags, n, dn, w.cand, kRefineRows, w.count, sel_ws, sel_bytes, s);
+  for (int d = 0; d < 2; ++d) {
+    st = compact_flags(w[d].flags, n[d], dn[d], w[d].cand, kRefineRows, w[d].count, sel_ws, sel_bytes, s);
+    if (st) return st;
+  }
+  return PROHD_OK;
 }
 
 prohd_status init_mins(uint32_t* p, int64_t n, hipStream_t s) {
@@ -1054,11 +1062,13 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   PROHD_TRY(init_mins(L.rowA, capA, s));
   PROHD_TRY(init_mins(L.rowB, capB, s));
   for (int d = 0; d < 2; ++d) PROHD_TRY(init_best(L.w[d].best, s));
+  const uint32_t* const mins2[2] = {L.rowA, L.rowB};
+  const int64_t caps2[2] = {capA, capB};
+  const int64_t* const dns2[2] = {dnA, dnB};
   DirIn ab{}, ba{};
   if (!full) {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
-    PROHD_TRY(top_rows(L.rowA, capA, dnA, L.w[0], L.sel_ws, L.sel_bytes, s));
-    PROHD_TRY(top_rows(L.rowB, capB, dnB, L.w[1], L.sel_ws, L.sel_bytes, s));
+    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.xb.p, dnB, capB, L.w[0].best, s));
     PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, L.xa.p, dnA, capA, L.w[1].best, s));
     ab = DirIn{L.w[0].best, L.w[0].cand, L.w[0].count, idxA, idxB, A, B};
@@ -1066,8 +1076,7 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   } else {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
     PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.fa, nullptr, nA, L.maxabs, L.rowB, nullptr, s));
-    PROHD_TRY(top_rows(L.rowA, capA, dnA, L.w[0], L.sel_ws, L.sel_bytes, s));
-    PROHD_TRY(top_rows(L.rowB, capB, dnB, L.w[1], L.sel_ws, L.sel_bytes, s));
+    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
     PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.fb.p, nullptr, nB, L.w[0].best, s));
     PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, L.fa.p, nullptr, nA, L.w[1].best, s));
     ab = DirIn{L.w[0].best, L.w[0].cand, L.w[0].count, idxA, nullptr, A, B};

@@ -43,7 +43,7 @@ struct SegDev {
 
 // Segment descriptors travel as a kernel argument (no host-to-device copy,
 // so a chain of launches can be captured in a graph).
-constexpr int kSegPerLaunch = 32;
+constexpr int kSegPerLaunch = 64;   // 64 x 40-byte descriptors: 2.6 KB of kernel arguments
 struct SegPack {
   SegDev s[kSegPerLaunch];
   int32_t nseg;   // segments in this pack
