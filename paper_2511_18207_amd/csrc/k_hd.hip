@@ -641,7 +641,9 @@ __device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
     doublex4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
     const double* b0 = &ys[i16 * STY + kq];
     const double* b1 = &ys[(16 + i16) * STY + kq];
-#pragma unroll 16
+    // fully unrolled: a partial unroll leaves the accumulators crossing a
+    // loop edge, which the compiler pays for with register-class copies
+#pragma unroll
     for (int s = 0; s < KS; ++s) {
       c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b0[4 * s], c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b1[4 * s], c1, 0, 0, 0);
