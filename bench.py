@@ -370,7 +370,7 @@ def main():
     ap.add_argument("--exact-steps", type=int, default=1)
     ap.add_argument("--workload", default="heavy2m")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=500_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
