@@ -369,9 +369,15 @@ __global__ __launch_bounds__(256) void quant_rows(const float* __restrict__ Xp,
 // Same contract as dist_tile, on bfloat16 / float8 inputs with float32
 // accumulation: v_mfma_f32_32x32x16_bf16 (K = 16) or
 // v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales (K = 64).  Each lane
-// supplies K/2 consecutive k of its half-wave's k range per op.  Y blocks of
-// 128 rows (four 32-column subtiles) per LDS buffer; two accumulators let
-// the epilogue of one subtile run while the next subtile's ops execute.
+// supplies K/2 consecutive k of its half-wave's k range per op.  A wave holds
+// two 32-row sets of X (512 rows per work-group), so every B operand read
+// from LDS feeds two ops: at these input widths one op per 32 or 64 cycles
+// would otherwise need the whole LDS bandwidth.  Y blocks of 128 rows (four
+// 32-column subtiles) per LDS buffer; rows of 256 bytes or more are copied
+// from memory straight into LDS (4-byte pieces, so the padded row stride that
+// keeps the b128 reads conflict-free survives), narrower rows through
+// registers.  Where the registers allow, two accumulator sets let the
+// epilogue of one subtile run while the next subtile's ops execute.
 template <int FMT>
 struct LpFmt {
   static constexpr int KPM = FMT == FMT_BF16 ? 16 : 64;   // k per op
@@ -380,24 +386,31 @@ struct LpFmt {
 };
 
 constexpr int kLpBN = 128;   // Y rows per LDS buffer
+constexpr int kLpXS = 2;     // 32-row X sets per wave
+constexpr int kLpTileRows = kTileRows * kLpXS;
 
 template <int DP, int FMT, bool COLMIN>
 __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
-                                                    const float* __restrict__ xn,
-                                                    const int64_t* __restrict__ dnX, int64_t hnX,
-                                                    const uint8_t* __restrict__ Yq,
-                                                    const float* __restrict__ yn,
-                                                    const int64_t* __restrict__ dnY, int64_t hnY,
-                                                    int ysplit, const uint32_t* __restrict__ maxabs,
-                                                    uint32_t* __restrict__ rowmin,
-                                                    uint32_t* __restrict__ colmin) {
+                                                     const float* __restrict__ xn,
+                                                     const int64_t* __restrict__ dnX, int64_t hnX,
+                                                     const uint8_t* __restrict__ Yq,
+                                                     const float* __restrict__ yn,
+                                                     const int64_t* __restrict__ dnY, int64_t hnY,
+                                                     int ysplit, const uint32_t* __restrict__ maxabs,
+                                                     uint32_t* __restrict__ rowmin,
+                                                     uint32_t* __restrict__ colmin) {
   using F = LpFmt<FMT>;
+  constexpr int XS = kLpXS;
   constexpr int RB = DP * F::EB;            // bytes per row
   constexpr int STB = RB + 16;              // LDS row stride (bytes): conflict-free b128
   constexpr int NS = DP / F::KPM;           // ops per 32x32 subtile
   constexpr int NA = RB / 2 / 16;           // 16-byte chunks of a lane's A operand
-  constexpr int NV = kLpBN * RB / 16;       // 16-byte chunks per Y buffer
-  constexpr int PF = (NV + 511) / 512;      // per thread
+  constexpr bool DMA = RB % 256 == 0;       // rows copied straight into LDS
+  constexpr int NV = kLpBN * RB / 16;       // 16-byte chunks per Y buffer (register path)
+  constexpr int PF = DMA ? 1 : (NV + 511) / 512;
+  // overlapped subtiles need a second accumulator set: not at BF16 and
+  // D = 256, whose two X sets already fill the registers
+  constexpr bool ILV = FMT == FMT_FP8 || DP <= 128;
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kLpBN * STB];
   __shared__ float yns[2][kLpBN];
   __shared__ uint32_t cmin[2][kLpBN];
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
   const int64_t nY = dev_or(dnY, hnY);
   const int xblk = blockIdx.x / ysplit;
   const int ysi = blockIdx.x - xblk * ysplit;
-  const int64_t x0 = (int64_t)xblk * kTileRows;
+  const int64_t x0 = (int64_t)xblk * kLpTileRows;
   if (x0 >= nX) return;
   const int64_t chunk = ((nY + ysplit - 1) / ysplit + kLpBN - 1) / kLpBN * kLpBN;
   const int64_t yb = (int64_t)ysi * chunk;
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 5;
   const int c = lane & 31;
   float dscale = -2.f;
@@ -424,48 +437,71 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
     dscale = -2.f / (sc * sc);
   }
 
-  uint4 a[NA];
-  {
-    const int64_t xr = x0 + 32 * wave + c;
+  // X set x of this wave: rows x0 + 32 (XS wave + x) ..
+  uint4 a[XS][NA];
+  float xq[XS][16], rmin[XS][16];
+#pragma unroll
+  for (int x = 0; x < XS; ++x) {
+    const int64_t rb0 = x0 + 32 * (XS * wave + x);
+    const int64_t xr = rb0 + c;
     if (xr < nX) {
       const uint4* src = reinterpret_cast<const uint4*>(Xq + xr * RB + g * (RB / 2));
 #pragma unroll
-      for (int j = 0; j < NA; ++j) a[j] = src[j];
+      for (int j = 0; j < NA; ++j) a[x][j] = src[j];
     } else {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) a[j] = make_uint4(0u, 0u, 0u, 0u);
+      for (int j = 0; j < NA; ++j) a[x][j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = rb0 + 8 * (v >> 2) + 4 * g + (v & 3);
+      xq[x][v] = (r < nX) ? xn[r] : __uint_as_float(kInfBits);
+      rmin[x][v] = __uint_as_float(kInfBits);
     }
   }
-  float xq[16], rmin[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int64_t r = x0 + 32 * wave + 8 * (v >> 2) + 4 * g + (v & 3);
-    xq[v] = (r < nX) ? xn[r] : __uint_as_float(kInfBits);
-    rmin[v] = __uint_as_float(kInfBits);
-  }
 
-  auto load_block = [&](int64_t y0, uint4 (&buf)[PF], float& ynv) {
-#pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const int f = tid + 512 * p;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (f < NV) {
-        const int r = f / (RB / 16);
-        const int q = f - r * (RB / 16);
-        if (y0 + r < ye) v = reinterpret_cast<const uint4*>(Yq + (y0 + r) * RB)[q];
+  // Y block -> LDS buffer b.  DMA: 4-byte pieces, RB / 256 instructions per
+  // row, spread over the waves; the buffer range ends at the last valid row,
+  // so rows past the end read as zero.
+  auto load_block = [&](int64_t y0, int b, uint4 (&buf)[PF], float& ynv) {
+    if constexpr (DMA) {
+      const int rows = (int)min<int64_t>(kLpBN, ye - y0);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t*>(Yq + y0 * RB), 0, rows * RB, 0x00020000);
+      constexpr int PPR = RB / 256;   // pieces per row
+      for (int i = wave; i < kLpBN * PPR; i += 8) {
+        const int r = i / PPR, h = i - r * PPR;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(&ys[b][r * STB + 256 * h]), 4,
+            r * RB + 256 * h + 4 * lane, 0, 0, 0);
       }
-      buf[p] = v;
+    } else {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int f = tid + 512 * p;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (f < NV) {
+          const int r = f / (RB / 16);
+          const int q = f - r * (RB / 16);
+          if (y0 + r < ye) v = reinterpret_cast<const uint4*>(Yq + (y0 + r) * RB)[q];
+        }
+        buf[p] = v;
+      }
     }
     ynv = (tid < kLpBN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
   };
   auto store_block = [&](int b, const uint4 (&buf)[PF], float ynv) {
+    if constexpr (DMA) {
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
+    } else {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const int f = tid + 512 * p;
-      if (f < NV) {
-        const int r = f / (RB / 16);
-        const int q = f - r * (RB / 16);
-        *reinterpret_cast<uint4*>(&ys[b][r * STB + 16 * q]) = buf[p];
+      for (int p = 0; p < PF; ++p) {
+        const int f = tid + 512 * p;
+        if (f < NV) {
+          const int r = f / (RB / 16);
+          const int q = f - r * (RB / 16);
+          *reinterpret_cast<uint4*>(&ys[b][r * STB + 16 * q]) = buf[p];
+        }
       }
     }
     if (tid < kLpBN) {
@@ -473,39 +509,47 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
       cmin[b][tid] = kInfBits;
     }
   };
-  auto subtile = [&](int b, int t) {
-    floatx16 acc = {0.f};
+  // one 32-column subtile against both X sets: each B read feeds XS ops
+  auto subtile = [&](int b, int t, floatx16 (&acc)[XS]) {
+#pragma unroll
+    for (int x = 0; x < XS; ++x) acc[x] = floatx16{0.f};
     const uint8_t* yrow = &ys[b][(32 * t + c) * STB + g * (RB / 2)];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if constexpr (FMT == FMT_BF16) {
         const uint4 bv = *reinterpret_cast<const uint4*>(yrow + 16 * s);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]),
-                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < XS; ++x)
+          acc[x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[x][s]),
+                                                           __builtin_bit_cast(bf16x8, bv), acc[x], 0, 0, 0);
       } else {
         const uint4 b0 = *reinterpret_cast<const uint4*>(yrow + 32 * s);
         const uint4 b1 = *reinterpret_cast<const uint4*>(yrow + 32 * s + 16);
-        const intx8 av = {(int)a[2 * s].x, (int)a[2 * s].y, (int)a[2 * s].z, (int)a[2 * s].w,
-                          (int)a[2 * s + 1].x, (int)a[2 * s + 1].y, (int)a[2 * s + 1].z,
-                          (int)a[2 * s + 1].w};
         const intx8 bw = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
                           (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
-        // formats 0/0 = e4m3 for both operands; scales 0x7f = 2^0
-        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bw, acc, 0, 0, 0, 0x7f7f7f7f, 0,
-                                                               0x7f7f7f7f);
+#pragma unroll
+        for (int x = 0; x < XS; ++x) {
+          const intx8 av = {(int)a[x][2 * s].x, (int)a[x][2 * s].y, (int)a[x][2 * s].z,
+                            (int)a[x][2 * s].w, (int)a[x][2 * s + 1].x, (int)a[x][2 * s + 1].y,
+                            (int)a[x][2 * s + 1].z, (int)a[x][2 * s + 1].w};
+          // formats 0/0 = e4m3 for both operands; scales 0x7f = 2^0
+          acc[x] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bw, acc[x], 0, 0, 0, 0x7f7f7f7f,
+                                                                   0, 0x7f7f7f7f);
+        }
       }
     }
-    return acc;
   };
-  auto epilogue = [&](int b, int t, const floatx16& acc) {
+  auto epilogue = [&](int b, int t, const floatx16 (&acc)[XS]) {
     const float ynv = yns[b][32 * t + c];
     float cm = __uint_as_float(kInfBits);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float d = fmaf(dscale, acc[v], xq[v] + ynv);
-      rmin[v] = fminf(rmin[v], d);
-      cm = fminf(cm, d);
-    }
+    for (int x = 0; x < XS; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float d = fmaf(dscale, acc[x][v], xq[x][v] + ynv);
+        rmin[x][v] = fminf(rmin[x][v], d);
+        cm = fminf(cm, d);
+      }
     if (COLMIN) {
       cm = fminf(cm, __shfl_xor(cm, 32));
       if (g == 0) atomicMin(&cmin[b][32 * t + c], clamp_bits(cm));
@@ -514,24 +558,34 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
 
   uint4 pf[PF];
   float pyn;
-  load_block(yb, pf, pyn);
+  load_block(yb, 0, pf, pyn);
   store_block(0, pf, pyn);
   __syncthreads();
 
   int cur = 0;
   for (int64_t y0 = yb; y0 < ye; y0 += kLpBN) {
     const bool more = y0 + kLpBN < ye;
-    if (more) load_block(y0 + kLpBN, pf, pyn);
+    if (more) load_block(y0 + kLpBN, cur ^ 1, pf, pyn);
     const int nsub = (int)min<int64_t>(4, (ye - y0 + 31) / 32);
-    floatx16 acc0 = subtile(cur, 0);
-    floatx16 acc1;
-    if (nsub > 1) acc1 = subtile(cur, 1);
-    epilogue(cur, 0, acc0);
-    if (nsub > 2) acc0 = subtile(cur, 2);
-    if (nsub > 1) epilogue(cur, 1, acc1);
-    if (nsub > 3) acc1 = subtile(cur, 3);
-    if (nsub > 2) epilogue(cur, 2, acc0);
-    if (nsub > 3) epilogue(cur, 3, acc1);
+    if constexpr (ILV) {
+      // two accumulator sets: one subtile's epilogue runs while the next
+      // subtile's ops execute
+      floatx16 p0[XS], p1[XS];
+      subtile(cur, 0, p0);
+      if (nsub > 1) subtile(cur, 1, p1);
+      epilogue(cur, 0, p0);
+      if (nsub > 2) subtile(cur, 2, p0);
+      if (nsub > 1) epilogue(cur, 1, p1);
+      if (nsub > 3) subtile(cur, 3, p1);
+      if (nsub > 2) epilogue(cur, 2, p0);
+      if (nsub > 3) epilogue(cur, 3, p1);
+    } else {
+      for (int t = 0; t < nsub; ++t) {
+        floatx16 acc[XS];
+        subtile(cur, t, acc);
+        epilogue(cur, t, acc);
+      }
+    }
     if (more) store_block(cur ^ 1, pf, pyn);
     __syncthreads();
     if (COLMIN && tid < kLpBN) {
@@ -541,19 +595,23 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
     cur ^= 1;
   }
 
+  // row minima: reduce over the 32 lanes of each half-wave (same rows)
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    float x = rmin[v];
+  for (int x = 0; x < XS; ++x) {
 #pragma unroll
-    for (int off = 1; off < 32; off <<= 1) x = fminf(x, __shfl_xor(x, off));
-    rmin[v] = x;
-  }
-  float mine = __uint_as_float(kInfBits);
+    for (int v = 0; v < 16; ++v) {
+      float t = rmin[x][v];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) mine = (c == v) ? rmin[v] : mine;
-  if (c < 16) {
-    const int64_t r = x0 + 32 * wave + 8 * (c >> 2) + 4 * g + (c & 3);
-    if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
+      for (int off = 1; off < 32; off <<= 1) t = fminf(t, __shfl_xor(t, off));
+      rmin[x][v] = t;
+    }
+    float mine = __uint_as_float(kInfBits);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) mine = (c == v) ? rmin[x][v] : mine;
+    if (c < 16) {
+      const int64_t r = x0 + 32 * (XS * wave + x) + 8 * (c >> 2) + 4 * g + (c & 3);
+      if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
+    }
   }
 }
 
@@ -893,7 +951,7 @@ template <int DP>
 prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
                          const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
                          uint32_t* colmin, hipStream_t s) {
-  const int64_t xblocks = cdiv(capX, kTileRows);
+  const int64_t xblocks = cdiv(capX, fmt == FMT_F32 ? kTileRows : kLpTileRows);
   const int split = choose_split(xblocks, capY, fmt == FMT_F32 ? 4 * kBN : 2 * kLpBN);
   const int64_t grid = xblocks * split;
   if (grid > 0x7fffffff) return fail(PROHD_EUNSUPPORTED, "tile grid too large");
