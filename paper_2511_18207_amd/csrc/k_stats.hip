@@ -329,7 +329,21 @@ __device__ __forceinline__ void gram_reduce_body(const double* __restrict__ gpar
   __shared__ double red[256];
   for (int k = threadIdx.x; k < DP; k += blockDim.x) {
     double a = 0.0, b = 0.0;
-    for (int g = 0; g < nwg; ++g) {
+    int g = 0;
+    for (; g + 8 <= nwg; g += 8) {
+      double va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        va[u] = spart[(size_t)(g + u) * 2 * DP + k];
+        vb[u] = spart[(size_t)(g + u) * 2 * DP + DP + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
+    for (; g < nwg; ++g) {
       a += spart[(size_t)g * 2 * DP + k];
       b += spart[(size_t)g * 2 * DP + DP + k];
     }
@@ -346,8 +360,20 @@ __device__ __forceinline__ void gram_reduce_body(const double* __restrict__ gpar
     const int j = e & 15;
     int I, J;
     block_ij(t, NB, I, J);
+    // partials added in slice order; loads issued eight at a time so the
+    // sum does not wait on one memory round trip per slice
     double g = 0.0;
-    for (int w = 0; w < nwg; ++w) g += gpart[((size_t)w * S::T + t) * 256 + i * 16 + j];
+    const double* gq = gpart + (size_t)t * 256 + i * 16 + j;
+    const size_t gs = (size_t)S::T * 256;
+    int w = 0;
+    for (; w + 8 <= nwg; w += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = gq[(size_t)(w + u) * gs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) g += v[u];
+    }
+    for (; w < nwg; ++w) g += gq[(size_t)w * gs];
     const int r = 16 * I + i, c = 16 * J + j;
     double v;
     if (r < D && c < D) {
