@@ -135,8 +135,9 @@ __device__ __forceinline__ double sum_mod8(double x) {
 // global variant does.
 template <int DP, int NT>
 __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, double* __restrict__ Vg,
-                                            double* col, double* pbuf, double* pw, double* red,
-                                            double* dd, double* ee, double* tau) {
+                                            double* col0, double* pbuf0, double* col1, double* pbuf1,
+                                            double* pw, double* red, double* dd, double* ee,
+                                            double* tau) {
   constexpr int W = NT / 64;
   constexpr int NB = DP / 16;
   constexpr int TPW = NB + 1;          // tiles of tile rows RA and RB
@@ -160,8 +161,12 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
   double* mypw = pw + (size_t)wave * DP;
   // one step; QJ = j % 2 is a compile-time constant so that the column
   // element is picked without indexing the register array
+  // col and pbuf alternate between two buffers by step parity, so a step
+  // can publish its column while slower waves still read the previous
+  // step's in their rank-2 update (no barrier at the start of a step)
   auto step = [&](const int j, auto QJ) {
-    __syncthreads();   // readers of col / pbuf / pw of the previous step are done
+    double* col = decltype(QJ)::value ? col1 : col0;
+    double* pbuf = decltype(QJ)::value ? pbuf1 : pbuf0;
     // per-lane offsets made opaque at every step, so that the compiler
     // recomputes the (cheap) addresses instead of keeping a tile row's worth
     // of loop-invariant addresses live in registers
@@ -336,7 +341,8 @@ __device__ __forceinline__ void eig_body(
 
   // ---------------------------------------------------- 1. tridiagonalise
   if constexpr (S::REG) {
-    tridiag_reg<DP, NT>(Mg, Vg, vs, wv, big, red, dd, ee, tau);   // col = vs, p = wv
+    static_assert(S::NQ >= 2, "the second column / p buffers live in part");
+    tridiag_reg<DP, NT>(Mg, Vg, vs, wv, part[0], part[1], big, red, dd, ee, tau);
   } else {
     const int ci = t % DP;        // column owned in the matvec / update
     const int cq = t / DP;        // row block of that column
