@@ -29,13 +29,22 @@ FLAGS = [
 ]
 
 
+# Per-file additions.  The covariance kernels keep their FP64 matrix-core
+# accumulators in ordinary VGPRs: left to itself the compiler puts some of
+# them in accumulation registers and copies them back and forth around every
+# loop edge (hundreds of copies per chunk at D = 64).
+FILE_FLAGS = {
+    "k_stats.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -48,7 +48,7 @@ template <int DP>
 struct GramShape {
   static constexpr int NB = DP / 16;                    // 16-column blocks
   static constexpr int T = NB * (NB + 1) / 2;           // blocks with I <= J
-  static constexpr int SB = DP >= 128 ? 2 : 1;          // super-block edge (blocks)
+  static constexpr int SB = DP >= 32 ? 2 : 1;           // super-block edge (blocks)
   static constexpr int NS = NB / SB;                    // super-blocks per edge
   static constexpr int TS = NS * (NS + 1) / 2;          // upper super-blocks
   static constexpr int TSPLIT = DP >= 256 ? 3 : 1;      // work-groups per row slice
