@@ -141,15 +141,15 @@ __global__ void fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned
 constexpr int kTileRows = 256;  // rows of X per work-group (8 waves x 32)
 constexpr int kBN = 32;         // rows of Y per LDS block
 
+// One segment of the distance matrix: X rows [x0, x0 + kTileRows) against
+// Y rows [yb, ye).  Row minima go to rowmin, column minima (COLMIN) to colmin,
+// both as order-preserving bit patterns through atomicMin.
 template <int DP, bool COLMIN>
-__device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
-                                               const float* __restrict__ xn,
-                                               const int64_t* __restrict__ dnX, int64_t hnX,
-                                               const float* __restrict__ Yp,
-                                               const float* __restrict__ yn,
-                                               const int64_t* __restrict__ dnY, int64_t hnY,
-                                               int ysplit, uint32_t* __restrict__ rowmin,
-                                               uint32_t* __restrict__ colmin, int bx) {
+__device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const float* __restrict__ xn,
+                                         int64_t nX, const float* __restrict__ Yp,
+                                         const float* __restrict__ yn, int64_t x0, int64_t yb,
+                                         int64_t ye, uint32_t* __restrict__ rowmin,
+                                         uint32_t* __restrict__ colmin) {
   constexpr int KH = DP / 2;       // k values per half-wave
   constexpr int ST = DP + 4;       // LDS row stride (floats): conflict-free b128 reads
   constexpr int NV4 = kBN * DP / 4;             // float4s per Y block
@@ -157,17 +157,6 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   __shared__ __attribute__((aligned(16))) float ys[2][kBN * ST];
   __shared__ float yns[2][kBN];
   __shared__ uint32_t cmin[2][kBN];
-
-  const int64_t nX = dev_or(dnX, hnX);
-  const int64_t nY = dev_or(dnY, hnY);
-  const int xblk = bx / ysplit;
-  const int ysi = bx - xblk * ysplit;
-  const int64_t x0 = (int64_t)xblk * kTileRows;
-  if (x0 >= nX) return;
-  const int64_t chunk = ((nY + ysplit - 1) / ysplit + kBN - 1) / kBN * kBN;
-  const int64_t yb = (int64_t)ysi * chunk;
-  const int64_t ye = min(nY, yb + chunk);
-  if (yb >= ye) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -293,16 +282,58 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   }
 }
 
+// Work-group bx of a (row tile) x (ysplit Y chunks) grid.
 template <int DP, bool COLMIN>
-__global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
-                                                 const float* __restrict__ xn,
-                                                 const int64_t* __restrict__ dnX, int64_t hnX,
-                                                 const float* __restrict__ Yp,
-                                                 const float* __restrict__ yn,
-                                                 const int64_t* __restrict__ dnY, int64_t hnY,
-                                                 int ysplit, uint32_t* __restrict__ rowmin,
-                                                 uint32_t* __restrict__ colmin) {
-  dist_tile_body<DP, COLMIN>(Xp, xn, dnX, hnX, Yp, yn, dnY, hnY, ysplit, rowmin, colmin, blockIdx.x);
+__device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
+                                               const float* __restrict__ xn,
+                                               const int64_t* __restrict__ dnX, int64_t hnX,
+                                               const float* __restrict__ Yp,
+                                               const float* __restrict__ yn,
+                                               const int64_t* __restrict__ dnY, int64_t hnY,
+                                               int ysplit, uint32_t* __restrict__ rowmin,
+                                               uint32_t* __restrict__ colmin, int bx) {
+  const int64_t nX = dev_or(dnX, hnX);
+  const int64_t nY = dev_or(dnY, hnY);
+  const int xblk = bx / ysplit;
+  const int ysi = bx - xblk * ysplit;
+  const int64_t x0 = (int64_t)xblk * kTileRows;
+  if (x0 >= nX) return;
+  const int64_t chunk = ((nY + ysplit - 1) / ysplit + kBN - 1) / kBN * kBN;
+  const int64_t yb = (int64_t)ysi * chunk;
+  const int64_t ye = min(nY, yb + chunk);
+  if (yb >= ye) return;
+  dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, x0, yb, ye, rowmin, colmin);
+}
+
+// Persistent form for one pair: the (row tile, Y block) cells of the whole
+// matrix, in row-major order, are cut into gridDim.x contiguous ranges whose
+// lengths differ by at most one, so all work-groups finish together whatever
+// the counts on the device turn out to be (a range crosses at most a few row
+// tiles; each crossing reloads the A operand and flushes the row minima).
+template <int DP, bool COLMIN>
+__global__ __launch_bounds__(512) void dist_tile_flat(const float* __restrict__ Xp,
+                                                      const float* __restrict__ xn,
+                                                      const int64_t* __restrict__ dnX, int64_t hnX,
+                                                      const float* __restrict__ Yp,
+                                                      const float* __restrict__ yn,
+                                                      const int64_t* __restrict__ dnY, int64_t hnY,
+                                                      uint32_t* __restrict__ rowmin,
+                                                      uint32_t* __restrict__ colmin) {
+  const int64_t nX = dev_or(dnX, hnX);
+  const int64_t nY = dev_or(dnY, hnY);
+  const int64_t nyb = (nY + kBN - 1) / kBN;
+  const int64_t cells = (nX + kTileRows - 1) / kTileRows * nyb;
+  const int64_t G = gridDim.x;
+  int64_t w = cells * blockIdx.x / G;
+  const int64_t hi = cells * (blockIdx.x + 1) / G;
+  while (w < hi) {
+    const int64_t xblk = w / nyb;
+    const int64_t end = min(hi, (xblk + 1) * nyb);
+    __syncthreads();  // LDS of the previous segment is no longer read
+    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, (w - xblk * nyb) * kBN,
+                         min(nY, (end - xblk * nyb) * kBN), rowmin, colmin);
+    w = end;
+  }
 }
 
 // ------------------------------------------------- low-precision copies
@@ -390,15 +421,13 @@ constexpr int kLpXS = 2;     // 32-row X sets per wave
 constexpr int kLpTileRows = kTileRows * kLpXS;
 
 template <int DP, int FMT, bool COLMIN>
-__global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
-                                                     const float* __restrict__ xn,
-                                                     const int64_t* __restrict__ dnX, int64_t hnX,
-                                                     const uint8_t* __restrict__ Yq,
-                                                     const float* __restrict__ yn,
-                                                     const int64_t* __restrict__ dnY, int64_t hnY,
-                                                     int ysplit, const uint32_t* __restrict__ maxabs,
-                                                     uint32_t* __restrict__ rowmin,
-                                                     uint32_t* __restrict__ colmin) {
+__device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
+                                            const float* __restrict__ xn, int64_t nX,
+                                            const uint8_t* __restrict__ Yq,
+                                            const float* __restrict__ yn, int64_t x0, int64_t yb,
+                                            int64_t ye, const uint32_t* __restrict__ maxabs,
+                                            uint32_t* __restrict__ rowmin,
+                                            uint32_t* __restrict__ colmin) {
   using F = LpFmt<FMT>;
   constexpr int XS = kLpXS;
   constexpr int RB = DP * F::EB;            // bytes per row
@@ -414,17 +443,6 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
   __shared__ __attribute__((aligned(16))) uint8_t ys[2][kLpBN * STB];
   __shared__ float yns[2][kLpBN];
   __shared__ uint32_t cmin[2][kLpBN];
-
-  const int64_t nX = dev_or(dnX, hnX);
-  const int64_t nY = dev_or(dnY, hnY);
-  const int xblk = blockIdx.x / ysplit;
-  const int ysi = blockIdx.x - xblk * ysplit;
-  const int64_t x0 = (int64_t)xblk * kLpTileRows;
-  if (x0 >= nX) return;
-  const int64_t chunk = ((nY + ysplit - 1) / ysplit + kLpBN - 1) / kLpBN * kLpBN;
-  const int64_t yb = (int64_t)ysi * chunk;
-  const int64_t ye = min(nY, yb + chunk);
-  if (yb >= ye) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -612,6 +630,35 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
       const int64_t r = x0 + 32 * (XS * wave + x) + 8 * (c >> 2) + 4 * g + (c & 3);
       if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
     }
+  }
+}
+
+// Persistent form of the low-precision tile (same cut of the matrix into
+// equal contiguous ranges of (row tile, Y block) cells as dist_tile_flat).
+template <int DP, int FMT, bool COLMIN>
+__global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
+                                                     const float* __restrict__ xn,
+                                                     const int64_t* __restrict__ dnX, int64_t hnX,
+                                                     const uint8_t* __restrict__ Yq,
+                                                     const float* __restrict__ yn,
+                                                     const int64_t* __restrict__ dnY, int64_t hnY,
+                                                     const uint32_t* __restrict__ maxabs,
+                                                     uint32_t* __restrict__ rowmin,
+                                                     uint32_t* __restrict__ colmin) {
+  const int64_t nX = dev_or(dnX, hnX);
+  const int64_t nY = dev_or(dnY, hnY);
+  const int64_t nyb = (nY + kLpBN - 1) / kLpBN;
+  const int64_t cells = (nX + kLpTileRows - 1) / kLpTileRows * nyb;
+  const int64_t G = gridDim.x;
+  int64_t w = cells * blockIdx.x / G;
+  const int64_t hi = cells * (blockIdx.x + 1) / G;
+  while (w < hi) {
+    const int64_t xblk = w / nyb;
+    const int64_t end = min(hi, (xblk + 1) * nyb);
+    __syncthreads();  // LDS of the previous segment is no longer read
+    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, (w - xblk * nyb) * kLpBN,
+                                 min(nY, (end - xblk * nyb) * kLpBN), maxabs, rowmin, colmin);
+    w = end;
   }
 }
 
@@ -947,38 +994,57 @@ prohd_status launch_quant(int fmt, PrepSet o, const int64_t* dn, int64_t cap, co
   return PROHD_OK;
 }
 
+// resident work-groups of a persistent tile kernel (from its register and
+// LDS use), capped by the cells of the matrix
+template <typename K>
+int64_t flat_grid(K kernel, int64_t cells) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 512, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return std::max<int64_t>(1, std::min<int64_t>(cells, (int64_t)per_cu * cu_count()));
+}
+
 template <int DP>
 prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
                          const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
                          uint32_t* colmin, hipStream_t s) {
-  const int64_t xblocks = cdiv(capX, fmt == FMT_F32 ? kTileRows : kLpTileRows);
-  const int split = choose_split(xblocks, capY, fmt == FMT_F32 ? 4 * kBN : 2 * kLpBN);
-  const int64_t grid = xblocks * split;
-  if (grid > 0x7fffffff) return fail(PROHD_EUNSUPPORTED, "tile grid too large");
-  const dim3 G((unsigned)grid), T(512);
+  // one resident work-group per slot, at most one per (row tile, Y block)
+  // cell of the capacities
+  const dim3 T(512);
   if (fmt == FMT_F32) {
+    const int64_t cells = cdiv(capX, kTileRows) * cdiv(capY, kBN);
     if (colmin) {
-      PROHD_LAUNCH("hd_tile", (dist_tile<DP, true>), G, T, 0, s, X.p, X.n, dnX, capX, Y.p, Y.n, dnY,
-                   capY, split, rowmin, colmin);
+      auto k = dist_tile_flat<DP, true>;
+      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.p, X.n, dnX, capX,
+                   Y.p, Y.n, dnY, capY, rowmin, colmin);
     } else {
-      PROHD_LAUNCH("hd_tile", (dist_tile<DP, false>), G, T, 0, s, X.p, X.n, dnX, capX, Y.p, Y.n, dnY,
-                   capY, split, rowmin, colmin);
+      auto k = dist_tile_flat<DP, false>;
+      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.p, X.n, dnX, capX,
+                   Y.p, Y.n, dnY, capY, rowmin, colmin);
     }
-  } else if (fmt == FMT_BF16) {
+    return PROHD_OK;
+  }
+  const int64_t cells = cdiv(capX, kLpTileRows) * cdiv(capY, kLpBN);
+  if (fmt == FMT_BF16) {
     if (colmin) {
-      PROHD_LAUNCH("hd_tile_bf16", (dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, true>), G, T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+      auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, true>;
+      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     } else {
-      PROHD_LAUNCH("hd_tile_bf16", (dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, false>), G, T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+      auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, false>;
+      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     }
   } else {
     if (colmin) {
-      PROHD_LAUNCH("hd_tile_fp8", (dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, true>), G, T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+      auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, true>;
+      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     } else {
-      PROHD_LAUNCH("hd_tile_fp8", (dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, false>), G, T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, split, maxabs, rowmin, colmin);
+      auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, false>;
+      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     }
   }
   return PROHD_OK;
