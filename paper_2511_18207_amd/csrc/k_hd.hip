@@ -138,8 +138,18 @@ __global__ void fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned
 }
 
 // ------------------------------------------------------------------ tile
+// raw buffer descriptor word 3 for gfx950: offsets past num_records read zero
+constexpr int kBufferFlags = 0x00020000;
+
 constexpr int kTileRows = 256;  // rows of X per work-group (8 waves x 32)
-constexpr int kBN = 32;         // rows of Y per LDS block
+constexpr int kBN = 32;         // columns (Y rows) of one 32 x 32 subtile
+
+// Y rows per LDS buffer.  At D = 256 a buffer holds two subtiles, copied
+// from memory straight into LDS (one 1 KiB row per wave instruction, no
+// staging registers), so there is one barrier per 64 columns; narrower rows
+// stage one subtile at a time through registers.
+template <int DP>
+__host__ __device__ constexpr int tile_bn() { return DP == 256 ? 2 * kBN : kBN; }
 
 // One segment of the distance matrix: X rows [x0, x0 + kTileRows) against
 // Y rows [yb, ye).  Row minima go to rowmin, column minima (COLMIN) to colmin,
@@ -152,11 +162,14 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
                                          uint32_t* __restrict__ colmin) {
   constexpr int KH = DP / 2;       // k values per half-wave
   constexpr int ST = DP + 4;       // LDS row stride (floats): conflict-free b128 reads
-  constexpr int NV4 = kBN * DP / 4;             // float4s per Y block
-  constexpr int PF = (NV4 + 511) / 512;         // float4s per thread per block
-  __shared__ __attribute__((aligned(16))) float ys[2][kBN * ST];
-  __shared__ float yns[2][kBN];
-  __shared__ uint32_t cmin[2][kBN];
+  constexpr int BN = tile_bn<DP>();
+  constexpr int NSUB = BN / kBN;   // subtiles per buffer
+  constexpr bool DMA = DP == 256;  // rows of 1 KiB go straight into LDS
+  constexpr int NV4 = BN * DP / 4;              // float4s per Y block
+  constexpr int PF = DMA ? 1 : (NV4 + 511) / 512;   // float4s per thread per block
+  __shared__ __attribute__((aligned(16))) float ys[2][BN * ST];
+  __shared__ float yns[2][BN];
+  __shared__ uint32_t cmin[2][BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -190,31 +203,46 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
     rmin[v] = __uint_as_float(kInfBits);
   }
 
-  auto load_block = [&](int64_t y0, float4 (&buf)[PF], float& ynv) {
+  // Y block at y0 into buffer b: DMA rows past ye read as zero (buffer
+  // range), register-staged rows past ye are zero-filled
+  auto load_block = [&](int64_t y0, int b, float4 (&buf)[PF], float& ynv) {
+    if constexpr (DMA) {
+      const int rows = (int)min<int64_t>(BN, ye - y0);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(Yp + y0 * DP), 0, rows * DP * 4, kBufferFlags);
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const int f = tid + 512 * p;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (f < NV4) {
-        const int r = f / (DP / 4);
-        const int k4 = f - r * (DP / 4);
-        if (y0 + r < ye) v = reinterpret_cast<const float4*>(Yp + (y0 + r) * DP)[k4];
+      for (int r = wave; r < BN; r += 8)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(&ys[b][r * ST]), 16,
+            (r * DP + 4 * lane) * 4, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int f = tid + 512 * p;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (f < NV4) {
+          const int r = f / (DP / 4);
+          const int k4 = f - r * (DP / 4);
+          if (y0 + r < ye) v = reinterpret_cast<const float4*>(Yp + (y0 + r) * DP)[k4];
+        }
+        buf[p] = v;
       }
-      buf[p] = v;
     }
-    ynv = (tid < kBN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
+    ynv = (tid < BN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
   };
   auto store_block = [&](int b, const float4 (&buf)[PF], float ynv) {
+    if constexpr (!DMA) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const int f = tid + 512 * p;
-      if (f < NV4) {
-        const int r = f / (DP / 4);
-        const int k4 = f - r * (DP / 4);
-        *reinterpret_cast<float4*>(&ys[b][r * ST + 4 * k4]) = buf[p];
+      for (int p = 0; p < PF; ++p) {
+        const int f = tid + 512 * p;
+        if (f < NV4) {
+          const int r = f / (DP / 4);
+          const int k4 = f - r * (DP / 4);
+          *reinterpret_cast<float4*>(&ys[b][r * ST + 4 * k4]) = buf[p];
+        }
       }
     }
-    if (tid < kBN) {
+    if (tid < BN) {
       yns[b][tid] = ynv;
       cmin[b][tid] = kInfBits;
     }
@@ -222,43 +250,49 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
 
   float4 pf[PF];
   float pyn;
-  load_block(yb, pf, pyn);
+  load_block(yb, 0, pf, pyn);
   store_block(0, pf, pyn);
+  if (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
   __syncthreads();
 
   int cur = 0;
-  for (int64_t y0 = yb; y0 < ye; y0 += kBN) {
-    const bool more = y0 + kBN < ye;
-    if (more) load_block(y0 + kBN, pf, pyn);
-
-    // one accumulator: dependent 32x32x2 issues with the same destination
-    // accumulate back to back in the matrix pipe
-    floatx16 acc = {0.f};
-    const float* yrow = &ys[cur][c * ST + g * KH];
+  for (int64_t y0 = yb; y0 < ye; y0 += BN) {
+    const bool more = y0 + BN < ye;
+    if (more) load_block(y0 + BN, cur ^ 1, pf, pyn);
 #pragma unroll
-    for (int s = 0; s < KH; s += 4) {
-      const float4 b = *reinterpret_cast<const float4*>(yrow + s);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 0], b.x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 1], b.y, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 2], b.z, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 3], b.w, acc, 0, 0, 0);
-    }
-    // epilogue: lane holds column c of the block, rows 8*(v/4) + 4*g + v%4
-    const float ynv = yns[cur][c];
-    float cm = __uint_as_float(kInfBits);
+    for (int sub = 0; sub < NSUB; ++sub) {
+      // one accumulator: dependent 32x32x2 issues with the same destination
+      // accumulate back to back in the matrix pipe
+      floatx16 acc = {0.f};
+      const float* yrow = &ys[cur][(kBN * sub + c) * ST + g * KH];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float d = fmaf(-2.f, acc[v], xq[v] + ynv);
-      rmin[v] = fminf(rmin[v], d);
-      cm = fminf(cm, d);
-    }
-    if (COLMIN) {
-      cm = fminf(cm, __shfl_xor(cm, 32));
-      if (g == 0) atomicMin(&cmin[cur][c], clamp_bits(cm));
+      for (int s = 0; s < KH; s += 4) {
+        const float4 b = *reinterpret_cast<const float4*>(yrow + s);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 0], b.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 1], b.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 2], b.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 3], b.w, acc, 0, 0, 0);
+      }
+      // epilogue: lane holds column c of the subtile, rows 8*(v/4) + 4*g + v%4
+      const float ynv = yns[cur][kBN * sub + c];
+      float cm = __uint_as_float(kInfBits);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float d = fmaf(-2.f, acc[v], xq[v] + ynv);
+        rmin[v] = fminf(rmin[v], d);
+        cm = fminf(cm, d);
+      }
+      if (COLMIN) {
+        cm = fminf(cm, __shfl_xor(cm, 32));
+        if (g == 0) atomicMin(&cmin[cur][kBN * sub + c], clamp_bits(cm));
+      }
     }
     if (more) store_block(cur ^ 1, pf, pyn);
+    if (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
     __syncthreads();
-    if (COLMIN && wave == 0 && lane < kBN) {
+    // column minima of the block: wave 0 (which also resets cmin of the
+    // other buffer, so this read precedes that write in program order)
+    if (COLMIN && wave == 0 && lane < BN) {
       const uint32_t v = cmin[cur][lane];
       if (y0 + lane < ye) atomicMin(&colmin[y0 + lane], v);
     }
@@ -298,7 +332,8 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   const int ysi = bx - xblk * ysplit;
   const int64_t x0 = (int64_t)xblk * kTileRows;
   if (x0 >= nX) return;
-  const int64_t chunk = ((nY + ysplit - 1) / ysplit + kBN - 1) / kBN * kBN;
+  constexpr int BN = tile_bn<DP>();
+  const int64_t chunk = ((nY + ysplit - 1) / ysplit + BN - 1) / BN * BN;
   const int64_t yb = (int64_t)ysi * chunk;
   const int64_t ye = min(nY, yb + chunk);
   if (yb >= ye) return;
@@ -321,7 +356,8 @@ __global__ __launch_bounds__(512) void dist_tile_flat(const float* __restrict__ 
                                                       uint32_t* __restrict__ colmin) {
   const int64_t nX = dev_or(dnX, hnX);
   const int64_t nY = dev_or(dnY, hnY);
-  const int64_t nyb = (nY + kBN - 1) / kBN;
+  constexpr int BN = tile_bn<DP>();
+  const int64_t nyb = (nY + BN - 1) / BN;
   const int64_t cells = (nX + kTileRows - 1) / kTileRows * nyb;
   const int64_t G = gridDim.x;
   int64_t w = cells * blockIdx.x / G;
@@ -330,8 +366,8 @@ __global__ __launch_bounds__(512) void dist_tile_flat(const float* __restrict__ 
     const int64_t xblk = w / nyb;
     const int64_t end = min(hi, (xblk + 1) * nyb);
     __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, (w - xblk * nyb) * kBN,
-                         min(nY, (end - xblk * nyb) * kBN), rowmin, colmin);
+    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, (w - xblk * nyb) * BN,
+                         min(nY, (end - xblk * nyb) * BN), rowmin, colmin);
     w = end;
   }
 }
@@ -485,7 +521,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     if constexpr (DMA) {
       const int rows = (int)min<int64_t>(kLpBN, ye - y0);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<uint8_t*>(Yq + y0 * RB), 0, rows * RB, 0x00020000);
+          const_cast<uint8_t*>(Yq + y0 * RB), 0, rows * RB, kBufferFlags);
       constexpr int PPR = RB / 256;   // pieces per row
       for (int i = wave; i < kLpBN * PPR; i += 8) {
         const int r = i / PPR, h = i - r * PPR;
@@ -1013,7 +1049,7 @@ prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, P
   // cell of the capacities
   const dim3 T(512);
   if (fmt == FMT_F32) {
-    const int64_t cells = cdiv(capX, kTileRows) * cdiv(capY, kBN);
+    const int64_t cells = cdiv(capX, kTileRows) * cdiv(capY, tile_bn<DP>());
     if (colmin) {
       auto k = dist_tile_flat<DP, true>;
       PROHD_LAUNCH("hd_tile", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.p, X.n, dnX, capX,
