@@ -340,35 +340,53 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, x0, yb, ye, rowmin, colmin);
 }
 
-// Persistent form for one pair: the (row tile, Y block) cells of the whole
-// matrix, in row-major order, are cut into gridDim.x contiguous ranges whose
-// lengths differ by at most one, so all work-groups finish together whatever
-// the counts on the device turn out to be (a range crosses at most a few row
-// tiles; each crossing reloads the A operand and flushes the row minima).
+// Chunk count of a persistent tile launch: the matrix is cut into xt x S
+// (row tile, Y chunk) items and G work-groups take them in rounds, so S is
+// the smallest split (S <= min(16, nyb)) whose last round is at least
+// 98.5 % full, else the split that fills it best.  Decided on the device from
+// the actual counts.
+__device__ __forceinline__ int64_t tile_split(int64_t xt, int64_t nyb, int64_t G) {
+  int64_t S = 1, bi = 0, bs = 1;   // best split, its items and slots
+  for (int64_t s = 1; s <= 16 && s <= nyb; ++s) {
+    const int64_t items = xt * s;
+    const int64_t slots = (items + G - 1) / G * G;
+    if (items * bs > bi * slots) {
+      bi = items;
+      bs = slots;
+      S = s;
+    }
+    if (items * 1000 >= slots * 985) break;
+  }
+  return S;
+}
+
+// Persistent form for one pair.  Items are taken chunk-major (item i: chunk
+// i / xt, row tile i % xt), work-group b doing items b, b + G, ...: the items
+// of one round start together at the beginning of their chunk and sweep it in
+// step, so the work-groups of an XCD (ids congruent modulo 8), which hold
+// consecutive items of one or two chunks, read each Y block at about the same
+// time and one L2 fill serves them all.
 template <int DP, bool COLMIN>
-__global__ __launch_bounds__(512) void dist_tile_flat(const float* __restrict__ Xp,
-                                                      const float* __restrict__ xn,
-                                                      const int64_t* __restrict__ dnX, int64_t hnX,
-                                                      const float* __restrict__ Yp,
-                                                      const float* __restrict__ yn,
-                                                      const int64_t* __restrict__ dnY, int64_t hnY,
-                                                      uint32_t* __restrict__ rowmin,
-                                                      uint32_t* __restrict__ colmin) {
+__global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
+                                                 const float* __restrict__ xn,
+                                                 const int64_t* __restrict__ dnX, int64_t hnX,
+                                                 const float* __restrict__ Yp,
+                                                 const float* __restrict__ yn,
+                                                 const int64_t* __restrict__ dnY, int64_t hnY,
+                                                 uint32_t* __restrict__ rowmin,
+                                                 uint32_t* __restrict__ colmin) {
+  constexpr int BN = tile_bn<DP>();
   const int64_t nX = dev_or(dnX, hnX);
   const int64_t nY = dev_or(dnY, hnY);
-  constexpr int BN = tile_bn<DP>();
+  const int64_t xt = (nX + kTileRows - 1) / kTileRows;
   const int64_t nyb = (nY + BN - 1) / BN;
-  const int64_t cells = (nX + kTileRows - 1) / kTileRows * nyb;
-  const int64_t G = gridDim.x;
-  int64_t w = cells * blockIdx.x / G;
-  const int64_t hi = cells * (blockIdx.x + 1) / G;
-  while (w < hi) {
-    const int64_t xblk = w / nyb;
-    const int64_t end = min(hi, (xblk + 1) * nyb);
-    __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, (w - xblk * nyb) * BN,
-                         min(nY, (end - xblk * nyb) * BN), rowmin, colmin);
-    w = end;
+  if (xt == 0 || nyb == 0) return;
+  const int64_t S = tile_split(xt, nyb, gridDim.x);
+  for (int64_t i = blockIdx.x; i < xt * S; i += gridDim.x) {
+    const int64_t ysi = i / xt, xblk = i - ysi * xt;
+    __syncthreads();  // LDS of the previous item is no longer read
+    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, ysi * nyb / S * BN,
+                         min(nY, (ysi + 1) * nyb / S * BN), rowmin, colmin);
   }
 }
 
@@ -669,8 +687,8 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   }
 }
 
-// Persistent form of the low-precision tile (same cut of the matrix into
-// equal contiguous ranges of (row tile, Y block) cells as dist_tile_flat).
+// Persistent form of the low-precision tile (same rounds of chunk-major
+// items as dist_tile).
 template <int DP, int FMT, bool COLMIN>
 __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
                                                      const float* __restrict__ xn,
@@ -683,18 +701,15 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
                                                      uint32_t* __restrict__ colmin) {
   const int64_t nX = dev_or(dnX, hnX);
   const int64_t nY = dev_or(dnY, hnY);
+  const int64_t xt = (nX + kLpTileRows - 1) / kLpTileRows;
   const int64_t nyb = (nY + kLpBN - 1) / kLpBN;
-  const int64_t cells = (nX + kLpTileRows - 1) / kLpTileRows * nyb;
-  const int64_t G = gridDim.x;
-  int64_t w = cells * blockIdx.x / G;
-  const int64_t hi = cells * (blockIdx.x + 1) / G;
-  while (w < hi) {
-    const int64_t xblk = w / nyb;
-    const int64_t end = min(hi, (xblk + 1) * nyb);
-    __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, (w - xblk * nyb) * kLpBN,
-                                 min(nY, (end - xblk * nyb) * kLpBN), maxabs, rowmin, colmin);
-    w = end;
+  if (xt == 0 || nyb == 0) return;
+  const int64_t S = tile_split(xt, nyb, gridDim.x);
+  for (int64_t i = blockIdx.x; i < xt * S; i += gridDim.x) {
+    const int64_t ysi = i / xt, xblk = i - ysi * xt;
+    __syncthreads();  // LDS of the previous item is no longer read
+    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, ysi * nyb / S * kLpBN,
+                                 min(nY, (ysi + 1) * nyb / S * kLpBN), maxabs, rowmin, colmin);
   }
 }
 
@@ -1031,55 +1046,55 @@ prohd_status launch_quant(int fmt, PrepSet o, const int64_t* dn, int64_t cap, co
 }
 
 // resident work-groups of a persistent tile kernel (from its register and
-// LDS use), capped by the cells of the matrix
+// LDS use), capped by the items of the matrix
 template <typename K>
-int64_t flat_grid(K kernel, int64_t cells) {
+int64_t tile_grid(K kernel, int64_t items) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 512, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
-  return std::max<int64_t>(1, std::min<int64_t>(cells, (int64_t)per_cu * cu_count()));
+  return std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)per_cu * cu_count()));
 }
 
 template <int DP>
 prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
                          const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
                          uint32_t* colmin, hipStream_t s) {
-  // one resident work-group per slot, at most one per (row tile, Y block)
-  // cell of the capacities
+  // one resident work-group per slot, at most one per item the capacities
+  // allow (16 chunks per row tile at most)
   const dim3 T(512);
   if (fmt == FMT_F32) {
-    const int64_t cells = cdiv(capX, kTileRows) * cdiv(capY, tile_bn<DP>());
+    const int64_t items = cdiv(capX, kTileRows) * std::min<int64_t>(16, cdiv(capY, tile_bn<DP>()));
     if (colmin) {
-      auto k = dist_tile_flat<DP, true>;
-      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.p, X.n, dnX, capX,
+      auto k = dist_tile<DP, true>;
+      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, dnX, capX,
                    Y.p, Y.n, dnY, capY, rowmin, colmin);
     } else {
-      auto k = dist_tile_flat<DP, false>;
-      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.p, X.n, dnX, capX,
+      auto k = dist_tile<DP, false>;
+      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, dnX, capX,
                    Y.p, Y.n, dnY, capY, rowmin, colmin);
     }
     return PROHD_OK;
   }
-  const int64_t cells = cdiv(capX, kLpTileRows) * cdiv(capY, kLpBN);
+  const int64_t items = cdiv(capX, kLpTileRows) * std::min<int64_t>(16, cdiv(capY, kLpBN));
   if (fmt == FMT_BF16) {
     if (colmin) {
       auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, true>;
-      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
                    capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     } else {
       auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, false>;
-      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
                    capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     }
   } else {
     if (colmin) {
       auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, true>;
-      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
                    capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     } else {
       auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, false>;
-      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)flat_grid(k, cells)), T, 0, s, X.q, X.qn, dnX,
+      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
                    capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
     }
   }
