@@ -28,6 +28,7 @@
 // padding directions below every real eigenvalue), the centroid axis (dirs
 // row 0) and the status word.
 
+#include <type_traits>
 #include <utility>
 
 #include "batch.h"
@@ -174,45 +175,56 @@ __device__ __forceinline__ void gram_body(const float* __restrict__ shift, const
     const int lim = (int)min<int64_t>(RC, r_end - (r_begin + c * RC));
     if (lim == RC && D == DP) {
       // full chunk, no padding columns: no masks; each step reads the next
-      // step's values ahead (the scheduling barrier keeps that order)
+      // step's values ahead (the scheduling barrier keeps that order).  The
+      // loop is instantiated separately for diagonal and off-diagonal
+      // super-blocks (DG is wave-uniform), so neither carries the other's
+      // branches.
       const float* bq = buf + rsub * DP;
-      float f[SB], g[SB];
-#pragma unroll
-      for (int x = 0; x < SB; ++x) {
-        f[x] = bq[ca[x]];
-        g[x] = bq[cb[x]];
-      }
-#pragma unroll
-      for (int q = 0; q < RC / 4; ++q) {
-        float nf[SB], ng[SB];
+      auto fast = [&](auto DGC) {
+        constexpr bool DG = decltype(DGC)::value;
+        float f[SB], g[SB];
 #pragma unroll
         for (int x = 0; x < SB; ++x) {
-          nf[x] = q + 1 < RC / 4 ? bq[4 * (q + 1) * DP + ca[x]] : 0.f;
-          ng[x] = (q + 1 < RC / 4 && !diag) ? bq[4 * (q + 1) * DP + cb[x]] : 0.f;
+          f[x] = bq[ca[x]];
+          g[x] = DG ? 0.f : bq[cb[x]];
         }
-        double a[SB], b[SB];
 #pragma unroll
-        for (int x = 0; x < SB; ++x) {
-          a[x] = (double)f[x] - sha[x];
-          b[x] = diag ? a[x] : (double)g[x] - shb[x];
-          if (diag) {
-            bad |= !(f[x] - f[x] == 0.f);
-            sum[x] += a[x];
+        for (int q = 0; q < RC / 4; ++q) {
+          float nf[SB], ng[SB];
+#pragma unroll
+          for (int x = 0; x < SB; ++x) {
+            nf[x] = q + 1 < RC / 4 ? bq[4 * (q + 1) * DP + ca[x]] : 0.f;
+            ng[x] = (q + 1 < RC / 4 && !DG) ? bq[4 * (q + 1) * DP + cb[x]] : 0.f;
           }
+          double a[SB], b[SB];
+#pragma unroll
+          for (int x = 0; x < SB; ++x) {
+            a[x] = (double)f[x] - sha[x];
+            b[x] = DG ? a[x] : (double)g[x] - shb[x];
+            if (DG) {
+              bad |= !(f[x] - f[x] == 0.f);
+              sum[x] += a[x];
+            }
+          }
+#pragma unroll
+          for (int x = 0; x < SB; ++x)
+#pragma unroll
+            for (int y = 0; y < SB; ++y)
+              if (!DG || x <= y)
+                acc[x * SB + y] =
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x * SB + y], 0, 0, 0);
+#pragma unroll
+          for (int x = 0; x < SB; ++x) {
+            f[x] = nf[x];
+            g[x] = ng[x];
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
-#pragma unroll
-        for (int x = 0; x < SB; ++x)
-#pragma unroll
-          for (int y = 0; y < SB; ++y)
-            if (!diag || x <= y)
-              acc[x * SB + y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x * SB + y], 0, 0, 0);
-#pragma unroll
-        for (int x = 0; x < SB; ++x) {
-          f[x] = nf[x];
-          g[x] = ng[x];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      };
+      if (diag)
+        fast(std::true_type{});
+      else
+        fast(std::false_type{});
       continue;
     }
 #pragma unroll 2
