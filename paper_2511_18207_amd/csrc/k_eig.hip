@@ -188,7 +188,12 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
     // reflector (every wave computes the same values in the same order)
     const double alpha = col[j + 1];
     double s2 = 0.0;
-    for (int k = lane; k < DP; k += 64) s2 += (k > j + 1) ? col[k] * col[k] : 0.0;
+    // LDS values are loaded unconditionally and then selected: a load under
+    // a lane condition becomes an exec-masked branch
+    for (int k = lane; k < DP; k += 64) {
+      const double ck = col[k];
+      s2 += (k > j + 1) ? ck * ck : 0.0;
+    }
     const double sigma = wave_sum_dpp(s2);
     double tj = 0.0, beta = alpha, scale = 0.0;
     if (sigma > 0.0) {
@@ -197,7 +202,10 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       tj = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    auto vof = [&](int k) { return k == j + 1 ? 1.0 : (k > j + 1 ? col[k] * scale : 0.0); };
+    auto vof = [&](int k) {
+      const double ck = col[k];
+      return k == j + 1 ? 1.0 : (k > j + 1 ? ck * scale : 0.0);
+    };
     if (tid == 0) {
       ee[j] = beta;
       tau[j] = tj;
@@ -268,7 +276,10 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
     for (int k = lane; k < DP; k += 64) kd += pbuf[k] * vof(k);
     const double K = 0.5 * tj * wave_sum_dpp(kd);
     if (!owner) return;
-    auto wof = [&](int k) { return k > j ? pbuf[k] - K * vof(k) : 0.0; };
+    auto wof = [&](int k) {
+      const double pk = pbuf[k], vk = vof(k);
+      return k > j ? pk - K * vk : 0.0;
+    };
     const double wa0 = wof(16 * RA + rb2), wa1 = wof(16 * RA + rb2 + 1);
     const double wb0 = wof(16 * RB + rb2), wb1 = wof(16 * RB + rb2 + 1);
     const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
