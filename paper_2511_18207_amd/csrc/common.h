@@ -100,6 +100,12 @@ size_t compact_ws_bytes(int64_t n);
 prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n,
                            int32_t* idx, int64_t cap, int64_t* count, void* ws, size_t ws_bytes,
                            hipStream_t s);
+// Select, then compact, up to two small segments in one launch (one
+// work-group per segment, which also clears the segment's flags first):
+// meant for a few hundred thousand entries per segment or fewer.  Same
+// result as select_mark on cleared flags followed by compact_flags.
+prohd_status select_compact_small(const SelSegment* segs, int nseg, int32_t* const* idx,
+                                  int64_t cap, int64_t* const* count, hipStream_t s);
 // flags[idx[i]] = 1 for the first *count entries (count clipped to cap).
 prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64_t cap,
                                  uint8_t* flags, hipStream_t s);

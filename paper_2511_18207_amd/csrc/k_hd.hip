@@ -1173,9 +1173,22 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
 
 // Top-R rows of both directions' minima (`mins[d]`, device length dn[d] /
 // host n[d]) -> w[d].cand / w[d].count; one selection launch chain for both.
+// Segments up to this length take the one-launch selection.
+constexpr int64_t kSmallRows = 1 << 18;
+
 prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const int64_t* const dn[2],
                        DirWork* w, void* sel_ws, size_t sel_bytes, hipStream_t s) {
   SelSegment seg[2];
+  if (std::max(n[0], n[1]) <= kSmallRows) {
+    int32_t* idx[2];
+    int64_t* cnt[2];
+    for (int d = 0; d < 2; ++d) {
+      seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, kRefineRows, w[d].flags};
+      idx[d] = w[d].cand;
+      cnt[d] = w[d].count;
+    }
+    return select_compact_small(seg, 2, idx, kRefineRows, cnt, s);
+  }
   for (int d = 0; d < 2; ++d) {
     prohd_status st = zero_bytes(w[d].flags, (size_t)n[d], s);
     if (st) return st;

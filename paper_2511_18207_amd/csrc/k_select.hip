@@ -340,8 +340,10 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, size_t words, uint8_t* __r
 // index, as in the multi-launch selection).
 constexpr int kSegT = 256;
 constexpr int kSegBins = 2048;
+constexpr int kSegUnr = 8;   // loads in flight per thread in the streaming passes
 
-// Exclusive prefix over the work-group (256 threads); *total gets the sum.
+// Exclusive prefix over the work-group (NT threads); *total gets the sum.
+template <int NT>
 __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
@@ -354,7 +356,7 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint
   __syncthreads();
   uint32_t base = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kSegT / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     const uint32_t t = lds[w];
     base += (w < wave) ? t : 0u;
     tot += t;
@@ -364,130 +366,192 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint
   return base + x - v;
 }
 
+// Selection of one segment by one work-group (LDS scratch passed in); the
+// caller runs it uniformly over the work-group.
+template <int NT>
+__device__ __forceinline__ void select_seg_body(const SegJob& j, uint32_t (*hist)[kSegBins],
+                                                uint32_t* scan_lds, uint32_t* s_bin,
+                                                uint32_t* s_before) {
+  const int tid = threadIdx.x;
+  int64_t n = j.dn ? *j.dn : j.n;
+  n = n < j.n ? (n > 0 ? n : 0) : j.n;
+  const uint32_t k[2] = {(uint32_t)min<int64_t>(j.lo, n), (uint32_t)min<int64_t>(j.hi, n)};
+  if (n == 0 || (k[0] == 0 && k[1] == 0)) return;
+  uint32_t pre[2] = {0u, 0u}, rem[2] = {k[0], k[1]}, eq[2] = {0u, 0u};
+  const int shifts[3] = {21, 10, 0};
+  const uint32_t masks[3] = {0x7FFu, 0x7FFu, 0x3FFu};
+  const uint32_t pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
+  for (int p = 0; p < 3; ++p) {
+    __syncthreads();
+    for (int b = tid; b < 2 * kSegBins; b += NT) (&hist[0][0])[b] = 0u;
+    __syncthreads();
+    // kSegUnr loads in flight per thread (indices clamped, so the loads are
+    // unconditional), then their histogram updates
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)NT * kSegUnr) {
+      uint32_t keys[kSegUnr];
+#pragma unroll
+      for (int u = 0; u < kSegUnr; ++u) keys[u] = fkey(j.vals[min(i0 + u * NT + tid, n - 1)]);
+#pragma unroll
+      for (int u = 0; u < kSegUnr; ++u) {
+        if (i0 + u * NT + tid >= n) continue;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const uint32_t ke = e ? ~keys[u] : keys[u];
+          if (k[e] && (ke & pmasks[p]) == pre[e]) atomicAdd(&hist[e][(ke >> shifts[p]) & masks[p]], 1u);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (!k[e]) continue;   // uniform
+      uint32_t loc = 0;
+#pragma unroll
+      for (int b = 0; b < kSegBins / NT; ++b) loc += hist[e][tid * (kSegBins / NT) + b];
+      uint32_t tot;
+      const uint32_t ex = wg_excl_scan<NT>(loc, scan_lds, &tot);
+      if (ex < rem[e] && rem[e] <= ex + loc) {
+        uint32_t acc = ex;
+        for (int b = 0; b < kSegBins / NT; ++b) {
+          const int bin = tid * (kSegBins / NT) + b;
+          const uint32_t h = hist[e][bin];
+          if (acc + h >= rem[e]) {
+            s_bin[e] = (uint32_t)bin;
+            s_before[e] = acc;
+            break;
+          }
+          acc += h;
+        }
+      }
+      __syncthreads();
+      pre[e] |= s_bin[e] << shifts[p];
+      rem[e] -= s_before[e];
+      if (p == 2) eq[e] = hist[e][s_bin[e]];
+      __syncthreads();
+    }
+  }
+  // mark: below the k-th key, and ties when all of them fit
+  bool ordered[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) ordered[e] = k[e] && rem[e] < eq[e];
+  for (int64_t i0 = 0; i0 < n; i0 += (int64_t)NT * kSegUnr) {
+    uint32_t keys[kSegUnr];
+#pragma unroll
+    for (int u = 0; u < kSegUnr; ++u) keys[u] = fkey(j.vals[min(i0 + u * NT + tid, n - 1)]);
+#pragma unroll
+    for (int u = 0; u < kSegUnr; ++u) {
+      const int64_t i = i0 + u * NT + tid;
+      bool f = false;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const uint32_t ke = e ? ~keys[u] : keys[u];
+        if (k[e]) f |= ke < pre[e] || (ke == pre[e] && !ordered[e]);
+      }
+      if (f && i < n) j.flags[i] = 1;
+    }
+  }
+  // ties that do not all fit: rank them in index order
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (!ordered[e]) continue;   // uniform
+    uint32_t taken = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += NT) {
+      const int64_t i = c0 + tid;
+      bool tie = false;
+      if (i < n) {
+        const uint32_t key = fkey(j.vals[i]);
+        tie = (e ? ~key : key) == pre[e];
+      }
+      uint32_t tot;
+      const uint32_t ex = wg_excl_scan<NT>(tie ? 1u : 0u, scan_lds, &tot);
+      if (tie && taken + ex < rem[e]) j.flags[i] = 1;
+      taken += tot;
+      if (taken >= rem[e]) break;   // uniform
+    }
+  }
+}
+
 __global__ __launch_bounds__(kSegT) void select_seg(const SegJob* __restrict__ jobs, int njobs) {
   __shared__ uint32_t hist[2][kSegBins];
   __shared__ uint32_t scan_lds[kSegT / 64];
   __shared__ uint32_t s_bin[2], s_before[2];
-  const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const SegJob j = jobs[it];
-    int64_t n = j.dn ? *j.dn : j.n;
-    n = n < j.n ? (n > 0 ? n : 0) : j.n;
-    const uint32_t k[2] = {(uint32_t)min<int64_t>(j.lo, n), (uint32_t)min<int64_t>(j.hi, n)};
-    if (n == 0 || (k[0] == 0 && k[1] == 0)) continue;
-    uint32_t pre[2] = {0u, 0u}, rem[2] = {k[0], k[1]}, eq[2] = {0u, 0u};
-    const int shifts[3] = {21, 10, 0};
-    const uint32_t masks[3] = {0x7FFu, 0x7FFu, 0x3FFu};
-    const uint32_t pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
-    for (int p = 0; p < 3; ++p) {
-      __syncthreads();
-      for (int b = tid; b < 2 * kSegBins; b += kSegT) (&hist[0][0])[b] = 0u;
-      __syncthreads();
-      for (int64_t i = tid; i < n; i += kSegT) {
-        const uint32_t key = fkey(j.vals[i]);
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const uint32_t ke = e ? ~key : key;
-          if (k[e] && (ke & pmasks[p]) == pre[e]) atomicAdd(&hist[e][(ke >> shifts[p]) & masks[p]], 1u);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        if (!k[e]) continue;   // uniform
-        uint32_t loc = 0;
-#pragma unroll
-        for (int b = 0; b < kSegBins / kSegT; ++b) loc += hist[e][tid * (kSegBins / kSegT) + b];
-        uint32_t tot;
-        const uint32_t ex = wg_excl_scan(loc, scan_lds, &tot);
-        if (ex < rem[e] && rem[e] <= ex + loc) {
-          uint32_t acc = ex;
-          for (int b = 0; b < kSegBins / kSegT; ++b) {
-            const int bin = tid * (kSegBins / kSegT) + b;
-            const uint32_t h = hist[e][bin];
-            if (acc + h >= rem[e]) {
-              s_bin[e] = (uint32_t)bin;
-              s_before[e] = acc;
-              break;
-            }
-            acc += h;
-          }
-        }
-        __syncthreads();
-        pre[e] |= s_bin[e] << shifts[p];
-        rem[e] -= s_before[e];
-        if (p == 2) eq[e] = hist[e][s_bin[e]];
-        __syncthreads();
-      }
-    }
-    // mark: below the k-th key, and ties when all of them fit
-    bool ordered[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) ordered[e] = k[e] && rem[e] < eq[e];
-    for (int64_t i = tid; i < n; i += kSegT) {
-      const uint32_t key = fkey(j.vals[i]);
-      bool f = false;
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const uint32_t ke = e ? ~key : key;
-        if (k[e]) f |= ke < pre[e] || (ke == pre[e] && !ordered[e]);
-      }
-      if (f) j.flags[i] = 1;
-    }
-    // ties that do not all fit: rank them in index order
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      if (!ordered[e]) continue;   // uniform
-      uint32_t taken = 0;
-      for (int64_t c0 = 0; c0 < n; c0 += kSegT) {
-        const int64_t i = c0 + tid;
-        bool tie = false;
-        if (i < n) {
-          const uint32_t key = fkey(j.vals[i]);
-          tie = (e ? ~key : key) == pre[e];
-        }
-        uint32_t tot;
-        const uint32_t ex = wg_excl_scan(tie ? 1u : 0u, scan_lds, &tot);
-        if (tie && taken + ex < rem[e]) j.flags[i] = 1;
-        taken += tot;
-        if (taken >= rem[e]) break;   // uniform
-      }
-    }
+    select_seg_body<kSegT>(j, hist, scan_lds, s_bin, s_before);
   }
 }
 
 // Compaction of one flag array into ascending indices (at most cap) and its
 // count; one work-group per job.
+template <int NT>
+__device__ __forceinline__ void compact_seg_body(const CompactJob& j, uint32_t* scan_lds) {
+  const int tid = threadIdx.x;
+  int64_t n = j.dn ? *j.dn : j.n;
+  n = n < j.n ? (n > 0 ? n : 0) : j.n;
+  // 16 consecutive flags per thread per chunk (loads clamped, so all 16 are
+  // in flight together), one work-group scan per chunk
+  constexpr int Q = 16;
+  int64_t base = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += Q * NT) {
+    uint8_t fb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fb[q] = j.flags[min(c0 + Q * tid + q, n - 1)];
+    uint32_t f = 0, cnt = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const bool on = c0 + Q * tid + q < n && fb[q];
+      f |= (on ? 1u : 0u) << q;
+      cnt += on ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t pos = wg_excl_scan<NT>(cnt, scan_lds, &tot);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if ((f >> q) & 1u) {
+        const int64_t o = base + pos;
+        if (o < j.cap) j.idx[o] = (int32_t)(c0 + Q * tid + q);
+        ++pos;
+      }
+    }
+    base += tot;
+  }
+  if (tid == 0) *j.count = base < j.cap ? base : j.cap;
+}
+
 __global__ __launch_bounds__(kSegT) void compact_seg(const CompactJob* __restrict__ jobs, int njobs) {
   __shared__ uint32_t scan_lds[kSegT / 64];
-  const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const CompactJob j = jobs[it];
-    int64_t n = j.dn ? *j.dn : j.n;
-    n = n < j.n ? (n > 0 ? n : 0) : j.n;
-    int64_t base = 0;
-    for (int64_t c0 = 0; c0 < n; c0 += 4 * kSegT) {
-      uint32_t f[4], cnt = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t i = c0 + 4 * tid + q;
-        f[q] = (i < n && j.flags[i]) ? 1u : 0u;
-        cnt += f[q];
-      }
-      uint32_t tot;
-      uint32_t pos = wg_excl_scan(cnt, scan_lds, &tot);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (f[q]) {
-          const int64_t o = base + pos;
-          if (o < j.cap) j.idx[o] = (int32_t)(c0 + 4 * tid + q);
-          ++pos;
-        }
-      }
-      base += tot;
-    }
-    if (tid == 0) *j.count = base < j.cap ? base : j.cap;
+    __syncthreads();
+    compact_seg_body<kSegT>(j, scan_lds);
   }
+}
+
+// Small selections (a few hundred thousand entries or fewer) in one launch:
+// work-group b clears the flags of segment b, selects, and compacts the
+// flags into its index list.  The jobs travel as a kernel argument.
+constexpr int kSmallSel = 2;
+struct SmallSelPack {
+  SegJob sel[kSmallSel];
+  CompactJob cmp[kSmallSel];
+  int32_t njobs;
+};
+
+constexpr int kSmallT = 1024;   // threads of the one-launch selection
+
+__global__ __launch_bounds__(kSmallT) void select_compact_small(const SmallSelPack P) {
+  __shared__ uint32_t hist[2][kSegBins];
+  __shared__ uint32_t scan_lds[kSmallT / 64];
+  __shared__ uint32_t s_bin[2], s_before[2];
+  if ((int)blockIdx.x >= P.njobs) return;
+  const SegJob j = P.sel[blockIdx.x];
+  int64_t n = j.dn ? *j.dn : j.n;
+  n = n < j.n ? (n > 0 ? n : 0) : j.n;
+  for (int64_t i = threadIdx.x; i < n; i += kSmallT) j.flags[i] = 0;
+  __syncthreads();   // cleared flags are visible to the whole work-group
+  select_seg_body<kSmallT>(j, hist, scan_lds, s_bin, s_before);
+  __syncthreads();
+  compact_seg_body<kSmallT>(P.cmp[blockIdx.x], scan_lds);
 }
 
 struct SelLayout {
@@ -583,6 +647,21 @@ prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64
                                  hipStream_t s) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 1024));
   PROHD_LAUNCH("select_scatter", scatter_flags, dim3(grid), dim3(256), 0, s, idx, count, cap, flags);
+  return PROHD_OK;
+}
+
+prohd_status select_compact_small(const SelSegment* segs, int nseg, int32_t* const* idx,
+                                  int64_t cap, int64_t* const* count, hipStream_t s) {
+  if (nseg <= 0) return PROHD_OK;
+  if (nseg > kSmallSel) return fail(PROHD_EINVAL, "select_compact_small: at most 2 segments");
+  SmallSelPack P{};
+  for (int i = 0; i < nseg; ++i) {
+    const SelSegment& g = segs[i];
+    P.sel[i] = SegJob{g.vals, g.n, g.dev_n, g.lo, g.hi, g.flags};
+    P.cmp[i] = CompactJob{g.flags, g.n, g.dev_n, idx[i], cap, count[i]};
+  }
+  P.njobs = nseg;
+  PROHD_LAUNCH("select_small", select_compact_small, dim3(nseg), dim3(kSmallT), 0, s, P);
   return PROHD_OK;
 }
 
