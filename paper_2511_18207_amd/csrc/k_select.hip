@@ -31,7 +31,11 @@ struct EndState {
   uint32_t mask;    // which bits of prefix are fixed
   int32_t need;     // entries still to take among those matching prefix
   int32_t active;   // 1 if this end selects anything
+  int32_t eq;       // entries in the last located digit (after the final
+                    // pass: entries equal to the k-th key)
 };
+
+constexpr int kUnr = 8;   // loads in flight per thread in the streaming passes
 
 struct SegDev {
   const float* vals;
@@ -76,6 +80,7 @@ __global__ void init_state(const SegPack P, EndState* __restrict__ st, uint32_t*
     es.mask = 0u;
     es.need = (int32_t)(need > 0 ? need : 0);
     es.active = need > 0 ? 1 : 0;
+    es.eq = 0;
     st[2 * sid + e] = es;
   }
   uint32_t* h = hist + (size_t)sid * 2 * kBins;
@@ -99,16 +104,26 @@ __global__ __launch_bounds__(kThreads) void digit_hist(const SegPack P,
   for (int i = threadIdx.x; i < 2 * kBins; i += kThreads) (&h[0][0])[i] = 0u;
   __syncthreads();
   const int64_t end = min(n, base + kHistChunk);
-  for (int64_t i = base + threadIdx.x; i < end; i += kThreads) {
-    const uint32_t key = fkey(s.vals[i]);
-    const uint32_t d = (key >> shift) & dmask;
-    if (e0.active && (key & e0.mask) == e0.prefix) atomicAdd(&h[0][d], 1u);
-    if (e1.active && (key & e1.mask) == e1.prefix) atomicAdd(&h[1][d], 1u);
+  // both ends still on the same prefix (always so in the first pass): one
+  // histogram serves both
+  const bool same = e0.active && e1.active && e0.mask == e1.mask && e0.prefix == e1.prefix;
+  for (int64_t i0 = base; i0 < end; i0 += (int64_t)kThreads * kUnr) {
+    uint32_t keys[kUnr];
+#pragma unroll
+    for (int u = 0; u < kUnr; ++u) keys[u] = fkey(s.vals[min(i0 + u * kThreads + threadIdx.x, end - 1)]);
+#pragma unroll
+    for (int u = 0; u < kUnr; ++u) {
+      if (i0 + u * kThreads + threadIdx.x >= end) continue;
+      const uint32_t key = keys[u];
+      const uint32_t d = (key >> shift) & dmask;
+      if (e0.active && (key & e0.mask) == e0.prefix) atomicAdd(&h[0][d], 1u);
+      if (!same && e1.active && (key & e1.mask) == e1.prefix) atomicAdd(&h[1][d], 1u);
+    }
   }
   __syncthreads();
   uint32_t* g = hist + (size_t)sid * 2 * kBins;
   for (int i = threadIdx.x; i < 2 * kBins; i += kThreads) {
-    const uint32_t v = (&h[0][0])[i];
+    const uint32_t v = same ? h[0][i & (kBins - 1)] : (&h[0][0])[i];
     if (v) atomicAdd(&g[i], v);
   }
 }
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st
   uint32_t* h = hist + (size_t)sid * 2 * kBins + (size_t)e * kBins;
   EndState es = st[2 * sid + e];
   __shared__ uint32_t part[kThreads];
-  __shared__ uint32_t sel[2];
+  __shared__ uint32_t sel[3];
   constexpr int per = kBins / kThreads;  // 8 bins per thread
   const int nb = (int)dmask + 1;
   // ascending order of digits for the bottom end, descending for the top
@@ -154,6 +169,7 @@ __global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st
         const int pos = threadIdx.x * per + j;
         sel[0] = (uint32_t)(e == 0 ? pos : (nb - 1 - pos));
         sel[1] = acc;
+        sel[2] = v[j];
       }
       acc += v[j];
     }
@@ -163,6 +179,7 @@ __global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st
     es.prefix |= sel[0] << shift;
     es.mask |= dmask << shift;
     es.need -= (int32_t)sel[1];
+    es.eq = (int32_t)sel[2];
     st[2 * sid + e] = es;
   }
   for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0u;
@@ -181,12 +198,22 @@ __global__ __launch_bounds__(kThreads) void tie_count(const SegPack P,
   if (threadIdx.x < 2) c[threadIdx.x] = 0u;
   __syncthreads();
   const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
+  // ends whose ties all fit (need == eq) take them without ranking: no count
+  const bool c0 = e0.active && e0.need < e0.eq, c1 = e1.active && e1.need < e1.eq;
   uint32_t m0 = 0, m1 = 0;
   const int64_t end = min(n, base + kMarkChunk);
-  for (int64_t i = base + threadIdx.x; i < end; i += kThreads) {
-    const uint32_t key = fkey(s.vals[i]);
-    m0 += (e0.active && key == e0.prefix);
-    m1 += (e1.active && key == e1.prefix);
+  if (c0 || c1) {
+    for (int64_t i0 = base; i0 < end; i0 += (int64_t)kThreads * kUnr) {
+      uint32_t keys[kUnr];
+#pragma unroll
+      for (int u = 0; u < kUnr; ++u) keys[u] = fkey(s.vals[min(i0 + u * kThreads + threadIdx.x, end - 1)]);
+#pragma unroll
+      for (int u = 0; u < kUnr; ++u) {
+        const bool in = i0 + u * kThreads + threadIdx.x < end;
+        m0 += (in && c0 && keys[u] == e0.prefix);
+        m1 += (in && c1 && keys[u] == e1.prefix);
+      }
+    }
   }
   if (m0) atomicAdd(&c[0], m0);
   if (m1) atomicAdd(&c[1], m1);
@@ -258,6 +285,23 @@ __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
   if (base >= n) return;
   const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
   if (!e0.active && !e1.active) return;
+  if ((!e0.active || e0.need >= e0.eq) && (!e1.active || e1.need >= e1.eq)) {
+    // every tie fits at both ends: keep key <= k-th key (bottom) and
+    // key >= k-th key (top), no ranking
+    const int64_t end = min(n, base + kMarkChunk);
+    for (int64_t i0 = base; i0 < end; i0 += (int64_t)kThreads * kUnr) {
+      uint32_t keys[kUnr];
+#pragma unroll
+      for (int u = 0; u < kUnr; ++u) keys[u] = fkey(s.vals[min(i0 + u * kThreads + threadIdx.x, end - 1)]);
+#pragma unroll
+      for (int u = 0; u < kUnr; ++u) {
+        const int64_t i = i0 + u * kThreads + threadIdx.x;
+        const bool keep = (e0.active && keys[u] <= e0.prefix) || (e1.active && keys[u] >= e1.prefix);
+        if (keep && i < end) s.flags[i] = 1;
+      }
+    }
+    return;
+  }
   __shared__ uint32_t wsum[kThreads / 64];
   uint32_t r0 = toff[((size_t)sid * 2 + 0) * nchunks + blockIdx.x];
   uint32_t r1 = toff[((size_t)sid * 2 + 1) * nchunks + blockIdx.x];
