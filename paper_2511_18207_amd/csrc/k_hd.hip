@@ -167,9 +167,14 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
   constexpr bool DMA = DP == 256;  // rows of 1 KiB go straight into LDS
   constexpr int NV4 = BN * DP / 4;              // float4s per Y block
   constexpr int PF = DMA ? 1 : (NV4 + 511) / 512;   // float4s per thread per block
-  __shared__ __attribute__((aligned(16))) float ys[2][BN * ST];
-  __shared__ float yns[2][BN];
-  __shared__ uint32_t cmin[2][BN];
+  // the two Y buffers are distinct objects, and the loop below names them
+  // statically, so the compiler can tell that the copy into one does not
+  // touch the reads of the other (no wait for the copy in flight before the
+  // reads)
+  __shared__ __attribute__((aligned(16))) float ys0[BN * ST];
+  __shared__ __attribute__((aligned(16))) float ys1[BN * ST];
+  __shared__ float yns0[BN], yns1[BN];
+  __shared__ uint32_t cmin0[BN], cmin1[BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -205,7 +210,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
 
   // Y block at y0 into buffer b: DMA rows past ye read as zero (buffer
   // range), register-staged rows past ye are zero-filled
-  auto load_block = [&](int64_t y0, int b, float4 (&buf)[PF], float& ynv) {
+  auto load_block = [&](int64_t y0, float* ysb, float4 (&buf)[PF], float& ynv) {
     if constexpr (DMA) {
       const int rows = (int)min<int64_t>(BN, ye - y0);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -213,7 +218,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
 #pragma unroll
       for (int r = wave; r < BN; r += 8)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void*)(&ys[b][r * ST]), 16,
+            rs, (__attribute__((address_space(3))) void*)(ysb + r * ST), 16,
             (r * DP + 4 * lane) * 4, 0, 0, 0);
     } else {
 #pragma unroll
@@ -230,7 +235,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
     }
     ynv = (tid < BN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
   };
-  auto store_block = [&](int b, const float4 (&buf)[PF], float ynv) {
+  auto store_block = [&](float* ysb, float* ynb, uint32_t* cmb, const float4 (&buf)[PF], float ynv) {
     if constexpr (!DMA) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
@@ -238,33 +243,36 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
         if (f < NV4) {
           const int r = f / (DP / 4);
           const int k4 = f - r * (DP / 4);
-          *reinterpret_cast<float4*>(&ys[b][r * ST + 4 * k4]) = buf[p];
+          *reinterpret_cast<float4*>(ysb + r * ST + 4 * k4) = buf[p];
         }
       }
     }
     if (tid < BN) {
-      yns[b][tid] = ynv;
-      cmin[b][tid] = kInfBits;
+      ynb[tid] = ynv;
+      cmb[tid] = kInfBits;
     }
   };
 
   float4 pf[PF];
   float pyn;
-  load_block(yb, 0, pf, pyn);
-  store_block(0, pf, pyn);
+  load_block(yb, ys0, pf, pyn);
+  store_block(ys0, yns0, cmin0, pf, pyn);
   if (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
   __syncthreads();
 
-  int cur = 0;
-  for (int64_t y0 = yb; y0 < ye; y0 += BN) {
+  // block at y0 in buffer cur (cy), the next one copied into nyb
+  // (every LDS array is named statically at each call, for the same reason)
+  auto block = [&](int64_t y0, float* cy, float* cyn, uint32_t* ccm, float* ny, float* nyn,
+                   uint32_t* ncm) {
     const bool more = y0 + BN < ye;
-    if (more) load_block(y0 + BN, cur ^ 1, pf, pyn);
+    if (more) load_block(y0 + BN, ny, pf, pyn);
+    float cms[NSUB];   // column minima of each subtile (lanes g == 0 hold them)
 #pragma unroll
     for (int sub = 0; sub < NSUB; ++sub) {
       // one accumulator: dependent 32x32x2 issues with the same destination
       // accumulate back to back in the matrix pipe
       floatx16 acc = {0.f};
-      const float* yrow = &ys[cur][(kBN * sub + c) * ST + g * KH];
+      const float* yrow = cy + (kBN * sub + c) * ST + g * KH;
 #pragma unroll
       for (int s = 0; s < KH; s += 4) {
         const float4 b = *reinterpret_cast<const float4*>(yrow + s);
@@ -274,7 +282,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 3], b.w, acc, 0, 0, 0);
       }
       // epilogue: lane holds column c of the subtile, rows 8*(v/4) + 4*g + v%4
-      const float ynv = yns[cur][kBN * sub + c];
+      const float ynv = cyn[kBN * sub + c];
       float cm = __uint_as_float(kInfBits);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -282,21 +290,27 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
         rmin[v] = fminf(rmin[v], d);
         cm = fminf(cm, d);
       }
-      if (COLMIN) {
-        cm = fminf(cm, __shfl_xor(cm, 32));
-        if (g == 0) atomicMin(&cmin[cur][kBN * sub + c], clamp_bits(cm));
-      }
+      cms[sub] = COLMIN ? fminf(cm, __shfl_xor(cm, 32)) : cm;
     }
-    if (more) store_block(cur ^ 1, pf, pyn);
-    if (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
+    // LDS writes after the wait for this wave's row copies: the compiler
+    // would otherwise hold each of them until every copy in flight landed
+    if (DMA) __builtin_amdgcn_s_waitcnt(0);
+    if (COLMIN && g == 0) {
+#pragma unroll
+      for (int sub = 0; sub < NSUB; ++sub) atomicMin(&ccm[kBN * sub + c], clamp_bits(cms[sub]));
+    }
+    if (more) store_block(ny, nyn, ncm, pf, pyn);
     __syncthreads();
     // column minima of the block: wave 0 (which also resets cmin of the
     // other buffer, so this read precedes that write in program order)
     if (COLMIN && wave == 0 && lane < BN) {
-      const uint32_t v = cmin[cur][lane];
+      const uint32_t v = ccm[lane];
       if (y0 + lane < ye) atomicMin(&colmin[y0 + lane], v);
     }
-    cur ^= 1;
+  };
+  for (int64_t y0 = yb; y0 < ye; y0 += 2 * BN) {
+    block(y0, ys0, yns0, cmin0, ys1, yns1, cmin1);
+    if (y0 + BN < ye) block(y0 + BN, ys1, yns1, cmin1, ys0, yns0, cmin0);
   }
 
   // row minima: reduce over the 32 lanes of each half-wave (same rows)
