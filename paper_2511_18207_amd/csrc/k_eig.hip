@@ -294,10 +294,11 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
         const double vc0 = vof(c0), vc1 = vof(c0 + 1), wc0 = wof(c0), wc1 = wof(c0 + 1);
         const double vr0 = rowA ? va0 : vb0, vr1 = rowA ? va1 : vb1;
         const double wr0 = rowA ? wa0 : wb0, wr1 = rowA ? wa1 : wb1;
-        a[u][0][0] -= vr0 * wc0 + wr0 * vc0;
-        a[u][0][1] -= vr0 * wc1 + wr0 * vc1;
-        a[u][1][0] -= vr1 * wc0 + wr1 * vc0;
-        a[u][1][1] -= vr1 * wc1 + wr1 * vc1;
+        // two fused steps per element (a - v w^T, then - w v^T)
+        a[u][0][0] = fma(-wr0, vc0, fma(-vr0, wc0, a[u][0][0]));
+        a[u][0][1] = fma(-wr0, vc1, fma(-vr0, wc1, a[u][0][1]));
+        a[u][1][0] = fma(-wr1, vc0, fma(-vr1, wc0, a[u][1][0]));
+        a[u][1][1] = fma(-wr1, vc1, fma(-vr1, wc1, a[u][1][1]));
       }
     }
   };
