@@ -576,22 +576,26 @@ __device__ __forceinline__ void eig_body(
     }
     for (int it = 0; it < 5; ++it) {
       if (t < nr && ok) {
-        // forward: apply the row interchanges and multipliers
+        // forward: apply the row interchanges and multipliers; the running
+        // row stays in a register, so the only dependence between steps is
+        // through registers and the LDS loads can be issued ahead
+        double carry = x[0];
+#pragma unroll 8
         for (int i = 0; i < DP - 1; ++i) {
-          double bi = x[i], bn = x[i + 1];
-          if (pv[i]) {
-            const double tmp = bi;
-            bi = bn;
-            bn = tmp;
-          }
+          const double nxt = x[i + 1];
+          const bool sw = pv[i] != 0;
+          const double bi = sw ? nxt : carry, bn = sw ? carry : nxt;
           x[i] = bi;
-          x[i + 1] = bn - Lm[i] * bi;
+          carry = bn - Lm[i] * bi;
         }
+        x[DP - 1] = carry;
         // backward: U has diagonal, first and (when pivoted) second superdiagonal
         double x2 = 0.0, x1 = x[DP - 1] * U0[DP - 1];
         x[DP - 1] = x1;
+#pragma unroll 8
         for (int i = DP - 2; i >= 0; --i) {
-          const double u2 = (pv[i] && i + 2 < DP) ? ee[i + 1] : 0.0;
+          const double e1 = ee[i + 1 < DP ? i + 1 : i];
+          const double u2 = (pv[i] && i + 2 < DP) ? e1 : 0.0;
           const double xi = (x[i] - U1[i] * x1 - u2 * x2) * U0[i];
           x[i] = xi;
           x2 = x1;
