@@ -57,7 +57,8 @@ def kernel_source_hash():
     with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", "k_hd.hip")) as fh:
         src = fh.read()
     h = hashlib.sha256()
-    for start in ("void dist_seg(", "int64_t tile_split(", "void dist_tile(", "int64_t tile_grid(",
+    for start in ("void dist_seg(", "int64_t tile_split(", "void tile_schedule(", "void dist_tile(",
+                  "int64_t tile_grid(",
                   "prohd_status launch_tile("):
         h.update(_source_block(src, start).encode())
     return h.hexdigest()[:16]

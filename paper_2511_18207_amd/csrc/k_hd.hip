@@ -354,30 +354,64 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, x0, yb, ye, rowmin, colmin);
 }
 
-// Chunk count of a persistent tile launch: the matrix is cut into xt x S
-// (row tile, Y chunk) items and G work-groups take them in rounds, so S is
-// the smallest split (S <= min(16, nyb)) whose last round is at least
-// 98.5 % full, else the split that fills it best.  Decided on the device from
-// the actual counts.
+// Chunk count of a persistent tile launch.  The matrix is cut into xt x S
+// (row tile, Y chunk) items that G work-groups take in whole rounds; the
+// items left over after the last whole round are shared out in equal
+// contiguous ranges of Y blocks (tile_schedule), which balances the work
+// for any S but reads those blocks without the in-step L2 sharing.  So S is
+// the smallest split (S <= min(16, nyb)) that leaves at most 5 % of a round
+// over, else the one that leaves the fewest.  Decided on the device from the
+// actual counts.
 __device__ __forceinline__ int64_t tile_split(int64_t xt, int64_t nyb, int64_t G) {
-  int64_t S = 1, bi = 0, bs = 1;   // best split, its items and slots
+  int64_t S = 1, best = G;
   for (int64_t s = 1; s <= 16 && s <= nyb; ++s) {
-    const int64_t items = xt * s;
-    const int64_t slots = (items + G - 1) / G * G;
-    if (items * bs > bi * slots) {
-      bi = items;
-      bs = slots;
+    const int64_t left = xt * s % G;
+    if (left < best) {
+      best = left;
       S = s;
     }
-    if (items * 1000 >= slots * 985) break;
+    if (left * 20 <= G) break;
   }
   return S;
 }
 
-// Persistent form for one pair.  Items are taken chunk-major (item i: chunk
-// i / xt, row tile i % xt), work-group b doing items b, b + G, ...: the items
-// of one round start together at the beginning of their chunk and sweep it in
-// step, so the work-groups of an XCD (ids congruent modulo 8), which hold
+// Work of this work-group in a persistent tile launch: whole rounds of
+// chunk-major items (item i: chunk i / xt, row tile i % xt; work-group b
+// takes items b, b + G, ...), then its share of the leftover items' Y blocks.
+// seg(row tile, first block, end block) runs one segment; every thread of
+// the work-group reaches the same calls.
+template <class Seg>
+__device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S, Seg&& seg) {
+  const int64_t G = gridDim.x;
+  const int64_t items = xt * S;
+  const int64_t full = items / G * G;
+  for (int64_t i = blockIdx.x; i < full; i += G) {
+    const int64_t ysi = i / xt, xblk = i - ysi * xt;
+    seg(xblk, ysi * nyb / S, (ysi + 1) * nyb / S);
+  }
+  // leftover items as cmax block slots each (chunks differ by one block at
+  // most; slots past a chunk's end are empty), cut into G equal ranges
+  const int64_t left = items - full;
+  if (left == 0) return;
+  const int64_t cmax = (nyb + S - 1) / S;
+  const int64_t cells = left * cmax;
+  int64_t w = cells * blockIdx.x / G;
+  const int64_t hi = cells * (blockIdx.x + 1) / G;
+  while (w < hi) {
+    const int64_t q = w / cmax;
+    const int64_t end = min(hi, (q + 1) * cmax);
+    const int64_t i = full + q;
+    const int64_t ysi = i / xt, xblk = i - ysi * xt;
+    const int64_t c0 = ysi * nyb / S, c1 = (ysi + 1) * nyb / S;
+    const int64_t b0 = c0 + (w - q * cmax), b1 = min(c1, c0 + (end - q * cmax));
+    if (b0 < b1) seg(xblk, b0, b1);
+    w = end;
+  }
+}
+
+// Persistent form for one pair (schedule: tile_schedule).  The items of one
+// round start together at the beginning of their chunk and sweep it in step,
+// so the work-groups of an XCD (ids congruent modulo 8), which hold
 // consecutive items of one or two chunks, read each Y block at about the same
 // time and one L2 fill serves them all.
 template <int DP, bool COLMIN>
@@ -396,12 +430,11 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
   const int64_t nyb = (nY + BN - 1) / BN;
   if (xt == 0 || nyb == 0) return;
   const int64_t S = tile_split(xt, nyb, gridDim.x);
-  for (int64_t i = blockIdx.x; i < xt * S; i += gridDim.x) {
-    const int64_t ysi = i / xt, xblk = i - ysi * xt;
-    __syncthreads();  // LDS of the previous item is no longer read
-    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, ysi * nyb / S * BN,
-                         min(nY, (ysi + 1) * nyb / S * BN), rowmin, colmin);
-  }
+  tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
+    __syncthreads();  // LDS of the previous segment is no longer read
+    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, b0 * BN, min(nY, b1 * BN), rowmin,
+                         colmin);
+  });
 }
 
 // ------------------------------------------------- low-precision copies
@@ -701,8 +734,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   }
 }
 
-// Persistent form of the low-precision tile (same rounds of chunk-major
-// items as dist_tile).
+// Persistent form of the low-precision tile (same schedule as dist_tile).
 template <int DP, int FMT, bool COLMIN>
 __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
                                                      const float* __restrict__ xn,
@@ -719,12 +751,11 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
   const int64_t nyb = (nY + kLpBN - 1) / kLpBN;
   if (xt == 0 || nyb == 0) return;
   const int64_t S = tile_split(xt, nyb, gridDim.x);
-  for (int64_t i = blockIdx.x; i < xt * S; i += gridDim.x) {
-    const int64_t ysi = i / xt, xblk = i - ysi * xt;
-    __syncthreads();  // LDS of the previous item is no longer read
-    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, ysi * nyb / S * kLpBN,
-                                 min(nY, (ysi + 1) * nyb / S * kLpBN), maxabs, rowmin, colmin);
-  }
+  tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
+    __syncthreads();  // LDS of the previous segment is no longer read
+    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, b0 * kLpBN,
+                                 min(nY, b1 * kLpBN), maxabs, rowmin, colmin);
+  });
 }
 
 // ---------------------------------------------------------------- refine
