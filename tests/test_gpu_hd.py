@@ -33,6 +33,12 @@ def _check_dir(A, B, got_h, wa, wb, want_h, nn_of_wa):
 CASES = [
     (1, 1, 1), (5, 3, 2), (300, 257, 3), (1000, 700, 32), (777, 1234, 100),
     (2000, 1500, 128), (600, 900, 256), (513, 300, 16), (4099, 33, 64), (40, 5000, 48),
+    # several whole rounds of (row tile, Y chunk) items on a 256-CU grid plus
+    # leftover items shared out in block ranges that cross item boundaries:
+    # 157 row tiles x 110 blocks of 64 rows (5 chunks: 3 rounds + 17 items),
+    # and 196 x 188 blocks of 32 rows (4 chunks: 3 rounds + 16 items) through
+    # the register-staged path
+    (40000, 7000, 256), (50000, 6000, 64),
 ]
 
 
