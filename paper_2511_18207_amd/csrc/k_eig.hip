@@ -159,6 +159,10 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
         a[u][i][q] = owner ? Mg[(size_t)(16 * I + 2 * rb + i) * DP + 16 * J + 2 * cb + q] : 0.0;
   }
   double* mypw = pw + (size_t)wave * DP;
+  // per-wave copies of the step's v and w (only this wave reads them, in
+  // program order after its own writes, so no barrier guards them)
+  double* vp = pw + (size_t)(W + wave) * DP;
+  double* wp = pw + (size_t)(2 * W + wave) * DP;
   // one step; QJ = j % 2 is a compile-time constant so that the column
   // element is picked without indexing the register array
   // col and pbuf alternate between two buffers by step parity, so a step
@@ -202,10 +206,12 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       tj = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    auto vof = [&](int k) {
+    // v once per step into this wave's copy: every later use is one load
+    for (int k = lane; k < DP; k += 64) {
       const double ck = col[k];
-      return k == j + 1 ? 1.0 : (k > j + 1 ? ck * scale : 0.0);
-    };
+      vp[k] = k == j + 1 ? 1.0 : (k > j + 1 ? ck * scale : 0.0);
+    }
+    auto vof = [&](int k) { return vp[k]; };
     if (tid == 0) {
       ee[j] = beta;
       tau[j] = tj;
@@ -276,10 +282,11 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
     for (int k = lane; k < DP; k += 64) kd += pbuf[k] * vof(k);
     const double K = 0.5 * tj * wave_sum_dpp(kd);
     if (!owner) return;
-    auto wof = [&](int k) {
-      const double pk = pbuf[k], vk = vof(k);
-      return k > j ? pk - K * vk : 0.0;
-    };
+    for (int k = lane; k < DP; k += 64) {
+      const double pk = pbuf[k], vk = vp[k];
+      wp[k] = k > j ? pk - K * vk : 0.0;
+    }
+    auto wof = [&](int k) { return wp[k]; };
     const double wa0 = wof(16 * RA + rb2), wa1 = wof(16 * RA + rb2 + 1);
     const double wb0 = wof(16 * RB + rb2), wb1 = wof(16 * RB + rb2 + 1);
     const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
@@ -354,6 +361,7 @@ __device__ __forceinline__ void eig_body(
   // ---------------------------------------------------- 1. tridiagonalise
   if constexpr (S::REG) {
     static_assert(S::NQ >= 2, "the second column / p buffers live in part");
+    static_assert(S::BIG >= 3 * (NT / 64) * DP, "per-wave p partials, v and w live in big");
     tridiag_reg<DP, NT>(Mg, Vg, vs, wv, part[0], part[1], big, red, dd, ee, tau);
   } else {
     const int ci = t % DP;        // column owned in the matvec / update
