@@ -85,8 +85,11 @@ __device__ double block_sum(double x, double* red) {
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   const int lo = __double2loint(x), hi = __double2hiint(x);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  // every lane has a valid source under these controls, so no "old" value
+  // is needed (the plain move form leaves the destination free instead of
+  // tying it to a copied or zeroed register)
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __hiloint2double(h2, l2);
 }
 
