@@ -174,11 +174,7 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
   auto step = [&](const int j, auto QJ) {
     double* col = decltype(QJ)::value ? col1 : col0;
     double* pbuf = decltype(QJ)::value ? pbuf1 : pbuf0;
-    // per-lane offsets made opaque at every step, so that the compiler
-    // recomputes the (cheap) addresses instead of keeping a tile row's worth
-    // of loop-invariant addresses live in registers
-    int rb2 = 2 * rb, cb2 = 2 * cb;
-    asm volatile("" : "+v"(rb2), "+v"(cb2));
+    const int rb2 = 2 * rb, cb2 = 2 * cb;
     const int Jj = j >> 4, cj = (j & 15) >> 1;
     if (owner && cb == cj) {
 #pragma unroll
