@@ -648,7 +648,10 @@ __device__ __forceinline__ void eig_body(
 
   // ------------------------------------------------ 4. back-transform
   // wave w transforms vectors c = w, w + NW, ...; lane holds entries
-  // k = lane + 64 r.
+  // k = lane + 64 r.  Per reflector the wave forms the dot products of all
+  // its vectors first and reduces them together (independent cross-lane
+  // chains overlap); NV = 2 covers m <= 2 NW (the default m = 16 on eight
+  // waves) without carrying empty vectors through the reductions.
   constexpr int PR = (DP + 63) / 64;
   constexpr int NW = NT / 64;
   constexpr int VPW = (S::MAXD - 1 + NW - 1) / NW;
@@ -663,35 +666,42 @@ __device__ __forceinline__ void eig_body(
       z[v][r] = (c < m && k < DP && ok) ? Yg[(size_t)c * DP + k] : 0.0;
     }
   }
-  for (int hi = DP - 3; hi >= 0; hi -= S::VROWS) {
-    const int lo = hi - S::VROWS + 1 > 0 ? hi - S::VROWS + 1 : 0;
-    __syncthreads();
-    for (int e = t; e < (hi - lo + 1) * DP; e += NT) big[e] = Vg[(size_t)lo * DP + e];
-    __syncthreads();
-    for (int j = hi; j >= lo; --j) {
-      const double tj = tau[j];
-      if (tj == 0.0) continue;
-      const double* vj = big + (size_t)(j - lo) * DP;
+  auto apply = [&](auto NVC) {
+    constexpr int NV = decltype(NVC)::value;
+    for (int hi = DP - 3; hi >= 0; hi -= S::VROWS) {
+      const int lo = hi - S::VROWS + 1 > 0 ? hi - S::VROWS + 1 : 0;
+      __syncthreads();
+      for (int e = t; e < (hi - lo + 1) * DP; e += NT) big[e] = Vg[(size_t)lo * DP + e];
+      __syncthreads();
+      for (int j = hi; j >= lo; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        const double* vj = big + (size_t)(j - lo) * DP;
+        double vr[PR];
 #pragma unroll
-      for (int v = 0; v < VPW; ++v) {
-        const int c = wave + NW * v;
-        if (c < m) {
-          double d = 0.0;
+        for (int r = 0; r < PR; ++r) vr[r] = vj[(lane + 64 * r) % DP];
+        double d[NV];
 #pragma unroll
-          for (int r = 0; r < PR; ++r) {
-            const int k = lane + 64 * r;
-            if (k < DP) d += vj[k] * z[v][r];
-          }
-          d = tj * wave_sum(d);
+        for (int v = 0; v < NV; ++v) {
+          d[v] = 0.0;
 #pragma unroll
-          for (int r = 0; r < PR; ++r) {
-            const int k = lane + 64 * r;
-            if (k < DP) z[v][r] -= d * vj[k];
-          }
+          for (int r = 0; r < PR; ++r)
+            if (lane + 64 * r < DP) d[v] += vr[r] * z[v][r];
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d[v] = tj * wave_sum_dpp(d[v]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int r = 0; r < PR; ++r)
+            if (lane + 64 * r < DP) z[v][r] -= d[v] * vr[r];
       }
     }
-  }
+  };
+  if (m <= 2 * NW)
+    apply(std::integral_constant<int, 2 < VPW ? 2 : VPW>{});
+  else
+    apply(std::integral_constant<int, VPW>{});
   // unit length, canonical sign, float32 output rows 1..m
 #pragma unroll
   for (int v = 0; v < VPW; ++v) {
