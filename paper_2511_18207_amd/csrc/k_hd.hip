@@ -821,17 +821,41 @@ __device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
   }
   for (int64_t y0 = yb; y0 < ye; y0 += BNY) {
     __syncthreads();
-    // stage 32 rows as float64 and their squared norms (8 threads per row)
+    // stage 32 rows as float64 and their squared norms (8 threads per row;
+    // at DP >= 32 each thread moves float4 runs, all loads of a row issued
+    // before the conversions)
     {
       const int r = tid >> 3, part = tid & 7;
       const bool ok = y0 + r < ye;
       const float* src = Yp + (y0 + r) * DP;
       double sq = 0.0;
+      if constexpr (DP >= 32) {
+        constexpr int NQ = DP / 32;   // float4 runs per thread
+        float4 q[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j)
+          q[j] = ok ? *reinterpret_cast<const float4*>(src + 4 * part + 32 * j)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+          const int k = 4 * part + 32 * j;
+          const double v0 = q[j].x, v1 = q[j].y, v2 = q[j].z, v3 = q[j].w;
+          ys[r * STY + k] = v0;
+          ys[r * STY + k + 1] = v1;
+          ys[r * STY + k + 2] = v2;
+          ys[r * STY + k + 3] = v3;
+          sq = fma(v0, v0, sq);
+          sq = fma(v1, v1, sq);
+          sq = fma(v2, v2, sq);
+          sq = fma(v3, v3, sq);
+        }
+      } else {
 #pragma unroll 4
-      for (int k = part; k < DP; k += 8) {
-        const double v = ok ? (double)src[k] : 0.0;
-        ys[r * STY + k] = v;
-        sq = fma(v, v, sq);
+        for (int k = part; k < DP; k += 8) {
+          const double v = ok ? (double)src[k] : 0.0;
+          ys[r * STY + k] = v;
+          sq = fma(v, v, sq);
+        }
       }
       sq += __shfl_xor(sq, 1);
       sq += __shfl_xor(sq, 2);
