@@ -273,6 +273,10 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
       // accumulate back to back in the matrix pipe
       floatx16 acc = {0.f};
       const float* yrow = cy + (kBN * sub + c) * ST + g * KH;
+      // raised issue priority while this wave's matrix ops go out, normal
+      // again for the epilogue, so that the other wave on the SIMD gets the
+      // issue slots for its vector work in between
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s = 0; s < KH; s += 4) {
         const float4 b = *reinterpret_cast<const float4*>(yrow + s);
@@ -281,6 +285,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 2], b.z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 3], b.w, acc, 0, 0, 0);
       }
+      __builtin_amdgcn_s_setprio(0);
       // epilogue: lane holds column c of the subtile, rows 8*(v/4) + 4*g + v%4
       const float ynv = cyn[kBN * sub + c];
       float cm = __uint_as_float(kInfBits);
@@ -541,9 +546,13 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   // overlapped subtiles need a second accumulator set: not at BF16 and
   // D = 256, whose two X sets already fill the registers
   constexpr bool ILV = FMT == FMT_FP8 || DP <= 128;
-  __shared__ __attribute__((aligned(16))) uint8_t ys[2][kLpBN * STB];
-  __shared__ float yns[2][kLpBN];
-  __shared__ uint32_t cmin[2][kLpBN];
+  // distinct LDS objects per buffer, named statically below (as in
+  // dist_seg): the compiler then sees that the copy into one buffer does
+  // not touch the reads of the other
+  __shared__ __attribute__((aligned(16))) uint8_t ys0[kLpBN * STB];
+  __shared__ __attribute__((aligned(16))) uint8_t ys1[kLpBN * STB];
+  __shared__ float yns0[kLpBN], yns1[kLpBN];
+  __shared__ uint32_t cmin0[kLpBN], cmin1[kLpBN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -582,7 +591,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   // Y block -> LDS buffer b.  DMA: 4-byte pieces, RB / 256 instructions per
   // row, spread over the waves; the buffer range ends at the last valid row,
   // so rows past the end read as zero.
-  auto load_block = [&](int64_t y0, int b, uint4 (&buf)[PF], float& ynv) {
+  auto load_block = [&](int64_t y0, uint8_t* ysb, uint4 (&buf)[PF], float& ynv) {
     if constexpr (DMA) {
       const int rows = (int)min<int64_t>(kLpBN, ye - y0);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -591,7 +600,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
       for (int i = wave; i < kLpBN * PPR; i += 8) {
         const int r = i / PPR, h = i - r * PPR;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void*)(&ys[b][r * STB + 256 * h]), 4,
+            rs, (__attribute__((address_space(3))) void*)(ysb + r * STB + 256 * h), 4,
             r * RB + 256 * h + 4 * lane, 0, 0, 0);
       }
     } else {
@@ -609,30 +618,30 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     }
     ynv = (tid < kLpBN && y0 + tid < ye) ? yn[y0 + tid] : __uint_as_float(kInfBits);
   };
-  auto store_block = [&](int b, const uint4 (&buf)[PF], float ynv) {
-    if constexpr (DMA) {
-      __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
-    } else {
+  auto store_block = [&](uint8_t* ysb, float* ynb, uint32_t* cmb, const uint4 (&buf)[PF],
+                         float ynv) {
+    if constexpr (!DMA) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
         const int f = tid + 512 * p;
         if (f < NV) {
           const int r = f / (RB / 16);
           const int q = f - r * (RB / 16);
-          *reinterpret_cast<uint4*>(&ys[b][r * STB + 16 * q]) = buf[p];
+          *reinterpret_cast<uint4*>(ysb + r * STB + 16 * q) = buf[p];
         }
       }
     }
     if (tid < kLpBN) {
-      yns[b][tid] = ynv;
-      cmin[b][tid] = kInfBits;
+      ynb[tid] = ynv;
+      cmb[tid] = kInfBits;
     }
   };
   // one 32-column subtile against both X sets: each B read feeds XS ops
-  auto subtile = [&](int b, int t, floatx16 (&acc)[XS]) {
+  auto subtile = [&](const uint8_t* cy, int t, floatx16 (&acc)[XS]) {
+    __builtin_amdgcn_s_setprio(1);   // issue priority while the ops go out
 #pragma unroll
     for (int x = 0; x < XS; ++x) acc[x] = floatx16{0.f};
-    const uint8_t* yrow = &ys[b][(32 * t + c) * STB + g * (RB / 2)];
+    const uint8_t* yrow = cy + (32 * t + c) * STB + g * (RB / 2);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if constexpr (FMT == FMT_BF16) {
@@ -658,8 +667,10 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
       }
     }
   };
-  auto epilogue = [&](int b, int t, const floatx16 (&acc)[XS]) {
-    const float ynv = yns[b][32 * t + c];
+  // returns the subtile's column minima (lanes g == 0 hold them)
+  auto epilogue = [&](const float* cyn, int t, const floatx16 (&acc)[XS]) {
+    __builtin_amdgcn_s_setprio(0);
+    const float ynv = cyn[32 * t + c];
     float cm = __uint_as_float(kInfBits);
 #pragma unroll
     for (int x = 0; x < XS; ++x)
@@ -669,49 +680,64 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
         rmin[x][v] = fminf(rmin[x][v], d);
         cm = fminf(cm, d);
       }
-    if (COLMIN) {
-      cm = fminf(cm, __shfl_xor(cm, 32));
-      if (g == 0) atomicMin(&cmin[b][32 * t + c], clamp_bits(cm));
-    }
+    return COLMIN ? fminf(cm, __shfl_xor(cm, 32)) : cm;
   };
 
   uint4 pf[PF];
   float pyn;
-  load_block(yb, 0, pf, pyn);
-  store_block(0, pf, pyn);
+  load_block(yb, ys0, pf, pyn);
+  store_block(ys0, yns0, cmin0, pf, pyn);
+  if (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
   __syncthreads();
 
-  int cur = 0;
-  for (int64_t y0 = yb; y0 < ye; y0 += kLpBN) {
+  // block at y0 in buffer cy (norms cyn, column minima ccm); the next block
+  // is copied into ny
+  auto block = [&](int64_t y0, const uint8_t* cy, const float* cyn, uint32_t* ccm, uint8_t* ny,
+                   float* nyn, uint32_t* ncm) {
     const bool more = y0 + kLpBN < ye;
-    if (more) load_block(y0 + kLpBN, cur ^ 1, pf, pyn);
+    if (more) load_block(y0 + kLpBN, ny, pf, pyn);
     const int nsub = (int)min<int64_t>(4, (ye - y0 + 31) / 32);
+    float cms[4];
     if constexpr (ILV) {
       // two accumulator sets: one subtile's epilogue runs while the next
       // subtile's ops execute
       floatx16 p0[XS], p1[XS];
-      subtile(cur, 0, p0);
-      if (nsub > 1) subtile(cur, 1, p1);
-      epilogue(cur, 0, p0);
-      if (nsub > 2) subtile(cur, 2, p0);
-      if (nsub > 1) epilogue(cur, 1, p1);
-      if (nsub > 3) subtile(cur, 3, p1);
-      if (nsub > 2) epilogue(cur, 2, p0);
-      if (nsub > 3) epilogue(cur, 3, p1);
+      subtile(cy, 0, p0);
+      if (nsub > 1) subtile(cy, 1, p1);
+      cms[0] = epilogue(cyn, 0, p0);
+      if (nsub > 2) subtile(cy, 2, p0);
+      if (nsub > 1) cms[1] = epilogue(cyn, 1, p1);
+      if (nsub > 3) subtile(cy, 3, p1);
+      if (nsub > 2) cms[2] = epilogue(cyn, 2, p0);
+      if (nsub > 3) cms[3] = epilogue(cyn, 3, p1);
     } else {
-      for (int t = 0; t < nsub; ++t) {
-        floatx16 acc[XS];
-        subtile(cur, t, acc);
-        epilogue(cur, t, acc);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nsub) {
+          floatx16 acc[XS];
+          subtile(cy, t, acc);
+          cms[t] = epilogue(cyn, t, acc);
+        }
       }
     }
-    if (more) store_block(cur ^ 1, pf, pyn);
+    // LDS writes after the wait for this wave's row copies (the compiler
+    // would otherwise hold each of them until every copy in flight landed)
+    if (DMA) __builtin_amdgcn_s_waitcnt(0);
+    if (COLMIN && g == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nsub) atomicMin(&ccm[32 * t + c], clamp_bits(cms[t]));
+    }
+    if (more) store_block(ny, nyn, ncm, pf, pyn);
     __syncthreads();
     if (COLMIN && tid < kLpBN) {
-      const uint32_t v = cmin[cur][tid];
+      const uint32_t v = ccm[tid];
       if (y0 + tid < ye) atomicMin(&colmin[y0 + tid], v);
     }
-    cur ^= 1;
+  };
+  for (int64_t y0 = yb; y0 < ye; y0 += 2 * kLpBN) {
+    block(y0, ys0, yns0, cmin0, ys1, yns1, cmin1);
+    if (y0 + kLpBN < ye) block(y0 + kLpBN, ys1, yns1, cmin1, ys0, yns0, cmin0);
   }
 
   // row minima: reduce over the 32 lanes of each half-wave (same rows)
