@@ -2,7 +2,7 @@
 
 This form is not in the paper; it extends the method's candidate selection
 (the extremes of Alg. 1 / Alg. 2) with points a small network scores as
-likely Hausdorff witnesses.  The definitions below are this build's:
+likely Hausdorff witnesses.  The definitions below are this library's own:
 
 * features of a point x of one set, with c the centroid of the OTHER set:
   ``f = [x, x - c]`` (2D values);
