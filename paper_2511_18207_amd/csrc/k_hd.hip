@@ -47,6 +47,20 @@ __device__ __forceinline__ uint32_t clamp_bits(float d) {
   return __float_as_uint(d > 0.f ? d : 0.f);
 }
 
+// Running minimum as the median of (acc, d, ninf) with ninf = -inf held in
+// a scalar register.  Equal to fminf for non-NaN operands; fminf on a value
+// carried across blocks first gets a quieting max(acc, acc) from the
+// compiler, the median needs none.  The empty asm hides the constant, which
+// the compiler would otherwise fold the median back into a minimum with.
+__device__ __forceinline__ float neg_inf_sreg() {
+  float v = __uint_as_float(0xff800000u);
+  asm volatile("" : "+s"(v));
+  return v;
+}
+__device__ __forceinline__ float run_min(float acc, float d, float ninf) {
+  return __builtin_amdgcn_fmed3f(acc, d, ninf);
+}
+
 // Device count clipped to the host bound (capacity), or the host count.
 __device__ __forceinline__ int64_t dev_or(const int64_t* p, int64_t v) {
   if (!p) return v;
@@ -559,6 +573,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 5;
   const int c = lane & 31;
+  const float ninf = neg_inf_sreg();
   float dscale = -2.f;
   if (FMT == FMT_FP8) {
     const float sc = fp8_scale(maxabs);
@@ -677,10 +692,10 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const float d = fmaf(dscale, acc[x][v], xq[x][v] + ynv);
-        rmin[x][v] = fminf(rmin[x][v], d);
+        rmin[x][v] = run_min(rmin[x][v], d, ninf);
         cm = fminf(cm, d);
       }
-    return COLMIN ? fminf(cm, __shfl_xor(cm, 32)) : cm;
+    return COLMIN ? run_min(cm, __shfl_xor(cm, 32), ninf) : cm;
   };
 
   uint4 pf[PF];
@@ -747,7 +762,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     for (int v = 0; v < 16; ++v) {
       float t = rmin[x][v];
 #pragma unroll
-      for (int off = 1; off < 32; off <<= 1) t = fminf(t, __shfl_xor(t, off));
+      for (int off = 1; off < 32; off <<= 1) t = run_min(t, __shfl_xor(t, off), ninf);
       rmin[x][v] = t;
     }
     float mine = __uint_as_float(kInfBits);
