@@ -1,6 +1,6 @@
 // Directions and projections: the projection steps of the paper's Alg. 1
 // (onto the centroid axis) and Alg. 2 (onto each principal component), for
-// both sets, plus the driver that chains statistics -> eigensolve ->
+// both sets, plus the host routine that chains statistics -> eigensolve ->
 // projection without a host synchronisation.
 //
 // The projection of n rows onto up to 33 directions is a skinny product

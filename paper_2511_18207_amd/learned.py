@@ -1,7 +1,7 @@
 """Learned candidate proposal: a scorer network adds likely Hausdorff
 witnesses to ProHD's extreme candidates (Alg. 1 / Alg. 2 select extremes
 along directions; this form only ever adds points to those sets, so plain
-ProHD remains the fallback and the exact distance of Eq. (1) the judge).
+ProHD remains the fallback and the exact distance of Eq. (1) the yardstick).
 
 Every arithmetic step runs in the library's kernels through the C ABI:
 
