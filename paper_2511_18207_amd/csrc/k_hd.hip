@@ -580,9 +580,15 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     dscale = -2.f / (sc * sc);
   }
 
-  // X set x of this wave: rows x0 + 32 (XS wave + x) ..
+  // X set x of this wave: rows x0 + 32 (XS wave + x) ..  xc holds
+  // |x|^2 / dscale (a power-of-two multiple, exact) in the accumulator
+  // layout: it is the first op's C operand, so the accumulator ends at
+  // |x|^2 / dscale + (quantised x).(quantised y), and d2 = dscale acc + |y|^2
+  // costs one multiply-add.
   uint4 a[XS][NA];
-  float xq[XS][16], rmin[XS][16];
+  floatx16 xc[XS];
+  float rmin[XS][16];
+  const float inv_dscale = 1.f / dscale;
 #pragma unroll
   for (int x = 0; x < XS; ++x) {
     const int64_t rb0 = x0 + 32 * (XS * wave + x);
@@ -598,7 +604,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t r = rb0 + 8 * (v >> 2) + 4 * g + (v & 3);
-      xq[x][v] = (r < nX) ? xn[r] : __uint_as_float(kInfBits);
+      xc[x][v] = ((r < nX) ? xn[r] : __uint_as_float(kInfBits)) * inv_dscale;
       rmin[x][v] = __uint_as_float(kInfBits);
     }
   }
@@ -655,7 +661,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
   auto subtile = [&](const uint8_t* cy, int t, floatx16 (&acc)[XS]) {
     __builtin_amdgcn_s_setprio(1);   // issue priority while the ops go out
 #pragma unroll
-    for (int x = 0; x < XS; ++x) acc[x] = floatx16{0.f};
+    for (int x = 0; x < XS; ++x) acc[x] = xc[x];
     const uint8_t* yrow = cy + (32 * t + c) * STB + g * (RB / 2);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -691,7 +697,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     for (int x = 0; x < XS; ++x)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const float d = fmaf(dscale, acc[x][v], xq[x][v] + ynv);
+        const float d = fmaf(dscale, acc[x][v], ynv);
         rmin[x][v] = run_min(rmin[x][v], d, ninf);
         cm = fminf(cm, d);
       }
