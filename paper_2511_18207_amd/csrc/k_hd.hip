@@ -472,7 +472,10 @@ __host__ __device__ constexpr int qdim(int DP, int fmt) { return fmt == FMT_FP8 
 __device__ __forceinline__ float fp8_scale(const uint32_t* maxabs) {
   const float m = __uint_as_float(*maxabs);
   if (!(m > 0.f) || !(m < 3.0e38f)) return 1.f;
-  return exp2f(floorf(log2f(224.f / m)));
+  // at most 2^60, so that scale^2 and the tile's 2 / scale^2 stay finite
+  // normal numbers (values below about 2e-16 then quantise coarsely; the
+  // FP64 refinement still measures the witnesses exactly)
+  return exp2f(fminf(floorf(log2f(224.f / m)), 60.f));
 }
 
 // Xq[i] = quantised Xp[i] (DP elements), qn[i] = |dequantised row|^2.

@@ -50,6 +50,28 @@ def test_exact_low_precision(kind, nA, nB, D, prec):
     assert np.max(np.abs(dq - o["nnA"])) <= 2 * u * R + 1e-3 * R
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_exact_tiny_coordinates(prec):
+    """Coordinates near 1e-18: the FP8 scale 2^floor(log2(224 / max|x - s|))
+    would be 2^64 here, whose square overflows float32; the scale is capped
+    at 2^60 and the refined distance still meets the 1e-4 bar."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"exact_hd prec={prec} tiny coordinates")
+    A, B = synth.gauss_outliers(3000, 2500, 64, seed=11)
+    A *= np.float32(1e-18)
+    B *= np.float32(1e-18)
+    s = A[0].astype(np.float64)
+    m = max(np.abs(A - s).max(), np.abs(B - s).max())
+    assert np.floor(np.log2(224.0 / m)) >= 64   # the uncapped scale would overflow
+    o = oracle.exact_hd(A, B)
+    out = ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True, prec=prec)
+    r = ph.decode_result(out)
+    assert r["status"] == 0
+    assert rel(r["H"], o["H"]) <= 1e-4, (r["H"], o["H"])
+    assert rel(r["hAB"], o["hAB"]) <= 1e-4 and rel(r["hBA"], o["hBA"]) <= 1e-4
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("inner_full", [False, True])
 def test_prohd_hd_low_precision(prec, inner_full):
