@@ -174,7 +174,10 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
  * |a|^2 + |b|^2 - 2 a.b on rows shifted by a common point; the rows with
  * the largest approximate minima (up to 256 per direction) are re-measured
  * against every inner row by float32 direct differences, and the final
- * witness pair in float64.
+ * witness pair in float64.  Range: the search and re-measurement form
+ * float32 squared distances of the shifted rows, so these must stay below
+ * float32's maximum (coordinates spread by up to about 1e18); wider sets
+ * saturate the search and the witness pair is then not guaranteed.
  *
  *   A, B            device float32 point sets (nA x D, nB x D)
  *   idxA, nselA     device: selected rows of A (ascending int32) and their
