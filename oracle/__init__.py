@@ -30,6 +30,7 @@ from .hausdorff import (  # noqa: F401
     directed_hd_bruteforce,
     hd_bruteforce,
     nn_dist,
+    nn_both,
     exact_hd,
     directed_hd_1d,
     hd_1d,

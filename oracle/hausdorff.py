@@ -19,6 +19,7 @@ All inputs are converted to float64 first (an exact upcast of float32 data).
 
 from __future__ import annotations
 
+import ctypes
 import math
 
 import numpy as np
@@ -27,6 +28,7 @@ __all__ = [
     "directed_hd_bruteforce",
     "hd_bruteforce",
     "nn_dist",
+    "nn_both",
     "exact_hd",
     "directed_hd_1d",
     "hd_1d",
@@ -108,8 +110,69 @@ def nn_dist(Q, R, block_elems: int = 1 << 25):
     return dist, arg
 
 
-def exact_hd(A, B, block_elems: int = 1 << 25):
+def nn_both(A, B, block_rows: int = 4096, block_cols: int = 65536):
+    """Nearest-neighbour distances of both directions from one pass.
+
+    The same squared distances as ``nn_dist`` (``|a|^2 + |b|^2 - 2 a.b`` in
+    FP64, the product from the BLAS library), taken block by block over the
+    ``nA x nB`` matrix; each block serves both the minima over B of its A
+    rows and the minima over A of its B rows (the plain loops of
+    ``nnpass.c``, one read of the block), so the distance matrix is formed once, not once per
+    direction.  Ties keep the smallest index, as in ``nn_dist``; each minimum
+    is then re-measured as a direct difference at its arg-min.
+
+    Returns ``(distA, argA, distB, argB)``: for every row of A its NN
+    distance in B and the index, and the same for every row of B in A.
+    """
+    from . import _native
+
+    lib = _native.load()
+    A = _f64(A)
+    B = _f64(B)
+    nA, nB = A.shape[0], B.shape[0]
+    if nA == 0 or nB == 0:
+        raise ValueError("nn_both needs non-empty sets")
+    an = np.ascontiguousarray(np.einsum("ij,ij->i", A, A))
+    bn = np.ascontiguousarray(np.einsum("ij,ij->i", B, B))
+    rowd = np.full(nA, np.inf)
+    rowj = np.full(nA, -1, dtype=np.int64)
+    cold = np.full(nB, np.inf)
+    coli = np.full(nB, -1, dtype=np.int64)
+    def dp(a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def ip(a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    for i0 in range(0, nA, block_rows):
+        i1 = min(nA, i0 + block_rows)
+        rd = np.ascontiguousarray(rowd[i0:i1])
+        rj = np.ascontiguousarray(rowj[i0:i1])
+        qn = np.ascontiguousarray(an[i0:i1])
+        for j0 in range(0, nB, block_cols):
+            j1 = min(nB, j0 + block_cols)
+            G = np.ascontiguousarray(A[i0:i1] @ B[j0:j1].T)
+            rn = np.ascontiguousarray(bn[j0:j1])
+            cd = np.ascontiguousarray(cold[j0:j1])
+            ci = np.ascontiguousarray(coli[j0:j1])
+            if lib.nn_block(dp(G), i1 - i0, j1 - j0, dp(qn), dp(rn), i0, j0, dp(rd), ip(rj),
+                            dp(cd), ip(ci)):
+                raise MemoryError("nn_block: allocation failed")
+            cold[j0:j1] = cd
+            coli[j0:j1] = ci
+        rowd[i0:i1] = rd
+        rowj[i0:i1] = rj
+    dA = A - B[rowj]
+    dB = B - A[coli]
+    return (np.sqrt(np.einsum("ij,ij->i", dA, dA)), rowj,
+            np.sqrt(np.einsum("ij,ij->i", dB, dB)), coli)
+
+
+def exact_hd(A, B, block_elems: int = 1 << 25, one_pass: bool = False):
     """Exact H(A,B) of Eq. (1) with both directed parts and witnesses.
+
+    ``one_pass`` takes both directions' minima from one pass over the
+    distance matrix (``nn_both``) instead of one pass per direction.
 
     Returns a dict:
       ``H, hAB, hBA``        Euclidean distances (float)
@@ -122,8 +185,11 @@ def exact_hd(A, B, block_elems: int = 1 << 25):
     B = _f64(B)
     if A.shape[1] != B.shape[1]:
         raise ValueError("A and B must have the same dimension")
-    nnA, argA = nn_dist(A, B, block_elems)
-    nnB, argB = nn_dist(B, A, block_elems)
+    if one_pass:
+        nnA, argA, nnB, argB = nn_both(A, B)
+    else:
+        nnA, argA = nn_dist(A, B, block_elems)
+        nnB, argB = nn_dist(B, A, block_elems)
     ia = int(np.argmax(nnA))
     ib = int(np.argmax(nnB))
     hAB = float(nnA[ia])
