@@ -60,11 +60,39 @@ struct RefineJob {
   unsigned long long* best;
 };
 
+// bound keys of one side's rows, in place over its row minima
+struct KeyJob {
+  uint32_t* mins;
+  const float* xn;
+  const int64_t* dn;
+  int64_t hn;
+  int32_t nbx;          // blocks of this job (rows are strided over them)
+};
+
+// rows of one direction left uncertain by the first refinement (one
+// work-group each): key above the largest refined squared minimum, not
+// refined yet -> cand2 (ascending), count2, best2 initialised
+struct UncJob {
+  const uint32_t* key;               // bound keys (float bits)
+  const uint8_t* top;                // rows of the first refinement (flag 1)
+  const int64_t* dn;                 // device row count, or null
+  int64_t hn;                        // host bound on the row count
+  const unsigned long long* best;    // first-pass minima
+  const int64_t* dR;                 // first-pass count
+  const int32_t* status;
+  int32_t* cand2;                    // capacity hn
+  int64_t* count2;
+  unsigned long long* best2;         // capacity hn
+};
+
 // one directed half of the final witness search
 struct FinalDir {
   const unsigned long long* best;
   const int32_t* cand;
   const int64_t* dR;
+  const unsigned long long* best2;   // second refinement pass (or null)
+  const int32_t* cand2;
+  const int64_t* dR2;
   const int32_t* mapX;
   const int32_t* mapY;
   const float* Xo;
@@ -147,6 +175,12 @@ prohd_status batch_tile(int DP, const TileJob* jobs, const BItem* items, int nit
                         hipStream_t s);
 prohd_status batch_refine(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
                           hipStream_t s);
+prohd_status batch_keys(int DP, const KeyJob* jobs, const BItem* items, int nitems, int grid,
+                        hipStream_t s);
+prohd_status batch_uncertain(const UncJob* jobs, int njobs, hipStream_t s);
+// items (job, Y chunk); each walks every candidate block of its job's count
+prohd_status batch_refine_dyn(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
+                              hipStream_t s);
 prohd_status batch_finalize(const FinalJob* jobs, int njobs, hipStream_t s);
 prohd_status batch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 prohd_status batch_fill64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

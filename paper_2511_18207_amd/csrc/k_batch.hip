@@ -66,7 +66,10 @@ struct PairWs {
   int64_t* ccnt;      // [2] refined-candidate counts
   unsigned long long* best[2];
   int32_t* cand[2];
-  uint32_t* row[2];   // row minima of the A side / B side rows
+  int64_t* ccnt2;     // [2] second-pass counts
+  unsigned long long* best2[2];   // second refinement pass (one entry per row)
+  int32_t* cand2[2];
+  uint32_t* row[2];   // row minima (then bound keys) of the A side / B side rows
   uint8_t* top[2];    // top-row flags
   float* xp[2];       // prepared rows (DP wide)
   float* xn[2];
@@ -139,6 +142,9 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
   for (const Pair& q : b.pairs) L.nrow += side_rows(q, 0, mode) + side_rows(q, 1, mode);
   L.row = ar.take<uint32_t>(L.nrow);
   L.top = ar.take<uint8_t>(L.nrow);
+  int64_t* ccnt2 = ar.take<int64_t>(2 * (size_t)P);
+  int32_t* cand2 = ar.take<int32_t>(L.nrow);
+  unsigned long long* best2 = ar.take<unsigned long long>(L.nrow);
   L.nflags = 0;
   if (mode == PROHD_BATCH_PROHD)
     for (const Pair& q : b.pairs) L.nflags += q.nA + q.nB;
@@ -150,10 +156,13 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
     w.status = L.status + i;
     w.cnt = cnt + 2 * i;
     w.ccnt = ccnt + 2 * i;
+    w.ccnt2 = ccnt2 + 2 * i;
     for (int s = 0; s < 2; ++s) {
       const int64_t r = side_rows(q, s, mode);
       w.best[s] = L.best + ((size_t)2 * i + s) * kRefine;
       w.cand[s] = cand + ((size_t)2 * i + s) * kRefine;
+      w.cand2[s] = cand2 + ro;
+      w.best2[s] = best2 + ro;
       w.row[s] = L.row + ro;
       w.top[s] = L.top + ro;
       ro += r;
@@ -236,9 +245,10 @@ prohd_status build(prohd_batch* b) {
     int D, DP, m;
     size_t gram_jobs, gram_items, red_jobs, eig_jobs, proj_jobs, seg_jobs, cmp_jobs;
     int n_gram_items, n_red, n_eig, n_proj, n_seg, n_cmp;
-    size_t prep_jobs, prep_items, tile_jobs, tile_items, top_jobs, topc_jobs, ref_jobs, ref_items,
-        fin_jobs;
-    int n_prep_items, n_tile_items, n_top, n_topc, n_ref_items, n_fin;
+    size_t prep_jobs, prep_items, tile_jobs, tile_items, key_jobs, key_items, top_jobs, topc_jobs,
+        ref_jobs, ref_items, unc_jobs, ref2_jobs, ref2_items, fin_jobs;
+    int n_prep_items, n_tile_items, n_key_items, n_top, n_topc, n_ref_items, n_unc, n_ref2_items,
+        n_fin;
   };
   std::vector<Rec> recs;
   const bool prohd = mode == PROHD_BATCH_PROHD;
@@ -313,6 +323,11 @@ prohd_status build(prohd_batch* b) {
     std::vector<CompactJob> tcj;
     std::vector<RefineJob> rfj;
     std::vector<BItem> rfi;
+    std::vector<KeyJob> kyj;
+    std::vector<BItem> kyi;
+    std::vector<UncJob> ucj;
+    std::vector<RefineJob> r2j;
+    std::vector<BItem> r2i;
     std::vector<FinalJob> fj;
     for (int i : g) {
       const Pair& q = b->pairs[i];
@@ -347,12 +362,24 @@ prohd_status build(prohd_batch* b) {
         rfj.push_back(RefineJob{w.xp[s], w.cand[s], w.ccnt + s, w.xp[1 - s], s ? dA : dB, ry, ys,
                                 w.best[s]});
         for (int x = 0; x < (kRefine / 64) * ys; ++x) rfi.push_back(BItem{rjob, x});
+        // bound keys in place of the row minima, then the rows the first
+        // refinement leaves uncertain and their refinement
+        const int kbx = (int)std::max<int64_t>(1, cdiv(r, 256));
+        const int kjob = (int)kyj.size();
+        kyj.push_back(KeyJob{w.row[s], w.xn[s], s ? dB : dA, r, kbx});
+        for (int x = 0; x < kbx; ++x) kyi.push_back(BItem{kjob, x});
+        ucj.push_back(UncJob{w.row[s], w.top[s], s ? dB : dA, r, w.best[s], w.ccnt + s, w.status,
+                             w.cand2[s], w.ccnt2 + s, w.best2[s]});
+        const int r2job = (int)r2j.size();
+        r2j.push_back(RefineJob{w.xp[s], w.cand2[s], w.ccnt2 + s, w.xp[1 - s], s ? dA : dB, ry, ys,
+                                w.best2[s]});
+        for (int x = 0; x < ys; ++x) r2i.push_back(BItem{r2job, x});
       }
       FinalJob f{};
-      f.ab = FinalDir{w.best[0], w.cand[0], w.ccnt, prohd ? w.idx[0] : nullptr,
-                      prohd ? w.idx[1] : nullptr, Ap, Bp};
-      f.ba = FinalDir{w.best[1], w.cand[1], w.ccnt + 1, prohd ? w.idx[1] : nullptr,
-                      prohd ? w.idx[0] : nullptr, Bp, Ap};
+      f.ab = FinalDir{w.best[0], w.cand[0], w.ccnt, w.best2[0], w.cand2[0], w.ccnt2,
+                      prohd ? w.idx[0] : nullptr, prohd ? w.idx[1] : nullptr, Ap, Bp};
+      f.ba = FinalDir{w.best[1], w.cand[1], w.ccnt + 1, w.best2[1], w.cand2[1], w.ccnt2 + 1,
+                      prohd ? w.idx[1] : nullptr, prohd ? w.idx[0] : nullptr, Bp, Ap};
       f.dnA = dA;
       f.hnA = rA;
       f.dnB = dB;
@@ -375,6 +402,14 @@ prohd_status build(prohd_batch* b) {
     r.ref_jobs = T.add(rfj);
     r.ref_items = T.add(rfi);
     r.n_ref_items = (int)rfi.size();
+    r.key_jobs = T.add(kyj);
+    r.key_items = T.add(kyi);
+    r.n_key_items = (int)kyi.size();
+    r.unc_jobs = T.add(ucj);
+    r.n_unc = (int)ucj.size();
+    r.ref2_jobs = T.add(r2j);
+    r.ref2_items = T.add(r2i);
+    r.n_ref2_items = (int)r2i.size();
     r.fin_jobs = T.add(fj);
     r.n_fin = (int)fj.size();
     recs.push_back(r);
@@ -444,11 +479,22 @@ prohd_status build(prohd_batch* b) {
       return batch_tile(r.DP, (const TileJob*)at(r.tile_jobs), (const BItem*)at(r.tile_items),
                         r.n_tile_items, tile_grid, s);
     });
+    const int key_grid = persist(r.n_key_items, 8);
+    Ls.push_back([=](hipStream_t s) {
+      return batch_keys(r.DP, (const KeyJob*)at(r.key_jobs), (const BItem*)at(r.key_items),
+                        r.n_key_items, key_grid, s);
+    });
     Ls.push_back([=](hipStream_t s) { return batch_select((const SegJob*)at(r.top_jobs), r.n_top, s); });
     Ls.push_back([=](hipStream_t s) { return batch_compact((const CompactJob*)at(r.topc_jobs), r.n_topc, s); });
     Ls.push_back([=](hipStream_t s) {
       return batch_refine(r.DP, (const RefineJob*)at(r.ref_jobs), (const BItem*)at(r.ref_items),
                           r.n_ref_items, ref_grid, s);
+    });
+    Ls.push_back([=](hipStream_t s) { return batch_uncertain((const UncJob*)at(r.unc_jobs), r.n_unc, s); });
+    const int ref2_grid = persist(r.n_ref2_items, 4);
+    Ls.push_back([=](hipStream_t s) {
+      return batch_refine_dyn(r.DP, (const RefineJob*)at(r.ref2_jobs), (const BItem*)at(r.ref2_items),
+                              r.n_ref2_items, ref2_grid, s);
     });
     Ls.push_back([=](hipStream_t s) { return batch_finalize((const FinalJob*)at(r.fin_jobs), r.n_fin, s); });
   }

@@ -817,24 +817,21 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
 // LDS as float64, 32 rows per block (two 16-column accumulators).
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// Candidate block cb (rows 64 cb .. 64 cb + 63 of cand[0..R)) against Y
+// chunk ysi of ysplit.  Every thread of the work-group makes the same call;
+// LDS is reused from one call to the next (each Y block starts at a barrier).
 template <int DP>
-__device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
-                                            const int32_t* __restrict__ cand,
-                                            const int64_t* __restrict__ dR,
-                                            const float* __restrict__ Yp,
-                                            const int64_t* __restrict__ dnY, int64_t hnY,
-                                            int ysplit,
-                                            unsigned long long* __restrict__ best, int bx) {
+__device__ __forceinline__ void refine_block(const float* __restrict__ Xp,
+                                             const int32_t* __restrict__ cand, int64_t R,
+                                             const float* __restrict__ Yp, int64_t nY, int ysplit,
+                                             int ysi, int64_t cb,
+                                             unsigned long long* __restrict__ best) {
   constexpr int KS = DP / 4;        // k steps of the 16x16x4 op
   constexpr int BNY = 32;           // Y rows per LDS block
   constexpr int STY = DP + 4;       // LDS row stride (doubles)
   __shared__ double ys[BNY * STY];
   __shared__ double yq[BNY];
-  const int64_t R = *dR;
-  const int64_t nY = dev_or(dnY, hnY);
-  const int cb = bx / ysplit;
-  const int ysi = bx - cb * ysplit;
-  if ((int64_t)cb * 64 >= R) return;
+  if (cb * 64 >= R) return;
   const int64_t chunk = ((nY + ysplit - 1) / ysplit + BNY - 1) / BNY * BNY;
   const int64_t yb = (int64_t)ysi * chunk;
   const int64_t ye = min(nY, yb + chunk);
@@ -846,7 +843,7 @@ __device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
   const int kq = lane >> 4;    // k within the group of four
 
   // A operands: candidate row 64 cb + 16 wave + i16, k = 4 s + kq
-  const int64_t cr = (int64_t)cb * 64 + 16 * wave + i16;
+  const int64_t cr = cb * 64 + 16 * wave + i16;
   const float* xrow = (cr < R) ? (Xp + (int64_t)cand[cr] * DP) : nullptr;
   double a[KS];
 #pragma unroll
@@ -944,9 +941,43 @@ __device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
       const unsigned long long o = __shfl_xor(p, off);
       p = o < p ? o : p;
     }
-    const int64_t r = (int64_t)cb * 64 + 16 * wave + kq + 4 * v;
+    const int64_t r = cb * 64 + 16 * wave + kq + 4 * v;
     if (i16 == 0 && r < R) atomicMin(&best[r], p);
   }
+}
+
+// Work-group bx of a (candidate block) x (ysplit Y chunks) grid.
+template <int DP>
+__device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
+                                            const int32_t* __restrict__ cand,
+                                            const int64_t* __restrict__ dR,
+                                            const float* __restrict__ Yp,
+                                            const int64_t* __restrict__ dnY, int64_t hnY,
+                                            int ysplit,
+                                            unsigned long long* __restrict__ best, int bx) {
+  const int cb = bx / ysplit;
+  refine_block<DP>(Xp, cand, *dR, Yp, dev_or(dnY, hnY), ysplit, bx - cb * ysplit, cb, best);
+}
+
+// Second refinement pass: the candidate count is known only on the device,
+// so the grid is (groups) x (ysplit Y chunks) and each work-group walks the
+// candidate blocks cb = group, group + groups, ...; with no candidates (the
+// usual case) every work-group returns at once.
+template <int DP>
+__device__ __forceinline__ void refine_dyn_body(const float* __restrict__ Xp,
+                                                const int32_t* __restrict__ cand,
+                                                const int64_t* __restrict__ dR,
+                                                const float* __restrict__ Yp,
+                                                const int64_t* __restrict__ dnY, int64_t hnY,
+                                                int ysplit, unsigned long long* __restrict__ best,
+                                                int bx, int nbx) {
+  const int64_t R = *dR;
+  const int64_t nY = dev_or(dnY, hnY);
+  const int groups = nbx / ysplit;
+  const int g = bx / ysplit;
+  const int ysi = bx - g * ysplit;
+  for (int64_t cb = g; cb * 64 < R; cb += groups)
+    refine_block<DP>(Xp, cand, R, Yp, nY, ysplit, ysi, cb, best);
 }
 
 template <int DP>
@@ -960,11 +991,207 @@ __global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
   refine_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x);
 }
 
+template <int DP>
+__global__ __launch_bounds__(256) void refine_rows_dyn(const float* __restrict__ Xp,
+                                                       const int32_t* __restrict__ cand,
+                                                       const int64_t* __restrict__ dR,
+                                                       const float* __restrict__ Yp,
+                                                       const int64_t* __restrict__ dnY, int64_t hnY,
+                                                       int ysplit,
+                                                       unsigned long long* __restrict__ best) {
+  refine_dyn_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------- certified refinement
+// The tile search gives each row x an approximate squared minimum m2 of its
+// distance to the other set.  Which rows the float64 refinement re-measures
+// follows from a bound of the search error, so that the maximum it returns
+// is the exact directed distance (up to the float64 rounding of the
+// re-measured rows) for any data, not only where the approximate minima
+// happen to rank the witness among the first rows.
+//
+// Error model.  x, y are the shifted float32 rows; xq, yq the copies the
+// tile multiplies (x, y themselves in float32; rounded to nearest bfloat16,
+// or to e4m3 after the power-of-two scale sc, in the low-precision formats);
+// K is the number of products per dot product (padded width).
+//   quantisation  |xq - x| <= uq |x| + a        uq = 2^-8 (bfloat16: round to
+//                 nearest even), 2^-3 (e4m3: one unit in the last place, which
+//                 holds for any rounding of the conversion), 0 (float32); a
+//                 covers subnormals: sqrt(K) 2^-9 / sc for e4m3 (one subnormal
+//                 step), sqrt(K) 2^-126 (operands flushed to zero) otherwise
+//   expansion     |m2~ - |xq - yq|^2| <= c (|xq| + |yq|)^2 + eta  per pair,
+//                 c = 2 (K + 4) 2^-24: twice the worst-case error of a float32
+//                 sum of the K products and the two norms in any order; eta =
+//                 16 (K + 4) 2^-126 (flushed subnormal products; / sc^2 for e4m3)
+// For the row y* the search found (squared value m2) let t = |x - y*|; with
+// S >= |x| one has |x| + |y*| <= 2 S + t, so
+//   |xq - y*q| >= p t - b,               p = 1 - uq, b = 2 (uq S + a)
+//   |xq - y*q|^2 <= m2 + eta + (r t + e)^2,  r = sqrt(c)(1 + uq),
+//                                            e = sqrt(c)(2 (1 + uq) S + 2 a)
+// and (p t - b)^2 - (r t + e)^2 <= m2 + eta.  The larger root of that
+// quadratic bounds t, and the row's true minimum is at most t:
+//   U = ((p b + r e) + sqrt((p e + r b)^2 + (p^2 - r^2)(m2 + eta))) / (p^2 - r^2).
+// U replaces m2 as the ranking key (bits of U^2 rounded up to float32, in
+// place): the first refinement takes the 256 rows with the largest U; then
+// every other row whose U exceeds the largest refined minimum is refined
+// too (uncertain_rows + refine_rows_dyn, usually nothing), after which no
+// unrefined row can exceed the returned maximum.
+struct SearchModel {
+  double c, uq, a, eta;
+};
+
+__device__ __forceinline__ SearchModel search_model(int K, int fmt, const uint32_t* maxabs) {
+  SearchModel q;
+  q.c = 2.0 * (K + 4) * 0x1p-24;
+  q.eta = 16.0 * (K + 4) * 0x1p-126;
+  q.uq = 0.0;
+  q.a = sqrt((double)K) * 0x1p-126;
+  if (fmt == FMT_BF16) q.uq = 0x1p-8;
+  if (fmt == FMT_FP8) {
+    const double sc = fp8_scale(maxabs);
+    q.uq = 0x1p-3;
+    q.a = sqrt((double)K) * 0x1p-9 / sc;
+    q.eta /= sc * sc;
+  }
+  return q;
+}
+
+__device__ __forceinline__ double min_upper(double m2, double S, const SearchModel& q) {
+  const double rc = sqrt(q.c);
+  const double p = 1.0 - q.uq, b = 2.0 * (q.uq * S + q.a);
+  const double r = rc * (1.0 + q.uq), e = rc * (2.0 * (1.0 + q.uq) * S + 2.0 * q.a);
+  const double den = p * p - r * r;
+  const double g = p * e + r * b;
+  return ((p * b + r * e) + sqrt(g * g + den * (m2 + q.eta))) / den;
+}
+
+// float32 bits of the smallest float >= v (v >= 0)
+__device__ __forceinline__ uint32_t bits_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return __float_as_uint(f);
+}
+
+// float32 bits of the largest float <= v (v >= 0)
+__device__ __forceinline__ uint32_t bits_down(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return __float_as_uint(f);
+}
+
+// mins[i] (bits of the approximate squared minimum) -> bits of U^2 rounded
+// up, for the rows i < n.  xn[i]: float32 |x_i|^2 of the shifted row (DP
+// terms, so |x|^2 <= xn (1 + 2 (DP + 2) 2^-24)).
+__device__ __forceinline__ void bound_keys_body(uint32_t* __restrict__ mins,
+                                                const float* __restrict__ xn, int64_t n, int DP,
+                                                int K, int fmt, const uint32_t* __restrict__ maxabs,
+                                                int64_t i0, int64_t stride) {
+  const SearchModel q = search_model(K, fmt, maxabs);
+  const double grow = 1.0 + 2.0 * (DP + 2) * 0x1p-24;
+  for (int64_t i = i0; i < n; i += stride) {
+    const double m2 = (double)__uint_as_float(mins[i]);
+    const double S = sqrt((double)xn[i] * grow);
+    const double U = min_upper(m2, S, q);
+    mins[i] = bits_up(U * U * (1.0 + 0x1p-40));
+  }
+}
+
+__global__ __launch_bounds__(256) void bound_keys(uint32_t* __restrict__ mins,
+                                                  const float* __restrict__ xn,
+                                                  const int64_t* __restrict__ dn, int64_t hn, int DP,
+                                                  int K, int fmt, const uint32_t* __restrict__ maxabs) {
+  bound_keys_body(mins, xn, dev_or(dn, hn), DP, K, fmt, maxabs,
+                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Exclusive prefix sum over a work-group of NT threads; *total gets the sum.
+template <int NT>
+__device__ __forceinline__ uint32_t wg_excl_sum(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  __syncthreads();   // the previous call's reads of lds are done
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    const uint32_t x = lds[k];
+    before += k < w ? x : 0u;
+    tot += x;
+  }
+  *total = tot;
+  return before + inc - v;
+}
+
+// Rows left uncertain after the first refinement of one direction: key
+// above the largest refined squared minimum (lowered by 2^-20 of itself to
+// cover its rounding to float32 and the float64 expansion of the
+// refinement), not refined yet.  Their indices go to cand2 in ascending
+// order (one work-group: the order, and so any tie between equal refined
+// values, does not depend on timing), count2 gets their number and best2
+// the initial value of their minima.
+template <int NT>
+__device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
+  const int tid = threadIdx.x;
+  const bool ok = *j.status == ST_OK;
+  const int64_t R = ok ? *j.dR : 0;
+  const int64_t n = R > 0 ? dev_or(j.dn, j.hn) : 0;
+  uint32_t hb = 0;
+  for (int64_t r = tid; r < R; r += NT) hb = max(hb, (uint32_t)(j.best[r] >> 32));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) hb = max(hb, (uint32_t)__shfl_xor(hb, o));
+  __syncthreads();
+  if ((tid & 63) == 0) lds[tid >> 6] = hb;
+  __syncthreads();
+  hb = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) hb = max(hb, lds[k]);
+  const uint32_t tb = bits_down((double)__uint_as_float(hb) * (1.0 - 0x1p-20));
+  constexpr int Q = 8;
+  int64_t base = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += (int64_t)NT * Q) {
+    uint32_t f = 0, cnt = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = c0 + (int64_t)tid * Q + q;
+      const bool on = i < n && j.top[i] == 0 && j.key[i] > tb;
+      f |= (on ? 1u : 0u) << q;
+      cnt += on ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t pos = wg_excl_sum<NT>(cnt, lds, &tot);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if ((f >> q) & 1u) j.cand2[base + pos++] = (int32_t)(c0 + (int64_t)tid * Q + q);
+    base += tot;
+  }
+  if (tid == 0) *j.count2 = base;
+  for (int64_t i = tid; i < base; i += NT) j.best2[i] = ~0ull;
+}
+
+constexpr int kUncT = 1024;
+struct UncPair {
+  UncJob d[2];
+};
+
+__global__ __launch_bounds__(kUncT) void uncertain_rows(const UncPair P) {
+  __shared__ uint32_t lds[kUncT / 64];
+  uncertain_body<kUncT>(P.d[blockIdx.x], lds);
+}
+
 // -------------------------------------------------------------- finalize
 struct DirIn {
-  const unsigned long long* best;  // refined minima
-  const int32_t* cand;             // candidate rows (indices into the X list)
-  const int64_t* dR;               // number of candidates
+  const unsigned long long* best;  // refined minima, first pass
+  const int32_t* cand;             // its rows (indices into the X list)
+  const int64_t* dR;               // its number of rows
+  const unsigned long long* best2; // second pass (uncertain rows), or null
+  const int32_t* cand2;
+  const int64_t* dR2;
   const int32_t* mapX;             // X list -> original rows (or null)
   const int32_t* mapY;             // Y list -> original rows (or null)
   const float* Xo;                 // original X rows
@@ -996,32 +1223,53 @@ __device__ __forceinline__ void finalize_body(const DirIn& ab, const DirIn& ba, 
                                               prohd_result* __restrict__ out) {
   __shared__ double red[256];
   __shared__ unsigned long long bestp[256];
+  __shared__ int64_t bestpos[256];
   int64_t wx[2], wy[2];
   double h[2];
   const int64_t nA = dev_or(dnA, hnA), nB = dev_or(dnB, hnB);
   int32_t st = *status;
   if (nA < 1 || nB < 1) st = st ? st : ST_EMPTY;
+  int64_t refined = 0;
   for (int dir = 0; dir < 2; ++dir) {
     const DirIn& d = dir == 0 ? ab : ba;
     const int64_t R = (st == ST_OK) ? *d.dR : 0;
-    // largest refined minimum; ties -> smallest candidate position
+    const int64_t R2 = (st == ST_OK && d.dR2) ? *d.dR2 : 0;
+    refined = R + R2 > refined ? R + R2 : refined;
+    // largest refined minimum over both passes; ties -> smallest row of the
+    // X list (low word: its complement), then the first pass
     unsigned long long m = 0ull;
-    for (int64_t r = threadIdx.x; r < R; r += blockDim.x) {
-      const unsigned long long v = ((d.best[r] >> 32) << 32) | (0xFFFFFFFFull - (unsigned long long)r);
-      m = v > m ? v : m;
+    int64_t mpos = -1;
+    for (int64_t r = threadIdx.x; r < R + R2; r += blockDim.x) {
+      const bool first = r < R;
+      const unsigned long long b = first ? d.best[r] : d.best2[r - R];
+      const uint32_t xi = (uint32_t)(first ? d.cand[r] : d.cand2[r - R]);
+      const unsigned long long v = ((b >> 32) << 32) | (0xFFFFFFFFull - xi);
+      if (v > m) {
+        m = v;
+        mpos = r;
+      }
     }
     bestp[threadIdx.x] = m;
+    bestpos[threadIdx.x] = mpos;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) bestp[threadIdx.x] = max(bestp[threadIdx.x], bestp[threadIdx.x + w]);
+      if ((int)threadIdx.x < w) {
+        const unsigned long long o = bestp[threadIdx.x + w];
+        if (o > bestp[threadIdx.x] ||
+            (o == bestp[threadIdx.x] && bestpos[threadIdx.x + w] < bestpos[threadIdx.x])) {
+          bestp[threadIdx.x] = o;
+          bestpos[threadIdx.x] = bestpos[threadIdx.x + w];
+        }
+      }
       __syncthreads();
     }
-    const unsigned long long top = bestp[0];
+    const int64_t r = bestpos[0];
     __syncthreads();
-    if (R > 0) {
-      const int64_t r = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
-      const int64_t xi = d.cand[r];
-      const int64_t yi = (int64_t)(d.best[r] & 0xFFFFFFFFull);
+    if (r >= 0) {
+      const bool first = r < R;
+      const int64_t xi = first ? d.cand[r] : d.cand2[r - R];
+      const unsigned long long b = first ? d.best[r] : d.best2[r - R];
+      const int64_t yi = (int64_t)(b & 0xFFFFFFFFull);
       wx[dir] = d.mapX ? (int64_t)d.mapX[xi] : xi;
       wy[dir] = d.mapY ? (int64_t)d.mapY[yi] : yi;
       h[dir] = pair_dist64(d.Xo, wx[dir], d.Yo, wy[dir], D, red);
@@ -1042,7 +1290,7 @@ __device__ __forceinline__ void finalize_body(const DirIn& ab, const DirIn& ba, 
     r.nA_sel = nA;
     r.nB_sel = nB;
     r.status = st;
-    r.refined = 0;
+    r.refined = (int32_t)refined;
     *out = r;
   }
 }
@@ -1055,9 +1303,6 @@ __global__ __launch_bounds__(256) void finalize(DirIn ab, DirIn ba, int D,
   finalize_body(ab, ba, D, dnA, hnA, dnB, hnB, status, out);
 }
 
-__global__ void store_refined(prohd_result* out, const int64_t* dR1, const int64_t* dR2) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) out->refined = (int32_t)max(*dR1, *dR2);
-}
 
 // ------------------------------------------------------------ batched
 // Persistent versions: each work-group walks the item table and runs the
@@ -1102,12 +1347,53 @@ __global__ __launch_bounds__(256) void refine_batch(const RefineJob* __restrict_
 __global__ __launch_bounds__(256) void finalize_batch(const FinalJob* __restrict__ jobs, int njobs) {
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const FinalJob j = jobs[it];
-    const DirIn ab{j.ab.best, j.ab.cand, j.ab.dR, j.ab.mapX, j.ab.mapY, j.ab.Xo, j.ab.Yo};
-    const DirIn ba{j.ba.best, j.ba.cand, j.ba.dR, j.ba.mapX, j.ba.mapY, j.ba.Xo, j.ba.Yo};
+    const DirIn ab{j.ab.best, j.ab.cand, j.ab.dR, j.ab.best2, j.ab.cand2, j.ab.dR2,
+                   j.ab.mapX, j.ab.mapY, j.ab.Xo, j.ab.Yo};
+    const DirIn ba{j.ba.best, j.ba.cand, j.ba.dR, j.ba.best2, j.ba.cand2, j.ba.dR2,
+                   j.ba.mapX, j.ba.mapY, j.ba.Xo, j.ba.Yo};
     __syncthreads();
     finalize_body(ab, ba, j.D, j.dnA, j.hnA, j.dnB, j.hnB, j.status, j.out);
+  }
+}
+
+// Bound keys of one side's rows, in place over its row minima (float32
+// tiles: K = DP).
+__global__ __launch_bounds__(256) void keys_batch(const KeyJob* __restrict__ jobs, int DP,
+                                                  const BItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const KeyJob j = jobs[w.job];
+    bound_keys_body(j.mins, j.xn, dev_or(j.dn, j.hn), DP, DP, FMT_F32, nullptr,
+                    (int64_t)w.bx * blockDim.x + threadIdx.x, (int64_t)j.nbx * blockDim.x);
+  }
+}
+
+constexpr int kUncBatchT = 256;
+
+__global__ __launch_bounds__(kUncBatchT) void uncertain_batch(const UncJob* __restrict__ jobs,
+                                                              int njobs) {
+  __shared__ uint32_t lds[kUncBatchT / 64];
+  for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
+    const UncJob j = jobs[it];
     __syncthreads();
-    if (threadIdx.x == 0) j.out->refined = (int32_t)max(*j.ab.dR, *j.ba.dR);
+    uncertain_body<kUncBatchT>(j, lds);
+  }
+}
+
+// Second refinement pass of many pairs: item (job, Y chunk) walks every
+// candidate block of its job's device count (none in the usual case).
+template <int DP>
+__global__ __launch_bounds__(256) void refine_dyn_batch(const RefineJob* __restrict__ jobs,
+                                                        const BItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const RefineJob j = jobs[w.job];
+    const int64_t R = *j.dR;
+    const int64_t nY = dev_or(j.dnY, j.hnY);
+    for (int64_t cb = 0; cb * 64 < R; ++cb)
+      refine_block<DP>(j.Xp, j.cand, R, j.Yp, nY, j.ysplit, w.bx, cb, j.best);
   }
 }
 
@@ -1241,6 +1527,9 @@ struct DirWork {
   int32_t* cand;    // kRefineRows
   int64_t* count;   // 1
   unsigned long long* best;  // kRefineRows
+  int32_t* cand2;   // n: rows of the second refinement pass
+  int64_t* count2;  // 1
+  unsigned long long* best2;  // n
 };
 
 struct HdLayout {
@@ -1283,6 +1572,9 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
     L.w[d].cand = ar.take<int32_t>(kRefineRows);
     L.w[d].count = ar.take<int64_t>(1);
     L.w[d].best = ar.take<unsigned long long>(kRefineRows);
+    L.w[d].cand2 = ar.take<int32_t>(caps[d]);
+    L.w[d].count2 = ar.take<int64_t>(1);
+    L.w[d].best2 = ar.take<unsigned long long>(caps[d]);
   }
   const int64_t mx = std::max(capA, capB);
   L.sel_bytes = std::max(select_ws_bytes(2, mx), compact_ws_bytes(mx));
@@ -1319,6 +1611,28 @@ prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const 
     st = compact_flags(w[d].flags, n[d], dn[d], w[d].cand, kRefineRows, w[d].count, sel_ws, sel_bytes, s);
     if (st) return st;
   }
+  return PROHD_OK;
+}
+
+// Bound keys in place of the row minima (see the certified refinement).
+prohd_status launch_keys(uint32_t* mins, const float* xn, const int64_t* dn, int64_t cap, int DP,
+                         int fmt, const uint32_t* maxabs, hipStream_t s) {
+  const int K = fmt == FMT_F32 ? DP : qdim(DP, fmt);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 8 * cu_count()));
+  PROHD_LAUNCH("hd_keys", bound_keys, dim3(grid), dim3(256), 0, s, mins, xn, dn, cap, DP, K, fmt,
+               maxabs);
+  return PROHD_OK;
+}
+
+// Second refinement pass of one direction: cand2 / count2 / best2 against
+// Y (device count known only on the device).
+template <int DP>
+prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64_t* dR,
+                               const float* Yp, const int64_t* dnY, int64_t capY,
+                               unsigned long long* best, hipStream_t s) {
+  const int split = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 128));
+  PROHD_LAUNCH("hd_refine2", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
+               dR, Yp, dnY, capY, split, best);
   return PROHD_OK;
 }
 
@@ -1374,28 +1688,42 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   const uint32_t* const mins2[2] = {L.rowA, L.rowB};
   const int64_t caps2[2] = {capA, capB};
   const int64_t* const dns2[2] = {dnA, dnB};
-  DirIn ab{}, ba{};
+  PrepSet ysA = full ? L.fa : L.xa;   // the sets the refinement measures against
+  PrepSet ysB = full ? L.fb : L.xb;
+  const int64_t* ydnA = full ? nullptr : dnA;
+  const int64_t* ydnB = full ? nullptr : dnB;
+  const int64_t ycapA = full ? nA : capA;
+  const int64_t ycapB = full ? nB : capB;
   if (!full) {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
-    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
-    PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.xb.p, dnB, capB, L.w[0].best, s));
-    PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, L.xa.p, dnA, capA, L.w[1].best, s));
-    ab = DirIn{L.w[0].best, L.w[0].cand, L.w[0].count, idxA, idxB, A, B};
-    ba = DirIn{L.w[1].best, L.w[1].cand, L.w[1].count, idxB, idxA, B, A};
   } else {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
     PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.fa, nullptr, nA, L.maxabs, L.rowB, nullptr, s));
-    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
-    PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, L.fb.p, nullptr, nB, L.w[0].best, s));
-    PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, L.fa.p, nullptr, nA, L.w[1].best, s));
-    ab = DirIn{L.w[0].best, L.w[0].cand, L.w[0].count, idxA, nullptr, A, B};
-    ba = DirIn{L.w[1].best, L.w[1].cand, L.w[1].count, idxB, nullptr, B, A};
   }
-  PROHD_LAUNCH("hd_finalize", finalize, dim3(1), dim3(256), 0, s, ab, ba, D, dnA, capA, dnB, capB,
-               L.status, out);
-  PROHD_LAUNCH("hd_finalize", store_refined, dim3(1), dim3(64), 0, s, out, L.w[0].count, L.w[1].count);
   if (nn2A) PROHD_HIP(hipMemcpyAsync(nn2A, L.rowA, sizeof(float) * capA, hipMemcpyDeviceToDevice, s));
   if (nn2B) PROHD_HIP(hipMemcpyAsync(nn2B, L.rowB, sizeof(float) * capB, hipMemcpyDeviceToDevice, s));
+  // rank rows by the upper bound of their true minimum, refine the highest,
+  // then every row the first refinement leaves uncertain
+  PROHD_TRY(launch_keys(L.rowA, L.xa.n, dnA, capA, DP, fmt, L.maxabs, s));
+  PROHD_TRY(launch_keys(L.rowB, L.xb.n, dnB, capB, DP, fmt, L.maxabs, s));
+  PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
+  PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, ysB.p, ydnB, ycapB, L.w[0].best, s));
+  PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, ysA.p, ydnA, ycapA, L.w[1].best, s));
+  UncPair U{};
+  for (int d = 0; d < 2; ++d)
+    U.d[d] = UncJob{mins2[d], L.w[d].flags, dns2[d], caps2[d], L.w[d].best, L.w[d].count, L.status,
+                    L.w[d].cand2, L.w[d].count2, L.w[d].best2};
+  PROHD_LAUNCH("hd_uncertain", uncertain_rows, dim3(2), dim3(kUncT), 0, s, U);
+  PROHD_TRY(launch_refine_dyn<DP>(L.xa.p, L.w[0].cand2, L.w[0].count2, ysB.p, ydnB, ycapB,
+                                  L.w[0].best2, s));
+  PROHD_TRY(launch_refine_dyn<DP>(L.xb.p, L.w[1].cand2, L.w[1].count2, ysA.p, ydnA, ycapA,
+                                  L.w[1].best2, s));
+  const DirIn ab{L.w[0].best, L.w[0].cand, L.w[0].count, L.w[0].best2, L.w[0].cand2, L.w[0].count2,
+                 idxA, full ? nullptr : idxB, A, B};
+  const DirIn ba{L.w[1].best, L.w[1].cand, L.w[1].count, L.w[1].best2, L.w[1].cand2, L.w[1].count2,
+                 idxB, full ? nullptr : idxA, B, A};
+  PROHD_LAUNCH("hd_finalize", finalize, dim3(1), dim3(256), 0, s, ab, ba, D, dnA, capA, dnB, capB,
+               L.status, out);
   return PROHD_OK;
 }
 
@@ -1492,6 +1820,30 @@ prohd_status batch_refine(int DP, const RefineJob* jobs, const BItem* items, int
   return by_dp_batch(DP, [&](auto dp) {
     PROHD_LAUNCH("batch_refine", refine_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0, s, jobs,
                  items, nitems);
+    return PROHD_OK;
+  });
+}
+
+prohd_status batch_keys(int DP, const KeyJob* jobs, const BItem* items, int nitems, int grid,
+                        hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  PROHD_LAUNCH("batch_keys", keys_batch, dim3(grid), dim3(256), 0, s, jobs, DP, items, nitems);
+  return PROHD_OK;
+}
+
+prohd_status batch_uncertain(const UncJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PROHD_OK;
+  const int grid = std::min(njobs, 8 * cu_count());
+  PROHD_LAUNCH("batch_uncertain", uncertain_batch, dim3(grid), dim3(kUncBatchT), 0, s, jobs, njobs);
+  return PROHD_OK;
+}
+
+prohd_status batch_refine_dyn(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
+                              hipStream_t s) {
+  if (nitems <= 0) return PROHD_OK;
+  return by_dp_batch(DP, [&](auto dp) {
+    PROHD_LAUNCH("batch_refine2", refine_dyn_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0, s,
+                 jobs, items, nitems);
     return PROHD_OK;
   });
 }
