@@ -383,6 +383,8 @@ def main():
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--batched-pairs", type=int, default=4096)
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full results (empty: stderr only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (HBM-counter calibration)")
     args = ap.parse_args()
@@ -551,7 +553,7 @@ def main():
     del cws
     log(f"certificate [{cert['lb']:.6f}, {cert['ub']:.6f}] in {cert['ms']:.3f} ms")
 
-    def time_prohd(prec, kA_, kB_, reps):
+    def time_prohd(prec, kA_, kB_, reps, full=False):
         capA_ = int(min(nA, 2 * sum(min(k, nA) for k in kA_)))
         capB_ = int(min(nB, 2 * sum(min(k, nB) for k in kB_)))
         o = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
@@ -559,7 +561,8 @@ def main():
         def run():
             _, pA, pB, _, _ = ph.prohd_project(dA, dB, m, ws=ws, evals=False)
             iA_, cA_, iB_, cB_ = ph.prohd_select(pA, pB, kA_, kB_, capA=capA_, capB=capB_, ws=ws)
-            ph.prohd_hd(dA, dB, iA_, cA_, iB_, cB_, capA=capA_, capB=capB_, ws=ws, out=o, prec=prec)
+            ph.prohd_hd(dA, dB, iA_, cA_, iB_, cB_, capA=capA_, capB=capB_, ws=ws, out=o, prec=prec,
+                        inner_full=full)
         run()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -610,21 +613,29 @@ def main():
             exact[prec]["rel_err_vs_fp32_exact"] = abs(exact[prec]["H"] - Hx) / Hx
         exact["prohd_fp32_rel_err_vs_exact"] = abs(res["H"] - Hx) / Hx
         exact["certificate_contains_exact"] = bool(cert["lb"] <= Hx <= cert["ub"])
-        # precision form: ProHD with low-precision tiles, at the same budget and
-        # at a 4x larger alpha (about the same time as the float32 path)
+        # precision form: ProHD with low-precision tiles against the float32
+        # path, in candidate mode (Alg. 3's value) and in inner-full mode
+        # (inner minimum over the whole other set, where the tiles carry the
+        # n x |I| search), at the paper's alpha and at 4x alpha
         forms = []
-        for prec, mult in (("bf16", 1), ("fp8", 1), ("bf16", 4), ("fp8", 4)):
-            if alpha is None:
-                kA_, kB_ = [k * mult for k in kA], [k * mult for k in kB]
-            else:
-                a_ = alpha * mult
-                kA_ = [ph.k_rule(a_, nA)] + [ph.k_rule(a_ / m, nA)] * m
-                kB_ = [ph.k_rule(a_, nB)] + [ph.k_rule(a_ / m, nB)] * m
-            ms_, r_ = time_prohd(prec, kA_, kB_, 3)
-            forms.append({"prec": prec, "alpha": None if alpha is None else alpha * mult, "ms": ms_,
-                          "H": r_["H"], "nA_sel": r_["nA_sel"], "nB_sel": r_["nB_sel"],
-                          "rel_err_vs_exact": abs(r_["H"] - Hx) / Hx})
-            log(f"prohd[{prec}, alpha x{mult}] {ms_:.2f} ms H={r_['H']:.6f} err={forms[-1]['rel_err_vs_exact']:.2e}")
+        for full in (False, True):
+            for mult in (1, 4):
+                for prec in ("fp32", "bf16", "fp8"):
+                    if not full and mult == 1 and prec == "fp32":
+                        continue   # the headline step itself
+                    if alpha is None:
+                        kA_, kB_ = [k * mult for k in kA], [k * mult for k in kB]
+                    else:
+                        a_ = alpha * mult
+                        kA_ = [ph.k_rule(a_, nA)] + [ph.k_rule(a_ / m, nA)] * m
+                        kB_ = [ph.k_rule(a_, nB)] + [ph.k_rule(a_ / m, nB)] * m
+                    ms_, r_ = time_prohd(prec, kA_, kB_, 3, full=full)
+                    forms.append({"prec": prec, "mode": "inner_full" if full else "candidates",
+                                  "alpha": None if alpha is None else alpha * mult, "ms": ms_,
+                                  "H": r_["H"], "nA_sel": r_["nA_sel"], "nB_sel": r_["nB_sel"],
+                                  "refined": r_["refined"], "rel_err_vs_exact": abs(r_["H"] - Hx) / Hx})
+                    log(f"prohd[{prec}, {forms[-1]['mode']}, alpha x{mult}] {ms_:.2f} ms "
+                        f"H={r_['H']:.6f} err={forms[-1]['rel_err_vs_exact']:.2e} refined={r_['refined']}")
         exact["precision_form"] = forms
 
     # sampling baselines at ProHD's budget and an alpha sweep on random clouds
@@ -671,6 +682,59 @@ def main():
         cpu = cpu_baseline(A, B, m, alpha if alpha is not None else 0.01, min(args.cpu_sample, nA))
         log(f"cpu baseline {time.perf_counter() - t0:.1f}s: {cpu['value']:.4g} pairs/s")
 
+    # stored FP64 oracle values for this workload and seed (written by
+    # tests/golden/make_golden.py from oracle/ alone), when present
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_seed{args.seed}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            golden = json.load(fh)
+    vs_oracle = {}
+    if golden is not None:
+        Ho = golden["prohd"]["H"]
+        vs_oracle["prohd_H_oracle"] = Ho
+        vs_oracle["prohd_rel_err"] = abs(res["H"] - Ho) / Ho
+        if "exact" in golden and exact is not None:
+            Hx_o = golden["exact"]["H"]
+            vs_oracle["exact_H_oracle"] = Hx_o
+            for prec in ("fp32", "bf16", "fp8"):
+                vs_oracle[f"exact_{prec}_rel_err"] = abs(exact[prec]["H"] - Hx_o) / Hx_o
+        if cpu is not None and "seconds_prohd" in golden:
+            cpu["full_pair_recorded_s"] = golden["seconds_prohd"]
+
+    detail = {
+        "result": {"H": res["H"], "hAB": res["hAB"], "hBA": res["hBA"], "nA_sel": res["nA_sel"],
+                   "nB_sel": res["nB_sel"], "status": res["status"], "refined": res.get("refined")},
+        "vs_oracle": vs_oracle,
+        "check": check,
+        "certificate": cert,
+        "roofline": roof,
+        "path_roofline": path_roof,
+        "attainable": peaks,
+        "exact": exact,
+        "kernels": kernels,
+        "baselines": base,
+        "learned": learned,
+        "batched": batched,
+        "cpu_baseline": cpu,
+    }
+    dpath = args.detail_out
+    if dpath:
+        os.makedirs(os.path.dirname(os.path.abspath(dpath)), exist_ok=True)
+        with open(dpath, "w") as fh:
+            json.dump(detail, fh, indent=1)
+        log(f"details written to {dpath}")
+    log("detail " + json.dumps(detail))
+
+    # the one stdout line: headline, roofline of the dominant kernel, CPU
+    # oracle baseline, errors against the FP64 oracle and short summaries of
+    # the forms (everything else is in the detail file / stderr line)
+    def r4(x):
+        return None if x is None else float(f"{x:.4g}")
+
+    head_roof = {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}
+    head_roof["avg_ms"] = roof["per_launch"]["avg_ms"]
+    head_roof["algorithmic_flops"] = roof["per_launch"]["algorithmic_flops"]
     line = {
         "metric": METRIC,
         "value": 1e3 / ms_step,
@@ -685,21 +749,27 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "nA": nA, "nB": nB, "D": D, "alpha": alpha, "m": m,
-                   "k_per_end_A": kA[:2], "k_per_end_B": kB[:2], "seed": args.seed,
-                   "law": "128-cluster Gaussian mixture, centres N(0,4I), sigma 1, B centres + N(0,0.25I), 0.1% t3 outliers"},
-        "result": {"H": res["H"], "hAB": res["hAB"], "hBA": res["hBA"], "nA_sel": res["nA_sel"],
-                   "nB_sel": res["nB_sel"], "status": res["status"]},
-        "check": check,
-        "certificate": cert,
-        "roofline": roof,
-        "path_roofline": path_roof,
-        "attainable": peaks,
-        "exact": exact,
-        "kernels": kernels,
-        "baselines": base,
-        "learned": learned,
-        "batched": batched,
-        "cpu_baseline": cpu,
+                   "seed": args.seed},
+        "result": {"H": res["H"], "nA_sel": res["nA_sel"], "nB_sel": res["nB_sel"],
+                   "status": res["status"], "refined": res.get("refined")},
+        "rel_err_vs_oracle": {k: r4(v) for k, v in vs_oracle.items() if k.endswith("rel_err")},
+        "roofline": head_roof,
+        "cpu_baseline": None if cpu is None else {
+            k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "full_pair_recorded_s")
+            if k in cpu},
+        "exact": None if exact is None else {
+            p_: {"ms": r4(exact[p_]["ms"]), "pairs_per_s": r4(exact[p_]["pairs_per_s"]),
+                 "tile_frac": r4(exact[p_]["tile_frac"])} for p_ in ("fp32", "bf16", "fp8")},
+        "forms": {
+            "precision": None if exact is None else [
+                [f_["prec"], f_["mode"], f_["alpha"], r4(f_["ms"]), r4(f_["rel_err_vs_exact"])]
+                for f_ in exact["precision_form"]],
+            "batched_prohd_pairs_per_s": None if batched is None else r4(batched["prohd"]["pairs_per_s"]),
+            "batched_exact_pairs_per_s": None if batched is None else r4(batched["exact"]["pairs_per_s"]),
+            "learned_mean_rel_err": None if learned is None else {
+                m_: {k: r4(v) for k, v in learned["mean_rel_err"][m_].items()} for m_ in ("candidates", "full")},
+        },
+        "detail": dpath or "stderr",
     }
     print(json.dumps(line), flush=True)
     return 0
