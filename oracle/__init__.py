@@ -9,7 +9,9 @@ generators in ``synth/`` (which hold none of the method's arithmetic).
 
 Contents
 --------
-hausdorff   exact Hausdorff distance (paper Eq. (1), Sec. II-A), the 1-D
+hausdorff   exact Hausdorff distance (paper Eq. (1), Sec. II-A; per direction,
+            or both directions from one pass over the distance matrix with
+            the plain C loops of nnpass.c), the 1-D
             projected distance ``h_u``/``H_u`` (Sec. II-E.1) and the
             off-axis spread ``delta(u)`` (Eq. (2)).
 prohd       the ProHD method: centroid axis (Alg. 1), principal directions
@@ -22,8 +24,9 @@ Every function is FP64 on FP32 inputs upcast exactly.  Readings taken where
 the paper is silent or inconsistent are listed in the module docstrings.
 
 Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
-(brute force, closed forms, invariants, library reductions); none is
-"parity unpinned" except where a module docstring says so.
+(brute force, closed forms, invariants, library reductions, hand examples);
+``tests/test_oracle_mutations.py`` plants slips in a copy of this package and
+checks that the pins catch each one.  None is "parity unpinned".
 """
 
 from .hausdorff import (  # noqa: F401

@@ -345,3 +345,41 @@ def test_adamw_first_step():
     g = np.array([0.5, -4.0])
     p2, m, v = mlp.adamw(p, g, np.zeros(2), np.zeros(2), t=1, lr=0.1, wd=0.01, eps=0.0)
     assert np.allclose(p2, p - 0.1 * (np.sign(g) + 0.01 * p), rtol=1e-14)
+
+
+def test_certificate_hand_example():
+    # A = {(0,0), (4,0)}, B = {(0,3), (4,0)}, directions e1 and e2, spread
+    # measured from the origin line (Eq. (2)).
+    #   e1: projections A {0, 4}, B {0, 4}  -> H_e1 = 0;  delta(e1) = 3 (point (0,3))
+    #   e2: projections A {0, 0}, B {3, 0}  -> H_e2 = 3;  delta(e2) = 4 (point (4,0))
+    # Sec. II-E: lb = max_u H_u = 3, ub = min_u (H_u + 2 delta(u)) = min(6, 11) = 6,
+    # around H = 3 (each point's nearest neighbour in the other set is at 0 or 3).
+    A = [[0.0, 0.0], [4.0, 0.0]]
+    B = [[0.0, 3.0], [4.0, 0.0]]
+    c = oracle.certificate(A, B, [[1.0, 0.0], [0.0, 1.0]])
+    assert list(c["hu"]) == [0.0, 3.0] and list(c["delta"]) == [3.0, 4.0]
+    assert (c["lb"], c["ub"]) == (3.0, 6.0)
+    assert oracle.exact_hd(A, B)["H"] == 3.0
+
+
+@pytest.mark.parametrize("nA,nB,D,br,bc", [(300, 250, 5, 64, 37), (97, 130, 3, 1000, 1000),
+                                           (40, 700, 17, 7, 128)])
+def test_one_pass_matches_per_direction_search(nA, nB, D, br, bc):
+    """Both directions' minima from one pass (nn_both) equal the brute-force
+    nearest neighbours, blocks of any shape, ties to the smallest index."""
+    A = _rand(20 + D, nA, D)
+    B = _rand(21 + D, nB, D, shift=0.2)
+    B[5] = A[3]
+    B[9] = A[3]              # tie in A's row 3, and between B rows 5 and 9
+    A[11] = A[12]            # equal A rows: ties for the column minima
+    dA, jA, dB, iB = oracle.nn_both(A, B, block_rows=br, block_cols=bc)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    for i in range(nA):
+        d = np.sqrt(((A64[i] - B64) ** 2).sum(1))
+        assert jA[i] == int(np.argmin(d)) and dA[i] == pytest.approx(d.min(), rel=1e-13, abs=1e-300)
+    for j in range(nB):
+        d = np.sqrt(((B64[j] - A64) ** 2).sum(1))
+        assert iB[j] == int(np.argmin(d)) and dB[j] == pytest.approx(d.min(), rel=1e-13, abs=1e-300)
+    r1, r2 = oracle.exact_hd(A, B), oracle.exact_hd(A, B, one_pass=True)
+    for k in ("H", "hAB", "hBA", "ab_a", "ab_b", "ba_b", "ba_a"):
+        assert r1[k] == r2[k]
