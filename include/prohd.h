@@ -209,6 +209,40 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * exact_hd_noalloc -- exact_hd without a workspace argument and without any
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Computes what exact_hd computes, with the same kernels, into `out` (and
+ * nn2A / nn2B when non-null).  Its scratch is a file-scope device array of
+ * PROHD_NOALLOC_SCRATCH_BYTES (64 MiB) in the library, one per GPU, held
+ * until the process ends; the sets must fit in it (the same bytes as
+ * exact_hd's workspace: about (nA + nB) (4 DP + 42) bytes in float32, with
+ * DP = D rounded up to a power of two >= 16, plus 2 DP per row for bfloat16
+ * or 1 DP for float8; e.g. nA + nB up to about 60 000 rows at D = 256,
+ * 380 000 at D = 32), otherwise PROHD_EWORKSPACE before any launch.  The
+ * first call on a device looks up that device's copy of the array; the
+ * call then makes no allocation of any kind (no hipMalloc, no library
+ * allocation) and every launch is a kernel (no memset), so it can be
+ * captured into a graph.  Kernel timing (prohd_profile_enable) must be off.
+ *
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (each call initialises what it needs): calls that overlap
+ * in time on one GPU -- on different streams, or from different threads --
+ * race on it and give undefined results.  Serialise them.
+ *
+ *   flags  PROHD_PREC_BF16 or PROHD_PREC_FP8 (or 0); PROHD_SYNC is not
+ *          accepted (the call never blocks: read out->status after the
+ *          stream has completed)
+ * Errors: EINVAL, EUNSUPPORTED, EWORKSPACE (sets too large for the
+ * scratch), EDEVICE.
+ */
+#define PROHD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+prohd_status exact_hd_noalloc(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                              uint32_t flags, prohd_result* out, float* nn2A, float* nn2B,
+                              void* stream);
+
+/*
  * Learned candidate proposal (an extension of the candidate selection of
  * Alg. 1 / Alg. 2, not in the paper).  A scorer MLP 2D -> 256 -> 128 -> 1
  * with GELU activations reads the per-point features f = [x, x - c_other]

@@ -16,6 +16,8 @@ from ._lib import (  # noqa: F401
     prohd_select,
     prohd_hd,
     exact_hd,
+    exact_hd_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     prohd,
     decode_result,
     RESULT_BYTES,

@@ -71,6 +71,8 @@ def lib() -> C.CDLL:
     L.prohd_hd.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, vp, i64, i64, u32, vp, vp, sz, vp]
     L.exact_hd.restype = C.c_int
     L.exact_hd.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp, sz, vp]
+    L.exact_hd_noalloc.restype = C.c_int
+    L.exact_hd_noalloc.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp]
     L.prohd_mlp_param_count.restype = sz
     L.prohd_mlp_param_count.argtypes = [i32]
     L.prohd_mlp_workspace_size.restype = sz
@@ -284,6 +286,27 @@ def exact_hd(A, B, sync=False, ws=None, out=None, nn2=False, prec="fp32"):
     _check(lib().exact_hd(A.data_ptr(), nA, B.data_ptr(), nB, D, (SYNC if sync else 0) | PREC[prec],
                           out.data_ptr(), _ptr(nnA), _ptr(nnB), buf.data_ptr(), nbytes,
                           _stream()))
+    return (out, nnA, nnB) if nn2 else out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def exact_hd_noalloc(A, B, out=None, nn2=False, prec="fp32"):
+    """exact_hd through the no-allocation entry point (library-held scratch
+    of NOALLOC_SCRATCH_BYTES per GPU; calls on one GPU must not overlap).
+    Returns the device result buffer (and the nn2 arrays with nn2=True)."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[0]
+    if out is None:
+        out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    nnA = torch.empty(nA, dtype=torch.float32, device=A.device) if nn2 else None
+    nnB = torch.empty(nB, dtype=torch.float32, device=A.device) if nn2 else None
+    _check(lib().exact_hd_noalloc(A.data_ptr(), nA, B.data_ptr(), nB, D, PREC[prec],
+                                  out.data_ptr(), _ptr(nnA), _ptr(nnB), _stream()))
     return (out, nnA, nnB) if nn2 else out
 
 

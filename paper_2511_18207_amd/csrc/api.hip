@@ -122,6 +122,33 @@ prohd_status finish(prohd_status st, uint32_t flags, hipStream_t s, const int32_
   return PROHD_OK;
 }
 
+// Scratch memory of exact_hd_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[PROHD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+prohd_status scratch_address(void** p) {
+  int dev = -1;
+  PROHD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PROHD_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || q == nullptr)
+      return fail(PROHD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = q;
+  }
+  *p = g_scratch_ptr[dev];
+  return PROHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -250,6 +277,28 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
   hipStream_t s = (hipStream_t)stream;
   st = hd_exact(A, nA, B, nB, D, flags, out, nn2A, nn2B, ws, ws_bytes, s);
   return finish(st, flags, s, out ? &out->status : nullptr);
+}
+
+prohd_status exact_hd_noalloc(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                              uint32_t flags, prohd_result* out, float* nn2A, float* nn2B,
+                              void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (flags & ~(uint32_t)(PROHD_PREC_BF16 | PROHD_PREC_FP8))
+    return fail(PROHD_EINVAL, "exact_hd_noalloc: only PROHD_PREC_BF16 / PROHD_PREC_FP8 are accepted");
+  if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
+    return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");
+  if (bad_ptr(out)) return fail(PROHD_EINVAL, "out must be non-null");
+  const size_t need = exact_ws_bytes(nA, nB, D, flags);
+  if (need > PROHD_NOALLOC_SCRATCH_BYTES)
+    return fail(PROHD_EWORKSPACE, "exact_hd_noalloc: the sets need " + std::to_string(need) +
+                                      " bytes of scratch, above PROHD_NOALLOC_SCRATCH_BYTES (" +
+                                      std::to_string((size_t)PROHD_NOALLOC_SCRATCH_BYTES) + ")");
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st) return st;
+  return hd_exact(A, nA, B, nB, D, flags, out, nn2A, nn2B, ws, PROHD_NOALLOC_SCRATCH_BYTES,
+                  (hipStream_t)stream);
 }
 
 size_t prohd_mlp_param_count(int32_t D) {
