@@ -415,8 +415,8 @@ def main():
         alpha = None
     else:
         alpha = params["alpha"]
-        kA = [ph.k_rule(alpha, nA)] + [ph.k_rule(alpha / m, nA)] * m
-        kB = [ph.k_rule(alpha, nB)] + [ph.k_rule(alpha / m, nB)] * m
+        kA = ph.alpha_k(alpha, nA, m)
+        kB = ph.alpha_k(alpha, nB, m)
     dA = torch.from_numpy(A).to(dev)
     dB = torch.from_numpy(B).to(dev)
     if args.copy_calibration:
@@ -627,8 +627,8 @@ def main():
                         kA_, kB_ = [k * mult for k in kA], [k * mult for k in kB]
                     else:
                         a_ = alpha * mult
-                        kA_ = [ph.k_rule(a_, nA)] + [ph.k_rule(a_ / m, nA)] * m
-                        kB_ = [ph.k_rule(a_, nB)] + [ph.k_rule(a_ / m, nB)] * m
+                        kA_ = ph.alpha_k(a_, nA, m)
+                        kB_ = ph.alpha_k(a_, nB, m)
                     ms_, r_ = time_prohd(prec, kA_, kB_, 3, full=full)
                     forms.append({"prec": prec, "mode": "inner_full" if full else "candidates",
                                   "alpha": None if alpha is None else alpha * mult, "ms": ms_,

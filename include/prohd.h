@@ -88,7 +88,9 @@ typedef struct {
   int64_t nA_sel;  /* rows of A taken part (nA for exact_hd)                 */
   int64_t nB_sel;  /* rows of B taken part (nB for exact_hd)                 */
   int32_t status;  /* prohd_status of the device-side work                   */
-  int32_t refined; /* rows re-measured per direction by the refinement pass  */
+  int32_t refined; /* rows re-measured in float64, the larger of the two
+                      directions (first pass: up to 256; more when the search
+                      error bound leaves rows uncertain)                    */
 } prohd_result;
 
 /*
@@ -99,6 +101,27 @@ typedef struct {
  */
 size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs,
                             int64_t capA, int64_t capB);
+
+/*
+ * Alpha mode of Alg. 3 (host functions, no device work).
+ *
+ * prohd_default_m -- m = floor(sqrt(D)), the number of principal components
+ * Alg. 3 uses; 0 when D is outside [1, PROHD_MAX_DIM].
+ *
+ * prohd_alpha_k -- the per-direction counts for prohd_select in alpha mode,
+ * for a set of n rows and m components:
+ *   k[0]      = max(1, floor(alpha n))        per end on the centroid axis
+ *               (Alg. 1, its k rule)
+ *   k[1..m]   = max(1, floor((alpha / m) n))  per end on each component
+ *               (Alg. 2 called by Alg. 3 with alpha' = alpha / m)
+ * each clipped to n; the floor is taken of alpha n + 1e-9, so that a decimal
+ * alpha does not lose an integer to binary rounding.
+ *   k    HOST int32 array of m + 1 entries, output
+ * Errors: EINVAL (alpha not positive and finite, n outside [1, 2^31),
+ * m outside [1, PROHD_MAX_DIRS - 1], k null).
+ */
+int32_t prohd_default_m(int32_t D);
+prohd_status prohd_alpha_k(double alpha, int64_t n, int32_t m, int32_t* k);
 
 /*
  * prohd_project -- directions and projections.
@@ -170,14 +193,22 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
  * With PROHD_INNER_FULL: max{ h(A_sel, B), h(B_sel, A) } (inner minimum
  * over the whole other set), which never exceeds H(A,B).
  *
- * Distances are searched with float32 matrix-core tiles of
- * |a|^2 + |b|^2 - 2 a.b on rows shifted by a common point; the rows with
- * the largest approximate minima (up to 256 per direction) are re-measured
- * against every inner row by float32 direct differences, and the final
- * witness pair in float64.  Range: the search and re-measurement form
- * float32 squared distances of the shifted rows, so these must stay below
- * float32's maximum (coordinates spread by up to about 1e18); wider sets
- * saturate the search and the witness pair is then not guaranteed.
+ * Distances are searched with float32 (or, with PROHD_PREC_BF16 /
+ * PROHD_PREC_FP8, bfloat16 / e4m3) matrix-core tiles of |a|^2 + |b|^2 - 2 a.b
+ * on rows shifted by a common point.  Each outer row gets an upper bound of
+ * its true minimum from the search's worst-case rounding and quantisation
+ * error; the 256 rows with the largest bounds, and then every further row
+ * whose bound exceeds the largest re-measured minimum, are re-measured
+ * against every inner row with the float64 expansion on the matrix cores
+ * (the float32 rows converted exactly), and the final witness pair is
+ * measured in float64 from the original rows.  So no row whose true minimum
+ * could exceed the returned value is left out, for any data (on data whose
+ * nearest-neighbour distances the expansion cannot resolve, such as a set
+ * against a slightly moved copy of itself, that may be every row).  Range:
+ * the search forms float32 squared distances of the shifted rows, so these
+ * must stay below float32's maximum (coordinates spread by up to about
+ * 1e18); wider sets saturate the search and the witness pair is then not
+ * guaranteed.
  *
  *   A, B            device float32 point sets (nA x D, nB x D)
  *   idxA, nselA     device: selected rows of A (ascending int32) and their

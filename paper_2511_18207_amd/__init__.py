@@ -22,6 +22,8 @@ from ._lib import (  # noqa: F401
     decode_result,
     RESULT_BYTES,
     k_rule,
+    alpha_k,
+    default_m,
     mlp_param_count,
     mlp_workspace_size,
     mlp_init,

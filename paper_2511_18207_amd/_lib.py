@@ -63,6 +63,10 @@ def lib() -> C.CDLL:
     i64, i32, u32, vp, sz = C.c_int64, C.c_int32, C.c_uint32, C.c_void_p, C.c_size_t
     L.prohd_workspace_size.restype = sz
     L.prohd_workspace_size.argtypes = [i64, i64, i32, i32, i64, i64]
+    L.prohd_default_m.restype = i32
+    L.prohd_default_m.argtypes = [i32]
+    L.prohd_alpha_k.restype = C.c_int
+    L.prohd_alpha_k.argtypes = [C.c_double, i64, i32, vp]
     L.prohd_project.restype = C.c_int
     L.prohd_project.argtypes = [vp, i64, vp, i64, i32, i32, u32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.prohd_select.restype = C.c_int
@@ -310,9 +314,25 @@ def exact_hd_noalloc(A, B, out=None, nn2=False, prec="fp32"):
     return (out, nnA, nnB) if nn2 else out
 
 
+def default_m(D: int) -> int:
+    """m = floor(sqrt(D)) (prohd_default_m)."""
+    m = int(lib().prohd_default_m(int(D)))
+    if m < 1:
+        raise ProhdError(1, f"D={D} outside [1, 256]")
+    return m
+
+
+def alpha_k(alpha: float, n: int, m: int) -> list:
+    """Per-direction counts of the alpha mode (prohd_alpha_k): k on the
+    centroid axis, then k for each of the m principal components."""
+    k = np.zeros(m + 1, dtype=np.int32)
+    _check(lib().prohd_alpha_k(float(alpha), int(n), int(m), k.ctypes.data))
+    return [int(x) for x in k]
+
+
 def k_rule(alpha: float, n: int) -> int:
-    """k = max(1, floor(alpha * n)) per end (paper Alg. 1 / Alg. 2), <= n."""
-    return min(n, max(1, int(math.floor(alpha * n + 1e-9))))
+    """k = max(1, floor(alpha * n)) per end (Alg. 1), <= n (prohd_alpha_k)."""
+    return alpha_k(alpha, n, 1)[0]
 
 
 def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None, prec="fp32"):
@@ -326,10 +346,10 @@ def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None
     nA, D = A.shape
     nB = B.shape[0]
     if m is None:
-        m = math.isqrt(D) if dirs is None else dirs.shape[0] - 1
+        m = default_m(D) if dirs is None else dirs.shape[0] - 1
     if k is None:
-        kA = [k_rule(alpha, nA)] + [k_rule(alpha / m, nA)] * m
-        kB = [k_rule(alpha, nB)] + [k_rule(alpha / m, nB)] * m
+        kA = alpha_k(alpha, nA, m)
+        kB = alpha_k(alpha, nB, m)
     else:
         ks = [int(k)] * (m + 1) if np.isscalar(k) else [int(x) for x in k]
         kA = [min(max(1, x), nA) for x in ks]

@@ -3,6 +3,8 @@
 
 #include <math.h>
 
+#include <cmath>
+
 #include <mutex>
 #include <string>
 #include <vector>
@@ -166,6 +168,18 @@ size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs, in
   need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true, PROHD_PREC_BF16));
   need = std::max(need, exact_ws_bytes(nA, nB, D, PROHD_PREC_BF16));
   return need;
+}
+
+int32_t prohd_default_m(int32_t D) { return (D < 1 || D > PROHD_MAX_DIM) ? 0 : default_m(D); }
+
+prohd_status prohd_alpha_k(double alpha, int64_t n, int32_t m, int32_t* k) {
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(PROHD_EINVAL, "alpha must be positive and finite");
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(PROHD_EINVAL, "n must be in [1, 2^31)");
+  if (m < 1 || m + 1 > PROHD_MAX_DIRS) return fail(PROHD_EINVAL, "m must be in [1, PROHD_MAX_DIRS - 1]");
+  if (bad_ptr(k)) return fail(PROHD_EINVAL, "k must be a non-null host array of m + 1 entries");
+  k[0] = (int32_t)alpha_k(alpha, n);
+  for (int d = 1; d <= m; ++d) k[d] = (int32_t)alpha_k(alpha / m, n);
+  return PROHD_OK;
 }
 
 prohd_status prohd_project(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,

@@ -74,6 +74,24 @@ inline int pad_dim(int D) {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Alpha mode of Alg. 3 (host): m = floor(sqrt(D)) principal components;
+// per set of n rows, k = max(1, floor(alpha n)) per end on the centroid axis
+// (Alg. 1) and max(1, floor((alpha / m) n)) per end on each component (Alg. 2
+// with alpha' = alpha / m), clipped to n.  The floor is taken of
+// alpha n + 1e-9, so a decimal alpha does not lose an integer to binary
+// rounding (0.29 * 100 = 28.999...).
+inline int32_t default_m(int32_t D) {
+  if (D < 1) return 0;
+  int32_t m = 1;
+  while ((int64_t)(m + 1) * (m + 1) <= D) ++m;
+  return m;
+}
+inline int64_t alpha_k(double alpha, int64_t n) {
+  const double f = alpha * (double)n + 1e-9;
+  const int64_t k = f >= (double)n ? n : (int64_t)f;   // floor of a non-negative value
+  return k < 1 ? 1 : (k > n ? n : k);
+}
+
 // Device status word values (int32), shared by kernels.
 constexpr int32_t ST_OK = PROHD_OK;
 constexpr int32_t ST_NONFINITE = PROHD_ENONFINITE;

@@ -54,10 +54,6 @@ struct Pair {
   std::vector<int32_t> kA, kB;
 };
 
-int64_t k_rule(double alpha, int64_t n) {
-  int64_t k = (int64_t)std::floor(alpha * (double)n + 1e-9);
-  return std::min<int64_t>(n, std::max<int64_t>(1, k));
-}
 
 // per-pair pieces of the workspace
 struct PairWs {
@@ -610,7 +606,7 @@ prohd_status prohd_batch_create(int32_t P, const int64_t* nA, const int64_t* nB,
     q.nB = nB[i];
     q.D = D[i];
     q.DP = pad_dim(D[i]);
-    q.m = (int32_t)std::floor(std::sqrt((double)D[i]) + 1e-9);
+    q.m = default_m(D[i]);
     q.offA = oa;
     q.offB = ob;
     oa += q.nA * q.D;
@@ -620,8 +616,8 @@ prohd_status prohd_batch_create(int32_t P, const int64_t* nA, const int64_t* nB,
     int64_t sA = 0, sB = 0;
     for (int d = 0; d <= q.m; ++d) {
       const double a = d == 0 ? alpha : alpha / q.m;
-      q.kA[d] = (int32_t)k_rule(a, q.nA);
-      q.kB[d] = (int32_t)k_rule(a, q.nB);
+      q.kA[d] = (int32_t)alpha_k(a, q.nA);
+      q.kB[d] = (int32_t)alpha_k(a, q.nB);
       sA += 2 * (int64_t)q.kA[d];
       sB += 2 * (int64_t)q.kB[d];
     }

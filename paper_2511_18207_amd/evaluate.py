@@ -92,7 +92,7 @@ def alpha_sweep(make_pair, dims, alphas, ws=None, reps=3):
         dA = torch.from_numpy(A).cuda()
         dB = torch.from_numpy(B).cuda()
         H = L.decode_result(L.exact_hd(dA, dB, ws=ws))["H"]
-        m = max(1, math.isqrt(D))
+        m = L.default_m(D)
         for a in alphas:
             L.prohd(dA, dB, alpha=a, m=m, ws=ws)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

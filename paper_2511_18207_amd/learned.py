@@ -148,7 +148,7 @@ def train(scorer, pairs, steps, batch=16384, lr=1e-3, lr_final=1e-4, pos_share=0
 
 
 def _alpha_k(alpha, m, n):
-    return [L.k_rule(alpha, n)] + [L.k_rule(alpha / m, n)] * m
+    return L.alpha_k(alpha, n, m)
 
 
 def proposal(A, B, scorer, alpha=0.01, m=None, add_frac=0.1, inner_full=False, ws=None,

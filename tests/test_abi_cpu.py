@@ -158,3 +158,25 @@ def test_profile_api_without_gpu():
     ph.profile_enable(False)
     ph.profile_reset()
     assert ph.profile_read("hd_tile") == (0, 0.0)
+
+
+def test_alpha_mode_helper_matches_the_oracle_k_rule():
+    """prohd_default_m / prohd_alpha_k (host functions of the C ABI) against
+    the oracle's k rule (Alg. 1, Alg. 2 with alpha / m, Alg. 3's m)."""
+    import math
+
+    import oracle
+    for D in range(1, 257):
+        assert ph.default_m(D) == math.isqrt(D)
+    L = ph.lib()
+    assert L.prohd_default_m(0) == 0 and L.prohd_default_m(257) == 0
+    for alpha in (0.01, 0.29, 0.07, 0.001, 0.5, 1.0, 1e-4, 0.3, 2.5):
+        for n in (1, 2, 7, 100, 999, 5000, 65_536, 2_000_000):
+            for m in (1, 2, 3, 5, 16):
+                k = ph.alpha_k(alpha, n, m)
+                assert k == [oracle.k_rule(alpha, n)] + [oracle.k_rule(alpha / m, n)] * m, (alpha, n, m)
+    buf = (C.c_int32 * 64)()
+    for alpha, n, m in ((0.0, 10, 1), (float("nan"), 10, 1), (float("inf"), 10, 1), (0.1, 0, 1),
+                        (0.1, 1 << 31, 1), (0.1, 10, 0), (0.1, 10, 64)):
+        assert L.prohd_alpha_k(alpha, n, m, buf) == 1
+    assert L.prohd_alpha_k(0.1, 10, 2, None) == 1
