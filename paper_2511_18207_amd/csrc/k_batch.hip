@@ -116,6 +116,11 @@ struct prohd_batch {
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // completion of the last run on the caller's stream: a rebuild (new
+  // binding or tuning) rewrites or frees the device tables and the graph,
+  // which a run still in flight on another stream may be reading
+  hipEvent_t done = nullptr;
+  bool pending = false;
 };
 
 namespace {
@@ -206,6 +211,24 @@ struct Tables {
     return add(v.data(), v.size() * sizeof(T));
   }
 };
+
+prohd_status mark_done(prohd_batch* b, hipStream_t s) {
+  if (!b->done && hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    b->done = nullptr;
+    return fail(PROHD_EDEVICE, "batch: cannot create the completion event");
+  }
+  if (hipEventRecord(b->done, s) != hipSuccess) return fail(PROHD_EDEVICE, "batch: cannot record completion");
+  b->pending = true;
+  return PROHD_OK;
+}
+
+prohd_status wait_done(prohd_batch* b) {
+  if (b->pending && b->done) {
+    b->pending = false;
+    if (hipEventSynchronize(b->done) != hipSuccess) return fail(PROHD_EDEVICE, "batch: previous run failed");
+  }
+  return PROHD_OK;
+}
 
 void release_graph(prohd_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
@@ -534,6 +557,8 @@ prohd_status bind(prohd_batch* b, uint32_t mode, const float* A, const float* B,
   if (b->bound && b->mode == mode && b->A == A && b->B == B && b->out == out && b->ws == ws &&
       b->ws_bytes == ws_bytes)
     return PROHD_OK;
+  const prohd_status w = wait_done(b);   // no run in flight reads the tables or the graph
+  if (w) return w;
   release_graph(b);
   b->bound = false;
   b->mode = mode;
@@ -632,6 +657,8 @@ prohd_status prohd_batch_create(int32_t P, const int64_t* nA, const int64_t* nB,
 
 void prohd_batch_destroy(prohd_batch* plan) {
   if (!plan) return;
+  wait_done(plan);
+  if (plan->done) hipEventDestroy(plan->done);
   release_graph(plan);
   if (plan->cs) hipStreamDestroy(plan->cs);
   if (plan->dtab) hipFree(plan->dtab);
@@ -665,6 +692,8 @@ prohd_status prohd_batch_run(prohd_batch* plan, uint32_t mode, const float* A, c
     }
     if (hipGraphLaunch(plan->exec, s) != hipSuccess) return fail(PROHD_EDEVICE, "batch: graph launch failed");
   }
+  if (st) return st;
+  st = mark_done(plan, s);
   if (st) return st;
   if (flags & PROHD_SYNC) {
     if (hipStreamSynchronize(s) != hipSuccess) return fail(PROHD_EDEVICE, "batch: stream error");
@@ -711,6 +740,7 @@ prohd_status prohd_batch_tune(prohd_batch* plan, uint32_t mode, const float* A, 
       if (!st) st = prohd_profile_reset();
       if (!st) st = prohd_profile_enable(1);
       if (!st) st = run_list(plan, s);
+      if (!st) st = mark_done(plan, s);
       int64_t n = 0;
       double ms = 0.0;
       if (!st) st = prohd_profile_read(k.kernel, &n, &ms);

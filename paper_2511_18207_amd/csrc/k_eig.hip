@@ -3,15 +3,22 @@
 //
 //   1. Householder tridiagonalisation  C = Q T Q^T  (Q = H_0 H_1 ... H_{n-3},
 //      H_j = I - tau_j v_j v_j^T); per step one symmetric matrix-vector
-//      product and one rank-2 update, spread over all threads.  The matrix
-//      lives in LDS for n <= 128 and in (L2-resident) global memory for
-//      n = 256; the reflectors go to global memory.
-//   2. All eigenvalues of T by bisection on Sturm counts (one per thread).
+//      product and one rank-2 update, spread over all threads.  With the
+//      wide work-group and n >= 64 the lower triangle is held in registers
+//      (16 x 16 tiles, each lane a 2 x 2 block); otherwise it lives in LDS
+//      (n <= 64) or in L2-resident global memory.  The reflectors go to
+//      global memory.
+//   2. Eigenvalues of T by bisection on Sturm counts; when only the m + 1
+//      largest are needed, multisection with one 16-lane group per
+//      eigenvalue.
 //   3. Eigenvectors of T for the m largest eigenvalues by inverse iteration
-//      with a pivoted tridiagonal LU; eigenvalues closer than 1e-3 of the
-//      spectral radius form a cluster and are solved in turn by one thread
-//      with modified Gram-Schmidt against the earlier members.
-//   4. Back-transformation z = Q y (reflectors staged through LDS), unit
+//      with a pivoted tridiagonal LU, one substitution thread per vector;
+//      eigenvalues closer than 1e-3 of the spectral radius form a cluster
+//      whose members iterate together, orthogonalised after every
+//      substitution against the earlier members of their cluster (modified
+//      Gram-Schmidt in index order, one wave per cluster) and normalised.
+//   4. Back-transformation z = Q y (reflectors staged through LDS, the dot
+//      products of a wave's vectors reduced together per reflector), unit
 //      length, sign fixed so the largest-magnitude entry is positive (first
 //      index on ties).
 // Rows and columns beyond D (padding to n = 16..256) carry -1 on the

@@ -28,7 +28,11 @@ def sample_indices(n, size, kind, seed, device="cuda"):
     """Ascending int32 indices of ``size`` rows out of ``n``.
 
     ``random``: uniformly without replacement (seeded permutation);
-    ``systematic``: every (n / size)-th row from a seeded random start."""
+    ``systematic``: the paper's systematic random sampling (Sec. III
+    baselines) -- a seeded random permutation of the rows, then every
+    (n / size)-th position of it from a seeded random start (the stride that
+    gives exactly ``size`` rows, where the paper's floor(1 / alpha) gives
+    about alpha n)."""
     torch = _torch()
     size = int(min(max(1, size), n))
     if kind == "random":
@@ -37,10 +41,12 @@ def sample_indices(n, size, kind, seed, device="cuda"):
         idx = torch.randperm(int(n), generator=g)[:size]
         idx, _ = torch.sort(idx)
     elif kind == "systematic":
+        g = np.random.default_rng(seed)
+        perm = g.permutation(int(n))
         step = n / size
-        start = np.random.default_rng(seed).uniform(0.0, step)
-        idx = torch.from_numpy(np.floor(start + step * np.arange(size)).astype(np.int64))
-        idx = torch.clamp(idx, 0, n - 1)
+        start = g.uniform(0.0, step)
+        pos = np.clip(np.floor(start + step * np.arange(size)).astype(np.int64), 0, n - 1)
+        idx = torch.from_numpy(np.sort(perm[pos]))
     else:
         raise ValueError(kind)
     return idx.to(device=device, dtype=torch.int32).contiguous()

@@ -26,7 +26,14 @@ def test_samplers_and_subset_hd():
         assert a.size == 137 and b.size == 90
         assert np.all(np.diff(a) > 0) and np.all(np.diff(b) > 0) and a.max() < 3000 and b.max() < 2500
         if kind == "systematic":
-            assert np.ptp(np.diff(a)) <= 1 and np.ptp(np.diff(b)) <= 1   # equal spacing (floor)
+            # the same seeded permutation, read at equally spaced positions
+            for idx, n, size, seed in ((a, 3000, 137, 1), (b, 2500, 90, 2)):
+                g = np.random.default_rng(seed)
+                perm = g.permutation(n)
+                step = n / size
+                pos = np.floor(g.uniform(0.0, step) + step * np.arange(size)).astype(np.int64)
+                assert np.ptp(np.diff(pos)) <= 1
+                assert np.array_equal(np.sort(perm[pos]), idx)
         for full in (False, True):
             got = EV.subset_hd(dA, dB, iA, iB, inner_full=full)
             want = oracle.subset_hd(A, B, a, b, inner="full" if full else "candidates")
