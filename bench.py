@@ -339,14 +339,17 @@ def batched_form(args, dev):
                                     "frac": a / PEAK_FP32_MFMA}
     # sampled parity: a few pairs against the oracle
     rp, rx = res["prohd"].pop("_results"), res["exact"].pop("_results")
-    sample = [int(i) for i in np.argsort(nA.astype(np.int64) * nB)[[0, 1, P // 4, P // 2]]]
+    work = nA.astype(np.int64) * nB * D
+    order = np.argsort(work)
+    # the smallest pairs, two from the middle, and the pair with the most work
+    sample = [int(i) for i in order[[0, 1, P // 4, P // 2, P - 1]]]
     checks = []
     for i in sample:
         a = hA[plan.offA[i]:plan.offA[i + 1]].reshape(int(nA[i]), int(D[i]))
         b = hB[plan.offB[i]:plan.offB[i + 1]].reshape(int(nB[i]), int(D[i]))
         m = int(np.floor(np.sqrt(D[i]) + 1e-9))
         wp = oracle.prohd(a, b, alpha=0.01, m=m)["H"]
-        we = oracle.exact_hd(a, b)["H"]
+        we = oracle.exact_hd(a, b, one_pass=True)["H"]
         checks.append({"pair": i, "nA": int(nA[i]), "nB": int(nB[i]), "D": int(D[i]),
                        "prohd_rel_err": abs(rp[i]["H"] - wp) / wp, "exact_rel_err": abs(rx[i]["H"] - we) / we})
     errs = np.array([abs(p_["H"] - x_["H"]) / x_["H"] for p_, x_ in zip(rp, rx) if x_["H"] > 0])

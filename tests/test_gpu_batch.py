@@ -110,3 +110,39 @@ def test_batch_tuner_writes_table_and_keeps_results(tmp_path):
             assert a["H"] == b["H"]
         plan2.close()
     plan.close()
+
+
+def test_batch_largest_pairs_of_the_bench_batch():
+    """The largest pairs of the 4 096-pair batch bench.py times
+    (synth.batch_sizes(4096, 0): pair 3210 is 63 206 x 63 310 at D = 256,
+    pairs 2948 and 3548 the next by work and by rows), drawn exactly as there
+    (synth.batch_pair), run as one batch with two small pairs of the same
+    batch; ProHD and the exact distance per pair against the oracle."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    nA_all, nB_all, D_all = synth.batch_sizes(4096, 0)
+    pick = [3210, 2948, 3548, 2953, 2439]
+    nA, nB, D = nA_all[pick], nB_all[pick], D_all[pick]
+    banner(f"batch largest pairs {list(zip(nA.tolist(), nB.tolist(), D.tolist()))}")
+    As, Bs = [], []
+    for i in pick:
+        a, b = synth.batch_pair(0, i, nA_all[i], nB_all[i], D_all[i])
+        As.append(a)
+        Bs.append(b)
+    plan = ph.BatchPlan(nA, nB, D, alpha=0.01)
+    dA, dB = plan.pack(As, Bs)
+    try:
+        ex = plan.results(plan.run(dA, dB, mode="exact", sync=True))
+        pr = plan.results(plan.run(dA, dB, mode="prohd", sync=True))
+    finally:
+        plan.close()
+    for j, i in enumerate(pick):
+        ox = oracle.exact_hd(As[j], Bs[j], one_pass=True)
+        op = oracle.prohd(As[j], Bs[j], alpha=0.01, m=int(np.floor(np.sqrt(D[j]) + 1e-9)))
+        print(f"[batch] pair {i} {nA[j]}x{nB[j]} D={D[j]}: exact {ex[j]['H']:.9g} vs {ox['H']:.9g}, "
+              f"prohd {pr[j]['H']:.9g} vs {op['H']:.9g}", flush=True)
+        assert ex[j]["status"] == 0 and pr[j]["status"] == 0
+        assert rel(ex[j]["H"], ox["H"]) <= 1e-5
+        assert rel(ex[j]["hAB"], ox["hAB"]) <= 1e-5 and rel(ex[j]["hBA"], ox["hBA"]) <= 1e-5
+        assert rel(pr[j]["H"], op["H"]) <= 1e-5
+        assert abs(pr[j]["nA_sel"] - op["nA_sel"]) <= 2 and abs(pr[j]["nB_sel"] - op["nB_sel"]) <= 2

@@ -4,8 +4,10 @@ synth/ only).
 
 * mix200k (200 000 x 200 000, D = 128, centroid + 8 PCs, k = 1 000), seeds
   0-2: ProHD value, directed values, candidate-set sizes and exact H;
-* heavy2m (2 000 000 x 2 000 000, D = 256, alpha = 0.01, m = 16), seed 0:
-  ProHD in the launch configuration bench.py times.
+* heavy2m (2 000 000 x 2 000 000, D = 256, alpha = 0.01, m = 16), seeds
+  0-2: ProHD in the launch configuration bench.py times; seed 0 also the
+  exact distance in all three search precisions (once the stored file holds
+  the oracle's exact value).
 
 Directions are compared where the eigengap separates them (float32 rounding
 of a separated eigenvector); the candidate sets may differ only at float32
@@ -67,12 +69,13 @@ def test_mix200k_against_golden(seed):
     assert rel(e["hAB"], g["exact"]["hAB"]) <= 1e-5 and rel(e["hBA"], g["exact"]["hBA"]) <= 1e-5
 
 
-def test_heavy2m_against_golden():
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_heavy2m_against_golden(seed):
     torch, dev = torch_gpu()
     import paper_2511_18207_amd as ph
-    g = _golden("heavy2m", 0)
-    banner("golden heavy2m seed=0 (2M x 2M, D=256)")
-    A, B, params = synth.workload("heavy2m", seed=0)
+    g = _golden("heavy2m", seed)
+    banner(f"golden heavy2m seed={seed} (2M x 2M, D=256)")
+    A, B, params = synth.workload("heavy2m", seed=seed)
     dA, dB = to_dev(torch, A), to_dev(torch, B)
     del A, B
     r = ph.prohd(dA, dB, alpha=params["alpha"], m=params["m"])
@@ -95,3 +98,26 @@ def test_heavy2m_against_golden():
     wantA, wantB = oracle.select(PA, PB, r["kA"], r["kB"])
     assert np.array_equal(IA, wantA)
     assert np.array_equal(r["idxB"][: r["nB_sel"]].cpu().numpy(), wantB)
+
+
+def test_heavy2m_exact_against_golden():
+    """Exact distance of Eq. (1) at 2M x 2M, D = 256 against the oracle's
+    one-pass FP64 value, with float32, bfloat16 and e4m3 search tiles (the
+    reported value is the float64-refined witness pair in every case)."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    g = _golden("heavy2m", 0)
+    if "exact" not in g:
+        pytest.skip("stored heavy2m result has no exact distance yet")
+    A, B, _ = synth.workload("heavy2m", seed=0)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    del A, B
+    w = g["exact"]
+    for prec in ("fp8", "bf16", "fp32"):
+        banner(f"golden heavy2m exact prec={prec}")
+        e = ph.decode_result(ph.exact_hd(dA, dB, prec=prec))
+        print(f"[golden] heavy2m exact {prec}: H {e['H']:.9g} vs {w['H']:.9g}, "
+              f"refined {e['refined']}", flush=True)
+        assert e["status"] == 0
+        assert rel(e["H"], w["H"]) <= 1e-5
+        assert rel(e["hAB"], w["hAB"]) <= 1e-5 and rel(e["hBA"], w["hBA"]) <= 1e-5
