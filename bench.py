@@ -663,6 +663,34 @@ def main():
                                (2, 4, 8, 16, 32, 64, 128), (0.001, 0.005, 0.01, 0.02, 0.05, 0.1), ws=ws)
         base["alpha_sweep_uniform_clouds"] = sweep
         log(f"alpha sweep: {len(sweep)} points")
+        # adaptive alpha (prohd_adaptive) at a 1e-3 budget on the random
+        # clouds and on this workload (e4m3 search tiles there)
+        adapt = []
+        kw = dict(alpha0=0.005, growth=2.0, alpha_max=0.32, tol=1e-3)
+        for D_ in (4, 16, 64):
+            A2, B2 = synth.uniform_clouds(100_000, 100_000, D_, seed=7)
+            a2, b2 = torch.from_numpy(A2).to(dev), torch.from_numpy(B2).to(dev)
+            H2 = ph.decode_result(ph.exact_hd(a2, b2, ws=ws))["H"]
+            t0 = time.perf_counter()
+            r_ = ph.adaptive(a2, b2, ws=ws, **kw)
+            adapt.append({"workload": f"uniform clouds 100k x 100k D={D_}", "H": H2,
+                          "ms": 1e3 * (time.perf_counter() - t0),
+                          "rel_err": abs(r_["H"] - H2) / H2,
+                          **{k: r_[k] for k in ("alpha", "H", "lb", "ub", "steps", "reason",
+                                                "nA_sel", "nB_sel")}})
+            del a2, b2
+        if exact is not None:
+            t0 = time.perf_counter()
+            r_ = ph.adaptive(dA, dB, ws=ws, prec="fp8", **kw)
+            Hx = exact["fp32"]["H"]
+            adapt.append({"workload": f"{args.workload} (e4m3 tiles)", "H_exact": Hx,
+                          "ms": 1e3 * (time.perf_counter() - t0), "rel_err": abs(r_["H"] - Hx) / Hx,
+                          **{k: r_[k] for k in ("alpha", "H", "lb", "ub", "steps", "reason",
+                                                "nA_sel", "nB_sel")}})
+        for a_ in adapt:
+            log(f"adaptive {a_['workload']}: alpha {a_['alpha']} after {a_['steps']} steps "
+                f"(reason {a_['reason']}), err {a_['rel_err']:.2e}, {a_['ms']:.1f} ms")
+        base["adaptive_alpha"] = adapt
 
     learned = None
     if not args.no_learned:
@@ -767,6 +795,9 @@ def main():
             "precision": None if exact is None else [
                 [f_["prec"], f_["mode"], f_["alpha"], r4(f_["ms"]), r4(f_["rel_err_vs_exact"])]
                 for f_ in exact["precision_form"]],
+            "adaptive": None if base is None else [
+                [a_["workload"], a_["alpha"], a_["steps"], a_["reason"], r4(a_["rel_err"]), r4(a_["ms"])]
+                for a_ in base.get("adaptive_alpha", [])],
             "batched_prohd_pairs_per_s": None if batched is None else r4(batched["prohd"]["pairs_per_s"]),
             "batched_exact_pairs_per_s": None if batched is None else r4(batched["exact"]["pairs_per_s"]),
             "learned_mean_rel_err": None if learned is None else {

@@ -407,6 +407,52 @@ prohd_status prohd_certificate(const float* A, int64_t nA, const float* B, int64
                                const float* projB, const prohd_result* lower, prohd_cert* out,
                                void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * prohd_adaptive -- alpha chosen under an error budget (this library's
+ * schedule for the adaptive alpha the paper's Conclusion names as future
+ * work; Sec. III shows the error falling as alpha grows).
+ *
+ * Directions (Alg. 1, Alg. 2, m = floor(sqrt(D))) and projections are
+ * computed once, with the Sec. II-E certificate of those directions
+ * (prohd_certificate: hu_lo <= H_U and ub >= H(A,B)).  Then for
+ * alpha_j = min(alpha0 growth^j, alpha_max), j = 0, 1, ..., the alpha-mode
+ * candidates (prohd_alpha_k, prohd_select) give the inner-full value
+ *   F_j = max{ h(A_sel, B), h(B_sel, A) }   (prohd_hd with PROHD_INNER_FULL),
+ * which never exceeds H(A,B) and cannot decrease as alpha grows (the
+ * candidate sets are nested).  The schedule stops at the first j with
+ *   ub - max(hu_lo, F_j) <= tol max(hu_lo, F_j)   reason 1 (certified gap)
+ *   j >= 1 and F_j - F_{j-1} <= tol F_j          reason 2 (converged)
+ *   alpha_j >= alpha_max                         reason 3
+ * Only reason 1 certifies the relative error; reason 2 is the empirical
+ * rule (no further gain from a growth-fold larger alpha).
+ *
+ *   alpha0, growth, alpha_max   0 < alpha0 <= alpha_max, growth > 1
+ *   tol      relative budget (>= 0)
+ *   flags    PROHD_PREC_BF16 / PROHD_PREC_FP8 for the distance search (or 0)
+ *   out      device prohd_result: the last step's inner-full result
+ *   res      HOST prohd_adaptive_result, output
+ * Workspace: prohd_adaptive_workspace_size(nA, nB, D, alpha_max, flags).
+ * The call blocks: it reads each step's result on the host (the schedule is
+ * decided there).  Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE, and
+ * the device status of the projection / distance (ENONFINITE).
+ */
+typedef struct {
+  double alpha;     /* alpha of the last step                               */
+  double H;         /* its inner-full value F (<= H(A,B))                   */
+  double lb, ub;    /* certified interval: lb = max(hu_lo, F) <= H <= ub    */
+  double change;    /* (F_j - F_{j-1}) / F_j of the last step, -1 at j = 0   */
+  int64_t nA_sel, nB_sel;  /* candidate-set sizes of the last step          */
+  int32_t steps;    /* alphas tried                                         */
+  int32_t reason;   /* 1 certified gap, 2 converged, 3 alpha_max reached    */
+} prohd_adaptive_result;
+
+size_t prohd_adaptive_workspace_size(int64_t nA, int64_t nB, int32_t D, double alpha_max,
+                                     uint32_t flags);
+prohd_status prohd_adaptive(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                            double alpha0, double growth, double alpha_max, double tol,
+                            uint32_t flags, prohd_result* out, prohd_adaptive_result* res,
+                            void* ws, size_t ws_bytes, void* stream);
+
 /* Message of the last non-OK return on this host thread ("" if none). */
 const char* prohd_last_error(void);
 

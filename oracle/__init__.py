@@ -50,4 +50,5 @@ from .prohd import (  # noqa: F401
     select,
     subset_hd,
     prohd,
+    adaptive_alpha,
 )

@@ -52,6 +52,7 @@ __all__ = [
     "select",
     "subset_hd",
     "prohd",
+    "adaptive_alpha",
 ]
 
 
@@ -238,3 +239,64 @@ def prohd(A, B, alpha: float = 0.01, m: int | None = None, k=None,
         "dirs": U, "kA": kA, "kB": kB, "evals": evals,
     })
     return r
+
+
+def adaptive_alpha(A, B, alpha0: float = 0.005, growth: float = 2.0, alpha_max: float = 0.32,
+                   tol: float = 1e-3):
+    """Adaptive alpha under an error budget (a reading: the paper's
+    Conclusion names adaptive alpha schedules for strict error budgets as
+    future work and Sec. III shows the error falling as alpha grows; the
+    schedule below is this implementation's).
+
+    Directions are found once (Alg. 1, Alg. 2; m = floor(sqrt(D))).  For
+    alpha_j = min(alpha0 growth^j, alpha_max), j = 0, 1, ...:
+      F_j  = the inner-full value max{h(A_sel, B), h(B_sel, A)} over the
+             alpha_j candidates -- never above H(A, B);
+      lb_j = max(H_U, F_j) and ub = min_u (H_u + 2 delta(u)) over the same
+             directions, delta measured from the line through the centroid
+             of A u B (Sec. II-E bounds: lb_j <= H <= ub);
+    and the schedule stops at the first j with
+      (ub - lb_j) <= tol lb_j                   reason 1 (certified gap),
+      j >= 1 and F_j - F_{j-1} <= tol F_j       reason 2 (converged),
+      alpha_j >= alpha_max                      reason 3.
+    Returns a dict: alpha, H (= F_j) with witnesses, lb, ub, reason, steps,
+    the per-step values and the candidate-set sizes.
+    """
+    A = _f64(A)
+    B = _f64(B)
+    nA, D = A.shape
+    nB = B.shape[0]
+    m = math.isqrt(D)
+    u0 = centroid_direction(A, B)
+    P, _ = principal_directions(A, B, m)
+    U = np.vstack([u0[None, :], P])
+    projA = U @ A.T
+    projB = U @ B.T
+    from .hausdorff import certificate
+    cert = certificate(A, B, U, c=np.vstack([A, B]).mean(axis=0))
+    hU, ub = float(cert["lb"]), float(cert["ub"])
+    values = []
+    alpha = float(alpha0)
+    j = 0
+    while True:
+        a = min(alpha, alpha_max)
+        kA = [k_rule(a, nA)] + [k_rule(a / m, nA)] * m
+        kB = [k_rule(a, nB)] + [k_rule(a / m, nB)] * m
+        IA, IB = select(projA, projB, kA, kB)
+        r = subset_hd(A, B, IA, IB, inner="full")
+        F = r["H"]
+        values.append(F)
+        lb = max(hU, F)
+        if ub - lb <= tol * lb:
+            reason = 1
+        elif j >= 1 and F - values[-2] <= tol * F:
+            reason = 2
+        elif a >= alpha_max:
+            reason = 3
+        else:
+            alpha *= growth
+            j += 1
+            continue
+        r.update({"alpha": a, "lb": lb, "ub": ub, "reason": reason, "steps": j + 1,
+                  "values": values, "nA_sel": int(IA.size), "nB_sel": int(IB.size), "m": m})
+        return r

@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     exact_hd_noalloc,
     NOALLOC_SCRATCH_BYTES,
     prohd,
+    adaptive,
     decode_result,
     RESULT_BYTES,
     k_rule,

@@ -39,6 +39,12 @@ RESULT_DTYPE = np.dtype([
 ])
 RESULT_BYTES = RESULT_DTYPE.itemsize
 
+# prohd_adaptive_result (host struct)
+ADAPTIVE_DTYPE = np.dtype([
+    ("alpha", "<f8"), ("H", "<f8"), ("lb", "<f8"), ("ub", "<f8"), ("change", "<f8"),
+    ("nA_sel", "<i8"), ("nB_sel", "<i8"), ("steps", "<i4"), ("reason", "<i4"),
+])
+
 
 class ProhdError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -77,6 +83,11 @@ def lib() -> C.CDLL:
     L.exact_hd.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp, sz, vp]
     L.exact_hd_noalloc.restype = C.c_int
     L.exact_hd_noalloc.argtypes = [vp, i64, vp, i64, i32, u32, vp, vp, vp, vp]
+    L.prohd_adaptive_workspace_size.restype = sz
+    L.prohd_adaptive_workspace_size.argtypes = [i64, i64, i32, C.c_double, u32]
+    L.prohd_adaptive.restype = C.c_int
+    L.prohd_adaptive.argtypes = [vp, i64, vp, i64, i32, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, u32, vp, vp, vp, sz, vp]
     L.prohd_mlp_param_count.restype = sz
     L.prohd_mlp_param_count.argtypes = [i32]
     L.prohd_mlp_workspace_size.restype = sz
@@ -362,6 +373,30 @@ def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None
                 "idxA": idxA, "nselA": nA_sel, "idxB": idxB, "nselB": nB_sel,
                 "kA": kA, "kB": kB})
     return res
+
+
+def adaptive(A, B, alpha0=0.005, growth=2.0, alpha_max=0.32, tol=1e-3, prec="fp32", ws=None,
+             out=None):
+    """ProHD with alpha chosen under an error budget (prohd_adaptive; blocks).
+    Returns a dict: the schedule's outcome (alpha, H = inner-full value,
+    lb, ub, change, steps, reason) and the last step's decoded result
+    (witnesses) under "result"."""
+    torch = _torch()
+    A = _f32_2d(A, "A")
+    B = _f32_2d(B, "B")
+    nA, D = A.shape
+    nB = B.shape[0]
+    if out is None:
+        out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    res = np.zeros(1, dtype=ADAPTIVE_DTYPE)
+    need = int(lib().prohd_adaptive_workspace_size(nA, nB, D, float(alpha_max), PREC[prec]))
+    buf, nbytes = _ws(ws, need)
+    _check(lib().prohd_adaptive(A.data_ptr(), nA, B.data_ptr(), nB, D, float(alpha0), float(growth),
+                                float(alpha_max), float(tol), PREC[prec], out.data_ptr(),
+                                res.ctypes.data, buf.data_ptr(), nbytes, _stream()))
+    d = {k: res[0][k].item() for k in ADAPTIVE_DTYPE.names}
+    d["result"] = decode_result(out)
+    return d
 
 
 def mlp_param_count(D: int) -> int:

@@ -315,6 +315,139 @@ prohd_status exact_hd_noalloc(const float* A, int64_t nA, const float* B, int64_
                   (hipStream_t)stream);
 }
 
+// ------------------------------------------------------- adaptive alpha
+// Host-driven schedule over device work: one projection and one certificate,
+// then per alpha one selection and one inner-full distance; the host reads
+// the 80-byte result after each step to decide whether to go on.
+namespace {
+
+struct AdaptiveLayout {
+  float* dirs;
+  float* projA;
+  float* projB;
+  int32_t* pstatus;
+  int32_t* idxA;
+  int32_t* idxB;
+  int64_t* cnt;
+  prohd_cert* cert;
+  void* sub;
+  size_t sub_bytes;
+};
+
+int64_t alpha_cap(double alpha, int64_t n, int32_t m) {
+  int64_t s = 2 * alpha_k(alpha, n);
+  for (int d = 1; d <= m; ++d) s += 2 * alpha_k(alpha / m, n);
+  return std::min(n, s);
+}
+
+AdaptiveLayout adaptive_layout(Arena& ar, int64_t nA, int64_t nB, int32_t D, int32_t m,
+                               double alpha_max, uint32_t flags) {
+  AdaptiveLayout L{};
+  const int32_t nd = m + 1;
+  const int64_t capA = alpha_cap(alpha_max, nA, m), capB = alpha_cap(alpha_max, nB, m);
+  L.dirs = ar.take<float>((size_t)nd * D);
+  L.projA = ar.take<float>((size_t)nd * nA);
+  L.projB = ar.take<float>((size_t)nd * nB);
+  L.pstatus = ar.take<int32_t>(64);
+  L.idxA = ar.take<int32_t>(capA);
+  L.idxB = ar.take<int32_t>(capB);
+  L.cnt = ar.take<int64_t>(2);
+  L.cert = ar.take<prohd_cert>(1);
+  size_t sub = project_ws_bytes(nA, nB, D, nd);
+  sub = std::max(sub, select_ws_bytes(2 * nd, std::max(nA, nB)) + compact_ws_bytes(std::max(nA, nB)) +
+                          (size_t)(nA + nB) + 1024);
+  sub = std::max(sub, hd_ws_bytes(nA, nB, D, capA, capB, true, flags));
+  sub = std::max(sub, cert_ws_bytes(D, nd));
+  L.sub_bytes = sub;
+  L.sub = ar.take<char>(sub);
+  return L;
+}
+
+}  // namespace
+
+size_t prohd_adaptive_workspace_size(int64_t nA, int64_t nB, int32_t D, double alpha_max,
+                                     uint32_t flags) {
+  if (nA < 1 || nB < 1 || D < 1 || D > PROHD_MAX_DIM || !(alpha_max > 0.0) || !std::isfinite(alpha_max))
+    return 0;
+  Arena ar(nullptr);
+  adaptive_layout(ar, nA, nB, D, default_m(D), alpha_max, flags);
+  return ar.used + 256;
+}
+
+prohd_status prohd_adaptive(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                            double alpha0, double growth, double alpha_max, double tol,
+                            uint32_t flags, prohd_result* out, prohd_adaptive_result* res,
+                            void* ws, size_t ws_bytes, void* stream) {
+  prohd_status st = check_sets(A, nA, B, nB, D);
+  if (st) return st;
+  if (flags & ~(uint32_t)(PROHD_PREC_BF16 | PROHD_PREC_FP8)) return fail(PROHD_EINVAL, "unknown flag");
+  if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
+    return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");
+  if (!(alpha0 > 0.0) || !(alpha_max >= alpha0) || !std::isfinite(alpha_max))
+    return fail(PROHD_EINVAL, "need 0 < alpha0 <= alpha_max < inf");
+  if (!(growth > 1.0) || !std::isfinite(growth)) return fail(PROHD_EINVAL, "growth must be > 1");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(PROHD_EINVAL, "tol must be >= 0");
+  if (bad_ptr(out) || bad_ptr(res) || bad_ptr(ws)) return fail(PROHD_EINVAL, "out, res and ws must be non-null");
+  const int32_t m = default_m(D);
+  if (m + 1 > PROHD_MAX_DIRS) return fail(PROHD_EUNSUPPORTED, "m + 1 exceeds PROHD_MAX_DIRS");
+  Arena ar(ws);
+  const AdaptiveLayout L = adaptive_layout(ar, nA, nB, D, m, alpha_max, flags);
+  if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t nd = m + 1;
+  st = project_run(A, nA, B, nB, D, m, false, L.dirs, L.projA, L.projB, nullptr, L.pstatus, L.sub,
+                   L.sub_bytes, s);
+  if (st) return st;
+  st = cert_run(A, nA, B, nB, D, L.dirs, nd, L.projA, L.projB, nullptr, L.cert, L.sub, L.sub_bytes, s);
+  if (st) return st;
+  prohd_cert cert{};
+  int32_t pst = 0;
+  PROHD_HIP(hipMemcpyAsync(&cert, L.cert, sizeof(cert), hipMemcpyDeviceToHost, s));
+  PROHD_HIP(hipMemcpyAsync(&pst, L.pstatus, sizeof(pst), hipMemcpyDeviceToHost, s));
+  PROHD_HIP(hipStreamSynchronize(s));
+  if (pst != PROHD_OK) return fail((prohd_status)pst, "projection reported status " + std::to_string(pst));
+  if (cert.status != PROHD_OK)
+    return fail((prohd_status)cert.status, "certificate reported status " + std::to_string(cert.status));
+  const int64_t capA = alpha_cap(alpha_max, nA, m), capB = alpha_cap(alpha_max, nB, m);
+  std::vector<int32_t> kA(nd), kB(nd);
+  double alpha = alpha0, prev = -1.0;
+  for (int32_t j = 0;; ++j) {
+    const double a = std::min(alpha, alpha_max);
+    st = prohd_alpha_k(a, nA, m, kA.data());
+    if (!st) st = prohd_alpha_k(a, nB, m, kB.data());
+    if (!st)
+      st = prohd_select(L.projA, nA, L.projB, nB, nd, kA.data(), kB.data(), L.idxA, capA, L.cnt,
+                        L.idxB, capB, L.cnt + 1, L.sub, L.sub_bytes, s);
+    if (!st)
+      st = prohd_hd(A, nA, B, nB, D, L.idxA, L.cnt, L.idxB, L.cnt + 1, alpha_cap(a, nA, m),
+                    alpha_cap(a, nB, m), flags | PROHD_INNER_FULL | PROHD_SYNC, out, L.sub,
+                    L.sub_bytes, s);
+    if (st) return st;
+    prohd_result r{};
+    PROHD_HIP(hipMemcpy(&r, out, sizeof(r), hipMemcpyDeviceToHost));
+    const double F = r.H;
+    const double lb = std::max(cert.hu_lo, F);
+    int32_t reason = 0;
+    if (cert.ub - lb <= tol * lb) reason = 1;
+    else if (j >= 1 && F - prev <= tol * F) reason = 2;
+    else if (a >= alpha_max) reason = 3;
+    if (reason) {
+      res->alpha = a;
+      res->H = F;
+      res->lb = lb;
+      res->ub = cert.ub;
+      res->change = j >= 1 && F > 0.0 ? (F - prev) / F : -1.0;
+      res->nA_sel = r.nA_sel;
+      res->nB_sel = r.nB_sel;
+      res->steps = j + 1;
+      res->reason = reason;
+      return PROHD_OK;
+    }
+    prev = F;
+    alpha *= growth;
+  }
+}
+
 size_t prohd_mlp_param_count(int32_t D) {
   if (D < 1 || D > PROHD_MAX_DIM) return 0;
   return mlp_param_count(D);

@@ -180,3 +180,19 @@ def test_alpha_mode_helper_matches_the_oracle_k_rule():
                         (0.1, 1 << 31, 1), (0.1, 10, 0), (0.1, 10, 64)):
         assert L.prohd_alpha_k(alpha, n, m, buf) == 1
     assert L.prohd_alpha_k(0.1, 10, 2, None) == 1
+
+
+def test_adaptive_validation():
+    L = ph.lib()
+    assert L.prohd_adaptive_workspace_size(0, 10, 4, 0.3, 0) == 0
+    assert L.prohd_adaptive_workspace_size(10, 10, 4, 0.0, 0) == 0
+    small = L.prohd_adaptive_workspace_size(1000, 1000, 16, 0.05, 0)
+    assert 0 < small < L.prohd_adaptive_workspace_size(1000, 1000, 16, 0.5, 0)
+    res = (C.c_char * 64)()
+    big = 1 << 30
+    for args, code in (((0.0, 2.0, 0.3, 1e-3, 0), 1), ((0.4, 2.0, 0.3, 1e-3, 0), 1),
+                       ((0.01, 1.0, 0.3, 1e-3, 0), 1), ((0.01, 2.0, 0.3, -1.0, 0), 1),
+                       ((0.01, 2.0, 0.3, 1e-3, 1 << 1), 1), ((0.01, 2.0, 0.3, 1e-3, 12), 1)):
+        assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, *args, FAKE, res, FAKE, big, None) == code
+    assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, 0.01, 2.0, 0.3, 1e-3, 0, FAKE, None, FAKE, big, None) == 1
+    assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, 0.01, 2.0, 0.3, 1e-3, 0, FAKE, res, FAKE, 16, None) == 3

@@ -57,6 +57,12 @@ MUTATIONS = [
      "return min(n, max(1, int(math.ceil(alpha * n))))", "k rule: ceiling for floor"),
     ("prohd.py", "dA, aA = nn_dist(A[IA], B)", "dA, aA = nn_dist(A[IA], B[IB])",
      "inner-full mode: inner minimum over the candidates only"),
+    ("prohd.py", "        if ub - lb <= tol * lb:", "        if ub - lb >= tol * lb:",
+     "adaptive alpha: certified-gap rule reversed"),
+    ("prohd.py", "        elif j >= 1 and F - values[-2] <= tol * F:", "        elif F - values[-1] <= tol * F:",
+     "adaptive alpha: gain measured against the current step"),
+    ("prohd.py", "        r = subset_hd(A, B, IA, IB, inner=\"full\")\n        F = r[\"H\"]",
+     "        r = subset_hd(A, B, IA, IB)\n        F = r[\"H\"]", "adaptive alpha: candidate-mode value"),
     ("mlp.py", "return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))",
      "return 0.5 * z * (1.0 + erf(z / 2.0))", "GELU: wrong argument scale"),
     ("mlp.py", "dz1 = (dz2 @ W2) * _gelu_grad(z1)", "dz1 = (dz2 @ W2) * _gelu_grad(z2 @ W2)",

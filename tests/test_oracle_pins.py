@@ -383,3 +383,50 @@ def test_one_pass_matches_per_direction_search(nA, nB, D, br, bc):
     r1, r2 = oracle.exact_hd(A, B), oracle.exact_hd(A, B, one_pass=True)
     for k in ("H", "hAB", "hBA", "ab_a", "ab_b", "ba_b", "ba_a"):
         assert r1[k] == r2[k]
+
+
+def test_adaptive_alpha_on_a_line_stops_certified():
+    """D = 1: every direction is the line itself, delta(u) = 0, so the
+    Sec. II-E bounds close: H_U = H = ub, and the schedule stops at once
+    with the certified-gap rule and the exact value."""
+    g = np.random.default_rng(31)
+    A = g.uniform(0, 10, size=(500, 1)).astype(np.float32)
+    B = g.uniform(1, 12, size=(400, 1)).astype(np.float32)
+    H = oracle.exact_hd(A, B)["H"]
+    r = oracle.adaptive_alpha(A, B, alpha0=0.01, tol=1e-9)
+    assert (r["reason"], r["steps"]) == (1, 1)
+    assert r["lb"] == pytest.approx(H, rel=1e-12) and r["ub"] == pytest.approx(H, rel=1e-12)
+    assert r["H"] <= H * (1 + 1e-12)
+
+
+def test_adaptive_alpha_schedule_on_random_clouds():
+    """The paper's random clouds (U[0,1]^D against the same plus 0.1): the
+    returned value is the inner-full value at the last alpha, never above H;
+    the values are non-decreasing (nested candidate sets); the stop is the
+    first step whose gain is within tol, else alpha_max; the Sec. II-E
+    upper bound is far from H here, so the certified rule does not fire."""
+    A, B = synth.uniform_clouds(2000, 2000, 4, seed=3)
+    H = oracle.exact_hd(A, B)["H"]
+    tol = 1e-3
+    r = oracle.adaptive_alpha(A, B, alpha0=0.005, growth=2.0, alpha_max=0.32, tol=tol)
+    v = r["values"]
+    assert r["reason"] in (2, 3) and r["steps"] == len(v)
+    assert all(b >= a for a, b in zip(v, v[1:]))
+    assert r["H"] == v[-1] <= H * (1 + 1e-12) and r["ub"] > 1.5 * H
+    assert r["alpha"] == min(0.005 * 2.0 ** (len(v) - 1), 0.32)
+    for j in range(1, len(v) - 1):
+        assert v[j] - v[j - 1] > tol * v[j]
+    if r["reason"] == 2:
+        assert v[-1] - v[-2] <= tol * v[-1]
+    full = oracle.prohd(A, B, alpha=r["alpha"], inner="full")
+    assert full["H"] == r["H"] and full["nA_sel"] == r["nA_sel"]
+
+
+def test_adaptive_alpha_full_selection_is_exact():
+    """alpha0 = alpha_max = 0.5: every row is a candidate (k >= n / 2 per
+    end), so the single step returns H itself (reason 3)."""
+    A, B = synth.uniform_clouds(600, 500, 3, seed=5)
+    H = oracle.exact_hd(A, B)["H"]
+    r = oracle.adaptive_alpha(A, B, alpha0=0.5, alpha_max=0.5, tol=0.0)
+    assert (r["reason"], r["steps"], r["nA_sel"], r["nB_sel"]) == (3, 1, 600, 500)
+    assert r["H"] == H
