@@ -146,6 +146,216 @@ __global__ void features(const float* __restrict__ X, int D, const int32_t* __re
   }
 }
 
+// ------------------------------------------------------- fused scoring
+// Scores only (no gradients): the feature layer folded,
+//   W1 [x; x - c] + b1 = (W1a + W1b) x + (b1 - W1b c),
+// W1a / W1b the halves of W1 acting on x and on x - c (fold_w1, once per
+// call: W1f = bf16(W1a + W1b) padded to KD columns, b1f = b1 - W1b c in
+// float64), then one launch over 64-row tiles: the tile's rows are read once
+// (float32 -> bfloat16 into LDS), layer 1 (64 x KD times KD x 256) and
+// layer 2 (64 x 256 times 256 x 128) run on v_mfma_f32_32x32x16_bf16 with
+// the weights read from L2 (192 KiB at D = 256, shared by every tile), the
+// GELU activations stay in LDS, and the head w3 . h2 + b3 is reduced in
+// registers.  The GELU's erf is the rational approximation 7.1.26 of
+// Abramowitz and Stegun (Handbook of Mathematical Functions, absolute error
+// below 1.5e-7), far below the bfloat16 rounding (2^-9) of the activations.
+
+// GELU(z) = z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2, with
+// erfc(a) = t P(t) e^{-a^2}, t = 1 / (1 + p a) for a >= 0 (7.1.26); the
+// halving and 1 / sqrt 2 are folded into the constants, e^{-a^2} is
+// exp2(-z^2 log2(e) / 2).
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float az = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.f));   // 1 ulp
+  float p = 0.5f * 1.061405429f;
+  p = fmaf(p, t, 0.5f * -1.453152027f);
+  p = fmaf(p, t, 0.5f * 1.421413741f);
+  p = fmaf(p, t, 0.5f * -0.284496736f);
+  p = fmaf(p, t, 0.5f * 0.254829592f);
+  const float e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);   // e^{-z^2 / 2}
+  return fmaf(-az * (p * t), e, fmaxf(z, 0.f));
+}
+
+constexpr int kScoreRows = 64;   // rows per scoring tile
+
+// Weight operands in load order.  Wave w of the scoring kernel reads, for
+// product step s, the 8 values k = 16 s + 8 g .. + 7 of unit 32 b + c in
+// lane (c, g) (b = the wave's 32-unit block); stored at
+// ((b KS + s) 64 + 32 g + c) 8, one load instruction of a wave reads 1 KiB
+// of contiguous memory (8 cache lines instead of 32).  KS = K / 16.
+__device__ __forceinline__ int64_t opnd_index(int j, int k, int KS) {
+  const int b = j >> 5, c = j & 31, s = k >> 4, g = (k >> 3) & 1, e = k & 7;
+  return ((((int64_t)b * KS + s) * 64 + 32 * g + c) << 3) + e;
+}
+
+// W1f (operand order) of bf16(W1[j][k] + W1[j][D + k]) for k < D, 0 up to
+// KD; b1f[j] = b1[j] - sum_k W1[j][D + k] c[k] (float64 sum).  Block j =
+// unit j.
+__global__ __launch_bounds__(256) void fold_w1(const float* __restrict__ W1, const float* __restrict__ b1,
+                                               int D, int KD, const float* __restrict__ c,
+                                               __bf16* __restrict__ W1f, float* __restrict__ b1f) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const float* w = W1 + (int64_t)j * 2 * D;
+  double acc = 0.0;
+  for (int k = tid; k < KD; k += 256) {
+    W1f[opnd_index(j, k, KD / 16)] = k < D ? (__bf16)(w[k] + w[D + k]) : (__bf16)0.f;
+    if (k < D) acc += (double)w[D + k] * (double)c[k];
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) b1f[j] = (float)((double)b1[j] - red[0]);
+}
+
+// W2 (128 x 256, float32) -> bfloat16 in operand order.
+__global__ __launch_bounds__(256) void w2_operands(const float* __restrict__ W2, __bf16* __restrict__ W2o) {
+  const int j = blockIdx.x;
+  for (int k = threadIdx.x; k < kH1; k += 256) W2o[opnd_index(j, k, kH1 / 16)] = (__bf16)W2[j * kH1 + k];
+}
+
+// One 64-row tile per work-group of 8 waves; the rows (bfloat16, stride
+// KD + 8) and then the layer-1 activations (stride 264) share one LDS
+// buffer, so three work-groups fit on a compute unit.  VEC: rows read as
+// float4 (D a multiple of 4, 16-byte aligned X).
+constexpr int kScoreT = 512;
+
+template <int KD, bool VEC>
+__global__ __launch_bounds__(kScoreT, 3) void score_fused(const float* __restrict__ X, int64_t n, int D,
+                                                          const __bf16* __restrict__ W1f,   // operand order
+                                                          const float* __restrict__ b1f,
+                                                          const __bf16* __restrict__ W2b,   // operand order
+                                                          const float* __restrict__ b2,
+                                                          const float* __restrict__ w3,
+                                                          const float* __restrict__ b3,
+                                                          float* __restrict__ scores) {
+  constexpr int R = kScoreRows;
+  constexpr int NT = kScoreT;
+  constexpr int STX = KD + 8;    // bfloat16 row strides: 16-byte aligned rows
+  constexpr int STH = kH1 + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 buf[R * STH];
+  __shared__ float rs[R][4];
+  __bf16* const Xs = buf;
+  __bf16* const Hs = buf;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 5, c = lane & 31;
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  // stage the tile's rows as bfloat16 (rows past n and columns past D are
+  // 0); all of a thread's loads are issued before the first conversion
+  if constexpr (VEC) {
+    constexpr int NL = (R * (KD / 4) + NT - 1) / NT;   // float4 loads per thread
+    float4 v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + NT * q;
+      const int r = e / (KD / 4), k = 4 * (e - r * (KD / 4));
+      v[q] = (e < R * (KD / 4) && r0 + r < n && k < D)
+                 ? *reinterpret_cast<const float4*>(X + (r0 + r) * D + k)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + NT * q;
+      if (e < R * (KD / 4)) {
+        const int r = e / (KD / 4), k = 4 * (e - r * (KD / 4));
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const bf16x4 q4 = {(__bf16)v[q].x, (__bf16)v[q].y, (__bf16)v[q].z, (__bf16)v[q].w};
+        *reinterpret_cast<bf16x4*>(&Xs[r * STX + k]) = q4;   // one 8-byte store
+      }
+    }
+  } else {
+    constexpr int NL = (R * KD + NT - 1) / NT;         // elements per thread
+    float v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + NT * q;
+      const int r = e / KD, k = e - r * KD;
+      v[q] = (e < R * KD && r0 + r < n && k < D) ? X[(r0 + r) * D + k] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + NT * q;
+      if (e < R * KD) Xs[(e / KD) * STX + (e % KD)] = (__bf16)v[q];
+    }
+  }
+  __syncthreads();
+  // layer 1: wave w owns units [32 w, 32 w + 32) for all 64 rows; its
+  // weight operands for the whole K range are loaded before the first
+  // product (one L2 latency per tile)
+  {
+    floatx16 acc0 = {0.f}, acc1 = {0.f};
+    const __bf16* wb = W1f + ((int64_t)w * (KD / 16) * 64 + lane) * 8;
+    bf16x8 Bw[KD / 16];
+#pragma unroll
+    for (int s = 0; s < KD / 16; ++s) Bw[s] = *reinterpret_cast<const bf16x8*>(wb + 512 * s);
+#pragma unroll
+    for (int s = 0; s < KD / 16; ++s) {
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Xs[c * STX + 16 * s + 8 * g]);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Xs[(32 + c) * STX + 16 * s + 8 * g]);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, Bw[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, Bw[s], acc1, 0, 0, 0);
+    }
+    __syncthreads();   // every wave's reads of the rows are done: Hs replaces them
+    // lane holds unit 32 w + c, rows 32 i + 8 (v / 4) + 4 g + v % 4
+    const int u = 32 * w + c;
+    const float bu = b1f[u];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 8 * (q >> 2) + 4 * g + (q & 3);
+      Hs[r * STH + u] = (__bf16)gelu_fast(acc0[q] + bu);
+      Hs[(32 + r) * STH + u] = (__bf16)gelu_fast(acc1[q] + bu);
+    }
+  }
+  __syncthreads();
+  // layer 2: wave w owns units [32 (w % 4), +32) for rows [32 (w / 4), +32);
+  // the head then sums gelu(z2) w3 over those 32 units per row
+  const int cb = w & 3, rb = w >> 2;
+  floatx16 acc2 = {0.f};
+  const __bf16* wb = W2b + ((int64_t)cb * (kH1 / 16) * 64 + lane) * 8;
+  bf16x8 B2[kH1 / 16];
+#pragma unroll
+  for (int s = 0; s < kH1 / 16; ++s) B2[s] = *reinterpret_cast<const bf16x8*>(wb + 512 * s);
+#pragma unroll
+  for (int s = 0; s < kH1 / 16; ++s) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[(32 * rb + c) * STH + 16 * s + 8 * g]);
+    acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, B2[s], acc2, 0, 0, 0);
+  }
+  const int u = 32 * cb + c;
+  const float bu = b2[u], wu = w3[u];
+  float h[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) h[q] = gelu_fast(acc2[q] + bu) * wu;
+  // butterfly over the 32 lanes of the half-wave: after the step with
+  // offset o a lane keeps the half of its list selected by bit o of c, so
+  // lane c (c < 16 after four steps; the offset-16 step then adds the two
+  // copies) ends with the 32-lane sum of entry c % 16, row 32 rb +
+  // 8 ((c % 16) / 4) + 4 g + c % 4.  The choice between the halves is a bit
+  // mask, not a select of array entries, which the compiler would turn into
+  // a run-time index into the whole register array.
+#pragma unroll
+  for (int o = 8, len = 16; o >= 1; o >>= 1, len >>= 1) {
+    const uint32_t m = (c & o) ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < len / 2) {
+        const uint32_t lo = __float_as_uint(h[q]), up = __float_as_uint(h[q + len / 2]);
+        const uint32_t d = (lo ^ up) & m;
+        const float keep = __uint_as_float(lo ^ d);   // up when the bit is set
+        const float send = __uint_as_float(up ^ d);   // lo when the bit is set
+        h[q] = keep + __shfl_xor(send, o);
+      }
+    }
+  }
+  const float tot = h[0] + __shfl_xor(h[0], 16);
+  if (c < 16) rs[32 * rb + 8 * (c >> 2) + 4 * g + (c & 3)][cb] = tot;
+  __syncthreads();
+  if (tid < R && r0 + tid < n)
+    scores[r0 + tid] = ((rs[tid][0] + rs[tid][1]) + (rs[tid][2] + rs[tid][3])) + b3[0];
+}
+
 // s[i] = w3 . h2[i] + b3 (one wave per row).
 __global__ void head_fwd(const __bf16* __restrict__ H2, int64_t n, const float* __restrict__ w3,
                          const float* __restrict__ b3, float* __restrict__ s) {
@@ -322,6 +532,8 @@ struct MlpWs {
   __bf16* dZ1;
   __bf16* W1b;
   __bf16* W2b;
+  __bf16* W1f;   // folded layer 1 (scoring): 256 x 256 at most
+  float* b1f;
   float* s;      // chunk
   float* part;   // split-K, column-sum and head partials
 };
@@ -339,6 +551,8 @@ MlpWs mlp_layout(Arena& ar, int64_t rows, int D) {
   W.dZ1 = ar.take<__bf16>((size_t)rows * kH1);
   W.W1b = ar.take<__bf16>((size_t)kH1 * 2 * D);
   W.W2b = ar.take<__bf16>((size_t)kH2 * kH1);
+  W.W1f = ar.take<__bf16>((size_t)kH1 * 256);
+  W.b1f = ar.take<float>(kH1);
   W.s = ar.take<float>(rows);
   W.part = ar.take<float>((size_t)kPartFloats);
   return W;
@@ -426,21 +640,39 @@ prohd_status mlp_init(float* params, int32_t D, uint64_t seed, hipStream_t s) {
   return PROHD_OK;
 }
 
+template <int KD>
+prohd_status launch_score(const float* X, int64_t n, int D, const MlpWs& W, const float* params,
+                          float* scores, hipStream_t s) {
+  const Layout L = layout(D);
+  const dim3 grid((unsigned)cdiv(n, kScoreRows));
+  if (D % 4 == 0 && ((uintptr_t)X & 15) == 0) {
+    PROHD_LAUNCH("mlp_score", (score_fused<KD, true>), grid, dim3(kScoreT), 0, s, X, n, D, W.W1f, W.b1f,
+                 W.W2b, params + L.ob2, params + L.ow3, params + L.ob3, scores);
+  } else {
+    PROHD_LAUNCH("mlp_score", (score_fused<KD, false>), grid, dim3(kScoreT), 0, s, X, n, D, W.W1f, W.b1f,
+                 W.W2b, params + L.ob2, params + L.ow3, params + L.ob3, scores);
+  }
+  return PROHD_OK;
+}
+
 prohd_status mlp_score(const float* X, int64_t n, int32_t D, const float* c_other,
                        const float* params, float* scores, void* ws, size_t ws_bytes,
                        hipStream_t s) {
   Arena ar(ws);
   MlpWs W = mlp_layout(ar, std::min<int64_t>(n, kChunk), D);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "mlp: workspace too small");
-  MLP_TRY(weights_bf16(W, D, params, s));
-  for (int64_t r0 = 0; r0 < n; r0 += kChunk) {
-    const int64_t rows = std::min<int64_t>(kChunk, n - r0);
-    PROHD_LAUNCH("mlp_features", features, dim3(2048), dim3(256), 0, s, X + r0 * D, D,
-                 (const int32_t*)nullptr, rows, c_other, W.Fb);
-    MLP_TRY(forward(W, rows, D, params, s));
-    PROHD_HIP(hipMemcpyAsync(scores + r0, W.s, sizeof(float) * rows, hipMemcpyDeviceToDevice, s));
+  const Layout L = layout(D);
+  const int KD = pad_dim(D);
+  PROHD_LAUNCH("mlp_fold", fold_w1, dim3(kH1), dim3(256), 0, s, params + L.oW1, params + L.ob1, D, KD,
+               c_other, W.W1f, W.b1f);
+  PROHD_LAUNCH("mlp_cvt", w2_operands, dim3(kH2), dim3(256), 0, s, params + L.oW2, W.W2b);
+  switch (KD) {
+    case 16: return launch_score<16>(X, n, D, W, params, scores, s);
+    case 32: return launch_score<32>(X, n, D, W, params, scores, s);
+    case 64: return launch_score<64>(X, n, D, W, params, scores, s);
+    case 128: return launch_score<128>(X, n, D, W, params, scores, s);
+    default: return launch_score<256>(X, n, D, W, params, scores, s);
   }
-  return PROHD_OK;
 }
 
 prohd_status mlp_grad(const float* X, int32_t D, const float* c_other, const float* labels,
