@@ -147,10 +147,10 @@ def cpu_baseline(A, B, m, alpha, n_sample):
     }
 
 
-LEARNED_LAW = {"K": 128, "nu": 30.0, "centre_seed": 77, "D": 256}
+LEARNED_LAW = {"K": 128, "centre_seed": 77, "D": 256}
 
 
-def learned_form(args, dev):
+def learned_form(args, dev, nu):
     """Learned proposal: train the scorer on pairs of one Student-t mixture
     (fixed centres, new samples per pair), then compare ProHD + top-scored
     points with plain ProHD at an equal candidate budget on held-out pairs,
@@ -165,7 +165,7 @@ def learned_form(args, dev):
     n, D = args.learned_n, LEARNED_LAW["D"]
 
     def draw(seed):
-        A, B = synth.t_mixture(n, n, D, seed, K=LEARNED_LAW["K"], nu=LEARNED_LAW["nu"],
+        A, B = synth.t_mixture(n, n, D, seed, K=LEARNED_LAW["K"], nu=nu,
                                centre_seed=LEARNED_LAW["centre_seed"])
         return torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
 
@@ -180,7 +180,7 @@ def learned_form(args, dev):
         pairs.append(LN.TrainPair(dA, dB, ws=ws))
         torch.cuda.synchronize()
         label_ms += 1e3 * (time.perf_counter() - l0)
-    log(f"learned: {len(pairs)} training pairs {n}x{n} labelled in {label_ms:.0f} ms "
+    log(f"learned[nu={nu:g}]: {len(pairs)} training pairs {n}x{n} labelled in {label_ms:.0f} ms "
         f"(total {time.perf_counter() - t0:.1f}s)")
     sc = LN.Scorer(D, seed=1)
     batch = 16384
@@ -192,7 +192,7 @@ def learned_form(args, dev):
     train_ms = 1e3 * (time.perf_counter() - t1)
     # training step FLOPs: forward 2 n (2D*256 + 256*128 + 128), backward about twice that
     fwd_flops = 2.0 * (2 * D * 256 + 256 * 128 + 128)
-    log(f"learned: {args.learned_steps} steps in {train_ms:.0f} ms, loss {losses[:50].mean():.4f} -> "
+    log(f"learned[nu={nu:g}]: {args.learned_steps} steps in {train_ms:.0f} ms, loss {losses[:50].mean():.4f} -> "
         f"{losses[-100:].mean():.4f}")
     del pairs
     torch.cuda.empty_cache()
@@ -215,7 +215,7 @@ def learned_form(args, dev):
         rep["prohd_ms"] = e0.elapsed_time(e1)
         rep["learned_extra_ms"] = e1.elapsed_time(e2)
         evals.append(rep)
-        log(f"learned eval {i}: H={H:.5f} full err prohd {rep['full']['prohd_err']:.3e} learned "
+        log(f"learned[nu={nu:g}] eval {i}: H={H:.5f} full err prohd {rep['full']['prohd_err']:.3e} learned "
             f"{rep['full']['learned_err']:.3e} plain {rep['full']['plain_err']:.3e} | candidates "
             f"prohd {rep['candidates']['prohd_err']:.3e} learned {rep['candidates']['learned_err']:.3e} "
             f"plain {rep['candidates']['plain_err']:.3e}")
@@ -235,7 +235,7 @@ def learned_form(args, dev):
         return float(np.mean([r[mode][key] for r in evals]))
 
     return {
-        "law": f"Student-t({LEARNED_LAW['nu']:g}) mixture, {LEARNED_LAW['K']} clusters, D={D}, "
+        "law": f"Student-t({nu:g}) mixture, {LEARNED_LAW['K']} clusters, D={D}, "
                "centres N(0,4I) fixed across pairs, B centres + N(0,0.25I)",
         "train": {"pairs": args.learned_pairs, "n_per_set": n, "points": 2 * n * args.learned_pairs,
                   "label_frac": LN.LABEL_FRAC, "label_ms": label_ms, "steps": args.learned_steps,
@@ -382,6 +382,7 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=4)
     ap.add_argument("--learned-n", type=int, default=500_000)
     ap.add_argument("--learned-steps", type=int, default=3000)
+    ap.add_argument("--learned-nu", type=float, nargs="+", default=[30.0, 3.0])
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
@@ -696,7 +697,9 @@ def main():
     if not args.no_learned:
         del ws
         torch.cuda.empty_cache()
-        learned = learned_form(args, dev)
+        # both tail laws of the learned form's workload: nu = 30 (the one it
+        # is built for) and nu = 3 (every cluster heavy-tailed)
+        learned = {f"nu{nu:g}": learned_form(args, dev, nu) for nu in args.learned_nu}
         ws = None
 
     batched = None
@@ -801,7 +804,10 @@ def main():
             "batched_prohd_pairs_per_s": None if batched is None else r4(batched["prohd"]["pairs_per_s"]),
             "batched_exact_pairs_per_s": None if batched is None else r4(batched["exact"]["pairs_per_s"]),
             "learned_mean_rel_err": None if learned is None else {
-                m_: {k: r4(v) for k, v in learned["mean_rel_err"][m_].items()} for m_ in ("candidates", "full")},
+                law: {m_: {k: r4(v) for k, v in L_["mean_rel_err"][m_].items()}
+                      for m_ in ("candidates", "full")} for law, L_ in learned.items()},
+            "learned_score_ms": None if learned is None else {
+                law: r4(L_["score"]["ms"]) for law, L_ in learned.items()},
         },
         "detail": dpath or "stderr",
     }
