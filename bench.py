@@ -463,7 +463,7 @@ def main():
     res = ph.decode_result(out)
     kernels = {}
     for name in ("stats_gram", "stats_reduce", "eig", "project_mfma", "select_", "compact_",
-                 "hd_prep", "hd_tile", "hd_refine", "hd_finalize"):
+                 "hd_prep", "hd_tile", "hd_keys", "hd_refine", "hd_uncertain", "hd_finalize"):
         n, tot = ph.profile_read(name)
         if n:
             kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tot / args.steps}
