@@ -148,9 +148,8 @@ def _check_selection(got, want, P64, ks):
 
 
 @pytest.mark.parametrize("kind,nA,nB,D,m,k,seed", [
-    ("gauss", 5000, 5000, 32, 3, 100, 0),
-    ("gauss", 5000, 5000, 32, 3, 100, 1),
-    ("gauss", 5000, 5000, 32, 3, 100, 2),
+    # the 5 000 x 5 000, D = 32 workload on its ten seeds
+    *[("gauss", 5000, 5000, 32, 3, 100, s) for s in range(10)],
     ("mix", 40000, 40000, 128, 8, 200, 0),
     ("heavy", 50000, 50000, 256, 16, None, 0),
 ])
@@ -176,3 +175,17 @@ def test_prohd_end_to_end(kind, nA, nB, D, m, k, seed):
     o_own = oracle.prohd(A, B, **kw)
     assert rel(r["H"], o_own["H"]) <= 1e-4
     assert (r["nA_sel"], r["nB_sel"]) == (IA.size, IB.size)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_gauss5k_exact_all_seeds(seed):
+    """Exact distance (Eq. (1)) of the 5 000 x 5 000, D = 32 workload on its
+    ten seeds, against the oracle at 1e-5."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"exact gauss5k seed={seed}")
+    A, B = _data("gauss", 5000, 5000, 32, seed)
+    o = oracle.exact_hd(A, B)
+    r = ph.decode_result(ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True))
+    assert r["status"] == 0 and rel(r["H"], o["H"]) <= 1e-5
+    assert rel(r["hAB"], o["hAB"]) <= 1e-5 and rel(r["hBA"], o["hBA"]) <= 1e-5
