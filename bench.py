@@ -59,7 +59,7 @@ def kernel_source_hash():
     h = hashlib.sha256()
     for start in ("void dist_seg(", "int64_t tile_split(", "void tile_schedule(", "void dist_tile(",
                   "int64_t tile_grid(",
-                  "prohd_status launch_tile("):
+                  "prohd_status launch_tile_k(", "prohd_status launch_tile("):
         h.update(_source_block(src, start).encode())
     return h.hexdigest()[:16]
 
@@ -463,7 +463,8 @@ def main():
     res = ph.decode_result(out)
     kernels = {}
     for name in ("stats_gram", "stats_reduce", "eig", "project_mfma", "select_", "compact_",
-                 "hd_prep", "hd_tile", "hd_keys", "hd_refine", "hd_uncertain", "hd_finalize"):
+                 "hd_prep", "hd_subset", "hd_tile", "hd_tile_rows", "hd_tile_gx", "hd_keys",
+                 "hd_refine", "hd_uncertain", "hd_finalize"):
         n, tot = ph.profile_read(name)
         if n:
             kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tot / args.steps}

@@ -73,7 +73,9 @@ enum {
                                  in bfloat16 (float32 accumulation)          */
   PROHD_PREC_FP8 = 1u << 3,   /* ... in float8 e4m3 with one power-of-two
                                  scale (float32 accumulation)                */
-  PROHD_SYNC = 1u << 4        /* wait for the stream; return device status  */
+  PROHD_SYNC = 1u << 4,       /* wait for the stream; return device status  */
+  PROHD_PRUNE = 1u << 5       /* prohd_hd (default mode) / exact_hd: pruned
+                                 distance search, same result (see prohd_hd) */
 };
 
 /* Result of prohd_hd / exact_hd, written by the device into caller memory. */
@@ -210,6 +212,18 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
  * 1e18); wider sets saturate the search and the witness pair is then not
  * guaranteed.
  *
+ * With PROHD_PRUNE (default mode only; ignored with PROHD_INNER_FULL and
+ * when either side has fewer than 16384 candidate rows) the search first
+ * measures every row against every 16th row of the other side (rows 0, 16,
+ * 32, ... of the selected list): the minimum over that subset bounds the
+ * row's minimum over the whole side from above.  The 256 rows with the
+ * largest such bounds are re-measured in float64 against the whole side; a
+ * row whose subset bound does not exceed the largest re-measured minimum
+ * cannot hold the directed distance and is dropped.  Every remaining row is
+ * searched against the whole side as above (bound, re-measurement).  The
+ * result is the same witness and value as without the flag; the work falls
+ * from nA nB to about nA nB / 16 when few rows remain (the usual case).
+ *
  *   A, B            device float32 point sets (nA x D, nB x D)
  *   idxA, nselA     device: selected rows of A (ascending int32) and their
  *                   count (int64), as written by prohd_select; likewise B
@@ -232,7 +246,9 @@ prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
  *
  *   nn2A   device float32, nA entries, or NULL: per row of A the squared
  *          distance to its nearest row of B, as found by the float32 tile
- *          search (before refinement); likewise nn2B (nB entries).
+ *          search (before refinement); likewise nn2B (nB entries).  When
+ *          either is non-null PROHD_PRUNE is ignored (every row's minimum is
+ *          then searched over the whole other set).
  * Errors: as prohd_hd.
  */
 prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,

@@ -43,6 +43,7 @@ from ._lib import (  # noqa: F401
     DIRS_GIVEN,
     INNER_FULL,
     SYNC,
+    PRUNE,
     PREC_BF16,
     PREC_FP8,
 )

@@ -20,6 +20,7 @@ INNER_FULL = 1 << 1
 PREC_BF16 = 1 << 2
 PREC_FP8 = 1 << 3
 SYNC = 1 << 4
+PRUNE = 1 << 5
 PREC = {"fp32": 0, "bf16": PREC_BF16, "fp8": PREC_FP8}
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENONFINITE", 3: "EWORKSPACE", 4: "EDEVICE", 5: "EUNSUPPORTED"}
@@ -262,10 +263,12 @@ def prohd_select(projA, projB, kA, kB, capA=None, capB=None, ws=None):
 
 
 def prohd_hd(A, B, idxA, nselA, idxB, nselB, capA=None, capB=None, inner_full=False,
-             sync=False, ws=None, out=None, prec="fp32"):
+             sync=False, ws=None, out=None, prec="fp32", prune=True):
     """Hausdorff distance over the selected rows.  ``prec`` selects the
     distance-search tiles ("fp32", "bf16", "fp8"; refinement is float64 in
-    every case).  Returns the device result buffer (uint8[80]); decode with
+    every case); ``prune`` the pruned search (PROHD_PRUNE: same result, used
+    in the default mode on candidate sets of at least 16384 rows each).
+    Returns the device result buffer (uint8[80]); decode with
     ``decode_result``."""
     torch = _torch()
     A = _f32_2d(A, "A")
@@ -274,7 +277,8 @@ def prohd_hd(A, B, idxA, nselA, idxB, nselB, capA=None, capB=None, inner_full=Fa
     nB = B.shape[1 - 1]
     capA = idxA.numel() if capA is None else capA
     capB = idxB.numel() if capB is None else capB
-    flags = (INNER_FULL if inner_full else 0) | (SYNC if sync else 0) | PREC[prec]
+    flags = (INNER_FULL if inner_full else 0) | (SYNC if sync else 0) | PREC[prec] | \
+        (PRUNE if prune else 0)
     if out is None:
         out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=A.device)
     buf, nbytes = _ws(ws, workspace_size(nA, nB, D, 1, capA, capB))
@@ -284,10 +288,11 @@ def prohd_hd(A, B, idxA, nselA, idxB, nselB, capA=None, capB=None, inner_full=Fa
     return out
 
 
-def exact_hd(A, B, sync=False, ws=None, out=None, nn2=False, prec="fp32"):
-    """Exact Hausdorff distance (``prec`` selects the search tiles, as in
-    prohd_hd).  Returns the device result buffer, and with ``nn2=True`` also
-    the per-row squared NN distance arrays of the tile search."""
+def exact_hd(A, B, sync=False, ws=None, out=None, nn2=False, prec="fp32", prune=True):
+    """Exact Hausdorff distance (``prec`` and ``prune`` as in prohd_hd; with
+    ``nn2`` the search is never pruned).  Returns the device result buffer,
+    and with ``nn2=True`` also the per-row squared NN distance arrays of the
+    tile search."""
     torch = _torch()
     A = _f32_2d(A, "A")
     B = _f32_2d(B, "B")
@@ -298,7 +303,8 @@ def exact_hd(A, B, sync=False, ws=None, out=None, nn2=False, prec="fp32"):
     nnA = torch.empty(nA, dtype=torch.float32, device=A.device) if nn2 else None
     nnB = torch.empty(nB, dtype=torch.float32, device=A.device) if nn2 else None
     buf, nbytes = _ws(ws, workspace_size(nA, nB, D, 1))
-    _check(lib().exact_hd(A.data_ptr(), nA, B.data_ptr(), nB, D, (SYNC if sync else 0) | PREC[prec],
+    flags = (SYNC if sync else 0) | PREC[prec] | (PRUNE if prune else 0)
+    _check(lib().exact_hd(A.data_ptr(), nA, B.data_ptr(), nB, D, flags,
                           out.data_ptr(), _ptr(nnA), _ptr(nnB), buf.data_ptr(), nbytes,
                           _stream()))
     return (out, nnA, nnB) if nn2 else out
@@ -346,7 +352,8 @@ def k_rule(alpha: float, n: int) -> int:
     return alpha_k(alpha, n, 1)[0]
 
 
-def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None, prec="fp32"):
+def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None, prec="fp32",
+          prune=True):
     """ProHD end to end on the device: project -> select -> hd.
 
     alpha mode: m = floor(sqrt(D)), k = k_rule(alpha, n) on the centroid axis
@@ -367,7 +374,8 @@ def prohd(A, B, alpha=0.01, m=None, k=None, dirs=None, inner_full=False, ws=None
         kB = [min(max(1, x), nB) for x in ks]
     d, pA, pB, ev, st = prohd_project(A, B, m, dirs=dirs, ws=ws)
     idxA, nA_sel, idxB, nB_sel = prohd_select(pA, pB, kA, kB, ws=ws)
-    out = prohd_hd(A, B, idxA, nA_sel, idxB, nB_sel, inner_full=inner_full, ws=ws, prec=prec)
+    out = prohd_hd(A, B, idxA, nA_sel, idxB, nB_sel, inner_full=inner_full, ws=ws, prec=prec,
+                   prune=prune)
     res = decode_result(out)
     res.update({"dirs": d, "projA": pA, "projB": pB, "evals": ev, "project_status": st,
                 "idxA": idxA, "nselA": nA_sel, "idxB": idxB, "nselB": nB_sel,

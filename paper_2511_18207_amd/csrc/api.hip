@@ -166,7 +166,8 @@ size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs, in
   need = std::max(need, select_ws_bytes(2 * ndirs, std::max(nA, nB)) +
                             compact_ws_bytes(std::max(nA, nB)) + (size_t)(nA + nB) + 1024);
   need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true, PROHD_PREC_BF16));
-  need = std::max(need, exact_ws_bytes(nA, nB, D, PROHD_PREC_BF16));
+  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, false, PROHD_PREC_BF16 | PROHD_PRUNE));
+  need = std::max(need, exact_ws_bytes(nA, nB, D, PROHD_PREC_BF16 | PROHD_PRUNE));
   return need;
 }
 
@@ -258,7 +259,7 @@ prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       prohd_result* out, void* ws, size_t ws_bytes, void* stream) {
   prohd_status st = check_sets(A, nA, B, nB, D);
   if (st) return st;
-  if (flags & ~(uint32_t)(PROHD_INNER_FULL | PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC))
+  if (flags & ~(uint32_t)(PROHD_INNER_FULL | PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC | PROHD_PRUNE))
     return fail(PROHD_EINVAL, "unknown flag");
   if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
     return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");
@@ -281,7 +282,7 @@ prohd_status exact_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       size_t ws_bytes, void* stream) {
   prohd_status st = check_sets(A, nA, B, nB, D);
   if (st) return st;
-  if (flags & ~(uint32_t)(PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC))
+  if (flags & ~(uint32_t)(PROHD_PREC_BF16 | PROHD_PREC_FP8 | PROHD_SYNC | PROHD_PRUNE))
     return fail(PROHD_EINVAL, "unknown flag");
   if ((flags & PROHD_PREC_BF16) && (flags & PROHD_PREC_FP8))
     return fail(PROHD_EINVAL, "PROHD_PREC_BF16 and PROHD_PREC_FP8 are exclusive");

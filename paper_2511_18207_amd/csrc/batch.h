@@ -74,7 +74,8 @@ struct KeyJob {
 // refined yet -> cand2 (ascending), count2, best2 initialised
 struct UncJob {
   const uint32_t* key;               // bound keys (float bits)
-  const uint8_t* top;                // rows of the first refinement (flag 1)
+  const uint8_t* top;                // rows of the first refinement (flag 1), or null
+  const int32_t* map;                // entry -> row (cand2 gets map[i]), or null
   const int64_t* dn;                 // device row count, or null
   int64_t hn;                        // host bound on the row count
   const unsigned long long* best;    // first-pass minima

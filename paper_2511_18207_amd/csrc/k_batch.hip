@@ -387,7 +387,7 @@ prohd_status build(prohd_batch* b) {
         const int kjob = (int)kyj.size();
         kyj.push_back(KeyJob{w.row[s], w.xn[s], s ? dB : dA, r, kbx});
         for (int x = 0; x < kbx; ++x) kyi.push_back(BItem{kjob, x});
-        ucj.push_back(UncJob{w.row[s], w.top[s], s ? dB : dA, r, w.best[s], w.ccnt + s, w.status,
+        ucj.push_back(UncJob{w.row[s], w.top[s], nullptr, s ? dB : dA, r, w.best[s], w.ccnt + s, w.status,
                              w.cand2[s], w.ccnt2 + s, w.best2[s]});
         const int r2job = (int)r2j.size();
         r2j.push_back(RefineJob{w.xp[s], w.cand2[s], w.ccnt2 + s, w.xp[1 - s], s ? dA : dB, ry, ys,

@@ -168,8 +168,9 @@ __host__ __device__ constexpr int tile_bn() { return DP == 256 ? 2 * kBN : kBN; 
 // One segment of the distance matrix: X rows [x0, x0 + kTileRows) against
 // Y rows [yb, ye).  Row minima go to rowmin, column minima (COLMIN) to colmin,
 // both as order-preserving bit patterns through atomicMin.
-template <int DP, bool COLMIN>
+template <int DP, bool COLMIN, bool GX = false>
 __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const float* __restrict__ xn,
+                                         const int32_t* __restrict__ xidx,
                                          int64_t nX, const float* __restrict__ Yp,
                                          const float* __restrict__ yn, int64_t x0, int64_t yb,
                                          int64_t ye, uint32_t* __restrict__ rowmin,
@@ -196,12 +197,14 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
   const int g = lane >> 5;   // half-wave: k range [g*KH, g*KH + KH)
   const int c = lane & 31;   // row (A operand) / column (B operand) within the 32-block
 
-  // A operand: row x0 + 32*wave + c, k in [g*KH, g*KH + KH)
+  // A operand: row x0 + 32*wave + c, k in [g*KH, g*KH + KH) (GX: the row
+  // of that position in the list xidx)
   float a[KH];
   {
     const int64_t xr = x0 + 32 * wave + c;
     if (xr < nX) {
-      const float4* src = reinterpret_cast<const float4*>(Xp + xr * DP + g * KH);
+      const int64_t xm = GX ? (int64_t)xidx[xr] : xr;
+      const float4* src = reinterpret_cast<const float4*>(Xp + xm * DP + g * KH);
 #pragma unroll
       for (int j = 0; j < KH / 4; ++j) {
         const float4 v = src[j];
@@ -218,7 +221,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int64_t r = x0 + 32 * wave + 8 * (v >> 2) + 4 * g + (v & 3);
-    xq[v] = (r < nX) ? xn[r] : __uint_as_float(kInfBits);
+    xq[v] = (r < nX) ? xn[GX ? (int64_t)xidx[r] : r] : __uint_as_float(kInfBits);
     rmin[v] = __uint_as_float(kInfBits);
   }
 
@@ -370,7 +373,7 @@ __device__ __forceinline__ void dist_tile_body(const float* __restrict__ Xp,
   const int64_t yb = (int64_t)ysi * chunk;
   const int64_t ye = min(nY, yb + chunk);
   if (yb >= ye) return;
-  dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, x0, yb, ye, rowmin, colmin);
+  dist_seg<DP, COLMIN>(Xp, xn, nullptr, nX, Yp, yn, x0, yb, ye, rowmin, colmin);
 }
 
 // Chunk count of a persistent tile launch.  The matrix is cut into xt x S
@@ -433,9 +436,10 @@ __device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S
 // so the work-groups of an XCD (ids congruent modulo 8), which hold
 // consecutive items of one or two chunks, read each Y block at about the same
 // time and one L2 fill serves them all.
-template <int DP, bool COLMIN>
+template <int DP, bool COLMIN, bool GX = false>
 __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
                                                  const float* __restrict__ xn,
+                                                 const int32_t* __restrict__ xidx,
                                                  const int64_t* __restrict__ dnX, int64_t hnX,
                                                  const float* __restrict__ Yp,
                                                  const float* __restrict__ yn,
@@ -451,8 +455,8 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
   const int64_t S = tile_split(xt, nyb, gridDim.x);
   tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
     __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg<DP, COLMIN>(Xp, xn, nX, Yp, yn, xblk * kTileRows, b0 * BN, min(nY, b1 * BN), rowmin,
-                         colmin);
+    dist_seg<DP, COLMIN, GX>(Xp, xn, xidx, nX, Yp, yn, xblk * kTileRows, b0 * BN, min(nY, b1 * BN),
+                             rowmin, colmin);
   });
 }
 
@@ -543,9 +547,10 @@ constexpr int kLpBN = 128;   // Y rows per LDS buffer
 constexpr int kLpXS = 2;     // 32-row X sets per wave
 constexpr int kLpTileRows = kTileRows * kLpXS;
 
-template <int DP, int FMT, bool COLMIN>
+template <int DP, int FMT, bool COLMIN, bool GX = false>
 __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
-                                            const float* __restrict__ xn, int64_t nX,
+                                            const float* __restrict__ xn,
+                                            const int32_t* __restrict__ xidx, int64_t nX,
                                             const uint8_t* __restrict__ Yq,
                                             const float* __restrict__ yn, int64_t x0, int64_t yb,
                                             int64_t ye, const uint32_t* __restrict__ maxabs,
@@ -597,7 +602,8 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     const int64_t rb0 = x0 + 32 * (XS * wave + x);
     const int64_t xr = rb0 + c;
     if (xr < nX) {
-      const uint4* src = reinterpret_cast<const uint4*>(Xq + xr * RB + g * (RB / 2));
+      const int64_t xm = GX ? (int64_t)xidx[xr] : xr;
+      const uint4* src = reinterpret_cast<const uint4*>(Xq + xm * RB + g * (RB / 2));
 #pragma unroll
       for (int j = 0; j < NA; ++j) a[x][j] = src[j];
     } else {
@@ -607,7 +613,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t r = rb0 + 8 * (v >> 2) + 4 * g + (v & 3);
-      xc[x][v] = ((r < nX) ? xn[r] : __uint_as_float(kInfBits)) * inv_dscale;
+      xc[x][v] = ((r < nX) ? xn[GX ? (int64_t)xidx[r] : r] : __uint_as_float(kInfBits)) * inv_dscale;
       rmin[x][v] = __uint_as_float(kInfBits);
     }
   }
@@ -785,9 +791,10 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
 }
 
 // Persistent form of the low-precision tile (same schedule as dist_tile).
-template <int DP, int FMT, bool COLMIN>
+template <int DP, int FMT, bool COLMIN, bool GX = false>
 __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ Xq,
                                                      const float* __restrict__ xn,
+                                                     const int32_t* __restrict__ xidx,
                                                      const int64_t* __restrict__ dnX, int64_t hnX,
                                                      const uint8_t* __restrict__ Yq,
                                                      const float* __restrict__ yn,
@@ -803,7 +810,7 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
   const int64_t S = tile_split(xt, nyb, gridDim.x);
   tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
     __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg_lp<DP, FMT, COLMIN>(Xq, xn, nX, Yq, yn, xblk * kLpTileRows, b0 * kLpBN,
+    dist_seg_lp<DP, FMT, COLMIN, GX>(Xq, xn, xidx, nX, Yq, yn, xblk * kLpTileRows, b0 * kLpBN,
                                  min(nY, b1 * kLpBN), maxabs, rowmin, colmin);
   });
 }
@@ -1082,15 +1089,17 @@ __device__ __forceinline__ uint32_t bits_down(double v) {
 // mins[i] (bits of the approximate squared minimum) -> bits of U^2 rounded
 // up, for the rows i < n.  xn[i]: float32 |x_i|^2 of the shifted row (DP
 // terms, so |x|^2 <= xn (1 + 2 (DP + 2) 2^-24)).
+// With `map`, entry i belongs to row map[i] (norm xn[map[i]]).
 __device__ __forceinline__ void bound_keys_body(uint32_t* __restrict__ mins,
                                                 const float* __restrict__ xn, int64_t n, int DP,
                                                 int K, int fmt, const uint32_t* __restrict__ maxabs,
-                                                int64_t i0, int64_t stride) {
+                                                int64_t i0, int64_t stride,
+                                                const int32_t* __restrict__ map = nullptr) {
   const SearchModel q = search_model(K, fmt, maxabs);
   const double grow = 1.0 + 2.0 * (DP + 2) * 0x1p-24;
   for (int64_t i = i0; i < n; i += stride) {
     const double m2 = (double)__uint_as_float(mins[i]);
-    const double S = sqrt((double)xn[i] * grow);
+    const double S = sqrt((double)xn[map ? (int64_t)map[i] : i] * grow);
     const double U = min_upper(m2, S, q);
     mins[i] = bits_up(U * U * (1.0 + 0x1p-40));
   }
@@ -1099,9 +1108,44 @@ __device__ __forceinline__ void bound_keys_body(uint32_t* __restrict__ mins,
 __global__ __launch_bounds__(256) void bound_keys(uint32_t* __restrict__ mins,
                                                   const float* __restrict__ xn,
                                                   const int64_t* __restrict__ dn, int64_t hn, int DP,
-                                                  int K, int fmt, const uint32_t* __restrict__ maxabs) {
+                                                  int K, int fmt, const uint32_t* __restrict__ maxabs,
+                                                  const int32_t* __restrict__ map) {
   bound_keys_body(mins, xn, dev_or(dn, hn), DP, K, fmt, maxabs,
-                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, map);
+}
+
+// Pruned search: the subset of a prepared set made of its rows at positions
+// 0, F, 2F, ... (all of them, float32 and low-precision copies with their
+// norms); *dsub = number of subset rows.  One wave per row.
+constexpr int kPruneStride = 16;       // F
+constexpr int64_t kPruneMinRows = 16384;   // smaller sets are searched in full
+
+template <int DP, int FMT>
+__global__ __launch_bounds__(256) void gather_subset(const float* __restrict__ Xp,
+                                                     const float* __restrict__ xn,
+                                                     const uint8_t* __restrict__ Xq,
+                                                     const float* __restrict__ xqn,
+                                                     const int64_t* __restrict__ dn, int64_t hn,
+                                                     float* __restrict__ Sp, float* __restrict__ sn,
+                                                     uint8_t* __restrict__ Sq, float* __restrict__ sqn,
+                                                     int64_t* __restrict__ dsub) {
+  constexpr int QB = FMT == FMT_F32 ? 0 : qdim(DP, FMT) * (FMT == FMT_BF16 ? 2 : 1);   // bytes per row
+  const int64_t n = dev_or(dn, hn);
+  const int64_t ns = (n + kPruneStride - 1) / kPruneStride;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dsub = ns;
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < ns; i += (int64_t)gridDim.x * 4) {
+    const int64_t src = i * kPruneStride;
+    for (int k = lane; k < DP; k += 64) Sp[i * DP + k] = Xp[src * DP + k];
+    if constexpr (QB > 0) {
+      for (int k = 4 * lane; k < QB; k += 256)
+        *reinterpret_cast<uint32_t*>(Sq + i * QB + k) = *reinterpret_cast<const uint32_t*>(Xq + src * QB + k);
+    }
+    if (lane == 0) {
+      sn[i] = xn[src];
+      if constexpr (QB > 0) sqn[i] = xqn[src];
+    }
+  }
 }
 
 // Exclusive prefix sum over a work-group of NT threads; *total gets the sum.
@@ -1159,7 +1203,7 @@ __device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int64_t i = c0 + (int64_t)tid * Q + q;
-      const bool on = i < n && j.top[i] == 0 && j.key[i] > tb;
+      const bool on = i < n && (!j.top || j.top[i] == 0) && j.key[i] > tb;
       f |= (on ? 1u : 0u) << q;
       cnt += on ? 1u : 0u;
     }
@@ -1167,7 +1211,10 @@ __device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
     uint32_t pos = wg_excl_sum<NT>(cnt, lds, &tot);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
-      if ((f >> q) & 1u) j.cand2[base + pos++] = (int32_t)(c0 + (int64_t)tid * Q + q);
+      if ((f >> q) & 1u) {
+        const int64_t i = c0 + (int64_t)tid * Q + q;
+        j.cand2[base + pos++] = j.map ? j.map[i] : (int32_t)i;
+      }
     base += tot;
   }
   if (tid == 0) *j.count2 = base;
@@ -1461,49 +1508,54 @@ int64_t tile_grid(K kernel, int64_t items) {
   return std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)per_cu * cu_count()));
 }
 
-template <int DP>
-prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
-                         const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
-                         uint32_t* colmin, hipStream_t s) {
+// One distance-tile launch: X rows (all of X, or with `xidx` the rows it
+// lists; row minima then go to positions of the list) against Y rows.
+template <int DP, bool COLMIN, bool GX>
+prohd_status launch_tile_k(int fmt, PrepSet X, const int32_t* xidx, const int64_t* dnX, int64_t capX,
+                           PrepSet Y, const int64_t* dnY, int64_t capY, const uint32_t* maxabs,
+                           uint32_t* rowmin, uint32_t* colmin, hipStream_t s) {
   // one resident work-group per slot, at most one per item the capacities
   // allow (16 chunks per row tile at most)
+  // timing names: "hd_tile*" for every form; "_rows" row minima only,
+  // "_gx" listed rows
   const dim3 T(512);
   if (fmt == FMT_F32) {
     const int64_t items = cdiv(capX, kTileRows) * std::min<int64_t>(16, cdiv(capY, tile_bn<DP>()));
-    if (colmin) {
-      auto k = dist_tile<DP, true>;
-      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, dnX, capX,
-                   Y.p, Y.n, dnY, capY, rowmin, colmin);
-    } else {
-      auto k = dist_tile<DP, false>;
-      PROHD_LAUNCH("hd_tile", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, dnX, capX,
-                   Y.p, Y.n, dnY, capY, rowmin, colmin);
-    }
+    auto k = dist_tile<DP, COLMIN, GX>;
+    const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
+    PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, xidx, dnX, capX,
+                 Y.p, Y.n, dnY, capY, rowmin, colmin);
     return PROHD_OK;
   }
   const int64_t items = cdiv(capX, kLpTileRows) * std::min<int64_t>(16, cdiv(capY, kLpBN));
   if (fmt == FMT_BF16) {
-    if (colmin) {
-      auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, true>;
-      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
-    } else {
-      auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, false>;
-      PROHD_LAUNCH("hd_tile_bf16", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
-    }
+    auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, COLMIN, GX>;
+    const char* name = GX ? "hd_tile_bf16_gx" : COLMIN ? "hd_tile_bf16" : "hd_tile_bf16_rows";
+    PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, xidx, dnX,
+                 capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
   } else {
-    if (colmin) {
-      auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, true>;
-      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
-    } else {
-      auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, false>;
-      PROHD_LAUNCH("hd_tile_fp8", k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, dnX,
-                   capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
-    }
+    auto k = dist_tile_lp<qdim(DP, FMT_FP8), FMT_FP8, COLMIN, GX>;
+    const char* name = GX ? "hd_tile_fp8_gx" : COLMIN ? "hd_tile_fp8" : "hd_tile_fp8_rows";
+    PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.q, X.qn, xidx, dnX,
+                 capX, Y.q, Y.qn, dnY, capY, maxabs, rowmin, colmin);
   }
   return PROHD_OK;
+}
+
+template <int DP>
+prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, PrepSet Y,
+                         const int64_t* dnY, int64_t capY, const uint32_t* maxabs, uint32_t* rowmin,
+                         uint32_t* colmin, hipStream_t s, const int32_t* xidx = nullptr) {
+  if (xidx) {
+    if (colmin) return fail(PROHD_EINVAL, "hd: listed rows take row minima only");
+    return launch_tile_k<DP, false, true>(fmt, X, xidx, dnX, capX, Y, dnY, capY, maxabs, rowmin,
+                                          nullptr, s);
+  }
+  if (colmin)
+    return launch_tile_k<DP, true, false>(fmt, X, nullptr, dnX, capX, Y, dnY, capY, maxabs, rowmin,
+                                          colmin, s);
+  return launch_tile_k<DP, false, false>(fmt, X, nullptr, dnX, capX, Y, dnY, capY, maxabs, rowmin,
+                                         nullptr, s);
 }
 
 template <int DP>
@@ -1532,12 +1584,24 @@ struct DirWork {
   unsigned long long* best2;  // n
 };
 
+// Pruned search (per direction): the second-stage row minima over the
+// listed rows, and the rows those leave uncertain.
+struct PruneWork {
+  uint32_t* rowF;   // cap: minima of the rows listed by the first-stage uncertain list
+  int32_t* cand3;   // cap
+  int64_t* count3;  // 1
+  unsigned long long* best3;  // cap
+};
+
 struct HdLayout {
   PrepSet xa, xb;          // prepared candidate (or full) rows
   PrepSet fa, fb;          // full prepared rows (inner-full mode)
+  PrepSet sa, sb;          // subsets of xa / xb (pruned search)
+  int64_t* dsub;           // [2] subset row counts
   uint32_t* rowA;          // minima of A-side rows
   uint32_t* rowB;          // minima of B-side rows
   DirWork w[2];
+  PruneWork pw[2];
   int32_t* status;
   uint32_t* maxabs;        // largest |shifted value| (float bits), fp8 scale
   void* sel_ws;
@@ -1554,7 +1618,7 @@ void take_set(Arena& ar, PrepSet& o, int64_t rows, int DP, int fmt) {
 }
 
 HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB, int DP,
-                   bool full, int fmt) {
+                   bool full, int fmt, bool prune) {
   HdLayout L{};
   L.status = ar.take<int32_t>(64);
   L.maxabs = ar.take<uint32_t>(64);
@@ -1575,6 +1639,17 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
     L.w[d].cand2 = ar.take<int32_t>(caps[d]);
     L.w[d].count2 = ar.take<int64_t>(1);
     L.w[d].best2 = ar.take<unsigned long long>(caps[d]);
+  }
+  if (prune) {
+    take_set(ar, L.sa, cdiv(capA, kPruneStride), DP, fmt);
+    take_set(ar, L.sb, cdiv(capB, kPruneStride), DP, fmt);
+    L.dsub = ar.take<int64_t>(2);
+    for (int d = 0; d < 2; ++d) {
+      L.pw[d].rowF = ar.take<uint32_t>(caps[d]);
+      L.pw[d].cand3 = ar.take<int32_t>(caps[d]);
+      L.pw[d].count3 = ar.take<int64_t>(1);
+      L.pw[d].best3 = ar.take<unsigned long long>(caps[d]);
+    }
   }
   const int64_t mx = std::max(capA, capB);
   L.sel_bytes = std::max(select_ws_bytes(2, mx), compact_ws_bytes(mx));
@@ -1616,11 +1691,28 @@ prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const 
 
 // Bound keys in place of the row minima (see the certified refinement).
 prohd_status launch_keys(uint32_t* mins, const float* xn, const int64_t* dn, int64_t cap, int DP,
-                         int fmt, const uint32_t* maxabs, hipStream_t s) {
+                         int fmt, const uint32_t* maxabs, hipStream_t s, const int32_t* map = nullptr) {
   const int K = fmt == FMT_F32 ? DP : qdim(DP, fmt);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 8 * cu_count()));
   PROHD_LAUNCH("hd_keys", bound_keys, dim3(grid), dim3(256), 0, s, mins, xn, dn, cap, DP, K, fmt,
-               maxabs);
+               maxabs, map);
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status launch_subset(int fmt, PrepSet X, const int64_t* dn, int64_t cap, PrepSet S, int64_t* dsub,
+                           hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cdiv(cap, kPruneStride), 4), 1024));
+  if (fmt == FMT_F32) {
+    PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_F32>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+  } else if (fmt == FMT_BF16) {
+    PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_BF16>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+  } else {
+    PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_FP8>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+  }
   return PROHD_OK;
 }
 
@@ -1658,10 +1750,11 @@ prohd_status init_best(unsigned long long* p, hipStream_t s) {
 template <int DP>
 prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int D,
                     const int32_t* idxA, const int64_t* dnA, int64_t capA, const int32_t* idxB,
-                    const int64_t* dnB, int64_t capB, bool full, int fmt, prohd_result* out,
-                    float* nn2A, float* nn2B, void* ws, size_t ws_bytes, hipStream_t s) {
+                    const int64_t* dnB, int64_t capB, bool full, int fmt, bool prune,
+                    prohd_result* out, float* nn2A, float* nn2B, void* ws, size_t ws_bytes,
+                    hipStream_t s) {
   Arena ar(ws);
-  HdLayout L = hd_layout(ar, capA, capB, nA, nB, DP, full, fmt);
+  HdLayout L = hd_layout(ar, capA, capB, nA, nB, DP, full, fmt, prune);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "hd: workspace too small");
   PROHD_TRY(zero_bytes(L.status, 256, s));
   PROHD_TRY(zero_bytes(L.maxabs, 256, s));
@@ -1694,7 +1787,16 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   const int64_t* ydnB = full ? nullptr : dnB;
   const int64_t ycapA = full ? nA : capA;
   const int64_t ycapB = full ? nB : capB;
-  if (!full) {
+  if (prune) {
+    // first stage: every row against a 1 / F subset of the other set; the
+    // subset minimum bounds the row's minimum over the whole set from above
+    PROHD_TRY(launch_subset<DP>(fmt, L.xa, dnA, capA, L.sa, L.dsub, s));
+    PROHD_TRY(launch_subset<DP>(fmt, L.xb, dnB, capB, L.sb, L.dsub + 1, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.sb, L.dsub + 1, cdiv(capB, kPruneStride), L.maxabs,
+                              L.rowA, nullptr, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.sa, L.dsub, cdiv(capA, kPruneStride), L.maxabs,
+                              L.rowB, nullptr, s));
+  } else if (!full) {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
   } else {
     PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
@@ -1711,16 +1813,40 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, ysA.p, ydnA, ycapA, L.w[1].best, s));
   UncPair U{};
   for (int d = 0; d < 2; ++d)
-    U.d[d] = UncJob{mins2[d], L.w[d].flags, dns2[d], caps2[d], L.w[d].best, L.w[d].count, L.status,
+    U.d[d] = UncJob{mins2[d], L.w[d].flags, nullptr, dns2[d], caps2[d], L.w[d].best, L.w[d].count, L.status,
                     L.w[d].cand2, L.w[d].count2, L.w[d].best2};
   PROHD_LAUNCH("hd_uncertain", uncertain_rows, dim3(2), dim3(kUncT), 0, s, U);
-  PROHD_TRY(launch_refine_dyn<DP>(L.xa.p, L.w[0].cand2, L.w[0].count2, ysB.p, ydnB, ycapB,
-                                  L.w[0].best2, s));
-  PROHD_TRY(launch_refine_dyn<DP>(L.xb.p, L.w[1].cand2, L.w[1].count2, ysA.p, ydnA, ycapA,
-                                  L.w[1].best2, s));
-  const DirIn ab{L.w[0].best, L.w[0].cand, L.w[0].count, L.w[0].best2, L.w[0].cand2, L.w[0].count2,
+  // the rows the second refinement measures: with pruning, those of the
+  // first-stage uncertain list (rows whose subset bound exceeds the largest
+  // refined minimum) that a search over the whole other set still leaves
+  // uncertain; otherwise the uncertain list itself
+  const int32_t* cand2[2] = {L.w[0].cand2, L.w[1].cand2};
+  const int64_t* count2[2] = {L.w[0].count2, L.w[1].count2};
+  unsigned long long* best2[2] = {L.w[0].best2, L.w[1].best2};
+  if (prune) {
+    PROHD_TRY(init_mins(L.pw[0].rowF, capA, s));
+    PROHD_TRY(init_mins(L.pw[1].rowF, capB, s));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xa, L.w[0].count2, capA, L.xb, dnB, capB, L.maxabs, L.pw[0].rowF,
+                              nullptr, s, L.w[0].cand2));
+    PROHD_TRY(launch_tile<DP>(fmt, L.xb, L.w[1].count2, capB, L.xa, dnA, capA, L.maxabs, L.pw[1].rowF,
+                              nullptr, s, L.w[1].cand2));
+    PROHD_TRY(launch_keys(L.pw[0].rowF, L.xa.n, L.w[0].count2, capA, DP, fmt, L.maxabs, s, L.w[0].cand2));
+    PROHD_TRY(launch_keys(L.pw[1].rowF, L.xb.n, L.w[1].count2, capB, DP, fmt, L.maxabs, s, L.w[1].cand2));
+    UncPair F{};
+    for (int d = 0; d < 2; ++d) {
+      F.d[d] = UncJob{L.pw[d].rowF, nullptr, L.w[d].cand2, L.w[d].count2, caps2[d], L.w[d].best,
+                      L.w[d].count, L.status, L.pw[d].cand3, L.pw[d].count3, L.pw[d].best3};
+      cand2[d] = L.pw[d].cand3;
+      count2[d] = L.pw[d].count3;
+      best2[d] = L.pw[d].best3;
+    }
+    PROHD_LAUNCH("hd_uncertain", uncertain_rows, dim3(2), dim3(kUncT), 0, s, F);
+  }
+  PROHD_TRY(launch_refine_dyn<DP>(L.xa.p, cand2[0], count2[0], ysB.p, ydnB, ycapB, best2[0], s));
+  PROHD_TRY(launch_refine_dyn<DP>(L.xb.p, cand2[1], count2[1], ysA.p, ydnA, ycapA, best2[1], s));
+  const DirIn ab{L.w[0].best, L.w[0].cand, L.w[0].count, best2[0], cand2[0], count2[0],
                  idxA, full ? nullptr : idxB, A, B};
-  const DirIn ba{L.w[1].best, L.w[1].cand, L.w[1].count, L.w[1].best2, L.w[1].cand2, L.w[1].count2,
+  const DirIn ba{L.w[1].best, L.w[1].cand, L.w[1].count, best2[1], cand2[1], count2[1],
                  idxB, full ? nullptr : idxA, B, A};
   PROHD_LAUNCH("hd_finalize", finalize, dim3(1), dim3(256), 0, s, ab, ba, D, dnA, capA, dnB, capB,
                L.status, out);
@@ -1747,16 +1873,22 @@ int fmt_of(uint32_t flags) {
 
 }  // namespace
 
+// Pruned search when asked for, in candidate / exact mode (not inner-full),
+// on sets large enough to profit (smaller ones: the full search, same value).
+bool use_prune(uint32_t flags, bool full, int64_t capA, int64_t capB) {
+  return (flags & PROHD_PRUNE) && !full && capA >= kPruneMinRows && capB >= kPruneMinRows;
+}
+
 size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
                    uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full, fmt_of(flags));
+  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full, fmt_of(flags), use_prune(flags, full, capA, capB));
   return ar.used + 256;
 }
 
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false, fmt_of(flags));
+  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false, fmt_of(flags), use_prune(flags, false, nA, nB));
   return ar.used + 256;
 }
 
@@ -1766,9 +1898,10 @@ prohd_status hd_candidates(const float* A, int64_t nA, const float* B, int64_t n
                            prohd_result* out, void* ws, size_t ws_bytes, hipStream_t s) {
   const bool full = (flags & PROHD_INNER_FULL) != 0;
   const int fmt = fmt_of(flags);
+  const bool prune = use_prune(flags, full, capA, capB);
   return by_dp(D, [&](auto dp) {
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, idxA, dnA, capA, idxB, dnB, capB, full, fmt,
-                                       out, nullptr, nullptr, ws, ws_bytes, s);
+                                       prune, out, nullptr, nullptr, ws, ws_bytes, s);
   });
 }
 
@@ -1776,9 +1909,11 @@ prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, in
                       uint32_t flags, prohd_result* out, float* nn2A, float* nn2B, void* ws,
                       size_t ws_bytes, hipStream_t s) {
   const int fmt = fmt_of(flags);
+  // the per-row minima asked for (nn2) come from the full search
+  const bool prune = !nn2A && !nn2B && use_prune(flags, false, nA, nB);
   return by_dp(D, [&](auto dp) {
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, nullptr, nullptr, nA, nullptr, nullptr, nB,
-                                       false, fmt, out, nn2A, nn2B, ws, ws_bytes, s);
+                                       false, fmt, prune, out, nn2A, nn2B, ws, ws_bytes, s);
   });
 }
 

@@ -79,7 +79,7 @@ FAKE = 0x1000  # never dereferenced: validation fails first
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 0, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 11, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "capA"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, None, FAKE, FAKE, FAKE, 5, 5, 0, FAKE, FAKE, 1 << 24, None), 1, "index"),
-    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 5, FAKE, FAKE, 1 << 24, None), 1, "flag"),
+    (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 6, FAKE, FAKE, 1 << 24, None), 1, "flag"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 12, FAKE, FAKE, 1 << 24, None), 1, "exclusive"),
     (lambda L: L.exact_hd(FAKE, 10, FAKE, 10, 4, 2, FAKE, None, None, FAKE, 1 << 24, None), 1, "flag"),
 ])

@@ -1,0 +1,171 @@
+"""GPU parity of the pruned distance search (PROHD_PRUNE) through the C ABI,
+against the FP64 oracle and against the unpruned search.
+
+The pruned search (k_hd.hip, pruned search) bounds every outer row's
+minimum from above by its minimum over every 16th inner row, re-measures
+the 256 rows with the largest bounds against the whole inner set, drops the
+rows whose bound cannot exceed the largest re-measured minimum, and searches
+the rest against the whole inner set.  It must return the unpruned search's
+result exactly (same witness rows, same float64 values) and the oracle's
+value of Eq. (1) / the candidate distance of Alg. 3:
+
+* exact distance on ragged Gaussian sets with outliers, three precisions;
+* the near-duplicate case (a set against a slightly moved copy of itself),
+  where no row can be dropped and every row goes through the second stage;
+* candidate lists (Alg. 3, default inner mode) of ragged sizes;
+* the size rule: below 16384 rows on either side the flag changes nothing.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import banner, rel, to_dev, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("H", "hAB", "hBA", "ab_a", "ab_b", "ba_b", "ba_a", "nA_sel", "nB_sel", "status")
+
+
+def _subset_launches(ph, fn):
+    """Result of fn() and the number of subset-gather launches it made."""
+    ph.profile_reset()
+    ph.profile_enable(True)
+    try:
+        r = fn()
+    finally:
+        ph.profile_enable(False)
+    n, _ = ph.profile_read("hd_subset")
+    return r, n
+
+
+def _same(a, b):
+    for k in KEYS:
+        assert a[k] == b[k], (k, a[k], b[k])
+
+
+def perturbed_copy(n, D, seed):
+    g = np.random.default_rng(seed)
+    A = g.uniform(0.0, 100.0, size=(n, D)).astype(np.float32)
+    v = g.standard_normal((n, D))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    step = g.uniform(0.01, 0.02, size=n)
+    j = int(g.integers(n))
+    step[j] = 0.05
+    B = (A.astype(np.float64) + v * step[:, None]).astype(np.float32)
+    return A, B, j
+
+
+@pytest.fixture(scope="module")
+def gauss40k():
+    A, B = synth.gauss_outliers(40000, 36017, 64, seed=4)
+    return A, B, oracle.exact_hd(A, B, one_pass=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_exact_pruned(gauss40k, prec):
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    A, B, o = gauss40k
+    banner(f"exact_hd pruned gauss 40000x36017x64 prec={prec}")
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec)))
+    assert n == 2                                       # the pruned form ran
+    ru = ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec, prune=False))
+    print(f"[prune] exact {prec}: H {rp['H']:.9g} (unpruned {ru['H']:.9g}, oracle {o['H']:.9g}), "
+          f"refined {rp['refined']} / {ru['refined']}", flush=True)
+    _same(rp, ru)
+    assert rel(rp["H"], o["H"]) <= 1e-5
+    assert rel(rp["hAB"], o["hAB"]) <= 1e-5 and rel(rp["hBA"], o["hBA"]) <= 1e-5
+    assert rp["ab_a"] == o["ab_a"] and rp["ba_b"] == o["ba_b"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_exact_pruned_near_duplicate(prec):
+    """Every row's subset bound exceeds the largest re-measured minimum (the
+    nearest row of the copy is almost never in the subset), so the second
+    stage searches every row against the whole copy, and the certified
+    refinement then re-measures the rows the expansion cannot resolve."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"exact_hd pruned near-duplicate 20000x64 prec={prec}")
+    A, B, j = perturbed_copy(20000, 64, seed=3)
+    o = oracle.exact_hd(A, B, one_pass=True)
+    assert o["ab_a"] == j
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec)))
+    assert n == 2
+    assert rp["status"] == 0
+    assert rel(rp["H"], o["H"]) <= 1e-4, (rp["H"], o["H"])
+    assert rel(rp["hAB"], o["hAB"]) <= 1e-4 and rel(rp["hBA"], o["hBA"]) <= 1e-4
+    assert rp["ab_a"] == j
+    assert rp["refined"] > 256
+    ru = ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec, prune=False))
+    _same(rp, ru)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_prohd_hd_pruned_candidates(prec):
+    """Candidate distance of Alg. 3 (inner minimum over the other candidate
+    list) on lists of 21 111 and 16 384 rows (the smallest pruned size)."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"prohd_hd pruned candidates t-mixture 60000x50000x128 prec={prec}")
+    A, B = synth.t_mixture(60000, 50000, 128, seed=6)
+    g = np.random.default_rng(7)
+    IA = np.sort(g.choice(60000, 21111, replace=False)).astype(np.int32)
+    IB = np.sort(g.choice(50000, 16384, replace=False)).astype(np.int32)
+    o = oracle.subset_hd(A, B, IA, IB, inner="candidates")
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    dIA, dIB = torch.from_numpy(IA).cuda(), torch.from_numpy(IB).cuda()
+    cnt = torch.tensor([IA.size, IB.size], dtype=torch.int64, device=dev)
+
+    def run(prune):
+        return ph.decode_result(ph.prohd_hd(dA, dB, dIA, cnt[0:1], dIB, cnt[1:2], sync=True,
+                                            prec=prec, prune=prune))
+
+    rp, n = _subset_launches(ph, lambda: run(True))
+    assert n == 2
+    ru = run(False)
+    print(f"[prune] candidates {prec}: H {rp['H']:.9g} (oracle {o['H']:.9g}), refined "
+          f"{rp['refined']} / {ru['refined']}", flush=True)
+    _same(rp, ru)
+    assert rel(rp["H"], o["H"]) <= 1e-5
+    assert rel(rp["hAB"], o["hAB"]) <= 1e-5 and rel(rp["hBA"], o["hBA"]) <= 1e-5
+
+
+def test_prune_size_rule():
+    """One side below 16384 rows: the flag is ignored (no subset launch) and
+    the result is the unpruned one; inner-full mode is never pruned."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd prune size rule 16383 x 30000 x 32")
+    A, B = synth.gauss_outliers(16383, 30000, 32, seed=8)
+    o = oracle.exact_hd(A, B, one_pass=True)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True)))
+    assert n == 0
+    assert rel(rp["H"], o["H"]) <= 1e-5
+    I = torch.arange(16383, dtype=torch.int32, device=dev)
+    J = torch.arange(30000, dtype=torch.int32, device=dev)
+    cnt = torch.tensor([16383, 30000], dtype=torch.int64, device=dev)
+    rf, n = _subset_launches(ph, lambda: ph.decode_result(
+        ph.prohd_hd(dA, dB, I, cnt[0:1], J, cnt[1:2], inner_full=True, sync=True)))
+    assert n == 0
+    assert rel(rf["H"], o["H"]) <= 1e-5
+
+
+def test_prohd_end_to_end_pruned_mix200k():
+    """ProHD (alpha mode) on the 200 000 x 200 000, D = 128 mixture: the
+    pruned and unpruned searches give the same result."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("prohd pruned vs unpruned mix200k seed 0 (alpha 0.1)")
+    A, B, _ = synth.workload("mix200k", seed=0)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    del A, B
+    rp, n = _subset_launches(ph, lambda: ph.prohd(dA, dB, alpha=0.1))
+    assert n == 2, (rp["nA_sel"], rp["nB_sel"])
+    ru = ph.prohd(dA, dB, alpha=0.1, prune=False)
+    _same(rp, ru)

@@ -149,3 +149,37 @@ def test_bound_covers_rounded_copies(uq, name):
     S = np.sqrt(xn.astype(np.float64) * (1.0 + 2.0 * (K + 2) * U_F32))
     U = min_upper(m2, S, K, uq=uq)
     assert np.all(nn <= U * (1 + 1e-12))
+
+
+def test_pruned_rule_returns_the_exact_value():
+    """The pruned search (PROHD_PRUNE): each row's float32 minimum over every
+    16th row of the other set gives, through the same bound U, an upper bound
+    of its minimum over the whole set; the 256 rows with the largest bounds
+    are re-measured exactly, rows whose bound does not exceed the largest
+    re-measured minimum are dropped, and the rest go through the full search
+    and the bound rule.  On clustered data with a few far rows the rule
+    returns the exact directed distance and drops most rows."""
+    g = np.random.default_rng(11)
+    A = (g.standard_normal((6000, 32)) * 0.3 + g.integers(0, 4, size=(6000, 1))).astype(np.float32)
+    A[:20] += 6.0 * g.standard_normal((20, 32)).astype(np.float32)   # far rows: the witnesses
+    B = (g.standard_normal((5000, 32)) * 0.3 + g.integers(0, 4, size=(5000, 1))).astype(np.float32)
+    X = (A - A[0]).astype(np.float32)
+    Y = (B - A[0]).astype(np.float32)
+    K = 32
+    nn, _ = oracle.nn_dist(X, Y)
+    sub = Y[::16]
+    m2s, xn = float32_search(X, sub)
+    S = np.sqrt(xn.astype(np.float64) * (1.0 + 2.0 * (K + 2) * U_F32))
+    Us = min_upper(m2s, S, K)
+    assert np.all(nn <= Us * (1 + 1e-12))              # subset bound >= true minimum
+    order = np.lexsort((np.arange(Us.size), -Us))
+    first = order[:256]
+    h1 = nn[first].max()
+    rest = order[256:]
+    keep = rest[Us[rest] ** 2 > h1 ** 2 * (1 - 2.0 ** -20)]
+    assert keep.size < 0.5 * X.shape[0]                # most rows dropped
+    m2f, _ = float32_search(X[keep], Y)
+    Uf = min_upper(m2f, S[keep], K)
+    second = keep[Uf ** 2 > h1 ** 2 * (1 - 2.0 ** -20)]
+    h = max(h1, nn[second].max() if second.size else 0.0)
+    assert h == nn.max()
