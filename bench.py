@@ -9,13 +9,14 @@ end on each principal component).
 
 One step = the whole ProHD path on the device: prohd_project (sums + float64
 Gram + eigensolve + projections), prohd_select (per-direction extremes,
-union) and prohd_hd (candidate distance with refinement), inputs resident in
-HBM.  ``value`` is ProHD set-pairs/s over the timed steps; the exact
-brute-force distance (exact_hd) of the same pair is timed after it and
-reported in ``exact``.  ``roofline`` is for the dominant kernel (the
-matrix-core distance tile of prohd_hd), timed with HIP events on the stream
-it runs on.  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
-the same workload and scales it to the full pair.
+union) and prohd_hd (candidate distance, pruned search with refinement),
+inputs resident in HBM.  ``value`` is ProHD set-pairs/s over the timed
+steps; the same step with the unpruned search is timed beside it, and the
+exact distance (exact_hd) of the same pair after it (``exact``).
+``roofline`` is for the kernel with the most time per step, timed with HIP
+events on the stream it runs on; ``path_roofline`` in the detail file rates
+the step's other kernels.  ``cpu_baseline`` times the FP64 oracle on a
+bounded sample of the same workload and scales it to the full pair.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -51,20 +52,30 @@ def _source_block(src, start):
     return src[i:j]
 
 
-def kernel_source_hash():
-    """Hash of the dominant kernel's source and of the host code that picks
-    its launch shape: the counter summary is valid while this is unchanged."""
-    with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", "k_hd.hip")) as fh:
+# source blocks (file, first line) of each measured kernel and of the host
+# code that picks its launch shape
+KERNEL_SOURCES = {
+    "hd_tile": ("k_hd.hip", ("void dist_seg(", "int64_t tile_split(", "void tile_schedule(",
+                             "void dist_tile(", "int64_t tile_grid(", "prohd_status launch_tile_k(",
+                             "prohd_status launch_tile(")),
+    "stats_gram": ("k_stats.hip", ("struct GramShape", "void gram_body(", "void gram_partial(",
+                                   "StatsLayout stats_layout(", "prohd_status stats_dp(")),
+}
+
+
+def kernel_source_hash(kernel="hd_tile"):
+    """Hash of a kernel's source and of the host code that picks its launch
+    shape: a counter summary is valid while this is unchanged."""
+    fname, starts = KERNEL_SOURCES[kernel]
+    with open(os.path.join(ROOT, "paper_2511_18207_amd", "csrc", fname)) as fh:
         src = fh.read()
     h = hashlib.sha256()
-    for start in ("void dist_seg(", "int64_t tile_split(", "void tile_schedule(", "void dist_tile(",
-                  "int64_t tile_grid(",
-                  "prohd_status launch_tile_k(", "prohd_status launch_tile("):
+    for start in starts:
         h.update(_source_block(src, start).encode())
     return h.hexdigest()[:16]
 
 
-def load_traffic(name):
+def load_traffic(name, kernel):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", f"{name}.json")
@@ -72,7 +83,7 @@ def load_traffic(name):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -371,7 +382,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--exact-steps", type=int, default=1)
+    ap.add_argument("--exact-steps", type=int, default=3)
     ap.add_argument("--workload", default="heavy2m")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
@@ -435,10 +446,10 @@ def main():
     ws.get(ph.workspace_size(nA, nB, D, m + 1, capA, capB))
     out = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
 
-    def step():
+    def step(prune=True):
         _, pA, pB, _, _ = ph.prohd_project(dA, dB, m, ws=ws, evals=False)
         iA, cA, iB, cB = ph.prohd_select(pA, pB, kA, kB, capA=capA, capB=capB, ws=ws)
-        ph.prohd_hd(dA, dB, iA, cA, iB, cB, capA=capA, capB=capB, ws=ws, out=out)
+        ph.prohd_hd(dA, dB, iA, cA, iB, cB, capA=capA, capB=capB, ws=ws, out=out, prune=prune)
         return iA, cA, iB, cB
 
     for _ in range(args.warmup):
@@ -463,15 +474,33 @@ def main():
     res = ph.decode_result(out)
     kernels = {}
     for name in ("stats_gram", "stats_reduce", "eig", "project_mfma", "select_", "compact_",
-                 "hd_prep", "hd_subset", "hd_tile", "hd_tile_rows", "hd_tile_gx", "hd_keys",
-                 "hd_refine", "hd_uncertain", "hd_finalize"):
+                 "hd_prep", "hd_subset", "hd_gather", "hd_tile", "hd_tile_rows", "hd_tile_gx", "hd_keys",
+                 "hd_refine", "hd_dyn_refine", "hd_uncertain", "hd_finalize"):
         n, tot = ph.profile_read(name)
         if n:
             kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tot / args.steps}
-    tile_n, tile_ms = ph.profile_read("hd_tile")
     ph.profile_reset()
     log(f"ProHD {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), H={res['H']:.6f} "
         f"|I|={res['nA_sel']}/{res['nB_sel']}")
+
+    # the same step with the unpruned distance search (same result), for
+    # comparison
+    uout = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    out_keep, out = out, uout
+    step(prune=False)
+    torch.cuda.synchronize()
+    u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    u0.record()
+    for _ in range(3):
+        step(prune=False)
+    u1.record()
+    torch.cuda.synchronize()
+    out = out_keep
+    ures = ph.decode_result(uout)
+    unpruned = {"ms_per_step": u0.elapsed_time(u1) / 3, "H": ures["H"],
+                "same_result": all(ures[k] == res[k] for k in ("H", "hAB", "hBA", "ab_a", "ab_b",
+                                                               "ba_b", "ba_a"))}
+    log(f"unpruned step {unpruned['ms_per_step']:.3f} ms, same result: {unpruned['same_result']}")
 
     # sampled parity at full size: the witness pair and 32 random candidate
     # rows re-measured in float64 on the host against all of B_sel
@@ -487,50 +516,74 @@ def main():
         "sampled_rows": int(sample.size),
     }
 
-    flops = 2.0 * res["nA_sel"] * res["nB_sel"] * D
-    tile_avg = tile_ms / max(tile_n, 1)
-    achieved = flops / (tile_avg * 1e-3) / 1e12
-    traffic = load_traffic(f"hd_tile_{args.workload}_counters")
-    roof = {"kernel": "hd_tile (prohd_hd candidate distance, float32 v_mfma_f32_32x32x2f32)",
-            "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
-            "per_launch": {"algorithmic_flops": flops, "avg_ms": tile_avg, "launches": tile_n}}
-
-    # the other kernels of the step against their own bounds (algorithmic
-    # work: the symmetric half of the union Gram, one read of both sets plus
-    # the projection writes, one read of the projections for selection)
+    # per-kernel rooflines of the step: algorithmic work per launch (stated
+    # per kernel) over the launch's average time from the HIP events; the
+    # kernel with the most time per step is the headline roofline
     def per_step(name):
         k = kernels.get(name)
         return k["ms_per_step"] if k else None
+
+    def avg_ms(name):
+        k = kernels[name]
+        return k["ms_per_step"] / k["launches_per_step"]
+
+    def entry(kernel, bound, work, ms, peak, unit, launches):
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        ach = work / (ms * 1e-3) / scale
+        key = "algorithmic_flops" if unit == "TFLOP/s" else "algorithmic_bytes"
+        return {"kernel": kernel, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                "frac": ach / peak, "avg_ms": ms, key: work, "launches_per_step": launches}
+
+    nAs, nBs = res["nA_sel"], res["nB_sel"]
+    lev = ph.prune_levels(nA, nB, capA, capB)
     path_roof = {}
-    g_ms = per_step("stats_gram")
-    if g_ms:
-        gf = float(nA + nB) * D * (D + 1)
-        path_roof["gram"] = {"bound": "mfma_fp64", "algorithmic_flops": gf, "ms": g_ms,
-                             "achieved": gf / (g_ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                             "frac": gf / (g_ms * 1e-3) / 1e12 / 78.6}
-    p_ms = per_step("project_mfma")
-    if p_ms:
-        pb = float(nA + nB) * 4 * (D + m + 1)
-        path_roof["project"] = {"bound": "hbm", "algorithmic_bytes": pb, "ms": p_ms,
-                                "achieved": pb / (p_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
-                                "frac": pb / (p_ms * 1e-3) / 1e9 / PEAK_HBM}
-    s_ms = per_step("select_")
-    if s_ms:
+    if "stats_gram" in kernels:
+        # the symmetric half of the union Gram: (nA + nB) D (D + 1) FP64 flops
+        path_roof["stats_gram"] = entry(
+            "gram_partial (covariance of the union, float64 v_mfma_f64_16x16x4f64)", "mfma",
+            float(nA + nB) * D * (D + 1), avg_ms("stats_gram"), 78.6, "TFLOP/s", 1)
+    if lev and "hd_tile_rows" in kernels:
+        # first pruning level: every candidate row against every F-th row of
+        # the other list, 2 D flops per pair, two launches (one per direction)
+        F = 16 ** lev
+        tf = 2.0 * D * (nAs * math.ceil(nBs / F) + nBs * math.ceil(nAs / F)) / 2
+        path_roof["hd_tile"] = entry(
+            f"dist_tile, first pruning level (F = {F}, float32 v_mfma_f32_32x32x2f32)", "mfma", tf,
+            avg_ms("hd_tile_rows"), PEAK_FP32_MFMA, "TFLOP/s", 2)
+    elif not lev and "hd_tile" in kernels:
+        path_roof["hd_tile"] = entry(
+            "dist_tile (candidate distance, float32 v_mfma_f32_32x32x2f32)", "mfma",
+            2.0 * nAs * nBs * D, avg_ms("hd_tile"), PEAK_FP32_MFMA, "TFLOP/s", 1)
+    if "project_mfma" in kernels:
+        # one read of both sets plus the projection writes
+        path_roof["project"] = entry("project_mfma", "hbm", float(nA + nB) * 4 * (D + m + 1),
+                                     avg_ms("project_mfma"), PEAK_HBM, "GB/s", 1)
+    if "select_" in kernels:
         sb = float(nA + nB) * 4 * (m + 1)
-        path_roof["select"] = {"bound": "hbm", "algorithmic_bytes": sb, "ms": s_ms,
-                               "achieved": sb / (s_ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
-                               "frac": sb / (s_ms * 1e-3) / 1e9 / PEAK_HBM}
+        path_roof["select"] = entry("selection passes (whole chain)", "hbm", sb, per_step("select_"),
+                                    PEAK_HBM, "GB/s", kernels["select_"]["launches_per_step"])
+    if "hd_refine" in kernels:
+        # 256 rows per direction against the other list, 2 D FP64 flops per pair
+        rf = 2.0 * D * 256 * (nAs + nBs) / 2
+        path_roof["refine"] = entry("refine_rows (first pass, float64 v_mfma_f64_16x16x4f64)", "mfma",
+                                    rf, avg_ms("hd_refine"), 78.6, "TFLOP/s", 2)
+    dom = max(path_roof, key=lambda k: path_roof[k]["avg_ms"] * path_roof[k]["launches_per_step"])
+    roof = dict(path_roof[dom])
+    roof["name"] = dom
+    roof["traffic"] = load_traffic(f"{dom}_{args.workload}_counters", dom) \
+        if dom in KERNEL_SOURCES else None
+    roof["share_of_step"] = roof["avg_ms"] * roof["launches_per_step"] / ms_step
     peaks = None
     if not args.no_peaks:
         peaks = attainable_peaks(dev)
         log("attainable: " + ", ".join(f"{k} {v:.1f}" for k, v in peaks.items()))
-        if "gram" in path_roof:
-            path_roof["gram"]["frac_of_attainable"] = path_roof["gram"]["achieved"] / peaks["gemm_fp64_tflops"]
-        if "project" in path_roof:
-            hbm = max(peaks["hbm_read_gbs"], peaks["hbm_copy_gbs"])
-            path_roof["project"]["frac_of_attainable"] = path_roof["project"]["achieved"] / hbm
-        roof["frac_of_attainable"] = achieved / peaks["gemm_fp32_tflops"]
+        att = {"stats_gram": peaks["gemm_fp64_tflops"], "refine": peaks["gemm_fp64_tflops"],
+               "hd_tile": peaks["gemm_fp32_tflops"],
+               "project": max(peaks["hbm_read_gbs"], peaks["hbm_copy_gbs"]),
+               "select": max(peaks["hbm_read_gbs"], peaks["hbm_copy_gbs"])}
+        for k, v in path_roof.items():
+            v["frac_of_attainable"] = v["achieved"] / att[k]
+        roof["frac_of_attainable"] = roof["achieved"] / att[dom]
 
     # error certificate (Sec. II-E bounds) of this step's directions and
     # projections, with the inner-minimum-over-the-full-set value as the
@@ -590,7 +643,7 @@ def main():
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             eout = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
-            reps = args.exact_steps if prec == "fp32" else max(1, args.exact_steps)
+            reps = max(1, args.exact_steps)
             e0.record()
             for _ in range(reps):
                 ph.exact_hd(dA, dB, ws=ws, out=eout, prec=prec)
@@ -599,19 +652,32 @@ def main():
             ph.profile_enable(False)
             ems = e0.elapsed_time(e1) / reps
             er = ph.decode_result(eout)
-            en, ems_tile = ph.profile_read("hd_tile")
+            ek = {}
+            for name in ("hd_prep", "hd_quant", "hd_subset", "hd_gather", "hd_tile_rows", "hd_tile_gx", "hd_tile",
+                         "hd_keys", "hd_refine", "hd_dyn_refine", "hd_uncertain", "hd_finalize"):
+                n_, t_ = ph.profile_read(name)
+                if n_:
+                    ek[name] = {"launches": n_ / reps, "ms": t_ / reps}
             ph.profile_reset()
-            eflops = 2.0 * nA * nB * D
             peak = {"fp32": PEAK_FP32_MFMA, "bf16": 2500.0, "fp8": 5000.0}[prec]
-            tile_ms = ems_tile / max(en, 1)
+            # first pruning level: every row of each set against every F-th
+            # row of the other, 2 D flops per pair
+            elev = ph.prune_levels(nA, nB)
+            first = None
+            if elev and "hd_tile_rows" in ek:
+                F = 16 ** elev
+                ff = 2.0 * D * (nA * math.ceil(nB / F) + nB * math.ceil(nA / F))
+                fms = ek["hd_tile_rows"]["ms"]
+                first = {"F": F, "algorithmic_flops": ff, "ms": fms,
+                         "tflops": ff / (fms * 1e-3) / 1e12, "frac": ff / (fms * 1e-3) / 1e12 / peak}
             # sampled parity: the witness row's NN over all of B in float64
             wnn = np.sqrt(((Bd - A[er["ab_a"]].astype(np.float64)) ** 2).sum(1)).min()
             exact[prec] = {"ms": ems, "pairs_per_s": 1e3 / ems, "H": er["H"], "hAB": er["hAB"],
-                           "hBA": er["hBA"], "tile_ms": tile_ms,
-                           "tile_tflops": eflops / (tile_ms * 1e-3) / 1e12,
-                           "tile_frac": eflops / (tile_ms * 1e-3) / 1e12 / peak,
+                           "hBA": er["hBA"], "refined": er["refined"], "prune_levels": elev,
+                           "first_level": first, "kernels": ek,
                            "witness_nn_rel_err": float(abs(wnn - er["hAB"]) / er["hAB"])}
-            log(f"exact[{prec}] {ems:.1f} ms, H={er['H']:.6f}, tile {exact[prec]['tile_tflops']:.1f} TF/s")
+            log(f"exact[{prec}] {ems:.1f} ms, H={er['H']:.6f}, levels {elev}, refined {er['refined']}, "
+                f"kernels " + ", ".join(f"{k} {v['ms']:.2f}" for k, v in ek.items()))
         del Bd
         Hx = exact["fp32"]["H"]
         for prec in ("bf16", "fp8"):
@@ -742,6 +808,7 @@ def main():
                    "nB_sel": res["nB_sel"], "status": res["status"], "refined": res.get("refined")},
         "vs_oracle": vs_oracle,
         "check": check,
+        "unpruned_step": unpruned,
         "certificate": cert,
         "roofline": roof,
         "path_roofline": path_roof,
@@ -767,9 +834,9 @@ def main():
     def r4(x):
         return None if x is None else float(f"{x:.4g}")
 
-    head_roof = {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}
-    head_roof["avg_ms"] = roof["per_launch"]["avg_ms"]
-    head_roof["algorithmic_flops"] = roof["per_launch"]["algorithmic_flops"]
+    head_roof = {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                      "avg_ms", "algorithmic_flops", "algorithmic_bytes",
+                                      "share_of_step") if k in roof}
     line = {
         "metric": METRIC,
         "value": 1e3 / ms_step,
@@ -788,13 +855,14 @@ def main():
         "result": {"H": res["H"], "nA_sel": res["nA_sel"], "nB_sel": res["nB_sel"],
                    "status": res["status"], "refined": res.get("refined")},
         "rel_err_vs_oracle": {k: r4(v) for k, v in vs_oracle.items() if k.endswith("rel_err")},
+        "unpruned_ms_per_step": r4(unpruned["ms_per_step"]),
         "roofline": head_roof,
         "cpu_baseline": None if cpu is None else {
             k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "full_pair_recorded_s")
             if k in cpu},
         "exact": None if exact is None else {
-            p_: {"ms": r4(exact[p_]["ms"]), "pairs_per_s": r4(exact[p_]["pairs_per_s"]),
-                 "tile_frac": r4(exact[p_]["tile_frac"])} for p_ in ("fp32", "bf16", "fp8")},
+            p_: {"ms": r4(exact[p_]["ms"]), "pairs_per_s": r4(exact[p_]["pairs_per_s"])}
+            for p_ in ("fp32", "bf16", "fp8")},
         "forms": {
             "precision": None if exact is None else [
                 [f_["prec"], f_["mode"], f_["alpha"], r4(f_["ms"]), r4(f_["rel_err_vs_exact"])]

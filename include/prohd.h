@@ -74,8 +74,8 @@ enum {
   PROHD_PREC_FP8 = 1u << 3,   /* ... in float8 e4m3 with one power-of-two
                                  scale (float32 accumulation)                */
   PROHD_SYNC = 1u << 4,       /* wait for the stream; return device status  */
-  PROHD_PRUNE = 1u << 5       /* prohd_hd (default mode) / exact_hd: pruned
-                                 distance search, same result (see prohd_hd) */
+  PROHD_PRUNE = 1u << 5       /* prohd_hd / exact_hd: pruned distance
+                                 search, same result (see prohd_hd)          */
 };
 
 /* Result of prohd_hd / exact_hd, written by the device into caller memory. */
@@ -212,17 +212,22 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
  * 1e18); wider sets saturate the search and the witness pair is then not
  * guaranteed.
  *
- * With PROHD_PRUNE (default mode only; ignored with PROHD_INNER_FULL and
- * when either side has fewer than 16384 candidate rows) the search first
- * measures every row against every 16th row of the other side (rows 0, 16,
- * 32, ... of the selected list): the minimum over that subset bounds the
- * row's minimum over the whole side from above.  The 256 rows with the
- * largest such bounds are re-measured in float64 against the whole side; a
- * row whose subset bound does not exceed the largest re-measured minimum
- * cannot hold the directed distance and is dropped.  Every remaining row is
- * searched against the whole side as above (bound, re-measurement).  The
- * result is the same witness and value as without the flag; the work falls
- * from nA nB to about nA nB / 16 when few rows remain (the usual case).
+ * With PROHD_PRUNE (ignored when either side has fewer than 16384 outer
+ * rows) the search runs in levels.  The first measures every outer row
+ * against every F-th row of its inner set (rows 0, F, 2F, ... of the
+ * selected list, or of the whole set in inner-full mode; F = 16^L with L
+ * the largest level count in [1, 4] that leaves at least 16 rows of the
+ * smaller inner set): the minimum over a subset bounds the row's minimum
+ * over the whole inner set from above.  The 256 rows with the largest such
+ * bounds are re-measured in float64 against the whole inner set; a row
+ * whose bound does not exceed the largest re-measured minimum cannot hold
+ * the directed distance and is dropped.  Each further level searches the
+ * remaining rows against a 16 times larger subset (F/16, ..., 16, and last
+ * the whole inner set) and drops rows by the same rule; what the last level
+ * leaves is re-measured as above.  The result is the same witness and value
+ * as without the flag; the work falls from about nA nB to about nA nB / F
+ * when few rows remain (the usual case) and rises by at most 1/15 when no
+ * row can be dropped.
  *
  *   A, B            device float32 point sets (nA x D, nB x D)
  *   idxA, nselA     device: selected rows of A (ascending int32) and their
@@ -238,6 +243,16 @@ prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, in
                       const int32_t* idxB, const int64_t* nselB,
                       int64_t capA, int64_t capB, uint32_t flags,
                       prohd_result* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * prohd_prune_levels -- subset levels L of the pruned search that prohd_hd
+ * (capacities capA / capB, `flags`) runs on sets of nA / nB rows: the first
+ * level searches against every 16^L-th row of the inner set; 0 when the
+ * call is not pruned (no PROHD_PRUNE, or a capacity below 16384).  For
+ * exact_hd pass capA = nA, capB = nB.  Pure host function; 0 for invalid
+ * sizes.
+ */
+int32_t prohd_prune_levels(int64_t nA, int64_t nB, int64_t capA, int64_t capB, uint32_t flags);
 
 /*
  * exact_hd -- exact Hausdorff distance H(A,B) of Eq. (1), both directed

@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     k_rule,
     alpha_k,
     default_m,
+    prune_levels,
     mlp_param_count,
     mlp_workspace_size,
     mlp_init,

@@ -72,6 +72,8 @@ def lib() -> C.CDLL:
     L.prohd_workspace_size.argtypes = [i64, i64, i32, i32, i64, i64]
     L.prohd_default_m.restype = i32
     L.prohd_default_m.argtypes = [i32]
+    L.prohd_prune_levels.restype = i32
+    L.prohd_prune_levels.argtypes = [i64, i64, i64, i64, u32]
     L.prohd_alpha_k.restype = C.c_int
     L.prohd_alpha_k.argtypes = [C.c_double, i64, i32, vp]
     L.prohd_project.restype = C.c_int
@@ -329,6 +331,15 @@ def exact_hd_noalloc(A, B, out=None, nn2=False, prec="fp32"):
     _check(lib().exact_hd_noalloc(A.data_ptr(), nA, B.data_ptr(), nB, D, PREC[prec],
                                   out.data_ptr(), _ptr(nnA), _ptr(nnB), _stream()))
     return (out, nnA, nnB) if nn2 else out
+
+
+def prune_levels(nA, nB, capA=None, capB=None, inner_full=False, prune=True) -> int:
+    """Subset levels of the pruned search for these sizes (prohd_prune_levels;
+    0: not pruned).  The first level's stride is 16 ** levels."""
+    capA = nA if capA is None else capA
+    capB = nB if capB is None else capB
+    flags = (INNER_FULL if inner_full else 0) | (PRUNE if prune else 0)
+    return int(lib().prohd_prune_levels(int(nA), int(nB), int(capA), int(capB), flags))
 
 
 def default_m(D: int) -> int:

@@ -165,13 +165,18 @@ size_t prohd_workspace_size(int64_t nA, int64_t nB, int32_t D, int32_t ndirs, in
   size_t need = project_ws_bytes(nA, nB, D, ndirs);
   need = std::max(need, select_ws_bytes(2 * ndirs, std::max(nA, nB)) +
                             compact_ws_bytes(std::max(nA, nB)) + (size_t)(nA + nB) + 1024);
-  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true, PROHD_PREC_BF16));
+  need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, true, PROHD_PREC_BF16 | PROHD_PRUNE));
   need = std::max(need, hd_ws_bytes(nA, nB, D, capA, capB, false, PROHD_PREC_BF16 | PROHD_PRUNE));
   need = std::max(need, exact_ws_bytes(nA, nB, D, PROHD_PREC_BF16 | PROHD_PRUNE));
   return need;
 }
 
 int32_t prohd_default_m(int32_t D) { return (D < 1 || D > PROHD_MAX_DIM) ? 0 : default_m(D); }
+
+int32_t prohd_prune_levels(int64_t nA, int64_t nB, int64_t capA, int64_t capB, uint32_t flags) {
+  if (nA < 1 || nB < 1 || capA < 1 || capB < 1 || capA > nA || capB > nB) return 0;
+  return hd_prune_levels(capA, capB, nA, nB, flags);
+}
 
 prohd_status prohd_alpha_k(double alpha, int64_t n, int32_t m, int32_t* k) {
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(PROHD_EINVAL, "alpha must be positive and finite");
@@ -357,7 +362,7 @@ AdaptiveLayout adaptive_layout(Arena& ar, int64_t nA, int64_t nB, int32_t D, int
   size_t sub = project_ws_bytes(nA, nB, D, nd);
   sub = std::max(sub, select_ws_bytes(2 * nd, std::max(nA, nB)) + compact_ws_bytes(std::max(nA, nB)) +
                           (size_t)(nA + nB) + 1024);
-  sub = std::max(sub, hd_ws_bytes(nA, nB, D, capA, capB, true, flags));
+  sub = std::max(sub, hd_ws_bytes(nA, nB, D, capA, capB, true, flags | PROHD_PRUNE));
   sub = std::max(sub, cert_ws_bytes(D, nd));
   L.sub_bytes = sub;
   L.sub = ar.take<char>(sub);
@@ -421,7 +426,7 @@ prohd_status prohd_adaptive(const float* A, int64_t nA, const float* B, int64_t 
                         L.idxB, capB, L.cnt + 1, L.sub, L.sub_bytes, s);
     if (!st)
       st = prohd_hd(A, nA, B, nB, D, L.idxA, L.cnt, L.idxB, L.cnt + 1, alpha_cap(a, nA, m),
-                    alpha_cap(a, nB, m), flags | PROHD_INNER_FULL | PROHD_SYNC, out, L.sub,
+                    alpha_cap(a, nB, m), flags | PROHD_INNER_FULL | PROHD_PRUNE | PROHD_SYNC, out, L.sub,
                     L.sub_bytes, s);
     if (st) return st;
     prohd_result r{};

@@ -134,6 +134,7 @@ prohd_status zero_bytes(void* p, size_t bytes, hipStream_t s);
 size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
                    uint32_t flags);
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags);
+int hd_prune_levels(int64_t capA, int64_t capB, int64_t nA, int64_t nB, uint32_t flags);
 
 // Column means of one set (k_mean.hip).
 size_t centroid_ws_bytes(int32_t D);

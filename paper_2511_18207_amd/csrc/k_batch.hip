@@ -34,7 +34,7 @@ using namespace prohd;
 
 namespace {
 
-constexpr int kRefine = 256;   // rows re-measured per direction (as the single-pair path)
+constexpr int kRefine = 256;   // rows re-measured first per direction
 
 struct Tuning {
   int gram_rows = 6144;   // rows per Gram slice

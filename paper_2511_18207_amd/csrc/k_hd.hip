@@ -23,12 +23,22 @@
 //            every compute unit; row minima then meet in a global atomicMin.
 //            Minima are kept as float bit patterns of non-negative values,
 //            whose unsigned order is the float order.
-//   refine   the R rows with the largest approximate minimum (R = 256, or all
-//            rows if fewer) are re-measured against every row of Y in float64
-//            (matrix-core float64 expansion of the exactly converted rows),
-//            keeping the arg-min (smallest index on ties).
+//   bounds   from each row's approximate minimum, certified bounds L <= t <=
+//            U of its true minimum t (the search's worst-case rounding and
+//            quantisation error, see min_upper / min_lower); the directed
+//            distance lies in [max L, max U].
+//   refine   every row whose U reaches max L is re-measured against every
+//            row of Y in float64 (matrix-core float64 expansion of the
+//            exactly converted rows), keeping the arg-min (smallest index on
+//            ties); on ordinary data these are a handful of rows.
 //   finalize the largest refined minimum per direction gives the witness pair,
 //            whose distance is recomputed in float64 from the original rows.
+//   pruning  optionally (PROHD_PRUNE) the search runs in levels against
+//            subsets of Y first (a subset minimum bounds the full minimum
+//            from above), dropping rows whose U falls below max L.
+// The batched form keeps an earlier refinement rule: the 256 rows with the
+// largest U are re-measured first, then every row whose U exceeds the
+// largest re-measured minimum.
 
 #include "batch.h"
 #include "common.h"
@@ -38,7 +48,8 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kRefineRows = 256;   // rows re-measured per direction
+constexpr int kSeedRows = 64;      // rows that seed the lower bound
+constexpr int kShortList = 64;     // lists searched as the inner side of a tile
 constexpr uint32_t kInfBits = 0x7f800000u;
 
 __device__ __forceinline__ uint32_t clamp_bits(float d) {
@@ -348,7 +359,7 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
   for (int v = 0; v < 16; ++v) mine = (c == v) ? rmin[v] : mine;
   if (c < 16) {
     const int64_t r = x0 + 32 * wave + 8 * (c >> 2) + 4 * g + (c & 3);
-    if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
+    if (r < nX && rowmin) atomicMin(&rowmin[r], clamp_bits(mine));
   }
 }
 
@@ -785,7 +796,7 @@ __device__ __forceinline__ void dist_seg_lp(const uint8_t* __restrict__ Xq,
     for (int v = 0; v < 16; ++v) mine = (c == v) ? rmin[x][v] : mine;
     if (c < 16) {
       const int64_t r = x0 + 32 * (XS * wave + x) + 8 * (c >> 2) + 4 * g + (c & 3);
-      if (r < nX) atomicMin(&rowmin[r], clamp_bits(mine));
+      if (r < nX && rowmin) atomicMin(&rowmin[r], clamp_bits(mine));
     }
   }
 }
@@ -966,6 +977,89 @@ __device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
   refine_block<DP>(Xp, cand, *dR, Yp, dev_or(dnY, hnY), ysplit, bx - cb * ysplit, cb, best);
 }
 
+// Few rows (R <= kThinRows): the float64 pass as direct differences on the
+// vector ALUs, each wave measuring whole Y rows of its chunk (lane l holds
+// dimensions l, l + 64, ...; loads of 256 contiguous bytes), the R rows in
+// registers; the matrix-core block would spend 64 rows' work on them.  Same
+// Y chunking, packing (float32 bits of d^2, then the index) and arg-min
+// rule (ties -> smallest index) as refine_block.
+constexpr int kThinRows = 8;
+
+template <int DP>
+__device__ __forceinline__ void refine_thin(const float* __restrict__ Xp,
+                                            const int32_t* __restrict__ cand, int64_t R,
+                                            const float* __restrict__ Yp, int64_t nY, int ysplit,
+                                            int ysi, unsigned long long* __restrict__ best) {
+  constexpr int BNY = 32;
+  constexpr int NJ = DP >= 64 ? DP / 64 : 1;
+  const int64_t chunk = ((nY + ysplit - 1) / ysplit + BNY - 1) / BNY * BNY;
+  const int64_t yb = (int64_t)ysi * chunk;
+  const int64_t ye = min(nY, yb + chunk);
+  if (yb >= ye) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  double xv[kThinRows][NJ];
+#pragma unroll
+  for (int r = 0; r < kThinRows; ++r)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int k = lane + 64 * j;
+      xv[r][j] = (r < R && k < DP) ? (double)Xp[(int64_t)cand[r] * DP + k] : 0.0;
+    }
+  double bv[kThinRows];
+  int bi[kThinRows];
+#pragma unroll
+  for (int r = 0; r < kThinRows; ++r) {
+    bv[r] = __longlong_as_double(0x7ff0000000000000ll);
+    bi[r] = 0x7fffffff;
+  }
+  // UY rows per step, all their loads issued before any use
+  constexpr int UY = 4;
+  for (int64_t y0 = yb + (int64_t)UY * wave; y0 < ye; y0 += (int64_t)UY * nw) {
+    // unconditional loads (rows clamped to the chunk, columns to the row);
+    // rows past the chunk are skipped below, columns past DP zeroed
+    float yf[UY][NJ];
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      const int64_t yy = min(y0 + u, ye - 1);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = lane + 64 * j;
+        const float v = Yp[yy * DP + (k < DP ? k : 0)];
+        yf[u][j] = k < DP ? v : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      if (y0 + u >= ye) break;
+#pragma unroll
+      for (int r = 0; r < kThinRows; ++r) {
+        if (r >= R) break;
+        double sq = 0.0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const double t = xv[r][j] - (double)yf[u][j];
+          sq = fma(t, t, sq);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+        if (sq < bv[r]) {
+          bv[r] = sq;
+          bi[r] = (int)(y0 + u);
+        }
+      }
+    }
+  }
+  if (lane != 0) return;
+#pragma unroll
+  for (int r = 0; r < kThinRows; ++r) {
+    if (r >= R) break;
+    const float f = bv[r] > 0.0 ? (float)bv[r] : 0.f;
+    atomicMin(&best[r], ((unsigned long long)__float_as_uint(f) << 32) | (uint32_t)bi[r]);
+  }
+}
+
 // Second refinement pass: the candidate count is known only on the device,
 // so the grid is (groups) x (ysplit Y chunks) and each work-group walks the
 // candidate blocks cb = group, group + groups, ...; with no candidates (the
@@ -983,19 +1077,9 @@ __device__ __forceinline__ void refine_dyn_body(const float* __restrict__ Xp,
   const int groups = nbx / ysplit;
   const int g = bx / ysplit;
   const int ysi = bx - g * ysplit;
+  if (R <= kThinRows) return;   // refine_rows_thin takes these
   for (int64_t cb = g; cb * 64 < R; cb += groups)
     refine_block<DP>(Xp, cand, R, Yp, nY, ysplit, ysi, cb, best);
-}
-
-template <int DP>
-__global__ __launch_bounds__(256) void refine_rows(const float* __restrict__ Xp,
-                                                   const int32_t* __restrict__ cand,
-                                                   const int64_t* __restrict__ dR,
-                                                   const float* __restrict__ Yp,
-                                                   const int64_t* __restrict__ dnY, int64_t hnY,
-                                                   int ysplit,
-                                                   unsigned long long* __restrict__ best) {
-  refine_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x);
 }
 
 template <int DP>
@@ -1007,6 +1091,21 @@ __global__ __launch_bounds__(256) void refine_rows_dyn(const float* __restrict__
                                                        int ysplit,
                                                        unsigned long long* __restrict__ best) {
   refine_dyn_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x, gridDim.x);
+}
+
+// The same pass for R <= kThinRows rows (a kernel of its own: it needs far
+// fewer registers than the matrix-core block, so more waves hide the
+// memory latency); with more rows it returns at once.
+template <int DP>
+__global__ __launch_bounds__(256) void refine_rows_thin(const float* __restrict__ Xp,
+                                                        const int32_t* __restrict__ cand,
+                                                        const int64_t* __restrict__ dR,
+                                                        const float* __restrict__ Yp,
+                                                        const int64_t* __restrict__ dnY, int64_t hnY,
+                                                        unsigned long long* __restrict__ best) {
+  const int64_t R = *dR;
+  if (R < 1 || R > kThinRows) return;
+  refine_thin<DP>(Xp, cand, R, Yp, dev_or(dnY, hnY), gridDim.x, blockIdx.x, best);
 }
 
 // ------------------------------------------------- certified refinement
@@ -1105,19 +1204,113 @@ __device__ __forceinline__ void bound_keys_body(uint32_t* __restrict__ mins,
   }
 }
 
-__global__ __launch_bounds__(256) void bound_keys(uint32_t* __restrict__ mins,
-                                                  const float* __restrict__ xn,
-                                                  const int64_t* __restrict__ dn, int64_t hn, int DP,
-                                                  int K, int fmt, const uint32_t* __restrict__ maxabs,
-                                                  const int32_t* __restrict__ map) {
-  bound_keys_body(mins, xn, dev_or(dn, hn), DP, K, fmt, maxabs,
-                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, map);
+// Lower bound L of a row's true minimum t' from the search's approximate
+// squared minimum m2: for the true nearest row y', m2 <= d~(x, y') and, with
+// the same error model and symbols as min_upper,
+//   m2 <= ((1 + uq) t' + b)^2 + (r t' + e)^2 + eta,
+// whose right side increases with t' >= 0; L is the root of equality (0
+// when m2 - eta <= b^2 + e^2).  A stored minimum clamped at zero gives 0.
+__device__ __forceinline__ double min_lower(double m2, double S, const SearchModel& q) {
+  const double rc = sqrt(q.c);
+  const double P = 1.0 + q.uq, b = 2.0 * (q.uq * S + q.a);
+  const double r = rc * (1.0 + q.uq), e = rc * (2.0 * (1.0 + q.uq) * S + 2.0 * q.a);
+  const double w = m2 - q.eta - b * b - e * e;   // -(constant term)
+  if (!(w > 0.0)) return 0.0;
+  const double A2 = P * P + r * r, B1 = P * b + r * e;
+  return w / (B1 + sqrt(B1 * B1 + A2 * w));
+}
+
+// Row bounds of one direction's search results: key[i] (bits of the row's
+// approximate squared minimum) -> bits of U^2 rounded up, as bound_keys_body;
+// with `hlow`, the largest L^2 (rounded down) over the rows is merged into
+// *hlow (float bits of non-negative values order as unsigned integers).
+// `zero` (optional) is cleared: the count of the list the next step fills.
+struct BoundJob {
+  uint32_t* key;
+  const float* xn;          // norms of the outer rows (indexed through map)
+  const int32_t* map;       // entry i -> outer row map[i] (or null: i)
+  const int64_t* dn;        // entries (device) or null
+  int64_t hn;               // entries (host bound)
+  uint32_t* hlow;           // or null
+  int64_t* zero;            // or null
+};
+struct BoundPair {
+  BoundJob d[2];
+};
+
+__global__ __launch_bounds__(256) void row_bounds(const BoundPair P, int DP, int K, int fmt,
+                                                  const uint32_t* __restrict__ maxabs) {
+  const BoundJob& j = P.d[blockIdx.y];
+  if (j.zero && blockIdx.x == 0 && threadIdx.x == 0) *j.zero = 0;
+  const SearchModel q = search_model(K, fmt, maxabs);
+  const double grow = 1.0 + 2.0 * (DP + 2) * 0x1p-24;
+  const int64_t n = dev_or(j.dn, j.hn);
+  double lmax = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double m2 = (double)__uint_as_float(j.key[i]);
+    const double S = sqrt((double)j.xn[j.map ? (int64_t)j.map[i] : i] * grow);
+    const double U = min_upper(m2, S, q);
+    j.key[i] = bits_up(U * U * (1.0 + 0x1p-40));
+    if (j.hlow) lmax = fmax(lmax, min_lower(m2, S, q));
+  }
+  if (!j.hlow) return;
+  uint32_t lb = bits_down(lmax * lmax * (1.0 - 0x1p-40));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lb = max(lb, (uint32_t)__shfl_xor(lb, o));
+  if ((threadIdx.x & 63) == 0 && lb > 0) atomicMax(j.hlow, lb);
+}
+
+// Rows that may hold the directed distance: every entry whose key (U^2 of
+// its row) is at least *hlow (the largest certified L^2) is appended to
+// cand (as map[i], or i), with best[pos] = ~0 for the float64 pass that
+// follows.  Order of the list: arbitrary (wave-aggregated atomic appends);
+// everything that reads it is order-independent.  The count must be zero
+// before the launch.  Nothing is appended after a device error.
+struct AppendJob {
+  const uint32_t* key;
+  const int32_t* map;
+  const int64_t* dn;
+  int64_t hn;
+  const uint32_t* hlow;
+  int32_t* cand;
+  int64_t* count;
+  unsigned long long* best;
+};
+struct AppendPair {
+  AppendJob d[2];
+};
+
+__global__ __launch_bounds__(256) void append_uncertain(const AppendPair P,
+                                                        const int32_t* __restrict__ status) {
+  const AppendJob& j = P.d[blockIdx.y];
+  if (*status != ST_OK) return;
+  const int64_t n = dev_or(j.dn, j.hn);
+  const uint32_t tb = *j.hlow;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // every lane of a wave runs the same number of iterations
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+    const int64_t i = base + lane;
+    const bool on = i < n && j.key[i] >= tb;
+    const unsigned long long m = __ballot(on);
+    if (m == 0) continue;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(reinterpret_cast<unsigned long long*>(j.count), (unsigned long long)__popcll(m));
+    at = __shfl(at, 0);
+    if (on) {
+      const int64_t pos = (int64_t)at + __popcll(m & ((1ull << lane) - 1ull));
+      j.cand[pos] = j.map ? j.map[i] : (int32_t)i;
+      j.best[pos] = ~0ull;
+    }
+  }
 }
 
 // Pruned search: the subset of a prepared set made of its rows at positions
 // 0, F, 2F, ... (all of them, float32 and low-precision copies with their
-// norms); *dsub = number of subset rows.  One wave per row.
-constexpr int kPruneStride = 16;       // F
+// norms); *dsub = number of subset rows.  One wave per row.  The search
+// runs levels of strides 16^L, ..., 16, 1 (see prune_levels).
+constexpr int kPruneMaxLevels = 4;       // strides up to 16^4
 constexpr int64_t kPruneMinRows = 16384;   // smaller sets are searched in full
 
 template <int DP, int FMT>
@@ -1128,14 +1321,56 @@ __global__ __launch_bounds__(256) void gather_subset(const float* __restrict__ X
                                                      const int64_t* __restrict__ dn, int64_t hn,
                                                      float* __restrict__ Sp, float* __restrict__ sn,
                                                      uint8_t* __restrict__ Sq, float* __restrict__ sqn,
-                                                     int64_t* __restrict__ dsub) {
+                                                     int64_t* __restrict__ dsub, int F) {
   constexpr int QB = FMT == FMT_F32 ? 0 : qdim(DP, FMT) * (FMT == FMT_BF16 ? 2 : 1);   // bytes per row
   const int64_t n = dev_or(dn, hn);
-  const int64_t ns = (n + kPruneStride - 1) / kPruneStride;
+  const int64_t ns = (n + F - 1) / F;
   if (blockIdx.x == 0 && threadIdx.x == 0) *dsub = ns;
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < ns; i += (int64_t)gridDim.x * 4) {
-    const int64_t src = i * kPruneStride;
+    const int64_t src = i * F;
+    for (int k = lane; k < DP; k += 64) Sp[i * DP + k] = Xp[src * DP + k];
+    if constexpr (QB > 0) {
+      for (int k = 4 * lane; k < QB; k += 256)
+        *reinterpret_cast<uint32_t*>(Sq + i * QB + k) = *reinterpret_cast<const uint32_t*>(Xq + src * QB + k);
+    }
+    if (lane == 0) {
+      sn[i] = xn[src];
+      if constexpr (QB > 0) sqn[i] = xqn[src];
+    }
+  }
+}
+
+// A short list of rows as a set of its own: when the device count of the
+// list `idx` is at most `limit`, rows idx[0..count) of X (float32 and
+// low-precision copies with their norms) are copied to S and *dsmall =
+// count, *dbig = 0; otherwise nothing is copied, *dsmall = 0 and *dbig =
+// count.  The search of a short list runs with the list as the inner side
+// of the tile (column minima), a long one with the listed rows as its outer
+// side; each launch sees an empty side when it is not the one.  One wave
+// per row.
+template <int DP, int FMT>
+__global__ __launch_bounds__(256) void gather_list(const float* __restrict__ Xp,
+                                                   const float* __restrict__ xn,
+                                                   const uint8_t* __restrict__ Xq,
+                                                   const float* __restrict__ xqn,
+                                                   const int32_t* __restrict__ idx,
+                                                   const int64_t* __restrict__ dcount, int limit,
+                                                   float* __restrict__ Sp, float* __restrict__ sn,
+                                                   uint8_t* __restrict__ Sq, float* __restrict__ sqn,
+                                                   int64_t* __restrict__ dsmall,
+                                                   int64_t* __restrict__ dbig) {
+  constexpr int QB = FMT == FMT_F32 ? 0 : qdim(DP, FMT) * (FMT == FMT_BF16 ? 2 : 1);   // bytes per row
+  const int64_t n = *dcount;
+  const bool small = n <= limit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *dsmall = small ? n : 0;
+    if (dbig) *dbig = small ? 0 : n;
+  }
+  if (!small) return;
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    const int64_t src = idx[i];
     for (int k = lane; k < DP; k += 64) Sp[i * DP + k] = Xp[src * DP + k];
     if constexpr (QB > 0) {
       for (int k = 4 * lane; k < QB; k += 256)
@@ -1221,16 +1456,6 @@ __device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
   for (int64_t i = tid; i < base; i += NT) j.best2[i] = ~0ull;
 }
 
-constexpr int kUncT = 1024;
-struct UncPair {
-  UncJob d[2];
-};
-
-__global__ __launch_bounds__(kUncT) void uncertain_rows(const UncPair P) {
-  __shared__ uint32_t lds[kUncT / 64];
-  uncertain_body<kUncT>(P.d[blockIdx.x], lds);
-}
-
 // -------------------------------------------------------------- finalize
 struct DirIn {
   const unsigned long long* best;  // refined minima, first pass
@@ -1279,7 +1504,7 @@ __device__ __forceinline__ void finalize_body(const DirIn& ab, const DirIn& ba, 
   int64_t refined = 0;
   for (int dir = 0; dir < 2; ++dir) {
     const DirIn& d = dir == 0 ? ab : ba;
-    const int64_t R = (st == ST_OK) ? *d.dR : 0;
+    const int64_t R = (st == ST_OK && d.dR) ? *d.dR : 0;
     const int64_t R2 = (st == ST_OK && d.dR2) ? *d.dR2 : 0;
     refined = R + R2 > refined ? R + R2 : refined;
     // largest refined minimum over both passes; ties -> smallest row of the
@@ -1452,27 +1677,6 @@ struct PrepSet {
   float* qn = nullptr;     // squared norms of the dequantised rows
 };
 
-// ysplit so that (x blocks) x (ysplit) fills the compute units in whole waves
-// of work-groups, with at least `min_rows` Y rows per work-group.
-int choose_split(int64_t xblocks, int64_t ny, int64_t min_rows) {
-  const int64_t cus = cu_count();
-  const int64_t max_split = std::max<int64_t>(1, ny / std::max<int64_t>(1, min_rows));
-  int best = 1;
-  double best_eff = -1.0;
-  for (int64_t s = 1; s <= std::min<int64_t>(max_split, 4096); ++s) {
-    const int64_t tot = xblocks * s;
-    const int64_t waves = cdiv(tot, cus);
-    double eff = (double)tot / (double)(waves * cus);
-    // prefer fewer splits unless the fill improves noticeably
-    if (eff > best_eff + 0.02) {
-      best_eff = eff;
-      best = (int)s;
-    }
-    if (tot >= 8 * cus && eff > 0.97) break;
-  }
-  return best;
-}
-
 template <int DP>
 prohd_status launch_prep(const float* X, int D, const int32_t* idx, const int64_t* dn, int64_t cap,
                          const float* S, const int32_t* sidx, const int64_t* sdn, PrepSet o,
@@ -1514,20 +1718,21 @@ template <int DP, bool COLMIN, bool GX>
 prohd_status launch_tile_k(int fmt, PrepSet X, const int32_t* xidx, const int64_t* dnX, int64_t capX,
                            PrepSet Y, const int64_t* dnY, int64_t capY, const uint32_t* maxabs,
                            uint32_t* rowmin, uint32_t* colmin, hipStream_t s) {
-  // one resident work-group per slot, at most one per item the capacities
-  // allow (16 chunks per row tile at most)
+  // one resident work-group per slot, at most one per (row tile, Y block)
+  // the capacities allow: a few rows against a large Y still fill the chip
+  // (the kernel shares the Y blocks of its items out over the work-groups)
   // timing names: "hd_tile*" for every form; "_rows" row minima only,
   // "_gx" listed rows
   const dim3 T(512);
   if (fmt == FMT_F32) {
-    const int64_t items = cdiv(capX, kTileRows) * std::min<int64_t>(16, cdiv(capY, tile_bn<DP>()));
+    const int64_t items = cdiv(capX, kTileRows) * cdiv(capY, tile_bn<DP>());
     auto k = dist_tile<DP, COLMIN, GX>;
     const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
     PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, xidx, dnX, capX,
                  Y.p, Y.n, dnY, capY, rowmin, colmin);
     return PROHD_OK;
   }
-  const int64_t items = cdiv(capX, kLpTileRows) * std::min<int64_t>(16, cdiv(capY, kLpBN));
+  const int64_t items = cdiv(capX, kLpTileRows) * cdiv(capY, kLpBN);
   if (fmt == FMT_BF16) {
     auto k = dist_tile_lp<qdim(DP, FMT_BF16), FMT_BF16, COLMIN, GX>;
     const char* name = GX ? "hd_tile_bf16_gx" : COLMIN ? "hd_tile_bf16" : "hd_tile_bf16_rows";
@@ -1558,46 +1763,37 @@ prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, P
                                          nullptr, s);
 }
 
-template <int DP>
-prohd_status launch_refine(const float* Xp, const int32_t* cand, const int64_t* dR, const float* Yp,
-                           const int64_t* dnY, int64_t capY, unsigned long long* best,
-                           hipStream_t s) {
-  const int64_t cblocks = cdiv(kRefineRows, 64);
-  // at least two work-groups per CU, so that one's staging of Y overlaps the
-  // other's matrix work (each SIMD then holds two waves)
-  const int64_t want = cdiv(2 * (int64_t)cu_count(), cblocks);
-  const int split = (int)std::max<int64_t>(choose_split(cblocks, capY, 256),
-                                           std::min<int64_t>(want, std::max<int64_t>(1, capY / 128)));
-  PROHD_LAUNCH("hd_refine", refine_rows<DP>, dim3((unsigned)(cblocks * split)), dim3(256), 0, s, Xp,
-               cand, dR, Yp, dnY, capY, split, best);
-  return PROHD_OK;
-}
 
-// One directed refinement: top-R of `mins` (n entries), then refine vs Y.
+// Per direction: the seed rows of the pruned search (top-kSeedRows of the
+// first level's bounds) and the list of rows the float64 pass re-measures.
 struct DirWork {
-  uint8_t* flags;   // n bytes
-  int32_t* cand;    // kRefineRows
+  uint8_t* flags;   // n bytes (selection marks)
+  int32_t* cand;    // kSeedRows
   int64_t* count;   // 1
-  unsigned long long* best;  // kRefineRows
-  int32_t* cand2;   // n: rows of the second refinement pass
+  int32_t* cand2;   // n: rows of the float64 pass (or of a pruning level)
   int64_t* count2;  // 1
   unsigned long long* best2;  // n
 };
 
-// Pruned search (per direction): the second-stage row minima over the
-// listed rows, and the rows those leave uncertain.
+// Pruned search (per direction): the row minima of the listed rows at the
+// current level, and two row lists (a level reads one, writes the other).
 struct PruneWork {
-  uint32_t* rowF;   // cap: minima of the rows listed by the first-stage uncertain list
-  int32_t* cand3;   // cap
-  int64_t* count3;  // 1
-  unsigned long long* best3;  // cap
+  uint32_t* rowF;                 // cap
+  int32_t* cand[2];               // cap each
+  int64_t* count[2];              // 1 each
+  unsigned long long* best[2];    // cap each
 };
 
 struct HdLayout {
+  uint32_t* hlow;          // [2] largest certified L^2 per direction (bits)
+  uint32_t* rowS[2];       // minima of the seed rows
+  PrepSet sh[2];           // short lists (seeds, last pruning level) as sets
+  int64_t* dshort;         // [2][2]: rows of sh[d] / of the long-list search
   PrepSet xa, xb;          // prepared candidate (or full) rows
   PrepSet fa, fb;          // full prepared rows (inner-full mode)
-  PrepSet sa, sb;          // subsets of xa / xb (pruned search)
-  int64_t* dsub;           // [2] subset row counts
+  int nlev;                // pruned search: subset levels (0: not pruned)
+  PrepSet sub[2][kPruneMaxLevels];   // per direction, its inner set's subsets
+  int64_t* dsub;           // [2][kPruneMaxLevels] subset row counts
   uint32_t* rowA;          // minima of A-side rows
   uint32_t* rowB;          // minima of B-side rows
   DirWork w[2];
@@ -1617,11 +1813,22 @@ void take_set(Arena& ar, PrepSet& o, int64_t rows, int DP, int fmt) {
   }
 }
 
+// Levels of the pruned search for inner sets of at least n rows: strides
+// 16^nlev, ..., 16 (level j: 16^(nlev - j)), the coarsest subset keeping
+// at least 16 rows, at most kPruneMaxLevels levels.
+int prune_levels(int64_t n) {
+  int lev = 1;
+  while (lev < kPruneMaxLevels && n / ((int64_t)1 << (4 * (lev + 1))) >= 16) ++lev;
+  return lev;
+}
+int64_t prune_stride(int nlev, int j) { return (int64_t)1 << (4 * (nlev - j)); }
+
 HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB, int DP,
                    bool full, int fmt, bool prune) {
   HdLayout L{};
   L.status = ar.take<int32_t>(64);
   L.maxabs = ar.take<uint32_t>(64);
+  L.hlow = ar.take<uint32_t>(64);
   take_set(ar, L.xa, capA, DP, fmt);
   take_set(ar, L.xb, capB, DP, fmt);
   if (full) {
@@ -1630,25 +1837,34 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
   }
   L.rowA = ar.take<uint32_t>(capA);
   L.rowB = ar.take<uint32_t>(capB);
+  for (int d = 0; d < 2; ++d) {   // seeds and short lists (every mode)
+    L.rowS[d] = ar.take<uint32_t>(kSeedRows);
+    take_set(ar, L.sh[d], std::max(kSeedRows, kShortList), DP, fmt);
+  }
+  L.dshort = ar.take<int64_t>(4);
   const int64_t caps[2] = {capA, capB};
   for (int d = 0; d < 2; ++d) {
     L.w[d].flags = ar.take<uint8_t>(caps[d]);
-    L.w[d].cand = ar.take<int32_t>(kRefineRows);
+    L.w[d].cand = ar.take<int32_t>(kSeedRows);
     L.w[d].count = ar.take<int64_t>(1);
-    L.w[d].best = ar.take<unsigned long long>(kRefineRows);
     L.w[d].cand2 = ar.take<int32_t>(caps[d]);
     L.w[d].count2 = ar.take<int64_t>(1);
     L.w[d].best2 = ar.take<unsigned long long>(caps[d]);
   }
+  L.nlev = 0;
   if (prune) {
-    take_set(ar, L.sa, cdiv(capA, kPruneStride), DP, fmt);
-    take_set(ar, L.sb, cdiv(capB, kPruneStride), DP, fmt);
-    L.dsub = ar.take<int64_t>(2);
+    const int64_t ycap[2] = {full ? nB : capB, full ? nA : capA};
+    L.nlev = prune_levels(std::min(ycap[0], ycap[1]));
+    L.dsub = ar.take<int64_t>(2 * kPruneMaxLevels);
     for (int d = 0; d < 2; ++d) {
+      for (int j = 0; j < L.nlev; ++j)
+        take_set(ar, L.sub[d][j], cdiv(ycap[d], prune_stride(L.nlev, j)), DP, fmt);
       L.pw[d].rowF = ar.take<uint32_t>(caps[d]);
-      L.pw[d].cand3 = ar.take<int32_t>(caps[d]);
-      L.pw[d].count3 = ar.take<int64_t>(1);
-      L.pw[d].best3 = ar.take<unsigned long long>(caps[d]);
+      for (int b = 0; b < 2; ++b) {
+        L.pw[d].cand[b] = ar.take<int32_t>(caps[d]);
+        L.pw[d].count[b] = ar.take<int64_t>(1);
+        L.pw[d].best[b] = ar.take<unsigned long long>(caps[d]);
+      }
     }
   }
   const int64_t mx = std::max(capA, capB);
@@ -1657,61 +1873,85 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
   return L;
 }
 
-// Top-R rows of both directions' minima (`mins[d]`, device length dn[d] /
+// Top-k rows of both directions' minima (`mins[d]`, device length dn[d] /
 // host n[d]) -> w[d].cand / w[d].count; one selection launch chain for both.
 // Segments up to this length take the one-launch selection.
 constexpr int64_t kSmallRows = 1 << 18;
 
 prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const int64_t* const dn[2],
-                       DirWork* w, void* sel_ws, size_t sel_bytes, hipStream_t s) {
+                       DirWork* w, void* sel_ws, size_t sel_bytes, hipStream_t s, int k) {
   SelSegment seg[2];
   if (std::max(n[0], n[1]) <= kSmallRows) {
     int32_t* idx[2];
     int64_t* cnt[2];
     for (int d = 0; d < 2; ++d) {
-      seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, kRefineRows, w[d].flags};
+      seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, k, w[d].flags};
       idx[d] = w[d].cand;
       cnt[d] = w[d].count;
     }
-    return select_compact_small(seg, 2, idx, kRefineRows, cnt, s);
+    return select_compact_small(seg, 2, idx, k, cnt, s);
   }
   for (int d = 0; d < 2; ++d) {
     prohd_status st = zero_bytes(w[d].flags, (size_t)n[d], s);
     if (st) return st;
-    seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, kRefineRows, w[d].flags};
+    seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, k, w[d].flags};
   }
   prohd_status st = select_mark(seg, 2, sel_ws, sel_bytes, s);
   if (st) return st;
   for (int d = 0; d < 2; ++d) {
-    st = compact_flags(w[d].flags, n[d], dn[d], w[d].cand, kRefineRows, w[d].count, sel_ws, sel_bytes, s);
+    st = compact_flags(w[d].flags, n[d], dn[d], w[d].cand, k, w[d].count, sel_ws, sel_bytes, s);
     if (st) return st;
   }
   return PROHD_OK;
 }
 
 // Bound keys in place of the row minima (see the certified refinement).
-prohd_status launch_keys(uint32_t* mins, const float* xn, const int64_t* dn, int64_t cap, int DP,
-                         int fmt, const uint32_t* maxabs, hipStream_t s, const int32_t* map = nullptr) {
+// Row bounds of both directions (one launch; grid y = direction).
+prohd_status launch_bounds(const BoundPair& P, int64_t cap, int DP, int fmt, const uint32_t* maxabs,
+                           hipStream_t s) {
   const int K = fmt == FMT_F32 ? DP : qdim(DP, fmt);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 8 * cu_count()));
-  PROHD_LAUNCH("hd_keys", bound_keys, dim3(grid), dim3(256), 0, s, mins, xn, dn, cap, DP, K, fmt,
-               maxabs, map);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 4 * cu_count()));
+  PROHD_LAUNCH("hd_keys", row_bounds, dim3(grid, 2), dim3(256), 0, s, P, DP, K, fmt, maxabs);
+  return PROHD_OK;
+}
+
+// Uncertain rows of both directions (one launch; grid y = direction).
+prohd_status launch_append(const AppendPair& P, int64_t cap, const int32_t* status, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 256), 4 * cu_count()));
+  PROHD_LAUNCH("hd_uncertain", append_uncertain, dim3(grid, 2), dim3(256), 0, s, P, status);
   return PROHD_OK;
 }
 
 template <int DP>
-prohd_status launch_subset(int fmt, PrepSet X, const int64_t* dn, int64_t cap, PrepSet S, int64_t* dsub,
-                           hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cdiv(cap, kPruneStride), 4), 1024));
+prohd_status launch_subset(int fmt, PrepSet X, const int64_t* dn, int64_t cap, int64_t F, PrepSet S,
+                           int64_t* dsub, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cdiv(cap, F), 4), 1024));
   if (fmt == FMT_F32) {
     PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_F32>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub, (int)F);
   } else if (fmt == FMT_BF16) {
     PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_BF16>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub, (int)F);
   } else {
     PROHD_LAUNCH("hd_subset", (gather_subset<DP, FMT_FP8>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub);
+                 X.qn, dn, cap, S.p, S.n, S.q, S.qn, dsub, (int)F);
+  }
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status launch_gather_list(int fmt, PrepSet X, const int32_t* idx, const int64_t* dcount, int limit,
+                                PrepSet S, int64_t* dsmall, int64_t* dbig, hipStream_t s) {
+  const int grid = (int)cdiv(limit, 4);
+  if (fmt == FMT_F32) {
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_F32>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
+  } else if (fmt == FMT_BF16) {
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_BF16>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
+  } else {
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_FP8>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
+                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
   }
   return PROHD_OK;
 }
@@ -1723,8 +1963,11 @@ prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64
                                const float* Yp, const int64_t* dnY, int64_t capY,
                                unsigned long long* best, hipStream_t s) {
   const int split = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 128));
-  PROHD_LAUNCH("hd_refine2", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
+  PROHD_LAUNCH("hd_dyn_refine", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
                dR, Yp, dnY, capY, split, best);
+  const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(8 * (int64_t)cu_count(), capY / 64));
+  PROHD_LAUNCH("hd_dyn_refine", refine_rows_thin<DP>, dim3((unsigned)tsplit), dim3(256), 0, s, Xp, cand,
+               dR, Yp, dnY, capY, best);
   return PROHD_OK;
 }
 
@@ -1734,10 +1977,6 @@ prohd_status init_mins(uint32_t* p, int64_t n, hipStream_t s) {
   return PROHD_OK;
 }
 
-prohd_status init_best(unsigned long long* p, hipStream_t s) {
-  PROHD_LAUNCH("hd_fill", fill_u64, dim3(1), dim3(256), 0, s, p, (int64_t)kRefineRows, ~0ull);
-  return PROHD_OK;
-}
 
 #define PROHD_TRY(x)                 \
   do {                               \
@@ -1758,6 +1997,7 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "hd: workspace too small");
   PROHD_TRY(zero_bytes(L.status, 256, s));
   PROHD_TRY(zero_bytes(L.maxabs, 256, s));
+  PROHD_TRY(zero_bytes(L.hlow, 256, s));
   uint32_t* mx = fmt == FMT_FP8 ? L.maxabs : nullptr;
   // common shift: the first (selected) row of A
   const int32_t* sidx = idxA;
@@ -1777,77 +2017,137 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   }
   PROHD_TRY(init_mins(L.rowA, capA, s));
   PROHD_TRY(init_mins(L.rowB, capB, s));
-  for (int d = 0; d < 2; ++d) PROHD_TRY(init_best(L.w[d].best, s));
   const uint32_t* const mins2[2] = {L.rowA, L.rowB};
   const int64_t caps2[2] = {capA, capB};
   const int64_t* const dns2[2] = {dnA, dnB};
-  PrepSet ysA = full ? L.fa : L.xa;   // the sets the refinement measures against
+  PrepSet ysA = full ? L.fa : L.xa;   // the inner sets of the two directions
   PrepSet ysB = full ? L.fb : L.xb;
   const int64_t* ydnA = full ? nullptr : dnA;
   const int64_t* ydnB = full ? nullptr : dnB;
   const int64_t ycapA = full ? nA : capA;
   const int64_t ycapB = full ? nB : capB;
-  if (prune) {
-    // first stage: every row against a 1 / F subset of the other set; the
-    // subset minimum bounds the row's minimum over the whole set from above
-    PROHD_TRY(launch_subset<DP>(fmt, L.xa, dnA, capA, L.sa, L.dsub, s));
-    PROHD_TRY(launch_subset<DP>(fmt, L.xb, dnB, capB, L.sb, L.dsub + 1, s));
-    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.sb, L.dsub + 1, cdiv(capB, kPruneStride), L.maxabs,
-                              L.rowA, nullptr, s));
-    PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.sa, L.dsub, cdiv(capA, kPruneStride), L.maxabs,
-                              L.rowB, nullptr, s));
-  } else if (!full) {
-    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
-  } else {
-    PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
-    PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.fa, nullptr, nA, L.maxabs, L.rowB, nullptr, s));
-  }
-  if (nn2A) PROHD_HIP(hipMemcpyAsync(nn2A, L.rowA, sizeof(float) * capA, hipMemcpyDeviceToDevice, s));
-  if (nn2B) PROHD_HIP(hipMemcpyAsync(nn2B, L.rowB, sizeof(float) * capB, hipMemcpyDeviceToDevice, s));
-  // rank rows by the upper bound of their true minimum, refine the highest,
-  // then every row the first refinement leaves uncertain
-  PROHD_TRY(launch_keys(L.rowA, L.xa.n, dnA, capA, DP, fmt, L.maxabs, s));
-  PROHD_TRY(launch_keys(L.rowB, L.xb.n, dnB, capB, DP, fmt, L.maxabs, s));
-  PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s));
-  PROHD_TRY(launch_refine<DP>(L.xa.p, L.w[0].cand, L.w[0].count, ysB.p, ydnB, ycapB, L.w[0].best, s));
-  PROHD_TRY(launch_refine<DP>(L.xb.p, L.w[1].cand, L.w[1].count, ysA.p, ydnA, ycapA, L.w[1].best, s));
-  UncPair U{};
-  for (int d = 0; d < 2; ++d)
-    U.d[d] = UncJob{mins2[d], L.w[d].flags, nullptr, dns2[d], caps2[d], L.w[d].best, L.w[d].count, L.status,
-                    L.w[d].cand2, L.w[d].count2, L.w[d].best2};
-  PROHD_LAUNCH("hd_uncertain", uncertain_rows, dim3(2), dim3(kUncT), 0, s, U);
-  // the rows the second refinement measures: with pruning, those of the
-  // first-stage uncertain list (rows whose subset bound exceeds the largest
-  // refined minimum) that a search over the whole other set still leaves
-  // uncertain; otherwise the uncertain list itself
+  // per direction d: outer rows xs[d], inner set ys[d] (A -> B, then B -> A)
+  const PrepSet xs[2] = {L.xa, L.xb};
+  const PrepSet ys[2] = {ysB, ysA};
+  const int64_t* const ydn[2] = {ydnB, ydnA};
+  const int64_t ycap[2] = {ycapB, ycapA};
+  uint32_t* const rmin[2] = {L.rowA, L.rowB};
+  const int64_t cmax = std::max(capA, capB);
+  // The rows the float64 pass re-measures (cand2 / count2 / best2 of each
+  // direction): every row whose certified upper bound U of its true minimum
+  // reaches the largest certified lower bound L of any row's true minimum
+  // (the directed distance lies between the two).
   const int32_t* cand2[2] = {L.w[0].cand2, L.w[1].cand2};
   const int64_t* count2[2] = {L.w[0].count2, L.w[1].count2};
   unsigned long long* best2[2] = {L.w[0].best2, L.w[1].best2};
-  if (prune) {
-    PROHD_TRY(init_mins(L.pw[0].rowF, capA, s));
-    PROHD_TRY(init_mins(L.pw[1].rowF, capB, s));
-    PROHD_TRY(launch_tile<DP>(fmt, L.xa, L.w[0].count2, capA, L.xb, dnB, capB, L.maxabs, L.pw[0].rowF,
-                              nullptr, s, L.w[0].cand2));
-    PROHD_TRY(launch_tile<DP>(fmt, L.xb, L.w[1].count2, capB, L.xa, dnA, capA, L.maxabs, L.pw[1].rowF,
-                              nullptr, s, L.w[1].cand2));
-    PROHD_TRY(launch_keys(L.pw[0].rowF, L.xa.n, L.w[0].count2, capA, DP, fmt, L.maxabs, s, L.w[0].cand2));
-    PROHD_TRY(launch_keys(L.pw[1].rowF, L.xb.n, L.w[1].count2, capB, DP, fmt, L.maxabs, s, L.w[1].cand2));
-    UncPair F{};
+  // Seeds: the kSeedRows rows with the largest upper bounds (keys in
+  // rmin[d]), searched against the whole inner set with the float32 tile
+  // (whose error bound is tight in every precision form), raise the lower
+  // bound; `zero` lists the counts the next append fills.
+  auto seeds = [&](int64_t* const zero[2]) -> prohd_status {
+    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s, kSeedRows));
+    BoundPair sp{};
     for (int d = 0; d < 2; ++d) {
-      F.d[d] = UncJob{L.pw[d].rowF, nullptr, L.w[d].cand2, L.w[d].count2, caps2[d], L.w[d].best,
-                      L.w[d].count, L.status, L.pw[d].cand3, L.pw[d].count3, L.pw[d].best3};
-      cand2[d] = L.pw[d].cand3;
-      count2[d] = L.pw[d].count3;
-      best2[d] = L.pw[d].best3;
+      // the seed rows as the inner side of a tile whose outer side is the
+      // whole inner set: their minima come out as column minima
+      PROHD_TRY(launch_gather_list<DP>(FMT_F32, xs[d], L.w[d].cand, L.w[d].count, kSeedRows, L.sh[d],
+                                       L.dshort + 2 * d, nullptr, s));
+      PROHD_TRY(init_mins(L.rowS[d], kSeedRows, s));
+      PROHD_TRY(launch_tile<DP>(FMT_F32, ys[d], ydn[d], ycap[d], L.sh[d], L.dshort + 2 * d, kSeedRows,
+                                L.maxabs, nullptr, L.rowS[d], s));
+      sp.d[d] = BoundJob{L.rowS[d], xs[d].n, L.w[d].cand, L.w[d].count, kSeedRows, L.hlow + d, zero[d]};
     }
-    PROHD_LAUNCH("hd_uncertain", uncertain_rows, dim3(2), dim3(kUncT), 0, s, F);
+    return launch_bounds(sp, kSeedRows, DP, FMT_F32, L.maxabs, s);
+  };
+  int64_t* const zero2[2] = {L.w[0].count2, L.w[1].count2};
+  if (L.nlev == 0) {
+    // one search of every outer row against its whole inner set
+    if (!full) {
+      PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.xb, dnB, capB, L.maxabs, L.rowA, L.rowB, s));
+    } else {
+      PROHD_TRY(launch_tile<DP>(fmt, L.xa, dnA, capA, L.fb, nullptr, nB, L.maxabs, L.rowA, nullptr, s));
+      PROHD_TRY(launch_tile<DP>(fmt, L.xb, dnB, capB, L.fa, nullptr, nA, L.maxabs, L.rowB, nullptr, s));
+    }
+    if (nn2A) PROHD_HIP(hipMemcpyAsync(nn2A, L.rowA, sizeof(float) * capA, hipMemcpyDeviceToDevice, s));
+    if (nn2B) PROHD_HIP(hipMemcpyAsync(nn2B, L.rowB, sizeof(float) * capB, hipMemcpyDeviceToDevice, s));
+    BoundPair bp{};
+    AppendPair ap{};
+    for (int d = 0; d < 2; ++d) {
+      bp.d[d] = BoundJob{rmin[d], xs[d].n, nullptr, dns2[d], caps2[d], L.hlow + d, L.w[d].count2};
+      ap.d[d] = AppendJob{rmin[d], nullptr, dns2[d], caps2[d], L.hlow + d, L.w[d].cand2, L.w[d].count2,
+                          L.w[d].best2};
+    }
+    PROHD_TRY(launch_bounds(bp, cmax, DP, fmt, L.maxabs, s));
+    // the low-precision forms' lower bounds are loose (e4m3 rounds to 4
+    // significant bits): seeds tighten them
+    if (fmt != FMT_F32) PROHD_TRY(seeds(zero2));
+    PROHD_TRY(launch_append(ap, cmax, L.status, s));
+  } else {
+    // Pruned search.  A row's minimum over any subset of its inner set
+    // bounds its minimum over the whole set from above, so U from a subset
+    // search is still an upper bound; lower bounds come only from searches
+    // over the whole inner set.  Level 1: every row against the coarsest
+    // subset.
+    for (int d = 0; d < 2; ++d)
+      for (int j = 0; j < L.nlev; ++j)
+        PROHD_TRY(launch_subset<DP>(fmt, ys[d], ydn[d], ycap[d], prune_stride(L.nlev, j), L.sub[d][j],
+                                    L.dsub + d * kPruneMaxLevels + j, s));
+    for (int d = 0; d < 2; ++d)
+      PROHD_TRY(launch_tile<DP>(fmt, xs[d], dns2[d], caps2[d], L.sub[d][0], L.dsub + d * kPruneMaxLevels,
+                                cdiv(ycap[d], prune_stride(L.nlev, 0)), L.maxabs, rmin[d], nullptr, s));
+    BoundPair bp{};
+    for (int d = 0; d < 2; ++d)
+      bp.d[d] = BoundJob{rmin[d], xs[d].n, nullptr, dns2[d], caps2[d], nullptr, nullptr};
+    PROHD_TRY(launch_bounds(bp, cmax, DP, fmt, L.maxabs, s));
+    // the seeds give the first lower bound
+    PROHD_TRY(seeds(zero2));
+    AppendPair ap{};
+    for (int d = 0; d < 2; ++d)
+      ap.d[d] = AppendJob{rmin[d], nullptr, dns2[d], caps2[d], L.hlow + d, L.w[d].cand2, L.w[d].count2,
+                          L.w[d].best2};
+    PROHD_TRY(launch_append(ap, cmax, L.status, s));
+    // finer levels: the listed rows against a 16 times larger subset, the
+    // last against the whole inner set (which also raises the lower bound)
+    for (int j = 1; j <= L.nlev; ++j) {
+      const int b = (j - 1) & 1;   // list this level writes
+      const bool last = j == L.nlev;
+      for (int d = 0; d < 2; ++d) {
+        PROHD_TRY(init_mins(L.pw[d].rowF, caps2[d], s));
+        if (!last) {
+          PROHD_TRY(launch_tile<DP>(fmt, xs[d], count2[d], caps2[d], L.sub[d][j],
+                                    L.dsub + d * kPruneMaxLevels + j, cdiv(ycap[d], prune_stride(L.nlev, j)),
+                                    L.maxabs, L.pw[d].rowF, nullptr, s, cand2[d]));
+        } else {
+          // against the whole inner set: a short list as the inner side of
+          // a tile over the inner set, a long one as the outer side
+          int64_t* dsm = L.dshort + 2 * d;
+          PROHD_TRY(launch_gather_list<DP>(fmt, xs[d], cand2[d], count2[d], kShortList, L.sh[d], dsm,
+                                           dsm + 1, s));
+          PROHD_TRY(launch_tile<DP>(fmt, ys[d], ydn[d], ycap[d], L.sh[d], dsm, kShortList, L.maxabs, nullptr,
+                                    L.pw[d].rowF, s));
+          PROHD_TRY(launch_tile<DP>(fmt, xs[d], dsm + 1, caps2[d], ys[d], ydn[d], ycap[d], L.maxabs,
+                                    L.pw[d].rowF, nullptr, s, cand2[d]));
+        }
+      }
+      for (int d = 0; d < 2; ++d) {
+        bp.d[d] = BoundJob{L.pw[d].rowF, xs[d].n, cand2[d], count2[d], caps2[d], last ? L.hlow + d : nullptr,
+                           L.pw[d].count[b]};
+        ap.d[d] = AppendJob{L.pw[d].rowF, cand2[d], count2[d], caps2[d], L.hlow + d, L.pw[d].cand[b],
+                            L.pw[d].count[b], L.pw[d].best[b]};
+      }
+      PROHD_TRY(launch_bounds(bp, cmax, DP, fmt, L.maxabs, s));
+      PROHD_TRY(launch_append(ap, cmax, L.status, s));
+      for (int d = 0; d < 2; ++d) {
+        cand2[d] = L.pw[d].cand[b];
+        count2[d] = L.pw[d].count[b];
+        best2[d] = L.pw[d].best[b];
+      }
+    }
   }
   PROHD_TRY(launch_refine_dyn<DP>(L.xa.p, cand2[0], count2[0], ysB.p, ydnB, ycapB, best2[0], s));
   PROHD_TRY(launch_refine_dyn<DP>(L.xb.p, cand2[1], count2[1], ysA.p, ydnA, ycapA, best2[1], s));
-  const DirIn ab{L.w[0].best, L.w[0].cand, L.w[0].count, best2[0], cand2[0], count2[0],
-                 idxA, full ? nullptr : idxB, A, B};
-  const DirIn ba{L.w[1].best, L.w[1].cand, L.w[1].count, best2[1], cand2[1], count2[1],
-                 idxB, full ? nullptr : idxA, B, A};
+  const DirIn ab{nullptr, nullptr, nullptr, best2[0], cand2[0], count2[0], idxA, full ? nullptr : idxB, A, B};
+  const DirIn ba{nullptr, nullptr, nullptr, best2[1], cand2[1], count2[1], idxB, full ? nullptr : idxA, B, A};
   PROHD_LAUNCH("hd_finalize", finalize, dim3(1), dim3(256), 0, s, ab, ba, D, dnA, capA, dnB, capB,
                L.status, out);
   return PROHD_OK;
@@ -1873,22 +2173,29 @@ int fmt_of(uint32_t flags) {
 
 }  // namespace
 
-// Pruned search when asked for, in candidate / exact mode (not inner-full),
-// on sets large enough to profit (smaller ones: the full search, same value).
-bool use_prune(uint32_t flags, bool full, int64_t capA, int64_t capB) {
-  return (flags & PROHD_PRUNE) && !full && capA >= kPruneMinRows && capB >= kPruneMinRows;
+// Pruned search when asked for, on outer row lists large enough to profit
+// (smaller ones: the unpruned search, same value); the inner sets are at
+// least as large (the other list, or in inner-full mode the whole set).
+bool use_prune(uint32_t flags, int64_t capA, int64_t capB) {
+  return (flags & PROHD_PRUNE) && capA >= kPruneMinRows && capB >= kPruneMinRows;
+}
+
+int hd_prune_levels(int64_t capA, int64_t capB, int64_t nA, int64_t nB, uint32_t flags) {
+  if (!use_prune(flags, capA, capB)) return 0;
+  const bool full = (flags & PROHD_INNER_FULL) != 0;
+  return prune_levels(std::min(full ? nB : capB, full ? nA : capA));
 }
 
 size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB, bool full,
                    uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full, fmt_of(flags), use_prune(flags, full, capA, capB));
+  hd_layout(ar, capA, capB, nA, nB, pad_dim(D), full, fmt_of(flags), use_prune(flags, capA, capB));
   return ar.used + 256;
 }
 
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags) {
   Arena ar(nullptr);
-  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false, fmt_of(flags), use_prune(flags, false, nA, nB));
+  hd_layout(ar, nA, nB, nA, nB, pad_dim(D), false, fmt_of(flags), use_prune(flags, nA, nB));
   return ar.used + 256;
 }
 
@@ -1898,7 +2205,7 @@ prohd_status hd_candidates(const float* A, int64_t nA, const float* B, int64_t n
                            prohd_result* out, void* ws, size_t ws_bytes, hipStream_t s) {
   const bool full = (flags & PROHD_INNER_FULL) != 0;
   const int fmt = fmt_of(flags);
-  const bool prune = use_prune(flags, full, capA, capB);
+  const bool prune = use_prune(flags, capA, capB);
   return by_dp(D, [&](auto dp) {
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, idxA, dnA, capA, idxB, dnB, capB, full, fmt,
                                        prune, out, nullptr, nullptr, ws, ws_bytes, s);
@@ -1910,7 +2217,7 @@ prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, in
                       size_t ws_bytes, hipStream_t s) {
   const int fmt = fmt_of(flags);
   // the per-row minima asked for (nn2) come from the full search
-  const bool prune = !nn2A && !nn2B && use_prune(flags, false, nA, nB);
+  const bool prune = !nn2A && !nn2B && use_prune(flags, nA, nB);
   return by_dp(D, [&](auto dp) {
     return run_hd<decltype(dp)::value>(A, nA, B, nB, D, nullptr, nullptr, nA, nullptr, nullptr, nB,
                                        false, fmt, prune, out, nn2A, nn2B, ws, ws_bytes, s);

@@ -196,3 +196,19 @@ def test_adaptive_validation():
         assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, *args, FAKE, res, FAKE, big, None) == code
     assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, 0.01, 2.0, 0.3, 1e-3, 0, FAKE, None, FAKE, big, None) == 1
     assert L.prohd_adaptive(FAKE, 100, FAKE, 100, 8, 0.01, 2.0, 0.3, 1e-3, 0, FAKE, res, FAKE, 16, None) == 3
+
+
+def test_prune_levels():
+    """Levels of the pruned search (host rule, no device work): strides
+    16^L with the coarsest subset of the smaller inner set at least 16 rows,
+    L in [1, 4]; no pruning below 16384 outer rows or without the flag."""
+    assert ph.prune_levels(16383, 50000) == 0
+    assert ph.prune_levels(16384, 16384) == 2          # 16384 / 256 = 64, / 4096 = 4
+    assert ph.prune_levels(65535, 65535) == 2          # 65535 / 4096 = 15.99
+    assert ph.prune_levels(65536, 65536) == 3
+    assert ph.prune_levels(2_000_000, 2_000_000) == 4  # 2M / 65536 = 30
+    assert ph.prune_levels(2_000_000, 2_000_000, 78_966, 78_462) == 3
+    assert ph.prune_levels(2_000_000, 2_000_000, 78_966, 78_462, inner_full=True) == 4
+    assert ph.prune_levels(2_000_000, 2_000_000, prune=False) == 0
+    assert ph.prune_levels(1 << 31, 1 << 31) == 4
+    assert ph.prune_levels(5, 5, 6, 5) == 0             # invalid capacity

@@ -2,17 +2,18 @@
 against the FP64 oracle and against the unpruned search.
 
 The pruned search (k_hd.hip, pruned search) bounds every outer row's
-minimum from above by its minimum over every 16th inner row, re-measures
+minimum from above by its minimum over every F-th inner row, re-measures
 the 256 rows with the largest bounds against the whole inner set, drops the
 rows whose bound cannot exceed the largest re-measured minimum, and searches
-the rest against the whole inner set.  It must return the unpruned search's
-result exactly (same witness rows, same float64 values) and the oracle's
-value of Eq. (1) / the candidate distance of Alg. 3:
+the rest against 16 times finer subsets level by level, the last level
+against the whole inner set.  It must return the unpruned search's result
+exactly (same witness rows, same float64 values) and the oracle's value of
+Eq. (1) / the candidate distance of Alg. 3:
 
 * exact distance on ragged Gaussian sets with outliers, three precisions;
 * the near-duplicate case (a set against a slightly moved copy of itself),
-  where no row can be dropped and every row goes through the second stage;
-* candidate lists (Alg. 3, default inner mode) of ragged sizes;
+  where no row can be dropped and every row goes through every level;
+* candidate lists (Alg. 3, both inner modes) of ragged sizes;
 * the size rule: below 16384 rows on either side the flag changes nothing.
 """
 
@@ -71,7 +72,7 @@ def test_exact_pruned(gauss40k, prec):
     banner(f"exact_hd pruned gauss 40000x36017x64 prec={prec}")
     dA, dB = to_dev(torch, A), to_dev(torch, B)
     rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec)))
-    assert n == 2                                       # the pruned form ran
+    assert n == 2 * 2                                   # pruned, levels of strides 256 and 16
     ru = ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec, prune=False))
     print(f"[prune] exact {prec}: H {rp['H']:.9g} (unpruned {ru['H']:.9g}, oracle {o['H']:.9g}), "
           f"refined {rp['refined']} / {ru['refined']}", flush=True)
@@ -95,7 +96,7 @@ def test_exact_pruned_near_duplicate(prec):
     assert o["ab_a"] == j
     dA, dB = to_dev(torch, A), to_dev(torch, B)
     rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True, prec=prec)))
-    assert n == 2
+    assert n == 2 * 2
     assert rp["status"] == 0
     assert rel(rp["H"], o["H"]) <= 1e-4, (rp["H"], o["H"])
     assert rel(rp["hAB"], o["hAB"]) <= 1e-4 and rel(rp["hBA"], o["hBA"]) <= 1e-4
@@ -105,30 +106,41 @@ def test_exact_pruned_near_duplicate(prec):
     _same(rp, ru)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_prohd_hd_pruned_candidates(prec):
-    """Candidate distance of Alg. 3 (inner minimum over the other candidate
-    list) on lists of 21 111 and 16 384 rows (the smallest pruned size)."""
-    torch, dev = torch_gpu()
-    import paper_2511_18207_amd as ph
-    banner(f"prohd_hd pruned candidates t-mixture 60000x50000x128 prec={prec}")
+@pytest.fixture(scope="module")
+def tmix60k():
     A, B = synth.t_mixture(60000, 50000, 128, seed=6)
     g = np.random.default_rng(7)
     IA = np.sort(g.choice(60000, 21111, replace=False)).astype(np.int32)
     IB = np.sort(g.choice(50000, 16384, replace=False)).astype(np.int32)
-    o = oracle.subset_hd(A, B, IA, IB, inner="candidates")
+    return A, B, IA, IB, {}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("inner_full", [False, True])
+def test_prohd_hd_pruned_candidates(tmix60k, prec, inner_full):
+    """Candidate distance of Alg. 3 (inner minimum over the other candidate
+    list, or over the whole other set) on lists of 21 111 and 16 384 rows
+    (the smallest pruned size)."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    A, B, IA, IB, memo = tmix60k
+    mode = "full" if inner_full else "candidates"
+    banner(f"prohd_hd pruned t-mixture 60000x50000x128 lists 21111/16384 prec={prec} inner={mode}")
+    if mode not in memo:
+        memo[mode] = oracle.subset_hd(A, B, IA, IB, inner=mode)
+    o = memo[mode]
     dA, dB = to_dev(torch, A), to_dev(torch, B)
     dIA, dIB = torch.from_numpy(IA).cuda(), torch.from_numpy(IB).cuda()
     cnt = torch.tensor([IA.size, IB.size], dtype=torch.int64, device=dev)
 
     def run(prune):
         return ph.decode_result(ph.prohd_hd(dA, dB, dIA, cnt[0:1], dIB, cnt[1:2], sync=True,
-                                            prec=prec, prune=prune))
+                                            prec=prec, prune=prune, inner_full=inner_full))
 
     rp, n = _subset_launches(ph, lambda: run(True))
-    assert n == 2
+    assert n == 2 * 2
     ru = run(False)
-    print(f"[prune] candidates {prec}: H {rp['H']:.9g} (oracle {o['H']:.9g}), refined "
+    print(f"[prune] {mode} {prec}: H {rp['H']:.9g} (oracle {o['H']:.9g}), refined "
           f"{rp['refined']} / {ru['refined']}", flush=True)
     _same(rp, ru)
     assert rel(rp["H"], o["H"]) <= 1e-5
@@ -137,7 +149,7 @@ def test_prohd_hd_pruned_candidates(prec):
 
 def test_prune_size_rule():
     """One side below 16384 rows: the flag is ignored (no subset launch) and
-    the result is the unpruned one; inner-full mode is never pruned."""
+    the result is the unpruned one, in both inner modes."""
     torch, dev = torch_gpu()
     import paper_2511_18207_amd as ph
     banner("exact_hd prune size rule 16383 x 30000 x 32")
@@ -166,6 +178,27 @@ def test_prohd_end_to_end_pruned_mix200k():
     dA, dB = to_dev(torch, A), to_dev(torch, B)
     del A, B
     rp, n = _subset_launches(ph, lambda: ph.prohd(dA, dB, alpha=0.1))
-    assert n == 2, (rp["nA_sel"], rp["nB_sel"])
+    lev = ph.prune_levels(200_000, 200_000, rp["idxA"].numel(), rp["idxB"].numel())
+    assert lev >= 2 and n == 2 * lev, (rp["nA_sel"], rp["nB_sel"], lev, n)
     ru = ph.prohd(dA, dB, alpha=0.1, prune=False)
     _same(rp, ru)
+
+
+def test_exact_pruned_four_levels():
+    """Exact distance at 1 200 000 x 1 100 000, D = 16 (strides 65536, 4096,
+    256, 16): pruned against unpruned field by field, and the witness rows'
+    nearest-neighbour distances re-measured in float64 on the host."""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner("exact_hd pruned gauss 1200000x1100000x16 (four levels)")
+    A, B = synth.gauss_outliers(1_200_000, 1_100_000, 16, seed=9)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    rp, n = _subset_launches(ph, lambda: ph.decode_result(ph.exact_hd(dA, dB, sync=True)))
+    assert n == 2 * 4
+    ru = ph.decode_result(ph.exact_hd(dA, dB, sync=True, prune=False))
+    _same(rp, ru)
+    Bd = B.astype(np.float64)
+    Ad = A.astype(np.float64)
+    nnA = np.sqrt(((Bd - Ad[rp["ab_a"]]) ** 2).sum(1)).min()
+    nnB = np.sqrt(((Ad - Bd[rp["ba_b"]]) ** 2).sum(1)).min()
+    assert rel(rp["hAB"], nnA) <= 1e-12 and rel(rp["hBA"], nnB) <= 1e-12

@@ -1,14 +1,17 @@
 """GPU parity of the certified refinement, through the C ABI, against the
 FP64 oracle.
 
-The distance search ranks rows by an upper bound of their true minimum and
-re-measures, after the first 256, every row the bound cannot rule out
-(k_hd.hip, certified refinement).  The case that needs the second pass: a
-cloud in [0, 100]^64 against a copy of itself moved by 0.01-0.02 per row,
-one row moved by 0.05, so that the expanded form cannot resolve the
+The distance search bounds every row's true minimum from both sides (from
+the search's worst-case error) and re-measures in float64 every row whose
+upper bound reaches the largest lower bound (k_hd.hip, certified
+refinement; the batched form re-measures 256 rows first, then every row the
+bound cannot rule out).  The case that needs many rows re-measured: a cloud
+in [0, 100]^64 against a copy of itself moved by 0.01-0.02 per row, one row
+moved by 0.05, so that the expanded form cannot resolve the
 nearest-neighbour distances in any of the three search precisions.  Exact
 distance (Eq. (1)) and the candidate distance (Alg. 3, both inner modes)
-must match the oracle at 1e-4; on ordinary data the second pass stays empty.
+must match the oracle at 1e-4; on ordinary data a handful of rows is
+re-measured.
 """
 
 import numpy as np
@@ -46,7 +49,7 @@ def test_exact_near_duplicate(prec):
     assert rel(r["H"], o["H"]) <= 1e-4, (r["H"], o["H"])
     assert rel(r["hAB"], o["hAB"]) <= 1e-4 and rel(r["hBA"], o["hBA"]) <= 1e-4
     assert r["ab_a"] == o["ab_a"]
-    assert r["refined"] > 256          # the second pass re-measured the uncertain rows
+    assert r["refined"] > 256          # the uncertain rows were re-measured
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
@@ -69,7 +72,7 @@ def test_prohd_hd_near_duplicate(prec, inner_full):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_second_pass_empty_on_ordinary_data(prec):
+def test_few_rows_refined_on_ordinary_data(prec):
     torch, dev = torch_gpu()
     import paper_2511_18207_amd as ph
     banner(f"exact_hd gauss 5000x5000x32 prec={prec} (refined rows)")
@@ -77,10 +80,11 @@ def test_second_pass_empty_on_ordinary_data(prec):
     o = oracle.exact_hd(A, B)
     r = ph.decode_result(ph.exact_hd(to_dev(torch, A), to_dev(torch, B), sync=True, prec=prec))
     assert r["status"] == 0 and rel(r["H"], o["H"]) <= 1e-5
+    print(f"[refine] gauss 5000 {prec}: refined {r['refined']}", flush=True)
     if prec == "fp32":
-        assert r["refined"] == 256, r["refined"]
+        assert 1 <= r["refined"] <= 16, r["refined"]
     else:
-        assert r["refined"] < 5000, r["refined"]
+        assert 1 <= r["refined"] < 5000, r["refined"]
 
 
 def test_batched_near_duplicate():

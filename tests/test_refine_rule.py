@@ -1,5 +1,11 @@
 """Which rows the distance search must re-measure: a CPU emulation (no GPU).
 
+(The certified lower bound L and the rule "re-measure every row whose U
+reaches the largest L" that the single-pair kernels follow are emulated at
+the end of this file; the earlier rule, 256 rows first and then every row
+whose U exceeds the largest re-measured minimum, is what the batched form
+runs.)
+
 The distance kernels search with the expanded form |x|^2 + |y|^2 - 2 x.y in
 float32 (or on bfloat16 / e4m3 copies), then re-measure rows in float64.
 This test emulates the float32 search with numpy's float32 arithmetic on a
@@ -183,3 +189,79 @@ def test_pruned_rule_returns_the_exact_value():
     second = keep[Uf ** 2 > h1 ** 2 * (1 - 2.0 ** -20)]
     h = max(h1, nn[second].max() if second.size else 0.0)
     assert h == nn.max()
+
+
+
+def min_lower(m2, S, K, uq=0.0, a=0.0, eta=0.0):
+    """Lower bound of a row's true minimum t' from the approximate squared
+    minimum m2 (written out from its derivation, independently of the HIP
+    source): for the true nearest row y', m2 <= d~(x, y') <= ((1 + uq) t' +
+    b)^2 + (r t' + e)^2 + eta with b, r, e as in min_upper; the right side
+    increases with t', so t' is at least the root of equality."""
+    c = 2.0 * (K + 4) * U_F32
+    rc = math.sqrt(c)
+    P, b = 1.0 + uq, 2.0 * (uq * S + a)
+    r, e = rc * (1.0 + uq), rc * (2.0 * (1.0 + uq) * S + 2.0 * a)
+    w = np.asarray(m2 - eta - b * b - e * e, dtype=np.float64)
+    A2, B1 = P * P + r * r, P * b + r * e
+    out = np.zeros_like(w)
+    pos = w > 0
+    out[pos] = w[pos] / (B1[pos] + np.sqrt(B1[pos] ** 2 + A2 * w[pos])) if np.ndim(B1) else \
+        w[pos] / (B1 + np.sqrt(B1 ** 2 + A2 * w[pos]))
+    return out
+
+
+def _bounds(X, Y, uq=0.0, Xq=None, Yq=None):
+    K = X.shape[1]
+    m2, _ = float32_search(X if Xq is None else Xq, Y if Yq is None else Yq)
+    xn = np.einsum("ij,ij->i", X, X, dtype=np.float32)
+    S = np.sqrt(xn.astype(np.float64) * (1.0 + 2.0 * (K + 2) * U_F32))
+    return min_lower(m2, S, K, uq=uq), min_upper(m2, S, K, uq=uq)
+
+
+def test_lower_bound_rule_on_the_moved_copy(case):
+    """L <= true minimum <= U for every row; re-measuring the rows whose U
+    reaches max L returns the exact directed distance (here nearly every row
+    is re-measured: the expansion cannot resolve these distances)."""
+    X, Y, j, m2, xn, nn = case
+    L, U = _bounds(X, Y)
+    assert np.all(L <= nn * (1 + 1e-12)) and np.all(nn <= U * (1 + 1e-12))
+    keep = U >= L.max()
+    assert keep[j]
+    assert nn[keep].max() == nn.max()
+
+
+def test_lower_bound_rule_is_tight_on_ordinary_data():
+    """Clustered data with far rows: the rule keeps a handful of rows, the
+    witness among them."""
+    g = np.random.default_rng(12)
+    A = (g.standard_normal((4000, 32)) * 0.3 + g.integers(0, 4, size=(4000, 1))).astype(np.float32)
+    A[:15] += 5.0 * g.standard_normal((15, 32)).astype(np.float32)
+    B = (g.standard_normal((3500, 32)) * 0.3 + g.integers(0, 4, size=(3500, 1))).astype(np.float32)
+    X = (A - A[0]).astype(np.float32)
+    Y = (B - A[0]).astype(np.float32)
+    nn, _ = oracle.nn_dist(X, Y)
+    L, U = _bounds(X, Y)
+    assert np.all(L <= nn * (1 + 1e-12)) and np.all(nn <= U * (1 + 1e-12))
+    keep = np.flatnonzero(U >= L.max())
+    assert 1 <= keep.size <= 4, keep.size
+    assert nn[keep].max() == nn.max()
+
+
+@pytest.mark.parametrize("uq, bits", [(2.0 ** -8, 8), (2.0 ** -3, 4)])
+def test_lower_bound_covers_rounded_copies(uq, bits):
+    g = np.random.default_rng(13)
+    A = g.standard_normal((1500, 64)).astype(np.float32)
+    B = (g.standard_normal((1200, 64)) * 1.1 + 0.1).astype(np.float32)
+    X = (A - A[0]).astype(np.float32)
+    Y = (B - A[0]).astype(np.float32)
+
+    def rnd(Z):
+        m, e = np.frexp(Z.astype(np.float64))
+        return (np.round(m * 2.0 ** bits) / 2.0 ** bits * 2.0 ** e).astype(np.float32)
+
+    nn, _ = oracle.nn_dist(X, Y)
+    L, U = _bounds(X, Y, uq=uq, Xq=rnd(X), Yq=rnd(Y))
+    assert np.all(L <= nn * (1 + 1e-12)) and np.all(nn <= U * (1 + 1e-12))
+    keep = U >= L.max()
+    assert nn[keep].max() == nn.max()
