@@ -311,6 +311,187 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
                 spart + (size_t)slice * 2 * DP, status);
 }
 
+// D = 256 exactly, single pair: one work-group of 16 waves per row slice
+// forms all 136 upper-triangle 16 x 16 blocks.  Matrix and vector
+// instructions of one SIMD share its issue (a probe loop of independent
+// v_mfma_f64_16x16x4f64 loses about 4.4 cycles per 64 for every vector op
+// beside it), so each value is converted to float64 and shifted once, into
+// an LDS tile, instead of by every wave that uses it (5.5 times over):
+//   per 32-row chunk: the rows arrive by DMA (float32, double-buffered);
+//   after a barrier each thread converts 8 values of one column (its
+//   shift in a register) into the float64 tile; after a second barrier
+//   the waves multiply from it.
+//   waves 0-11   a 32 x 64 unit (block rows 2P, 2P+1 x block columns 4Q'..
+//                4Q'+3, all above the diagonal quads): 8 ops per 4 rows;
+//   waves 12-15  a diagonal 64 x 64 quad (block rows = columns 4Q..4Q+3,
+//                the 10 blocks with I <= J): 10 ops per 4 rows.
+// With waves assigned to SIMDs round-robin each SIMD gets three units and
+// one quad: 3 x 8 + 10 = 34 ops per group of four rows on every SIMD.
+// The converting threads also sum their column (each column is converted
+// by exactly the four threads t = c, c + 256, c + 512, c + 768) and check
+// it for non-finite values at the end (an Inf or NaN anywhere in a column
+// makes its float64 sum non-finite; finite float32 values cannot overflow
+// it).
+constexpr int kG256Units[12][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3},
+                                   {2, 2}, {2, 3}, {3, 2}, {3, 3}, {4, 3}, {5, 3}};
+constexpr int kG256RC = 32;           // rows per chunk
+constexpr int kG256ST = 256 + 16;     // float64 tile row stride (doubles)
+
+// The multiply phase of one wave kind (DG: diagonal quad, else a 32 x 64
+// unit) over one chunk of the float64 tile; accumulators live in the
+// caller's loop (one instantiation per kind, so the register allocation is
+// the larger kind's).
+template <bool DG>
+__device__ __forceinline__ void g256_mul(const double* __restrict__ t64, int ca0, int cb0, int rsub,
+                                         doublex4* acc) {
+  constexpr int NA = DG ? 4 : 2;
+  constexpr int NBV = DG ? 0 : 4;
+  auto rd = [&](int q, double (&a)[NA], double (&b)[NBV > 0 ? NBV : 1]) {
+    const double* rp = t64 + (4 * q + rsub) * kG256ST;
+#pragma unroll
+    for (int x = 0; x < NA; ++x) a[x] = rp[ca0 + 16 * x];
+#pragma unroll
+    for (int y = 0; y < NBV; ++y) b[y] = rp[cb0 + 16 * y];
+  };
+  double a[NA], b[NBV > 0 ? NBV : 1];
+  rd(0, a, b);
+#pragma unroll
+  for (int q = 0; q < kG256RC / 4; ++q) {
+    double na[NA], nb[NBV > 0 ? NBV : 1];
+    if (q + 1 < kG256RC / 4) rd(q + 1, na, nb);
+    if constexpr (DG) {
+      int k = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = x; y < 4; ++y, ++k)
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], a[y], acc[k], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[4 * x + y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[4 * x + y], 0, 0, 0);
+    }
+    if (q + 1 < kG256RC / 4) {
+#pragma unroll
+      for (int x = 0; x < NA; ++x) a[x] = na[x];
+#pragma unroll
+      for (int y = 0; y < NBV; ++y) b[y] = nb[y];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <bool DG>
+__device__ __forceinline__ void g256_slice(const float* __restrict__ X, int64_t r_begin, int64_t r_end,
+                                           int br, int bc, double shv, float (*xs)[kG256RC * 256],
+                                           double* t64, double* __restrict__ gp, double& csum) {
+  constexpr int DP = 256, NB = 16, RC = kG256RC;
+  constexpr int NACC = DG ? 10 : 8;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int col = lane & 15, rsub = lane >> 4;
+  const int ca0 = 16 * br + col, cb0 = 16 * bc + col;
+  const int ccol = tid & 255, crow = tid >> 8;   // conversion: column, first row
+  const int64_t nch = (r_end - r_begin + RC - 1) / RC;
+  // chunk c: 32 rows of 1 KiB, one row per wave instruction (16 bytes per
+  // lane); rows past the slice's end read as zero (buffer range)
+  auto copy = [&](int64_t c) {
+    const int64_t r0 = r_begin + c * RC;
+    const int rows = (int)min<int64_t>(RC, r_end - r0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(X + r0 * DP), 0, rows * DP * 4, 0x00020000);
+    float* dst = xs[c & 1];
+#pragma unroll
+    for (int i = wave; i < RC; i += 16)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (__attribute__((address_space(3))) void*)(dst + 256 * i), 16, (256 * i + 4 * lane) * 4, 0, 0,
+          0);
+  };
+  doublex4 acc[NACC];
+#pragma unroll
+  for (int x = 0; x < NACC; ++x) acc[x] = doublex4{0.0, 0.0, 0.0, 0.0};
+  if (nch > 0) copy(0);
+  for (int64_t c = 0; c < nch; ++c) {
+    // chunk c has landed (every wave waited for its own copies), and every
+    // wave is done with the float64 tile of chunk c - 1
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const float* buf = xs[c & 1];
+    const int lim = (int)min<int64_t>(RC, r_end - (r_begin + c * RC));
+    // convert and shift: rows crow, crow + 4, ... of column ccol; rows past
+    // the slice's end become zero
+#pragma unroll
+    for (int k = 0; k < RC / 4; ++k) {
+      const int r = crow + 4 * k;
+      const double v = (double)buf[r * DP + ccol] - shv;
+      const double z = r < lim ? v : 0.0;
+      csum += z;
+      t64[r * kG256ST + ccol] = z;
+    }
+    __syncthreads();
+    // buffer c & 1 is free: the copy of chunk c + 2 can go in after the
+    // multiply phase of this chunk started; chunk c + 1 goes into the other
+    if (c + 1 < nch) copy(c + 1);
+    g256_mul<DG>(t64, ca0, cb0, rsub, acc);
+  }
+  // element v of lane l of the 16x16x4 f64 result is row l/16 + 4 v, column l%16
+  int k = 0;
+#pragma unroll
+  for (int x = 0; x < (DG ? 4 : 2); ++x)
+#pragma unroll
+    for (int y = DG ? x : 0; y < 4; ++y, ++k) {
+      const int t = cblock_t(br + x, bc + y, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gp[(size_t)t * 256 + (rsub + 4 * v) * 16 + col] = acc[k][v];
+    }
+}
+
+__global__ __launch_bounds__(1024) void gram_partial256(const float* __restrict__ A, int64_t nA,
+                                                        const float* __restrict__ B, int64_t nB,
+                                                        int64_t rows_per_wg, int nslices,
+                                                        double* __restrict__ gpart,
+                                                        double* __restrict__ spart,
+                                                        int32_t* __restrict__ status) {
+  constexpr int DP = 256, NB = 16, T = NB * (NB + 1) / 2;
+  __shared__ __attribute__((aligned(16))) float xs[2][kG256RC * 256];
+  __shared__ __attribute__((aligned(16))) double t64[kG256RC * kG256ST];
+  __shared__ double red[4][256];
+  const int slice = blockIdx.x;
+  if (slice >= nslices) return;
+  const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
+  const bool setA = (int64_t)slice < wgA;
+  const float* X = setA ? A : B;
+  const int64_t nX = setA ? nA : nB;
+  const int64_t r_begin = (setA ? (int64_t)slice : (int64_t)slice - wgA) * rows_per_wg;
+  const int64_t r_end = min(nX, r_begin + rows_per_wg);
+  double* gp = gpart + (size_t)slice * T * 256;
+  double* spo = spart + (size_t)slice * 2 * DP;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool diag = wave >= 12;
+  const int br = diag ? 4 * (wave - 12) : 2 * kG256Units[diag ? 0 : wave][0];
+  const int bc = diag ? br : 4 * kG256Units[diag ? 0 : wave][1];
+  const double shv = (double)A[tid & 255];   // the shift (row 0 of A) at this thread's column
+  double csum = 0.0;
+  if (diag)
+    g256_slice<true>(X, r_begin, r_end, br, bc, shv, xs, t64, gp, csum);
+  else
+    g256_slice<false>(X, r_begin, r_end, br, bc, shv, xs, t64, gp, csum);
+  // column sums: the four threads of a column, in a fixed order
+  red[tid >> 8][tid & 255] = csum;
+  __syncthreads();
+  if (tid < DP) {
+    const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    spo[setA ? tid : DP + tid] = v;
+    spo[setA ? DP + tid : tid] = 0.0;
+    if (!(v - v == 0.0)) atomicOr(status, ST_NONFINITE);
+  }
+}
+
 // Batched: item (slice job, ts); the host orders items so that the TSPLIT
 // shares of a slice are congruent modulo 8 (same XCD) for a grid that is a
 // multiple of 8.
@@ -462,9 +643,14 @@ prohd_status stats_dp(const float* A, int64_t nA, const float* B, int64_t nB, in
   StatsLayout L = stats_layout(ar, nA, nB, DP, cu_count());
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "stats: workspace too small");
   const int nwg = L.nwg;
-  const int grid = (int)(cdiv(nwg, 8) * 8) * GramShape<DP>::TSPLIT;
-  PROHD_LAUNCH("stats_gram", gram_partial<DP>, dim3(grid), dim3(GramShape<DP>::THREADS), 0, s, A,
-               nA, B, nB, D, L.rows, nwg, L.gpart, L.spart, status);
+  if (DP == 256 && D == 256) {
+    PROHD_LAUNCH("stats_gram", gram_partial256, dim3(nwg), dim3(1024), 0, s, A, nA, B, nB, L.rows, nwg,
+                 L.gpart, L.spart, status);
+  } else {
+    const int grid = (int)(cdiv(nwg, 8) * 8) * GramShape<DP>::TSPLIT;
+    PROHD_LAUNCH("stats_gram", gram_partial<DP>, dim3(grid), dim3(GramShape<DP>::THREADS), 0, s, A,
+                 nA, B, nB, D, L.rows, nwg, L.gpart, L.spart, status);
+  }
   const int nb = DP / 16;
   const int T = nb * (nb + 1) / 2;
   const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)T * 256, 256), 256));
