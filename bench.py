@@ -58,7 +58,7 @@ KERNEL_SOURCES = {
     "hd_tile": ("k_hd.hip", ("void dist_seg(", "int64_t tile_split(", "void tile_schedule(",
                              "void dist_tile(", "int64_t tile_grid(", "prohd_status launch_tile_k(",
                              "prohd_status launch_tile(")),
-    "stats_gram": ("k_stats.hip", ("struct GramShape", "void gram_body(", "void gram_partial(",
+    "stats_gram": ("k_stats.hip", ("void g256_mul(", "void g256_slice(", "void gram_partial256(",
                                    "StatsLayout stats_layout(", "prohd_status stats_dp(")),
 }
 
