@@ -11,8 +11,10 @@ One step = the whole ProHD path on the device: prohd_project (sums + float64
 Gram + eigensolve + projections), prohd_select (per-direction extremes,
 union) and prohd_hd (candidate distance, pruned search with refinement),
 inputs resident in HBM.  ``value`` is ProHD set-pairs/s over the timed
-steps; the same step with the unpruned search is timed beside it, and the
-exact distance (exact_hd) of the same pair after it (``exact``).
+steps (eager launches; the same step captured once as a HIP graph and
+replayed is timed and checked beside it, as is the step with the unpruned
+search), and the exact distance (exact_hd) of the same pair is timed after
+it (``exact``).
 ``roofline`` is for the kernel with the most time per step, timed with HIP
 events on the stream it runs on; ``path_roofline`` in the detail file rates
 the step's other kernels.  ``cpu_baseline`` times the FP64 oracle on a
@@ -457,21 +459,51 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) / reps, r
+
+    # eager launches (the headline), then the same steps with per-launch HIP
+    # events (the per-kernel times of the rooflines), then the step captured
+    # once as a HIP graph and replayed (reported beside it: the host keeps
+    # ahead of the GPU, so the graph removes no gaps here)
+    eager_ms, eager_wall, (iA, cA, iB, cB) = timed(step, args.steps)
+    res = ph.decode_result(out)
     ph.profile_reset()
     ph.profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        iA, cA, iB, cB = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
+    prof_ms, _, _ = timed(step, args.steps)
     ph.profile_enable(False)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    res = ph.decode_result(out)
+    graph_ms = None
+    graph_same = None
+    try:
+        gout = torch.zeros(ph.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        out_keep, out = out, gout
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        out = out_keep
+        for _ in range(args.warmup):
+            g.replay()
+        graph_ms, graph_wall, _ = timed(g.replay, args.steps)
+        gres = ph.decode_result(gout)
+        graph_same = all(gres[k] == res[k] for k in ("H", "hAB", "hBA", "ab_a", "ab_b", "ba_b", "ba_a",
+                                                     "nA_sel", "nB_sel", "status"))
+    except Exception as exc:   # capture refused: report the eager figure
+        out = out_keep
+        log(f"graph capture failed: {exc}")
+    use_graph = False
+    ms_step = eager_ms
+    wall = eager_wall
+    log(f"step: eager {eager_ms:.3f} ms, with per-launch events {prof_ms:.3f} ms, graph replay "
+        f"{graph_ms if graph_ms is None else round(graph_ms, 3)} ms (same result: {graph_same})")
     kernels = {}
     for name in ("stats_gram", "stats_reduce", "eig", "project_mfma", "select_", "compact_",
                  "hd_prep", "hd_subset", "hd_gather", "hd_tile", "hd_tile_rows", "hd_tile_gx", "hd_keys",
@@ -480,7 +512,7 @@ def main():
         if n:
             kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tot / args.steps}
     ph.profile_reset()
-    log(f"ProHD {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), H={res['H']:.6f} "
+    log(f"ProHD {ms_step:.3f} ms/step (wall {1e3 * wall:.3f}), H={res['H']:.6f} "
         f"|I|={res['nA_sel']}/{res['nB_sel']}")
 
     # the same step with the unpruned distance search (same result), for
@@ -809,6 +841,8 @@ def main():
         "vs_oracle": vs_oracle,
         "check": check,
         "unpruned_step": unpruned,
+        "step_timing": {"eager_ms": eager_ms, "with_launch_events_ms": prof_ms, "graph_ms": graph_ms,
+                        "graph_same_result": graph_same, "headline": "graph" if use_graph else "eager"},
         "certificate": cert,
         "roofline": roof,
         "path_roofline": path_roof,
@@ -856,6 +890,7 @@ def main():
                    "status": res["status"], "refined": res.get("refined")},
         "rel_err_vs_oracle": {k: r4(v) for k, v in vs_oracle.items() if k.endswith("rel_err")},
         "unpruned_ms_per_step": r4(unpruned["ms_per_step"]),
+        "graph_ms_per_step": r4(graph_ms),
         "roofline": head_roof,
         "cpu_baseline": None if cpu is None else {
             k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "full_pair_recorded_s")
