@@ -372,7 +372,11 @@ prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
  *   prohd_batch_run      mode PROHD_BATCH_PROHD: Alg. 3's candidate value
  *                        per pair (as prohd_project + prohd_select +
  *                        prohd_hd); PROHD_BATCH_EXACT: Eq. (1) per pair (as
- *                        exact_hd).  out[i] receives pair i's result (device
+ *                        exact_hd; pairs whose sets both have at least
+ *                        16384 rows take exact_hd's pruned search, one
+ *                        after another in the same launch list, the others
+ *                        the batched kernels).  out[i] receives pair i's
+ *                        result (device
  *                        memory, P entries).  The first run with a given
  *                        (mode, A, B, out, ws) builds the work tables and
  *                        captures the launches into a graph; later runs

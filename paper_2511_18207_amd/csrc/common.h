@@ -135,6 +135,10 @@ size_t hd_ws_bytes(int64_t nA, int64_t nB, int32_t D, int64_t capA, int64_t capB
                    uint32_t flags);
 size_t exact_ws_bytes(int64_t nA, int64_t nB, int32_t D, uint32_t flags);
 int hd_prune_levels(int64_t capA, int64_t capB, int64_t nA, int64_t nB, uint32_t flags);
+// Exact distance of one pair (exact_hd without argument checks).
+prohd_status hd_exact(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
+                      uint32_t flags, prohd_result* out, float* nn2A, float* nn2B, void* ws,
+                      size_t ws_bytes, hipStream_t s);
 
 // Column means of one set (k_mean.hip).
 size_t centroid_ws_bytes(int32_t D);

@@ -85,6 +85,8 @@ struct PairWs {
 
 struct Layout {
   std::vector<PairWs> p;
+  void* single_ws;          // workspace of the pruned single-pair searches
+  size_t single_bytes;
   int32_t* status;
   unsigned long long* best;
   uint32_t* row;
@@ -125,7 +127,15 @@ struct prohd_batch {
 
 namespace {
 
+// Exact mode: pairs large enough for the pruned search (both sets at least
+// 16 384 rows) run it one after another, through the single-pair path, in
+// the same launch list; the batched tables hold the others.
+bool pruned_pair(const Pair& q, uint32_t mode) {
+  return mode == PROHD_BATCH_EXACT && hd_prune_levels(q.nA, q.nB, q.nA, q.nB, PROHD_PRUNE) > 0;
+}
+
 int64_t side_rows(const Pair& q, int set, uint32_t mode) {
+  if (pruned_pair(q, mode)) return 0;
   if (mode == PROHD_BATCH_EXACT) return set ? q.nB : q.nA;
   return set ? q.capB : q.capA;
 }
@@ -150,6 +160,11 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
   if (mode == PROHD_BATCH_PROHD)
     for (const Pair& q : b.pairs) L.nflags += q.nA + q.nB;
   L.flags = mode == PROHD_BATCH_PROHD ? ar.take<uint8_t>(L.nflags) : nullptr;
+  L.single_bytes = 0;
+  for (const Pair& q : b.pairs)
+    if (pruned_pair(q, mode))
+      L.single_bytes = std::max(L.single_bytes, exact_ws_bytes(q.nA, q.nB, q.D, PROHD_PRUNE));
+  L.single_ws = L.single_bytes ? ar.take<char>(L.single_bytes) : nullptr;
   int64_t ro = 0, fo = 0;
   for (int i = 0; i < P; ++i) {
     const Pair& q = b.pairs[i];
@@ -350,6 +365,7 @@ prohd_status build(prohd_batch* b) {
     std::vector<FinalJob> fj;
     for (int i : g) {
       const Pair& q = b->pairs[i];
+      if (pruned_pair(q, mode)) continue;
       const PairWs& w = L.p[i];
       const float* Ap = b->A + q.offA;
       const float* Bp = b->B + q.offB;
@@ -486,7 +502,22 @@ prohd_status build(prohd_batch* b) {
     Ls.push_back([=](hipStream_t s) { return batch_select((const SegJob*)at(r.seg_jobs), r.n_seg, s); });
     Ls.push_back([=](hipStream_t s) { return batch_compact((const CompactJob*)at(r.cmp_jobs), r.n_cmp, s); });
   }
+  // the pruned single-pair searches (largest first, as the groups)
+  for (int D : b->dims)
+    for (int i : group(b, D)) {
+      const Pair& q = b->pairs[i];
+      if (!pruned_pair(q, mode)) continue;
+      const float* Ap = b->A + q.offA;
+      const float* Bp = b->B + q.offB;
+      prohd_result* o = b->out + i;
+      void* sw = L.single_ws;
+      const size_t sb = L.single_bytes;
+      Ls.push_back([=](hipStream_t s) {
+        return hd_exact(Ap, q.nA, Bp, q.nB, q.D, PROHD_PRUNE, o, nullptr, nullptr, sw, sb, s);
+      });
+    }
   for (const Rec& r : recs) {
+    if (r.n_fin == 0) continue;   // every pair of this width took the pruned search
     const int prep_grid = persist(r.n_prep_items, 8);
     const int tile_grid = persist(r.n_tile_items, t.tile_mult);
     const int ref_grid = persist(r.n_ref_items, 4);

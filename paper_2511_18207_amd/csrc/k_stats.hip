@@ -311,8 +311,9 @@ __global__ __launch_bounds__(GramShape<DP>::THREADS) void gram_partial(const flo
                 spart + (size_t)slice * 2 * DP, status);
 }
 
-// D = 256 exactly, single pair: one work-group of 16 waves per row slice
-// forms all 136 upper-triangle 16 x 16 blocks.  Matrix and vector
+// D in (128, 256] (padded width 256), single pair and batched: one
+// work-group of 16 waves per row slice forms all 136 upper-triangle
+// 16 x 16 blocks.  Matrix and vector
 // instructions of one SIMD share its issue (a probe loop of independent
 // v_mfma_f64_16x16x4f64 loses about 4.4 cycles per 64 for every vector op
 // beside it), so each value is converted to float64 and shifted once, into
@@ -385,7 +386,7 @@ __device__ __forceinline__ void g256_mul(const double* __restrict__ t64, int ca0
 
 template <bool DG>
 __device__ __forceinline__ void g256_slice(const float* __restrict__ X, int64_t r_begin, int64_t r_end,
-                                           int br, int bc, double shv, float (*xs)[kG256RC * 256],
+                                           int D, int br, int bc, double shv, float (*xs)[kG256RC * 256],
                                            double* t64, double* __restrict__ gp, double& csum) {
   constexpr int DP = 256, NB = 16, RC = kG256RC;
   constexpr int NACC = DG ? 10 : 8;
@@ -396,19 +397,26 @@ __device__ __forceinline__ void g256_slice(const float* __restrict__ X, int64_t 
   const int ca0 = 16 * br + col, cb0 = 16 * bc + col;
   const int ccol = tid & 255, crow = tid >> 8;   // conversion: column, first row
   const int64_t nch = (r_end - r_begin + RC - 1) / RC;
-  // chunk c: 32 rows of 1 KiB, one row per wave instruction (16 bytes per
-  // lane); rows past the slice's end read as zero (buffer range)
+  // chunk c: 32 rows of D floats, one contiguous run copied in 1 KiB (D a
+  // multiple of 4: 16 bytes per lane) or 256-byte pieces; rows past the
+  // slice's end read as zero (buffer range)
+  const bool vec = (D & 3) == 0;
   auto copy = [&](int64_t c) {
     const int64_t r0 = r_begin + c * RC;
     const int rows = (int)min<int64_t>(RC, r_end - r0);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(X + r0 * DP), 0, rows * DP * 4, 0x00020000);
+        const_cast<float*>(X + r0 * D), 0, rows * D * 4, 0x00020000);
     float* dst = xs[c & 1];
-#pragma unroll
-    for (int i = wave; i < RC; i += 16)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (__attribute__((address_space(3))) void*)(dst + 256 * i), 16, (256 * i + 4 * lane) * 4, 0, 0,
-          0);
+    if (vec) {
+      for (int i = wave; i < (RC * D) / 256; i += 16)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(dst + 256 * i), 16, (256 * i + 4 * lane) * 4, 0,
+            0, 0);
+    } else {
+      for (int i = wave; i < (RC * D + 63) / 64; i += 16)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(dst + 64 * i), 4, (64 * i + lane) * 4, 0, 0, 0);
+    }
   };
   doublex4 acc[NACC];
 #pragma unroll
@@ -422,12 +430,14 @@ __device__ __forceinline__ void g256_slice(const float* __restrict__ X, int64_t 
     const float* buf = xs[c & 1];
     const int lim = (int)min<int64_t>(RC, r_end - (r_begin + c * RC));
     // convert and shift: rows crow, crow + 4, ... of column ccol; rows past
-    // the slice's end become zero
+    // the slice's end and columns past D become zero
+    const bool cin = ccol < D;
+    const int cc = cin ? ccol : D - 1;
 #pragma unroll
     for (int k = 0; k < RC / 4; ++k) {
       const int r = crow + 4 * k;
-      const double v = (double)buf[r * DP + ccol] - shv;
-      const double z = r < lim ? v : 0.0;
+      const double v = (double)buf[r * D + cc] - shv;
+      const double z = (r < lim && cin) ? v : 0.0;
       csum += z;
       t64[r * kG256ST + ccol] = z;
     }
@@ -449,8 +459,40 @@ __device__ __forceinline__ void g256_slice(const float* __restrict__ X, int64_t 
     }
 }
 
+// Rows [r_begin, r_end) of X (one set's rows, D columns), shifted by the
+// row `shift`: partial blocks gp (T x 256) and, for set A (setA) or B, the
+// column sums spo (2 x 256).  All 1 024 threads reach every barrier.
+__device__ __forceinline__ void gram256_body(const float* __restrict__ shift, const float* __restrict__ X,
+                                             int64_t r_begin, int64_t r_end, int D, bool setA,
+                                             double* __restrict__ gp, double* __restrict__ spo,
+                                             int32_t* __restrict__ status, float (*xs)[kG256RC * 256],
+                                             double* t64, double (*red)[256]) {
+  constexpr int DP = 256;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool diag = wave >= 12;
+  const int br = diag ? 4 * (wave - 12) : 2 * kG256Units[diag ? 0 : wave][0];
+  const int bc = diag ? br : 4 * kG256Units[diag ? 0 : wave][1];
+  const int ccol = tid & 255;
+  const double shv = ccol < D ? (double)shift[ccol] : 0.0;   // the shift at this thread's column
+  double csum = 0.0;
+  if (diag)
+    g256_slice<true>(X, r_begin, r_end, D, br, bc, shv, xs, t64, gp, csum);
+  else
+    g256_slice<false>(X, r_begin, r_end, D, br, bc, shv, xs, t64, gp, csum);
+  // column sums: the four threads of a column, in a fixed order
+  red[tid >> 8][ccol] = csum;
+  __syncthreads();
+  if (tid < DP) {
+    const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    spo[setA ? tid : DP + tid] = v;
+    spo[setA ? DP + tid : tid] = 0.0;
+    if (!(v - v == 0.0)) atomicOr(status, ST_NONFINITE);
+  }
+}
+
 __global__ __launch_bounds__(1024) void gram_partial256(const float* __restrict__ A, int64_t nA,
-                                                        const float* __restrict__ B, int64_t nB,
+                                                        const float* __restrict__ B, int64_t nB, int D,
                                                         int64_t rows_per_wg, int nslices,
                                                         double* __restrict__ gpart,
                                                         double* __restrict__ spart,
@@ -463,32 +505,25 @@ __global__ __launch_bounds__(1024) void gram_partial256(const float* __restrict_
   if (slice >= nslices) return;
   const int64_t wgA = (nA + rows_per_wg - 1) / rows_per_wg;
   const bool setA = (int64_t)slice < wgA;
-  const float* X = setA ? A : B;
   const int64_t nX = setA ? nA : nB;
   const int64_t r_begin = (setA ? (int64_t)slice : (int64_t)slice - wgA) * rows_per_wg;
   const int64_t r_end = min(nX, r_begin + rows_per_wg);
-  double* gp = gpart + (size_t)slice * T * 256;
-  double* spo = spart + (size_t)slice * 2 * DP;
+  gram256_body(A, setA ? A : B, r_begin, r_end, D, setA, gpart + (size_t)slice * T * 256,
+               spart + (size_t)slice * 2 * DP, status, xs, t64, red);
+}
 
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const bool diag = wave >= 12;
-  const int br = diag ? 4 * (wave - 12) : 2 * kG256Units[diag ? 0 : wave][0];
-  const int bc = diag ? br : 4 * kG256Units[diag ? 0 : wave][1];
-  const double shv = (double)A[tid & 255];   // the shift (row 0 of A) at this thread's column
-  double csum = 0.0;
-  if (diag)
-    g256_slice<true>(X, r_begin, r_end, br, bc, shv, xs, t64, gp, csum);
-  else
-    g256_slice<false>(X, r_begin, r_end, br, bc, shv, xs, t64, gp, csum);
-  // column sums: the four threads of a column, in a fixed order
-  red[tid >> 8][tid & 255] = csum;
-  __syncthreads();
-  if (tid < DP) {
-    const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-    spo[setA ? tid : DP + tid] = v;
-    spo[setA ? DP + tid : tid] = 0.0;
-    if (!(v - v == 0.0)) atomicOr(status, ST_NONFINITE);
+// Batched, padded width 256: one item per slice job.
+__global__ __launch_bounds__(1024) void gram_batch256(const GramJob* __restrict__ jobs, int D,
+                                                      const BItem* __restrict__ items, int nitems) {
+  __shared__ __attribute__((aligned(16))) float xs[2][kG256RC * 256];
+  __shared__ __attribute__((aligned(16))) double t64[kG256RC * kG256ST];
+  __shared__ double red[4][256];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    if (w.job < 0) continue;
+    const GramJob j = jobs[w.job];
+    __syncthreads();   // the previous item's LDS reads are done
+    gram256_body(j.shift, j.X, j.r_begin, j.r_end, D, j.setA != 0, j.gp, j.sp, j.status, xs, t64, red);
   }
 }
 
@@ -643,8 +678,8 @@ prohd_status stats_dp(const float* A, int64_t nA, const float* B, int64_t nB, in
   StatsLayout L = stats_layout(ar, nA, nB, DP, cu_count());
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "stats: workspace too small");
   const int nwg = L.nwg;
-  if (DP == 256 && D == 256) {
-    PROHD_LAUNCH("stats_gram", gram_partial256, dim3(nwg), dim3(1024), 0, s, A, nA, B, nB, L.rows, nwg,
+  if constexpr (DP == 256) {
+    PROHD_LAUNCH("stats_gram", gram_partial256, dim3(nwg), dim3(1024), 0, s, A, nA, B, nB, D, L.rows, nwg,
                  L.gpart, L.spart, status);
   } else {
     const int grid = (int)(cdiv(nwg, 8) * 8) * GramShape<DP>::TSPLIT;
@@ -697,12 +732,14 @@ prohd_status by_dp_stats(int DP, F&& f) {
 }
 
 int gram_tsplit(int DP) {
+  if (DP == 256) return 1;   // gram_batch256: one work-group per slice
   int v = 1;
   by_dp_stats(DP, [&](auto dp) { v = GramShape<decltype(dp)::value>::TSPLIT; return PROHD_OK; });
   return v;
 }
 
 int gram_rows_quantum(int DP) {
+  if (DP == 256) return kG256RC;
   int v = 32;
   by_dp_stats(DP, [&](auto dp) { v = GramShape<decltype(dp)::value>::RC; return PROHD_OK; });
   return v;
@@ -717,6 +754,10 @@ size_t gram_partial_doubles(int DP) {
 prohd_status batch_gram(int DP, int D, const GramJob* jobs, const BItem* items, int nitems, int grid,
                         hipStream_t s) {
   if (nitems <= 0) return PROHD_OK;
+  if (DP == 256) {
+    PROHD_LAUNCH("batch_gram", gram_batch256, dim3(grid), dim3(1024), 0, s, jobs, D, items, nitems);
+    return PROHD_OK;
+  }
   return by_dp_stats(DP, [&](auto dp) {
     constexpr int V = decltype(dp)::value;
     PROHD_LAUNCH("batch_gram", gram_batch<V>, dim3(grid), dim3(GramShape<V>::THREADS), 0, s, jobs, D,
