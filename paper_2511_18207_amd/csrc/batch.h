@@ -67,11 +67,14 @@ struct KeyJob {
   const int64_t* dn;
   int64_t hn;
   int32_t nbx;          // blocks of this job (rows are strided over them)
+  uint32_t* hlow;       // largest certified L^2 of the rows (float bits, atomicMax), or null
 };
 
-// rows of one direction left uncertain by the first refinement (one
-// work-group each): key above the largest refined squared minimum, not
-// refined yet -> cand2 (ascending), count2, best2 initialised
+// rows of one direction that may hold the directed distance (one
+// work-group each) -> cand2 (ascending), count2, best2 initialised: with
+// `hlow`, every row whose key reaches it (the largest certified lower
+// bound); else every row whose key exceeds the largest first-pass minimum
+// and is not one of the first pass's rows
 struct UncJob {
   const uint32_t* key;               // bound keys (float bits)
   const uint8_t* top;                // rows of the first refinement (flag 1), or null
@@ -84,6 +87,7 @@ struct UncJob {
   int32_t* cand2;                    // capacity hn
   int64_t* count2;
   unsigned long long* best2;         // capacity hn
+  const uint32_t* hlow;              // or null
 };
 
 // one directed half of the final witness search
@@ -174,8 +178,6 @@ prohd_status batch_prep(int DP, int D, const PrepJob* jobs, const BItem* items, 
                         hipStream_t s);
 prohd_status batch_tile(int DP, const TileJob* jobs, const BItem* items, int nitems, int grid,
                         hipStream_t s);
-prohd_status batch_refine(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
-                          hipStream_t s);
 prohd_status batch_keys(int DP, const KeyJob* jobs, const BItem* items, int nitems, int grid,
                         hipStream_t s);
 prohd_status batch_uncertain(const UncJob* jobs, int njobs, hipStream_t s);

@@ -34,7 +34,7 @@ using namespace prohd;
 
 namespace {
 
-constexpr int kRefine = 256;   // rows re-measured first per direction
+
 
 struct Tuning {
   int gram_rows = 6144;   // rows per Gram slice
@@ -59,14 +59,11 @@ struct Pair {
 struct PairWs {
   int32_t* status;
   int64_t* cnt;       // [2] selected counts (ProHD)
-  int64_t* ccnt;      // [2] refined-candidate counts
-  unsigned long long* best[2];
-  int32_t* cand[2];
-  int64_t* ccnt2;     // [2] second-pass counts
-  unsigned long long* best2[2];   // second refinement pass (one entry per row)
+  uint32_t* hlow;     // [2] largest certified lower bound (squared, float bits) per direction
+  int64_t* ccnt2;     // [2] counts of the rows the float64 pass re-measures
+  unsigned long long* best2[2];   // float64 pass (one entry per row)
   int32_t* cand2[2];
   uint32_t* row[2];   // row minima (then bound keys) of the A side / B side rows
-  uint8_t* top[2];    // top-row flags
   float* xp[2];       // prepared rows (DP wide)
   float* xn[2];
   // ProHD only
@@ -88,10 +85,9 @@ struct Layout {
   void* single_ws;          // workspace of the pruned single-pair searches
   size_t single_bytes;
   int32_t* status;
-  unsigned long long* best;
+  uint32_t* hlow;
   uint32_t* row;
   int64_t nrow;
-  uint8_t* top;
   uint8_t* flags;
   int64_t nflags;
 };
@@ -146,13 +142,10 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
   L.p.resize(P);
   L.status = ar.take<int32_t>(P);
   int64_t* cnt = ar.take<int64_t>(2 * (size_t)P);
-  int64_t* ccnt = ar.take<int64_t>(2 * (size_t)P);
-  L.best = ar.take<unsigned long long>(2 * (size_t)P * kRefine);
-  int32_t* cand = ar.take<int32_t>(2 * (size_t)P * kRefine);
+  L.hlow = ar.take<uint32_t>(2 * (size_t)P);
   L.nrow = 0;
   for (const Pair& q : b.pairs) L.nrow += side_rows(q, 0, mode) + side_rows(q, 1, mode);
   L.row = ar.take<uint32_t>(L.nrow);
-  L.top = ar.take<uint8_t>(L.nrow);
   int64_t* ccnt2 = ar.take<int64_t>(2 * (size_t)P);
   int32_t* cand2 = ar.take<int32_t>(L.nrow);
   unsigned long long* best2 = ar.take<unsigned long long>(L.nrow);
@@ -171,16 +164,13 @@ Layout make_layout(Arena& ar, const prohd_batch& b, uint32_t mode, const Tuning&
     PairWs& w = L.p[i];
     w.status = L.status + i;
     w.cnt = cnt + 2 * i;
-    w.ccnt = ccnt + 2 * i;
+    w.hlow = L.hlow + 2 * i;
     w.ccnt2 = ccnt2 + 2 * i;
     for (int s = 0; s < 2; ++s) {
       const int64_t r = side_rows(q, s, mode);
-      w.best[s] = L.best + ((size_t)2 * i + s) * kRefine;
-      w.cand[s] = cand + ((size_t)2 * i + s) * kRefine;
       w.cand2[s] = cand2 + ro;
       w.best2[s] = best2 + ro;
       w.row[s] = L.row + ro;
-      w.top[s] = L.top + ro;
       ro += r;
       w.xp[s] = ar.take<float>((size_t)r * q.DP);
       w.xn[s] = ar.take<float>(r);
@@ -279,9 +269,9 @@ prohd_status build(prohd_batch* b) {
     int D, DP, m;
     size_t gram_jobs, gram_items, red_jobs, eig_jobs, proj_jobs, seg_jobs, cmp_jobs;
     int n_gram_items, n_red, n_eig, n_proj, n_seg, n_cmp;
-    size_t prep_jobs, prep_items, tile_jobs, tile_items, key_jobs, key_items, top_jobs, topc_jobs,
-        ref_jobs, ref_items, unc_jobs, ref2_jobs, ref2_items, fin_jobs;
-    int n_prep_items, n_tile_items, n_key_items, n_top, n_topc, n_ref_items, n_unc, n_ref2_items,
+    size_t prep_jobs, prep_items, tile_jobs, tile_items, key_jobs, key_items, unc_jobs, ref2_jobs,
+        ref2_items, fin_jobs;
+    int n_prep_items, n_tile_items, n_key_items, n_unc, n_ref2_items,
         n_fin;
   };
   std::vector<Rec> recs;
@@ -353,10 +343,6 @@ prohd_status build(prohd_batch* b) {
     std::vector<BItem> pri;
     std::vector<TileJob> tlj;
     std::vector<BItem> tli;
-    std::vector<SegJob> tpj;
-    std::vector<CompactJob> tcj;
-    std::vector<RefineJob> rfj;
-    std::vector<BItem> rfi;
     std::vector<KeyJob> kyj;
     std::vector<BItem> kyi;
     std::vector<UncJob> ucj;
@@ -388,32 +374,26 @@ prohd_status build(prohd_batch* b) {
       for (int64_t x = 0; x < nbt; ++x) tli.push_back(BItem{job, (int)x});
       for (int s = 0; s < 2; ++s) {
         const int64_t r = s ? rB : rA;
-        tpj.push_back(SegJob{reinterpret_cast<const float*>(w.row[s]), r, s ? dB : dA, 0, kRefine,
-                             w.top[s]});
-        tcj.push_back(CompactJob{w.top[s], r, s ? dB : dA, w.cand[s], kRefine, w.ccnt + s});
         const int64_t ry = s ? rA : rB;
         const int ys = (int)std::max<int64_t>(1, cdiv(ry, t.refine_yc));
-        const int rjob = (int)rfj.size();
-        rfj.push_back(RefineJob{w.xp[s], w.cand[s], w.ccnt + s, w.xp[1 - s], s ? dA : dB, ry, ys,
-                                w.best[s]});
-        for (int x = 0; x < (kRefine / 64) * ys; ++x) rfi.push_back(BItem{rjob, x});
-        // bound keys in place of the row minima, then the rows the first
-        // refinement leaves uncertain and their refinement
+        // upper bounds as keys in place of the row minima and the largest
+        // lower bound, then every row whose upper bound reaches it, and
+        // their float64 re-measurement
         const int kbx = (int)std::max<int64_t>(1, cdiv(r, 256));
         const int kjob = (int)kyj.size();
-        kyj.push_back(KeyJob{w.row[s], w.xn[s], s ? dB : dA, r, kbx});
+        kyj.push_back(KeyJob{w.row[s], w.xn[s], s ? dB : dA, r, kbx, w.hlow + s});
         for (int x = 0; x < kbx; ++x) kyi.push_back(BItem{kjob, x});
-        ucj.push_back(UncJob{w.row[s], w.top[s], nullptr, s ? dB : dA, r, w.best[s], w.ccnt + s, w.status,
-                             w.cand2[s], w.ccnt2 + s, w.best2[s]});
+        ucj.push_back(UncJob{w.row[s], nullptr, nullptr, s ? dB : dA, r, nullptr, nullptr, w.status,
+                             w.cand2[s], w.ccnt2 + s, w.best2[s], w.hlow + s});
         const int r2job = (int)r2j.size();
         r2j.push_back(RefineJob{w.xp[s], w.cand2[s], w.ccnt2 + s, w.xp[1 - s], s ? dA : dB, ry, ys,
                                 w.best2[s]});
         for (int x = 0; x < ys; ++x) r2i.push_back(BItem{r2job, x});
       }
       FinalJob f{};
-      f.ab = FinalDir{w.best[0], w.cand[0], w.ccnt, w.best2[0], w.cand2[0], w.ccnt2,
+      f.ab = FinalDir{nullptr, nullptr, nullptr, w.best2[0], w.cand2[0], w.ccnt2,
                       prohd ? w.idx[0] : nullptr, prohd ? w.idx[1] : nullptr, Ap, Bp};
-      f.ba = FinalDir{w.best[1], w.cand[1], w.ccnt + 1, w.best2[1], w.cand2[1], w.ccnt2 + 1,
+      f.ba = FinalDir{nullptr, nullptr, nullptr, w.best2[1], w.cand2[1], w.ccnt2 + 1,
                       prohd ? w.idx[1] : nullptr, prohd ? w.idx[0] : nullptr, Bp, Ap};
       f.dnA = dA;
       f.hnA = rA;
@@ -430,13 +410,6 @@ prohd_status build(prohd_batch* b) {
     r.tile_jobs = T.add(tlj);
     r.tile_items = T.add(tli);
     r.n_tile_items = (int)tli.size();
-    r.top_jobs = T.add(tpj);
-    r.n_top = (int)tpj.size();
-    r.topc_jobs = T.add(tcj);
-    r.n_topc = (int)tcj.size();
-    r.ref_jobs = T.add(rfj);
-    r.ref_items = T.add(rfi);
-    r.n_ref_items = (int)rfi.size();
     r.key_jobs = T.add(kyj);
     r.key_items = T.add(kyi);
     r.n_key_items = (int)kyi.size();
@@ -465,20 +438,18 @@ prohd_status build(prohd_batch* b) {
 
   auto& Ls = b->launches;
   Ls.clear();
-  // initial state: statuses, flags, minima, best
+  // initial state: statuses and lower bounds (adjacent), flags, minima
   int32_t* status = L.status;
   const int P = b->P;
-  unsigned long long* best = L.best;
   uint32_t* row = L.row;
   const int64_t nrow = L.nrow;
-  uint8_t* top = L.top;
   uint8_t* flags = L.flags;
   const int64_t nflags = L.nflags;
+  uint32_t* hlow = L.hlow;
   Ls.push_back([=](hipStream_t s) { return zero_bytes(status, sizeof(int32_t) * P, s); });
-  Ls.push_back([=](hipStream_t s) { return zero_bytes(top, (size_t)nrow, s); });
+  Ls.push_back([=](hipStream_t s) { return zero_bytes(hlow, sizeof(uint32_t) * 2 * P, s); });
   if (prohd) Ls.push_back([=](hipStream_t s) { return zero_bytes(flags, (size_t)nflags, s); });
-  Ls.push_back([=](hipStream_t s) { return batch_fill32(row, nrow, 0x7f800000u, s); });
-  Ls.push_back([=](hipStream_t s) { return batch_fill64(best, 2 * (int64_t)P * kRefine, ~0ull, s); });
+  if (nrow > 0) Ls.push_back([=](hipStream_t s) { return batch_fill32(row, nrow, 0x7f800000u, s); });
   for (const Rec& r : recs) {
     if (!prohd) continue;
     const int gram_grid = (int)(cdiv(persist(r.n_gram_items, t.gram_mult), 8) * 8);
@@ -520,7 +491,6 @@ prohd_status build(prohd_batch* b) {
     if (r.n_fin == 0) continue;   // every pair of this width took the pruned search
     const int prep_grid = persist(r.n_prep_items, 8);
     const int tile_grid = persist(r.n_tile_items, t.tile_mult);
-    const int ref_grid = persist(r.n_ref_items, 4);
     Ls.push_back([=](hipStream_t s) {
       return batch_prep(r.DP, r.D, (const PrepJob*)at(r.prep_jobs), (const BItem*)at(r.prep_items),
                         r.n_prep_items, prep_grid, s);
@@ -533,12 +503,6 @@ prohd_status build(prohd_batch* b) {
     Ls.push_back([=](hipStream_t s) {
       return batch_keys(r.DP, (const KeyJob*)at(r.key_jobs), (const BItem*)at(r.key_items),
                         r.n_key_items, key_grid, s);
-    });
-    Ls.push_back([=](hipStream_t s) { return batch_select((const SegJob*)at(r.top_jobs), r.n_top, s); });
-    Ls.push_back([=](hipStream_t s) { return batch_compact((const CompactJob*)at(r.topc_jobs), r.n_topc, s); });
-    Ls.push_back([=](hipStream_t s) {
-      return batch_refine(r.DP, (const RefineJob*)at(r.ref_jobs), (const BItem*)at(r.ref_items),
-                          r.n_ref_items, ref_grid, s);
     });
     Ls.push_back([=](hipStream_t s) { return batch_uncertain((const UncJob*)at(r.unc_jobs), r.n_unc, s); });
     const int ref2_grid = persist(r.n_ref2_items, 4);

@@ -36,9 +36,9 @@
 //   pruning  optionally (PROHD_PRUNE) the search runs in levels against
 //            subsets of Y first (a subset minimum bounds the full minimum
 //            from above), dropping rows whose U falls below max L.
-// The batched form keeps an earlier refinement rule: the 256 rows with the
-// largest U are re-measured first, then every row whose U exceeds the
-// largest re-measured minimum.
+// The batched form runs the same bound rule per pair (keys_batch,
+// uncertain_batch, refine_dyn_batch) without pruning; its exact mode sends
+// the pairs large enough for pruning through the single-pair path.
 
 #include "batch.h"
 #include "common.h"
@@ -964,19 +964,6 @@ __device__ __forceinline__ void refine_block(const float* __restrict__ Xp,
   }
 }
 
-// Work-group bx of a (candidate block) x (ysplit Y chunks) grid.
-template <int DP>
-__device__ __forceinline__ void refine_body(const float* __restrict__ Xp,
-                                            const int32_t* __restrict__ cand,
-                                            const int64_t* __restrict__ dR,
-                                            const float* __restrict__ Yp,
-                                            const int64_t* __restrict__ dnY, int64_t hnY,
-                                            int ysplit,
-                                            unsigned long long* __restrict__ best, int bx) {
-  const int cb = bx / ysplit;
-  refine_block<DP>(Xp, cand, *dR, Yp, dev_or(dnY, hnY), ysplit, bx - cb * ysplit, cb, best);
-}
-
 // Few rows (R <= kThinRows): the float64 pass as direct differences on the
 // vector ALUs, each wave measuring whole Y rows of its chunk (lane l holds
 // dimensions l, l + 64, ...; loads of 256 contiguous bytes), the R rows in
@@ -1407,30 +1394,40 @@ __device__ __forceinline__ uint32_t wg_excl_sum(uint32_t v, uint32_t* lds, uint3
   return before + inc - v;
 }
 
-// Rows left uncertain after the first refinement of one direction: key
-// above the largest refined squared minimum (lowered by 2^-20 of itself to
-// cover its rounding to float32 and the float64 expansion of the
-// refinement), not refined yet.  Their indices go to cand2 in ascending
-// order (one work-group: the order, and so any tie between equal refined
-// values, does not depend on timing), count2 gets their number and best2
-// the initial value of their minima.
+// The rows of one direction the float64 pass must re-measure (one
+// work-group, batched form): with `hlow`, every row whose key (U^2) reaches
+// the largest certified L^2; without, every row not re-measured yet whose
+// key exceeds the largest re-measured minimum (lowered by 2^-20 of itself
+// to cover its rounding to float32 and the float64 expansion).  Their
+// indices go to cand2 in ascending order (the order does not depend on
+// timing), count2 gets their number and best2 the initial value of their
+// minima.
 template <int NT>
 __device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
   const int tid = threadIdx.x;
   const bool ok = *j.status == ST_OK;
-  const int64_t R = ok ? *j.dR : 0;
-  const int64_t n = R > 0 ? dev_or(j.dn, j.hn) : 0;
-  uint32_t hb = 0;
-  for (int64_t r = tid; r < R; r += NT) hb = max(hb, (uint32_t)(j.best[r] >> 32));
+  int64_t n;
+  int64_t tb;   // rows with key > tb are listed
+  if (j.hlow) {
+    // keys reaching the largest lower bound (with none above zero: every
+    // row, so that the list is never empty)
+    n = ok ? dev_or(j.dn, j.hn) : 0;
+    tb = (int64_t)*j.hlow - 1;
+  } else {
+    const int64_t R = ok ? *j.dR : 0;
+    n = R > 0 ? dev_or(j.dn, j.hn) : 0;
+    uint32_t hb = 0;
+    for (int64_t r = tid; r < R; r += NT) hb = max(hb, (uint32_t)(j.best[r] >> 32));
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) hb = max(hb, (uint32_t)__shfl_xor(hb, o));
-  __syncthreads();
-  if ((tid & 63) == 0) lds[tid >> 6] = hb;
-  __syncthreads();
-  hb = 0;
+    for (int o = 32; o > 0; o >>= 1) hb = max(hb, (uint32_t)__shfl_xor(hb, o));
+    __syncthreads();
+    if ((tid & 63) == 0) lds[tid >> 6] = hb;
+    __syncthreads();
+    hb = 0;
 #pragma unroll
-  for (int k = 0; k < NT / 64; ++k) hb = max(hb, lds[k]);
-  const uint32_t tb = bits_down((double)__uint_as_float(hb) * (1.0 - 0x1p-20));
+    for (int k = 0; k < NT / 64; ++k) hb = max(hb, lds[k]);
+    tb = (int64_t)bits_down((double)__uint_as_float(hb) * (1.0 - 0x1p-20));
+  }
   constexpr int Q = 8;
   int64_t base = 0;
   for (int64_t c0 = 0; c0 < n; c0 += (int64_t)NT * Q) {
@@ -1438,7 +1435,7 @@ __device__ __forceinline__ void uncertain_body(const UncJob& j, uint32_t* lds) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int64_t i = c0 + (int64_t)tid * Q + q;
-      const bool on = i < n && (!j.top || j.top[i] == 0) && j.key[i] > tb;
+      const bool on = i < n && (!j.top || j.top[i] == 0) && (int64_t)j.key[i] > tb;
       f |= (on ? 1u : 0u) << q;
       cnt += on ? 1u : 0u;
     }
@@ -1604,18 +1601,6 @@ __global__ __launch_bounds__(512) void tile_batch(const TileJob* __restrict__ jo
   }
 }
 
-template <int DP>
-__global__ __launch_bounds__(256) void refine_batch(const RefineJob* __restrict__ jobs,
-                                                    const BItem* __restrict__ items, int nitems) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const BItem w = items[it];
-    if (w.job < 0) continue;
-    const RefineJob j = jobs[w.job];
-    __syncthreads();
-    refine_body<DP>(j.Xp, j.cand, j.dR, j.Yp, j.dnY, j.hnY, j.ysplit, j.best, w.bx);
-  }
-}
-
 __global__ __launch_bounds__(256) void finalize_batch(const FinalJob* __restrict__ jobs, int njobs) {
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const FinalJob j = jobs[it];
@@ -1636,8 +1621,27 @@ __global__ __launch_bounds__(256) void keys_batch(const KeyJob* __restrict__ job
     const BItem w = items[it];
     if (w.job < 0) continue;
     const KeyJob j = jobs[w.job];
-    bound_keys_body(j.mins, j.xn, dev_or(j.dn, j.hn), DP, DP, FMT_F32, nullptr,
-                    (int64_t)w.bx * blockDim.x + threadIdx.x, (int64_t)j.nbx * blockDim.x);
+    if (!j.hlow) {
+      bound_keys_body(j.mins, j.xn, dev_or(j.dn, j.hn), DP, DP, FMT_F32, nullptr,
+                      (int64_t)w.bx * blockDim.x + threadIdx.x, (int64_t)j.nbx * blockDim.x);
+      continue;
+    }
+    // upper bounds as keys, and the largest lower bound into *hlow
+    const SearchModel q = search_model(DP, FMT_F32, nullptr);
+    const double grow = 1.0 + 2.0 * (DP + 2) * 0x1p-24;
+    const int64_t n = dev_or(j.dn, j.hn);
+    double lmax = 0.0;
+    for (int64_t i = (int64_t)w.bx * blockDim.x + threadIdx.x; i < n; i += (int64_t)j.nbx * blockDim.x) {
+      const double m2 = (double)__uint_as_float(j.mins[i]);
+      const double S = sqrt((double)j.xn[i] * grow);
+      const double U = min_upper(m2, S, q);
+      j.mins[i] = bits_up(U * U * (1.0 + 0x1p-40));
+      lmax = fmax(lmax, min_lower(m2, S, q));
+    }
+    uint32_t lb = bits_down(lmax * lmax * (1.0 - 0x1p-40));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lb = max(lb, (uint32_t)__shfl_xor(lb, o));
+    if ((threadIdx.x & 63) == 0 && lb > 0) atomicMax(j.hlow, lb);
   }
 }
 
@@ -2251,16 +2255,6 @@ prohd_status batch_tile(int DP, const TileJob* jobs, const BItem* items, int nit
   if (nitems <= 0) return PROHD_OK;
   return by_dp_batch(DP, [&](auto dp) {
     PROHD_LAUNCH("batch_tile", tile_batch<decltype(dp)::value>, dim3(grid), dim3(512), 0, s, jobs,
-                 items, nitems);
-    return PROHD_OK;
-  });
-}
-
-prohd_status batch_refine(int DP, const RefineJob* jobs, const BItem* items, int nitems, int grid,
-                          hipStream_t s) {
-  if (nitems <= 0) return PROHD_OK;
-  return by_dp_batch(DP, [&](auto dp) {
-    PROHD_LAUNCH("batch_refine", refine_batch<decltype(dp)::value>, dim3(grid), dim3(256), 0, s, jobs,
                  items, nitems);
     return PROHD_OK;
   });
