@@ -576,7 +576,7 @@ def main():
     if "stats_gram" in kernels:
         # the symmetric half of the union Gram: (nA + nB) D (D + 1) FP64 flops
         path_roof["stats_gram"] = entry(
-            "gram_partial (covariance of the union, float64 v_mfma_f64_16x16x4f64)", "mfma",
+            "gram_partial256 (covariance of the union, float64 v_mfma_f64_16x16x4f64)", "mfma",
             float(nA + nB) * D * (D + 1), avg_ms("stats_gram"), 78.6, "TFLOP/s", 1)
     if lev and "hd_tile_rows" in kernels:
         # first pruning level: every candidate row against every F-th row of
