@@ -56,9 +56,9 @@ struct EigShape {
   static constexpr int QS = DP / NQ > 0 ? DP / NQ : 1;  // rows per thread
   static constexpr bool REG = NT == 512 && DP >= 64;    // register-resident matrix
   static constexpr bool IN_LDS = LDSMAT && !REG;        // matrix in LDS
+  static constexpr int SS = 4 * DP + 1;                 // LU slot stride (odd)
   // LDS region reused: matrix (when in LDS), then LU slots, then reflector chunks
-  static constexpr int BIG = IN_LDS ? (DP * DP > 4 * SLOTS * DP ? DP * DP : 4 * SLOTS * DP)
-                                    : 4 * SLOTS * DP;
+  static constexpr int BIG = IN_LDS ? (DP * DP > SLOTS * SS ? DP * DP : SLOTS * SS) : SLOTS * SS;
   static constexpr int VROWS = BIG / DP;                // reflector rows per chunk
 };
 
@@ -138,11 +138,18 @@ __device__ __forceinline__ double sum_mod8(double x) {
 // wave forms the reflector v (Householder vector of the column below the
 // subdiagonal) from it; the trailing matvec p = tau A v is summed per wave
 // (row sums accumulated over a tile row before one cross-lane reduction,
-// column sums reduced within groups of 8 lanes per tile) into a private LDS
-// row, then across waves in a fixed order; every wave forms K = (tau/2) p.v
+// column sums reduced within groups of 8 lanes per tile) into two private
+// LDS rows, then across waves in a fixed order; every wave forms K = (tau/2) p.v
 // and the tiles take the rank-2 update A -= v w^T + w v^T, w = p - K v, in
 // registers.  Writes d, e, tau and the reflectors (Vg rows) as the LDS /
 // global variant does.
+//
+// The step is a chain of short phases between three barriers, bound by LDS
+// latency and LDS issue rather than arithmetic: every length-DP vector is
+// read once per phase with all of a lane's loads in flight together, the
+// tile loops fetch the column entries of tile u + 2 while tile u is worked
+// on, and the partial sums are plain stores (no LDS atomics).  The reflector
+// rows go to global memory from the last wave, which owns the fewest tiles.
 template <int DP, int NT>
 __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, double* __restrict__ Vg,
                                             double* col0, double* pbuf0, double* col1, double* pbuf1,
@@ -151,7 +158,9 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
   constexpr int W = NT / 64;
   constexpr int NB = DP / 16;
   constexpr int TPW = NB + 1;          // tiles of tile rows RA and RB
+  constexpr int PR = DP / 64;          // entries of a length-DP vector per lane
   static_assert(NB / 2 <= W, "one pair of tile rows per wave");
+  static_assert(DP % 64 == 0, "register path: DP a multiple of 64");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool owner = wave < NB / 2;
@@ -168,11 +177,33 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       for (int q = 0; q < 2; ++q)
         a[u][i][q] = owner ? Mg[(size_t)(16 * I + 2 * rb + i) * DP + 16 * J + 2 * cb + q] : 0.0;
   }
-  double* mypw = pw + (size_t)wave * DP;
+  // two partial rows of p per wave, written with plain stores (an LDS
+  // atomic costs the compute unit several times a load): pwA takes the
+  // column sums of the row-RA tiles (blocks J < RA) and the row sums of row
+  // RA, pwB those of row RB.  Within a step no entry is written twice;
+  // blocks a wave never writes stay zero from here on, and entries of
+  // skipped tiles keep stale values at indices <= j, which p never reads.
+  double* pwA = pw + (size_t)(2 * wave) * DP;
+  double* pwB = pwA + DP;
   // per-wave copies of the step's v and w (only this wave reads them, in
   // program order after its own writes, so no barrier guards them)
-  double* vp = pw + (size_t)(W + wave) * DP;
-  double* wp = pw + (size_t)(2 * W + wave) * DP;
+  double* vp = pw + (size_t)(2 * W + wave) * DP;
+  double* wp = pw + (size_t)(3 * W + wave) * DP;
+#pragma unroll
+  for (int r = 0; r < 2 * PR; ++r) pwA[lane + 64 * r] = 0.0;
+  struct Pair {
+    double x, y;
+  };
+  // entries 16 J + 2 cb and + 1 of a length-DP vector, J the tile column of tile u
+  auto tcol = [&](int u) { return u <= RA ? u : u - RA - 1; };
+  auto colpair = [&](const double* x, int u) {
+    const int J = tcol(u);
+    return Pair{x[16 * J + 2 * cb], x[16 * J + 2 * cb + 1]};
+  };
+  auto rowpair = [&](const double* x, int I) { return Pair{x[16 * I + 2 * rb], x[16 * I + 2 * rb + 1]}; };
+  // the matrix loads complete here, before the step loop (a wait on them
+  // inside the loop would also wait, every step, for the reflector stores)
+  __builtin_amdgcn_s_waitcnt(0);
   // one step; QJ = j % 2 is a compile-time constant so that the column
   // element is picked without indexing the register array
   // col and pbuf alternate between two buffers by step parity, so a step
@@ -181,7 +212,7 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
   auto step = [&](const int j, auto QJ) {
     double* col = decltype(QJ)::value ? col1 : col0;
     double* pbuf = decltype(QJ)::value ? pbuf1 : pbuf0;
-    const int rb2 = 2 * rb, cb2 = 2 * cb;
+    const int rb2 = 2 * rb;
     const int Jj = j >> 4, cj = (j & 15) >> 1;
     if (owner && cb == cj) {
 #pragma unroll
@@ -193,16 +224,17 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
         }
       }
     }
-    for (int k = lane; k < DP; k += 64) mypw[k] = 0.0;
     __syncthreads();
     // reflector (every wave computes the same values in the same order)
+    double ck[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) ck[r] = col[lane + 64 * r];
     const double alpha = col[j + 1];
     double s2 = 0.0;
-    // LDS values are loaded unconditionally and then selected: a load under
-    // a lane condition becomes an exec-masked branch
-    for (int k = lane; k < DP; k += 64) {
-      const double ck = col[k];
-      s2 += (k > j + 1) ? ck * ck : 0.0;
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+      const int k = lane + 64 * r;
+      s2 += (k > j + 1) ? ck[r] * ck[r] : 0.0;
     }
     const double sigma = wave_sum_dpp(s2);
     double tj = 0.0, beta = alpha, scale = 0.0;
@@ -213,32 +245,43 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       scale = 1.0 / (alpha - beta);
     }
     // v once per step into this wave's copy: every later use is one load
-    for (int k = lane; k < DP; k += 64) {
-      const double ck = col[k];
-      vp[k] = k == j + 1 ? 1.0 : (k > j + 1 ? ck * scale : 0.0);
+    double vk[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+      const int k = lane + 64 * r;
+      vk[r] = k == j + 1 ? 1.0 : (k > j + 1 ? ck[r] * scale : 0.0);
+      vp[k] = vk[r];
     }
-    auto vof = [&](int k) { return vp[k]; };
     if (tid == 0) {
       ee[j] = beta;
       tau[j] = tj;
-      dd[j] = col[j];
     }
-    if (wave == 0)
-      for (int k = lane; k < DP; k += 64) Vg[(size_t)j * DP + k] = vof(k);
+    if (wave == W - 1) {
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int k = lane + 64 * r;
+        if (k == j) dd[j] = ck[r];
+        Vg[(size_t)j * DP + k] = vk[r];
+      }
+    }
     if (tj == 0.0) return;   // uniform: nothing below the subdiagonal
     // p = A v over the trailing block, per wave
     if (owner) {
       double pa0 = 0.0, pa1 = 0.0, pb0 = 0.0, pb1 = 0.0;
-      const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
-      const double vb0 = vof(16 * RB + rb2), vb1 = vof(16 * RB + rb2 + 1);
+      const Pair va = rowpair(vp, RA), vb = rowpair(vp, RB);
+      Pair vq[TPW];
+      vq[0] = colpair(vp, 0);
+      vq[1] = colpair(vp, 1);
 #pragma unroll
       for (int u = 0; u < TPW; ++u) {
+        if (u + 2 < TPW) vq[u + 2] = colpair(vp, u + 2);
         const bool rowA = u <= RA;
-        const int I = rowA ? RA : RB, J = rowA ? u : u - RA - 1;
+        const int J = tcol(u);
+        const int I = rowA ? RA : RB;
         if (16 * J + 15 > j) {   // uniform per wave
-          const int c0 = 16 * J + cb2;
-          const double vc0 = vof(c0), vc1 = vof(c0 + 1);
-          const double vr0 = rowA ? va0 : vb0, vr1 = rowA ? va1 : vb1;
+          const int c0 = 16 * J + 2 * cb;
+          const double vc0 = vq[u].x, vc1 = vq[u].y;
+          const double vr0 = rowA ? va.x : vb.x, vr1 = rowA ? va.y : vb.y;
           const double r0s = a[u][0][0] * vc0 + a[u][0][1] * vc1;
           const double r1s = a[u][1][0] * vc0 + a[u][1][1] * vc1;
           if (rowA) {
@@ -249,13 +292,13 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
             pb1 += r1s;
           }
           if (I > J) {
-            // column sums over the 8 row-pair lanes; LDS adds in program
-            // order (one lane per address per instruction: deterministic)
+            // column sums over the 8 row-pair lanes
             const double pc0 = sum8(a[u][0][0] * vr0 + a[u][1][0] * vr1);
             const double pc1 = sum8(a[u][0][1] * vr0 + a[u][1][1] * vr1);
             if (rb == 0) {
-              atomicAdd(&mypw[c0], pc0);
-              atomicAdd(&mypw[c0 + 1], pc1);
+              double* dst = rowA ? pwA : pwB;
+              dst[c0] = pc0;
+              dst[c0 + 1] = pc1;
             }
           }
         }
@@ -265,10 +308,10 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       pb0 = sum_mod8(pb0);
       pb1 = sum_mod8(pb1);
       if (cb == 0) {
-        atomicAdd(&mypw[16 * RA + rb2], pa0);
-        atomicAdd(&mypw[16 * RA + rb2 + 1], pa1);
-        atomicAdd(&mypw[16 * RB + rb2], pb0);
-        atomicAdd(&mypw[16 * RB + rb2 + 1], pb1);
+        pwA[16 * RA + rb2] = pa0;
+        pwA[16 * RA + rb2 + 1] = pa1;
+        pwB[16 * RB + rb2] = pb0;
+        pwB[16 * RB + rb2 + 1] = pb1;
       }
     }
     __syncthreads();
@@ -277,36 +320,49 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       double p = 0.0;
       if (tid > j) {
 #pragma unroll
-        for (int w = 0; w < NB / 2; ++w) p += pw[(size_t)w * DP + tid];
+        for (int w = 0; w < NB; ++w) p += pw[(size_t)w * DP + tid];
         p *= tj;
       }
       pbuf[tid] = p;
     }
     __syncthreads();
     // K = (tau / 2) p.v (each wave, same order); w_k = p_k - K v_k
+    double pk[PR], vv[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+      pk[r] = pbuf[lane + 64 * r];
+      vv[r] = vp[lane + 64 * r];
+    }
     double kd = 0.0;
-    for (int k = lane; k < DP; k += 64) kd += pbuf[k] * vof(k);
+#pragma unroll
+    for (int r = 0; r < PR; ++r) kd += pk[r] * vv[r];
     const double K = 0.5 * tj * wave_sum_dpp(kd);
     if (!owner) return;
-    for (int k = lane; k < DP; k += 64) {
-      const double pk = pbuf[k], vk = vp[k];
-      wp[k] = k > j ? pk - K * vk : 0.0;
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+      const int k = lane + 64 * r;
+      wp[k] = k > j ? pk[r] - K * vv[r] : 0.0;
     }
-    auto wof = [&](int k) { return wp[k]; };
-    const double wa0 = wof(16 * RA + rb2), wa1 = wof(16 * RA + rb2 + 1);
-    const double wb0 = wof(16 * RB + rb2), wb1 = wof(16 * RB + rb2 + 1);
-    const double va0 = vof(16 * RA + rb2), va1 = vof(16 * RA + rb2 + 1);
-    const double vb0 = vof(16 * RB + rb2), vb1 = vof(16 * RB + rb2 + 1);
+    const Pair wa = rowpair(wp, RA), wb = rowpair(wp, RB);
+    const Pair va = rowpair(vp, RA), vb = rowpair(vp, RB);
     // A -= v w^T + w v^T
+    Pair vq[TPW], wq[TPW];
+    vq[0] = colpair(vp, 0);
+    wq[0] = colpair(wp, 0);
+    vq[1] = colpair(vp, 1);
+    wq[1] = colpair(wp, 1);
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
+      if (u + 2 < TPW) {
+        vq[u + 2] = colpair(vp, u + 2);
+        wq[u + 2] = colpair(wp, u + 2);
+      }
       const bool rowA = u <= RA;
       const int J = rowA ? u : u - RA - 1;
       if (16 * J + 15 > j) {
-        const int c0 = 16 * J + cb2;
-        const double vc0 = vof(c0), vc1 = vof(c0 + 1), wc0 = wof(c0), wc1 = wof(c0 + 1);
-        const double vr0 = rowA ? va0 : vb0, vr1 = rowA ? va1 : vb1;
-        const double wr0 = rowA ? wa0 : wb0, wr1 = rowA ? wa1 : wb1;
+        const double vc0 = vq[u].x, vc1 = vq[u].y, wc0 = wq[u].x, wc1 = wq[u].y;
+        const double vr0 = rowA ? va.x : vb.x, vr1 = rowA ? va.y : vb.y;
+        const double wr0 = rowA ? wa.x : wb.x, wr1 = rowA ? wa.y : wb.y;
         // two fused steps per element (a - v w^T, then - w v^T)
         a[u][0][0] = fma(-wr0, vc0, fma(-vr0, wc0, a[u][0][0]));
         a[u][0][1] = fma(-wr0, vc1, fma(-vr0, wc1, a[u][0][1]));
@@ -333,6 +389,43 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
   __syncthreads();
 }
 
+// Number of eigenvalues of the tridiagonal T (diagonal d, squared
+// off-diagonal e2) below x: the negative pivots of T - x I (Sturm sequence),
+// each pivot kept at least pivmin away from zero.
+template <int DP>
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, double pivmin, double x) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < DP; ++i) {
+    double r = __builtin_amdgcn_rcp(q);   // 1/q, refined by one Newton step
+    r = fma(r, fma(-q, r, 1.0), r);
+    q = d[i] - x - e2[i - 1] * r;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Eigenvalue bounds of T: Gershgorin interval [gl, gu], the largest squared
+// off-diagonal.  Minima and maxima are exact, so every caller and every
+// reduction order gets the same bits.
+struct TriBounds {
+  double gl, gu, tnorm, pivmin;
+};
+
+__device__ __forceinline__ double gersh_radius(const double* e, int i, int n) {
+  return (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+}
+
+// The stages of the solve run either in one work-group (ALL: the batched
+// form, one job per work-group) or split over three launches for one
+// matrix: TRI (tridiagonalisation, d / e / tau to global memory), then a
+// multi-work-group bisection, then VEC (inverse iteration and
+// back-transformation from the stored T and eigenvalues).
+enum EigMode { EIG_ALL = 0, EIG_TRI = 1, EIG_VEC = 2 };
+
 __device__ __forceinline__ double start_value(int k, int c) {
   // deterministic pseudo-random start vector entry in (-1, 1)
   uint32_t h = (uint32_t)k * 0x9E3779B1u ^ ((uint32_t)c + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -342,32 +435,41 @@ __device__ __forceinline__ double start_value(int k, int c) {
   return ((double)(h & 0xFFFFFFu) / 8388608.0) - 1.0 + 1.0 / 16777216.0;
 }
 
-template <int DP, class S>
+// tri: 4 DP doubles (d, e, tau, eigenvalues), used by the split modes.
+template <int DP, class S, int MODE = EIG_ALL>
 __device__ __forceinline__ void eig_body(
     double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
     const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
-    const int32_t* __restrict__ status) {
+    const int32_t* __restrict__ status, double* __restrict__ tri = nullptr) {
   constexpr int NT = S::NT;
   __shared__ double big[S::BIG];
   __shared__ double vs[DP], wv[DP], part[S::NQ][DP];
   __shared__ double dd[DP], ee[DP], e2[DP], tau[DP], lam[DP];
   __shared__ double red[NT / 64];
-  __shared__ uint8_t piv[S::SLOTS][DP];
+  __shared__ uint8_t piv[S::SLOTS][DP + 4];
   __shared__ int lead_of[64];
 
   const int t = threadIdx.x;
   const bool ok = (status == nullptr) || (*status == 0);
 
   double* M = S::IN_LDS ? big : Mg;
-  if (S::IN_LDS) {
+  if (S::IN_LDS && MODE != EIG_VEC) {
     for (int e = t; e < DP * DP; e += NT) big[e] = Mg[e];
   }
   __syncthreads();
 
   // ---------------------------------------------------- 1. tridiagonalise
-  if constexpr (S::REG) {
+  if constexpr (MODE == EIG_VEC) {
+    if (t < DP) {
+      dd[t] = tri[t];
+      ee[t] = tri[DP + t];
+      tau[t] = tri[2 * DP + t];
+      lam[t] = tri[3 * DP + t];
+    }
+    __syncthreads();
+  } else if constexpr (S::REG) {
     static_assert(S::NQ >= 2, "the second column / p buffers live in part");
-    static_assert(S::BIG >= 3 * (NT / 64) * DP, "per-wave p partials, v and w live in big");
+    static_assert(S::BIG >= 4 * (NT / 64) * DP, "per-wave p partials, v and w live in big");
     tridiag_reg<DP, NT>(Mg, Vg, vs, wv, part[0], part[1], big, red, dd, ee, tau);
   } else {
     const int ci = t % DP;        // column owned in the matvec / update
@@ -451,12 +553,21 @@ __device__ __forceinline__ void eig_body(
     __syncthreads();
   }
 
+  if constexpr (MODE == EIG_TRI) {
+    if (t < DP) {
+      tri[t] = dd[t];
+      tri[DP + t] = ee[t];
+      tri[2 * DP + t] = tau[t];
+    }
+    return;
+  }
+
   // ------------------------------------------------------- 2. bisection
   if (t < DP) e2[t] = ee[t] * ee[t];
   __syncthreads();
   double gl = 0.0, gu = 0.0, emax = 0.0;
   for (int i = 0; i < DP; ++i) {
-    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < DP - 1 ? fabs(ee[i]) : 0.0);
+    const double r = gersh_radius(ee, i, DP);
     gl = (i == 0) ? dd[i] - r : fmin(gl, dd[i] - r);
     gu = (i == 0) ? dd[i] + r : fmax(gu, dd[i] + r);
     emax = fmax(emax, e2[i]);
@@ -464,21 +575,10 @@ __device__ __forceinline__ void eig_body(
   const double tnorm = fmax(fabs(gl), fabs(gu));
   const double pivmin = 1e-290 * fmax(1.0, emax);
   // count(x) = number of eigenvalues below x (Sturm sequence of T - x I)
-  auto sturm = [&](double x) {
-    int cnt = 0;
-    double q = dd[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-    for (int i = 1; i < DP; ++i) {
-      double r = __builtin_amdgcn_rcp(q);   // 1/q, refined by one Newton step
-      r = fma(r, fma(-q, r, 1.0), r);
-      q = dd[i] - x - e2[i - 1] * r;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-    }
-    return cnt;
-  };
-  if (evals == nullptr && NT >= 512) {
+  auto sturm = [&](double x) { return sturm_count<DP>(dd, e2, pivmin, x); };
+  if (MODE == EIG_VEC) {
+    // eigenvalues from the bisection launch
+  } else if (evals == nullptr && NT >= 512) {
     // only the m + 1 largest and the smallest real eigenvalue are used:
     // 16-way multisection, one group of 16 lanes per eigenvalue
     constexpr int G = 16;
@@ -544,12 +644,18 @@ __device__ __forceinline__ void eig_body(
     }
   }
   __syncthreads();
-  double* slot_base = big;  // SLOTS x 4 x DP doubles: U0 inverse, U1, L, x
+  // Slots: U0 inverse, U1, L and x of one vector each, S::SS doubles apart
+  // (an odd stride puts the 16 substitution threads' entries in different
+  // LDS banks; so does the padded pivot row).
+  double* slot_base = big;
+  constexpr int SS = S::SS;
   constexpr int NWV = NT / 64;
+  constexpr int PRV = (DP + 63) / 64;     // entries of a vector per lane
+  constexpr int SB = 8;                   // substitution block
   const int lane3 = t & 63, wave3 = t >> 6;
   for (int r0 = 0; r0 < m; r0 += S::SLOTS) {
     const int nr = min(S::SLOTS, m - r0);
-    double* U0 = slot_base + (size_t)t * 4 * DP;
+    double* U0 = slot_base + (size_t)(t < S::SLOTS ? t : 0) * SS;
     double* U1 = U0 + DP;
     double* Lm = U0 + 2 * DP;
     double* x = U0 + 3 * DP;
@@ -557,31 +663,25 @@ __device__ __forceinline__ void eig_body(
     if (t < nr && ok) {
       const int c = r0 + t;
       const double lc = shift[c];
-      // pivoted LU of T - lc I
+      // pivoted LU of T - lc I, without branches: the pivot choice selects
+      // the operands of one reciprocal
       double dcur = dd[0] - lc, ucur = ee[0];
       for (int i = 0; i < DP - 1; ++i) {
         const double sub = ee[i];
         const double an = dd[i + 1] - lc;
         const double bn = (i + 1 < DP - 1) ? ee[i + 1] : 0.0;
-        if (fabs(dcur) >= fabs(sub)) {
-          double dpiv = dcur;
-          if (fabs(dpiv) < tol) dpiv = dpiv < 0.0 ? -tol : tol;
-          const double mult = sub / dpiv;
-          U0[i] = 1.0 / dpiv;
-          U1[i] = ucur;
-          Lm[i] = mult;
-          pv[i] = 0;
-          dcur = an - mult * ucur;
-          ucur = bn;
-        } else {
-          const double mult = dcur / sub;
-          U0[i] = 1.0 / sub;
-          U1[i] = an;
-          Lm[i] = mult;
-          pv[i] = 1;
-          dcur = ucur - mult * an;
-          ucur = -mult * bn;
-        }
+        const bool keep = fabs(dcur) >= fabs(sub);   // no row interchange
+        double dpiv = dcur;
+        if (fabs(dpiv) < tol) dpiv = dpiv < 0.0 ? -tol : tol;
+        const double rp = 1.0 / (keep ? dpiv : sub);
+        const double mult = (keep ? sub : dcur) * rp;
+        U0[i] = rp;
+        U1[i] = keep ? ucur : an;
+        Lm[i] = mult;
+        pv[i] = keep ? 0 : 1;
+        const double dn = keep ? an - mult * ucur : ucur - mult * an;
+        ucur = keep ? bn : -mult * bn;
+        dcur = dn;
       }
       if (fabs(dcur) < tol) dcur = dcur < 0.0 ? -tol : tol;
       U0[DP - 1] = 1.0 / dcur;
@@ -590,30 +690,58 @@ __device__ __forceinline__ void eig_body(
     }
     for (int it = 0; it < 5; ++it) {
       if (t < nr && ok) {
-        // forward: apply the row interchanges and multipliers; the running
-        // row stays in a register, so the only dependence between steps is
-        // through registers and the LDS loads can be issued ahead
+        // forward: apply the row interchanges and multipliers.  The running
+        // row stays in a register; the operands of SB steps are read into
+        // registers before those steps (x[i + 1] is read before step i + 1
+        // writes it, as in the step order), so a block costs one LDS round
+        // trip rather than one per step.
         double carry = x[0];
-#pragma unroll 8
-        for (int i = 0; i < DP - 1; ++i) {
-          const double nxt = x[i + 1];
-          const bool sw = pv[i] != 0;
-          const double bi = sw ? nxt : carry, bn = sw ? carry : nxt;
-          x[i] = bi;
-          carry = bn - Lm[i] * bi;
+        for (int ib = 0; ib < DP - 1; ib += SB) {
+          double xn[SB], lm[SB];
+          bool sw[SB];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            const int i = min(ib + q, DP - 2);
+            xn[q] = x[i + 1];
+            lm[q] = Lm[i];
+            sw[q] = pv[i] != 0;
+          }
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            const int i = ib + q;
+            if (i < DP - 1) {
+              const double bi = sw[q] ? xn[q] : carry, bnx = sw[q] ? carry : xn[q];
+              x[i] = bi;
+              carry = bnx - lm[q] * bi;
+            }
+          }
         }
         x[DP - 1] = carry;
-        // backward: U has diagonal, first and (when pivoted) second superdiagonal
+        // backward: U has diagonal, first and (when pivoted) second
+        // superdiagonal; blocks of SB steps as above
         double x2 = 0.0, x1 = x[DP - 1] * U0[DP - 1];
         x[DP - 1] = x1;
-#pragma unroll 8
-        for (int i = DP - 2; i >= 0; --i) {
-          const double e1 = ee[i + 1 < DP ? i + 1 : i];
-          const double u2 = (pv[i] && i + 2 < DP) ? e1 : 0.0;
-          const double xi = (x[i] - U1[i] * x1 - u2 * x2) * U0[i];
-          x[i] = xi;
-          x2 = x1;
-          x1 = xi;
+        for (int ib = DP - 2; ib >= 0; ib -= SB) {
+          double xo[SB], u1[SB], u0[SB], u2[SB];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            const int i = max(ib - q, 0);
+            const double e1 = ee[i + 1 < DP ? i + 1 : i];
+            xo[q] = x[i];
+            u1[q] = U1[i];
+            u0[q] = U0[i];
+            u2[q] = (pv[i] && i + 2 < DP) ? e1 : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            const int i = ib - q;
+            if (i >= 0) {
+              const double xi = (xo[q] - u1[q] * x1 - u2[q] * x2) * u0[q];
+              x[i] = xi;
+              x2 = x1;
+              x1 = xi;
+            }
+          }
         }
       }
       __syncthreads();
@@ -621,34 +749,53 @@ __device__ __forceinline__ void eig_body(
         for (int v = 0; v < nr; ++v) {
           const int c = r0 + v;
           if (lead_of[c] % NWV != wave3) continue;   // wave-uniform
-          double* xv = slot_base + (size_t)v * 4 * DP + 3 * DP;
+          double* xv = slot_base + (size_t)v * SS + 3 * DP;
+          double xr[PRV];
+#pragma unroll
+          for (int r = 0; r < PRV; ++r) {
+            const int k = lane3 + 64 * r;
+            xr[r] = k < DP ? xv[k] : 0.0;
+          }
           for (int p = lead_of[c]; p < c; ++p) {
-            const double* yp = p < r0 ? Yg + (size_t)p * DP : slot_base + (size_t)(p - r0) * 4 * DP + 3 * DP;
+            const double* yp = p < r0 ? Yg + (size_t)p * DP : slot_base + (size_t)(p - r0) * SS + 3 * DP;
+            double yr[PRV];
+#pragma unroll
+            for (int r = 0; r < PRV; ++r) {
+              const int k = lane3 + 64 * r;
+              yr[r] = k < DP ? yp[k] : 0.0;
+            }
             double d = 0.0;
-            for (int k = lane3; k < DP; k += 64) d += xv[k] * yp[k];
+#pragma unroll
+            for (int r = 0; r < PRV; ++r) d += xr[r] * yr[r];
             d = wave_sum_dpp(d);
-            for (int k = lane3; k < DP; k += 64) xv[k] -= d * yp[k];
+#pragma unroll
+            for (int r = 0; r < PRV; ++r) xr[r] -= d * yr[r];
           }
           double mx = 0.0;
-          for (int k = lane3; k < DP; k += 64) mx = fmax(mx, fabs(xv[k]));
+#pragma unroll
+          for (int r = 0; r < PRV; ++r) mx = fmax(mx, fabs(xr[r]));
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
           if (!(mx > 0.0)) mx = 1.0;
           double s2 = 0.0;
-          for (int k = lane3; k < DP; k += 64) {
-            const double xs = xv[k] / mx;
-            xv[k] = xs;
-            s2 += xs * xs;
+#pragma unroll
+          for (int r = 0; r < PRV; ++r) {
+            xr[r] = xr[r] / mx;
+            s2 += xr[r] * xr[r];
           }
           const double inv = 1.0 / sqrt(wave_sum_dpp(s2));
-          for (int k = lane3; k < DP; k += 64) xv[k] *= inv;
+#pragma unroll
+          for (int r = 0; r < PRV; ++r) {
+            const int k = lane3 + 64 * r;
+            if (k < DP) xv[k] = xr[r] * inv;
+          }
         }
       }
       __syncthreads();
     }
     for (int e = t; e < nr * DP; e += NT) {
       const int v = e / DP, k = e - v * DP;
-      Yg[(size_t)(r0 + v) * DP + k] = slot_base[(size_t)v * 4 * DP + 3 * DP + k];
+      Yg[(size_t)(r0 + v) * DP + k] = slot_base[(size_t)v * SS + 3 * DP + k];
     }
     __syncthreads();
   }
@@ -678,7 +825,16 @@ __device__ __forceinline__ void eig_body(
     for (int hi = DP - 3; hi >= 0; hi -= S::VROWS) {
       const int lo = hi - S::VROWS + 1 > 0 ? hi - S::VROWS + 1 : 0;
       __syncthreads();
-      for (int e = t; e < (hi - lo + 1) * DP; e += NT) big[e] = Vg[(size_t)lo * DP + e];
+      // chunk of reflector rows into LDS, eight loads in flight per thread
+      const int ne = (hi - lo + 1) * DP;
+      for (int e0 = t; e0 < ne; e0 += 8 * NT) {
+        double tmp[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tmp[q] = Vg[(size_t)lo * DP + min(e0 + q * NT, ne - 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (e0 + q * NT < ne) big[e0 + q * NT] = tmp[q];
+      }
       __syncthreads();
       for (int j = hi; j >= lo; --j) {
         const double tj = tau[j];
@@ -756,11 +912,91 @@ __device__ __forceinline__ void eig_body(
 }
 
 template <int DP>
-__global__ __launch_bounds__(EigShape<DP>::NT) void eig_kernel(
-    double* __restrict__ Mg, int D, int m, double* __restrict__ Vg, double* __restrict__ Yg,
-    const double* __restrict__ u0, float* __restrict__ dirs, double* __restrict__ evals,
-    const int32_t* __restrict__ status) {
-  eig_body<DP, EigShape<DP>>(Mg, D, m, Vg, Yg, u0, dirs, evals, status);
+__global__ __launch_bounds__(EigShape<DP>::NT) void eig_tri_kernel(double* __restrict__ Mg, int D,
+                                                                    double* __restrict__ Vg,
+                                                                    double* __restrict__ tri) {
+  eig_body<DP, EigShape<DP>, EIG_TRI>(Mg, D, 0, Vg, nullptr, nullptr, nullptr, nullptr, nullptr, tri);
+}
+
+template <int DP>
+__global__ __launch_bounds__(EigShape<DP>::NT) void eig_vec_kernel(
+    int D, int m, double* __restrict__ Vg, double* __restrict__ Yg, const double* __restrict__ u0,
+    float* __restrict__ dirs, double* __restrict__ evals, const int32_t* __restrict__ status,
+    double* __restrict__ tri) {
+  eig_body<DP, EigShape<DP>, EIG_VEC>(nullptr, D, m, Vg, Yg, u0, dirs, evals, status, tri);
+}
+
+// Bisection over work-groups: work-group b finds one eigenvalue of the
+// stored T (index DP-1-b, the (b+1)-th largest; with all == 0 the last
+// work-group takes the smallest real one, DP-D) by 256-way multisection,
+// one Sturm count per thread and step, so an interval shrinks 257-fold per
+// step (about seven steps to float64 resolution).  The stopping rule and
+// the final midpoint are those of the one-work-group solve.
+constexpr int kBisectThreads = 256;
+
+template <int DP>
+__global__ __launch_bounds__(kBisectThreads) void eig_bisect_kernel(double* __restrict__ tri, int D,
+                                                                    int m, int all) {
+  constexpr int G = kBisectThreads;
+  __shared__ double d[DP], e2[DP];
+  __shared__ double rmin[G / 64], rmax[G / 64], rem[G / 64];
+  __shared__ int cnt[2][G / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int b = blockIdx.x;
+  const int idx = all ? DP - 1 - b : (b <= m ? DP - 1 - b : DP - D);
+  const double* te = tri + DP;
+  double lo_t = 0.0, hi_t = 0.0, e2_t = 0.0;
+  if (t < DP) {
+    d[t] = tri[t];
+    e2[t] = te[t] * te[t];
+    const double r = gersh_radius(te, t, DP);
+    lo_t = tri[t] - r;
+    hi_t = tri[t] + r;
+    e2_t = e2[t];
+  } else {   // threads past DP repeat entry 0: minima and maxima unchanged
+    const double r = gersh_radius(te, 0, DP);
+    lo_t = tri[0] - r;
+    hi_t = tri[0] + r;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo_t = fmin(lo_t, __shfl_xor(lo_t, off));
+    hi_t = fmax(hi_t, __shfl_xor(hi_t, off));
+    e2_t = fmax(e2_t, __shfl_xor(e2_t, off));
+  }
+  if (lane == 0) {
+    rmin[wave] = lo_t;
+    rmax[wave] = hi_t;
+    rem[wave] = e2_t;
+  }
+  __syncthreads();
+  double gl = rmin[0], gu = rmax[0], emax = rem[0];
+#pragma unroll
+  for (int w = 1; w < G / 64; ++w) {
+    gl = fmin(gl, rmin[w]);
+    gu = fmax(gu, rmax[w]);
+    emax = fmax(emax, rem[w]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double pivmin = 1e-290 * fmax(1.0, emax);
+  double lo = gl - 1e-14 * tnorm - pivmin, hi = gu + 1e-14 * tnorm + pivmin;
+  for (int it = 0; it < 64; ++it) {
+    const double w = hi - lo;
+    if (!(w > 2.2e-16 * (fmax(fabs(lo), fabs(hi)) + tnorm) + pivmin)) break;
+    const double x = lo + w * (double)(t + 1) / (double)(G + 1);
+    const unsigned long long bal = __ballot(sturm_count<DP>(d, e2, pivmin, x) <= idx);
+    if (lane == 0) cnt[it & 1][wave] = __popcll(bal);
+    __syncthreads();
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < G / 64; ++q) k += cnt[it & 1][q];
+    const double nlo = k > 0 ? lo + w * (double)k / (double)(G + 1) : lo;
+    const double nhi = k < G ? lo + w * (double)(k + 1) / (double)(G + 1) : hi;
+    if (!(nlo >= lo && nhi <= hi && nlo < nhi)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (t == 0) tri[3 * DP + idx] = 0.5 * (lo + hi);
 }
 
 // One work-group per job (pair).
@@ -779,9 +1015,16 @@ prohd_status eig_dp(double* C, int32_t D, int32_t m, const double* u0, float* di
   Arena ar(ws);
   double* V = ar.take<double>((size_t)DP * DP);
   double* Y = ar.take<double>((size_t)PROHD_MAX_DIRS * DP);
+  double* T = ar.take<double>((size_t)4 * DP);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "eig: workspace too small");
-  PROHD_LAUNCH("eig", eig_kernel<DP>, dim3(1), dim3(EigShape<DP>::NT), 0, s, C, D, m, V, Y, u0, dirs,
-               evals, status);
+  // eigenvalues wanted: all D real ones with evals, else the m + 1 largest
+  // and the smallest real one
+  const int all = evals != nullptr;
+  const int nb = all ? D : m + 2;
+  PROHD_LAUNCH("eig_tri", eig_tri_kernel<DP>, dim3(1), dim3(EigShape<DP>::NT), 0, s, C, D, V, T);
+  PROHD_LAUNCH("eig_bisect", eig_bisect_kernel<DP>, dim3(nb), dim3(kBisectThreads), 0, s, T, D, m, all);
+  PROHD_LAUNCH("eig_vec", eig_vec_kernel<DP>, dim3(1), dim3(EigShape<DP>::NT), 0, s, D, m, V, Y, u0, dirs,
+               evals, status, T);
   return PROHD_OK;
 }
 
@@ -793,6 +1036,7 @@ size_t eig_ws_bytes(int32_t D, int32_t m) {
   Arena ar(nullptr);
   ar.take<double>((size_t)DP * DP);
   ar.take<double>((size_t)PROHD_MAX_DIRS * DP);
+  ar.take<double>((size_t)4 * DP);
   return ar.used + 256;
 }
 
@@ -836,3 +1080,4 @@ prohd_status batch_eig(int DP, int D, const EigJob* jobs, int njobs, bool narrow
 }
 
 }  // namespace prohd
+
