@@ -419,11 +419,52 @@ __device__ __forceinline__ double gersh_radius(const double* e, int i, int n) {
   return (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
 }
 
+// Unit length and canonical sign (largest-magnitude entry positive, first
+// index on ties) of one vector held by one wave, lane l holding entries
+// l + 64 r; written as float32 row 1 + c of dirs (entries below D).
+template <int DP, int PR>
+__device__ __forceinline__ void finish_vector(const double (&z)[PR], int lane, int c, int D,
+                                              float* __restrict__ dirs) {
+  double s2 = 0.0, bv = -1.0, sv = 0.0;
+  int bk = 0x7fffffff;
+#pragma unroll
+  for (int r = 0; r < PR; ++r) {
+    const int k = lane + 64 * r;
+    if (k < DP) {
+      s2 += z[r] * z[r];
+      const double a = fabs(z[r]);
+      if (a > bv || (a == bv && k < bk)) {
+        bv = a;
+        bk = k;
+        sv = z[r];
+      }
+    }
+  }
+  s2 = wave_sum(s2);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off);
+    const int ok2 = __shfl_xor(bk, off);
+    const double os = __shfl_xor(sv, off);
+    if (ov > bv || (ov == bv && ok2 < bk)) {
+      bv = ov;
+      bk = ok2;
+      sv = os;
+    }
+  }
+  const double f = (sv < 0.0 ? -1.0 : 1.0) / sqrt(s2);
+#pragma unroll
+  for (int r = 0; r < PR; ++r) {
+    const int k = lane + 64 * r;
+    if (k < D) dirs[(size_t)(1 + c) * D + k] = (float)(z[r] * f);
+  }
+}
+
 // The stages of the solve run either in one work-group (ALL: the batched
-// form, one job per work-group) or split over three launches for one
+// form, one job per work-group) or split over four launches for one
 // matrix: TRI (tridiagonalisation, d / e / tau to global memory), then a
-// multi-work-group bisection, then VEC (inverse iteration and
-// back-transformation from the stored T and eigenvalues).
+// multi-work-group bisection, then VEC (inverse iteration from the stored T
+// and eigenvalues), then a multi-work-group back-transformation.
 enum EigMode { EIG_ALL = 0, EIG_TRI = 1, EIG_VEC = 2 };
 
 __device__ __forceinline__ double start_value(int k, int c) {
@@ -801,6 +842,13 @@ __device__ __forceinline__ void eig_body(
   }
 
   // ------------------------------------------------ 4. back-transform
+  if constexpr (MODE == EIG_VEC) {   // the back-transformation launch follows
+    if (t < D) {
+      dirs[t] = (float)u0[t];
+      if (evals) evals[t] = lam[DP - 1 - t];
+    }
+    return;
+  }
   // wave w transforms vectors c = w, w + NW, ...; lane holds entries
   // k = lane + 64 r.  Per reflector the wave forms the dot products of all
   // its vectors first and reduces them together (independent cross-lane
@@ -869,41 +917,7 @@ __device__ __forceinline__ void eig_body(
 #pragma unroll
   for (int v = 0; v < VPW; ++v) {
     const int c = wave + NW * v;
-    if (c < m) {
-      double s2 = 0.0, bv = -1.0, sv = 0.0;
-      int bk = 0x7fffffff;
-#pragma unroll
-      for (int r = 0; r < PR; ++r) {
-        const int k = lane + 64 * r;
-        if (k < DP) {
-          s2 += z[v][r] * z[v][r];
-          const double a = fabs(z[v][r]);
-          if (a > bv || (a == bv && k < bk)) {
-            bv = a;
-            bk = k;
-            sv = z[v][r];
-          }
-        }
-      }
-      s2 = wave_sum(s2);
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int ok2 = __shfl_xor(bk, off);
-        const double os = __shfl_xor(sv, off);
-        if (ov > bv || (ov == bv && ok2 < bk)) {
-          bv = ov;
-          bk = ok2;
-          sv = os;
-        }
-      }
-      const double f = (sv < 0.0 ? -1.0 : 1.0) / sqrt(s2);
-#pragma unroll
-      for (int r = 0; r < PR; ++r) {
-        const int k = lane + 64 * r;
-        if (k < D) dirs[(size_t)(1 + c) * D + k] = (float)(z[v][r] * f);
-      }
-    }
+    if (c < m) finish_vector<DP>(z[v], lane, c, D, dirs);
   }
   if (t < D) {
     dirs[t] = (float)u0[t];
@@ -999,6 +1013,71 @@ __global__ __launch_bounds__(kBisectThreads) void eig_bisect_kernel(double* __re
   if (t == 0) tri[3 * DP + idx] = 0.5 * (lo + hi);
 }
 
+// Back-transformation over work-groups: work-group c (one wave) turns
+// eigenvector c of T into z = H_0 H_1 ... H_{DP-3} y, lane l holding entries
+// l + 64 r, with the arithmetic and order of the one-work-group form; the
+// reflector rows come from global memory (L2) a block of kBackRows ahead of
+// their use, so one vector's chain of dot products and updates never waits
+// for memory.  Then unit length and canonical sign (row 1 + c of dirs).
+constexpr int kBackRows = 8;
+
+template <int DP>
+__global__ __launch_bounds__(64) void eig_back_kernel(const double* __restrict__ Vg,
+                                                      const double* __restrict__ Yg,
+                                                      const double* __restrict__ tri, int D,
+                                                      float* __restrict__ dirs,
+                                                      const int32_t* __restrict__ status) {
+  constexpr int PR = (DP + 63) / 64;
+  constexpr int SB = kBackRows;
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const bool ok = (status == nullptr) || (*status == 0);
+  const double* tau = tri + 2 * DP;
+  double z[PR];
+#pragma unroll
+  for (int r = 0; r < PR; ++r) {
+    const int k = lane + 64 * r;
+    z[r] = (k < DP && ok) ? Yg[(size_t)c * DP + k] : 0.0;
+  }
+  double vb[2][SB][PR], tb[2][SB];
+  // reflectors jb, jb - 1, ..., jb - SB + 1 (those >= 0) into buffer b
+  auto fetch = [&](auto B, int jb) {
+    constexpr int b = decltype(B)::value;
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int j = jb - q, jj = j > 0 ? j : 0;
+      tb[b][q] = j >= 0 ? tau[jj] : 0.0;
+#pragma unroll
+      for (int r = 0; r < PR; ++r) vb[b][q][r] = Vg[(size_t)jj * DP + (lane + 64 * r) % DP];
+    }
+  };
+  auto apply = [&](auto B, int jb) {
+    constexpr int b = decltype(B)::value;
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const double tj = tb[b][q];
+      if (jb - q < 0 || tj == 0.0) continue;   // uniform
+      double d = 0.0;
+#pragma unroll
+      for (int r = 0; r < PR; ++r)
+        if (lane + 64 * r < DP) d += vb[b][q][r] * z[r];
+      d = tj * wave_sum_dpp(d);
+#pragma unroll
+      for (int r = 0; r < PR; ++r)
+        if (lane + 64 * r < DP) z[r] -= d * vb[b][q][r];
+    }
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  fetch(B0{}, DP - 3);
+  for (int jb = DP - 3; jb >= 0; jb -= 2 * SB) {
+    fetch(B1{}, jb - SB);
+    apply(B0{}, jb);
+    fetch(B0{}, jb - 2 * SB);
+    apply(B1{}, jb - SB);
+  }
+  finish_vector<DP>(z, lane, c, D, dirs);
+}
+
 // One work-group per job (pair).
 template <int DP, class S>
 __global__ __launch_bounds__(S::NT) void eig_batch(const EigJob* __restrict__ jobs, int D, int njobs) {
@@ -1025,6 +1104,7 @@ prohd_status eig_dp(double* C, int32_t D, int32_t m, const double* u0, float* di
   PROHD_LAUNCH("eig_bisect", eig_bisect_kernel<DP>, dim3(nb), dim3(kBisectThreads), 0, s, T, D, m, all);
   PROHD_LAUNCH("eig_vec", eig_vec_kernel<DP>, dim3(1), dim3(EigShape<DP>::NT), 0, s, D, m, V, Y, u0, dirs,
                evals, status, T);
+  if (m > 0) PROHD_LAUNCH("eig_back", eig_back_kernel<DP>, dim3(m), dim3(64), 0, s, V, Y, T, D, dirs, status);
   return PROHD_OK;
 }
 

@@ -588,6 +588,11 @@ __device__ __forceinline__ void gram_reduce_body(const double* __restrict__ gpar
     const int j = e & 15;
     int I, J;
     block_ij(t, NB, I, J);
+    // a diagonal tile holds both (i, j) and (j, i), which the matrix cores
+    // may round differently: the lower one (i >= j) writes both positions,
+    // so that no two threads race on an entry and C is the same bits on
+    // every run
+    if (I == J && i < j) continue;
     // partials added in slice order; loads issued eight at a time so the
     // sum does not wait on one memory round trip per slice
     double g = 0.0;

@@ -132,6 +132,32 @@ def test_project_identical_sets_fallback_axis():
     assert np.array_equal(dirs[0].cpu().numpy(), np.eye(16, dtype=np.float32)[0])
 
 
+@pytest.mark.parametrize("kind,nA,nB,D", [("mix", 60000, 50000, 128), ("heavy", 40000, 30000, 256),
+                                          ("gauss", 7000, 9000, 50)])
+def test_project_is_reproducible(kind, nA, nB, D):
+    """Two calls on the same input give the same bits: eigenvalues,
+    directions and projections.  (The covariance reduction used to let two
+    threads write the mirrored entries of a diagonal tile, whose matrix-core
+    sums can differ in the last bit, so the eigenvalues changed from run to
+    run at the 1e-15 level.)"""
+    torch, dev = torch_gpu()
+    import paper_2511_18207_amd as ph
+    banner(f"prohd_project reproducible {kind} {nA}x{nB}x{D}")
+    if kind == "mix":
+        A, B = synth.mixture(nA, nB, D, seed=5)
+    elif kind == "heavy":
+        A, B = synth.t_mixture(nA, nB, D, seed=5, nu=3.0)
+    else:
+        A, B = synth.gauss_outliers(nA, nB, D, seed=5)
+    dA, dB = to_dev(torch, A), to_dev(torch, B)
+    m = ph.default_m(D)
+    runs = [ph.prohd_project(dA, dB, m, sync=True) for _ in range(3)]
+    for d, pA, pB, ev, st in runs[1:]:
+        assert torch.equal(ev, runs[0][3])
+        assert torch.equal(d, runs[0][0])
+        assert torch.equal(pA, runs[0][1]) and torch.equal(pB, runs[0][2])
+
+
 def _check_selection(got, want, P64, ks):
     """Symmetric difference only at near-ties with a direction end's k-th value."""
     diff = np.setxor1d(got, want)
