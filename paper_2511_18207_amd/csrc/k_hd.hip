@@ -969,7 +969,9 @@ __device__ __forceinline__ void refine_block(const float* __restrict__ Xp,
 // dimensions l, l + 64, ...; loads of 256 contiguous bytes), the R rows in
 // registers; the matrix-core block would spend 64 rows' work on them.  Same
 // Y chunking, packing (float32 bits of d^2, then the index) and arg-min
-// rule (ties -> smallest index) as refine_block.
+// rule (ties -> smallest index) as refine_block.  The waves' minima meet in
+// LDS and each work-group makes one atomic per row (every work-group's
+// atomic hits the same R words, so their number sets the tail).
 constexpr int kThinRows = 8;
 
 template <int DP>
@@ -1038,12 +1040,19 @@ __device__ __forceinline__ void refine_thin(const float* __restrict__ Xp,
       }
     }
   }
-  if (lane != 0) return;
+  __shared__ unsigned long long red[kThinRows][16];
+  if (lane == 0) {
 #pragma unroll
-  for (int r = 0; r < kThinRows; ++r) {
-    if (r >= R) break;
-    const float f = bv[r] > 0.0 ? (float)bv[r] : 0.f;
-    atomicMin(&best[r], ((unsigned long long)__float_as_uint(f) << 32) | (uint32_t)bi[r]);
+    for (int r = 0; r < kThinRows; ++r) {
+      const float f = bv[r] > 0.0 ? (float)bv[r] : 0.f;
+      red[r][wave] = ((unsigned long long)__float_as_uint(f) << 32) | (uint32_t)bi[r];
+    }
+  }
+  __syncthreads();
+  if ((int64_t)threadIdx.x < R) {
+    unsigned long long k = red[threadIdx.x][0];
+    for (int w = 1; w < nw; ++w) k = red[threadIdx.x][w] < k ? red[threadIdx.x][w] : k;
+    atomicMin(&best[threadIdx.x], k);
   }
 }
 
@@ -1969,7 +1978,7 @@ prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64
   const int split = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 128));
   PROHD_LAUNCH("hd_dyn_refine", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
                dR, Yp, dnY, capY, split, best);
-  const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(8 * (int64_t)cu_count(), capY / 64));
+  const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 256));
   PROHD_LAUNCH("hd_dyn_refine", refine_rows_thin<DP>, dim3((unsigned)tsplit), dim3(256), 0, s, Xp, cand,
                dR, Yp, dnY, capY, best);
   return PROHD_OK;
