@@ -1978,7 +1978,7 @@ prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64
   const int split = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 128));
   PROHD_LAUNCH("hd_dyn_refine", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
                dR, Yp, dnY, capY, split, best);
-  const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 256));
+  const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(8 * (int64_t)cu_count(), capY / 256));
   PROHD_LAUNCH("hd_dyn_refine", refine_rows_thin<DP>, dim3((unsigned)tsplit), dim3(256), 0, s, Xp, cand,
                dR, Yp, dnY, capY, best);
   return PROHD_OK;

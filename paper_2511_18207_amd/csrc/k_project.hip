@@ -46,6 +46,10 @@ constexpr int kBlockRows = 16;     // rows per wave step (the MFMA's N)
 constexpr int kJobRows = 512;      // rows per batched job
 constexpr int kMaxGroup = 33;      // directions per launch: 2 MFMA blocks + 1 on the ALUs
 constexpr int kBufferFlags = 0x00020000;   // buffer descriptor word 3 (32-bit data, CDNA)
+constexpr int kRunBlocks = 4;      // 16-row blocks per run of the single-pair kernel
+// staging row stride (floats): 68 puts the four lane groups of a result
+// write (directions 4 apart) on disjoint LDS banks
+constexpr int kStgStride = 68;
 
 // directions [d0, d0 + nd) of row-major dirs (ndirs x D) -> LDS rows of
 // stride DP + 4, zero beyond nd and beyond D
@@ -65,9 +69,13 @@ __device__ __forceinline__ void stage_dirs(float* us, const float* __restrict__ 
 // so a dead lane (row >= n) reads zeros without a branch; a column k >= D of
 // a live row reads the next row or zero and meets a zero direction entry
 // (the staged directions are zero beyond D).  Inputs are taken to be finite.
+// With stg, the results go to this wave's LDS staging rows instead (row d at
+// stg + d * kStgStride, points at columns scol .. scol + 15) for a store of
+// whole runs later.
 template <int DP, int NB, bool TAIL, bool VEC>
 __device__ __forceinline__ void proj_block(const float* __restrict__ X, int64_t n, int64_t r0, int D,
-                                           const float* us, int nd, float* __restrict__ P) {
+                                           const float* us, int nd, float* __restrict__ P,
+                                           float* stg = nullptr, int scol = 0) {
   constexpr int S = DP + 4;
   constexpr int T = DP / 16;
   const int lane = threadIdx.x & 63;
@@ -135,6 +143,18 @@ __device__ __forceinline__ void proj_block(const float* __restrict__ X, int64_t 
     __builtin_amdgcn_sched_barrier(0);
   }
   // result block b: lane (p, g) holds directions 16 b + 4 g + v of point p
+  if (stg) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) stg[(16 * b + 4 * g + v) * kStgStride + scol + p] = acc[b][v];
+    if (TAIL) {
+      tl += __shfl_xor(tl, 16);
+      tl += __shfl_xor(tl, 32);
+      if (g == 0) stg[(16 * NB) * kStgStride + scol + p] = tl;
+    }
+    return;
+  }
   float* q = P + (live ? row : 0);
   if (live) {
 #pragma unroll
@@ -152,8 +172,13 @@ __device__ __forceinline__ void proj_block(const float* __restrict__ X, int64_t 
   }
 }
 
-// Single pair: every wave walks 16-row blocks of A, then B (blocks
-// w, w + W, ... over W waves in the grid); directions [d0, d0 + nd).
+// Single pair (rows read as float4s): every wave walks runs of kRunBlocks
+// 16-row blocks (64 rows) of A, then B (runs w, w + W, ... over the W waves
+// of the grid);
+// directions [d0, d0 + nd).  A run's results are staged in LDS and each
+// direction's 64 values leave in one 256-byte store: stored block by block,
+// every direction took a 64-byte piece per block, half a cache line, and the
+// projection pass lost about a seventh of its time to the writes.
 template <int DP, int NB, bool TAIL, bool VEC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void project_mfma(const float* __restrict__ A, int64_t nA,
                                                          const float* __restrict__ B, int64_t nB,
@@ -161,18 +186,49 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                                          int d0, int nd, float* __restrict__ PA,
                                                          float* __restrict__ PB) {
   constexpr int NDL = 16 * NB + (TAIL ? 1 : 0);
+  constexpr int RR = kRunBlocks * kBlockRows;   // rows per run
   __shared__ __attribute__((aligned(16))) float us[NDL * (DP + 4)];
   stage_dirs<DP, NDL>(us, dirs, d0, nd, D);
   __syncthreads();
-  const int64_t bA = (nA + kBlockRows - 1) / kBlockRows;
-  const int64_t nblk = bA + (nB + kBlockRows - 1) / kBlockRows;
   const int64_t W = (int64_t)gridDim.x * kWaves;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int64_t b = (int64_t)blockIdx.x * kWaves + wave; b < nblk; b += W) {
-    const bool inA = b < bA;
+  if constexpr (!VEC) {
+    // rows read a float at a time (unaligned or D % 4 != 0): blocks of 16
+    // rows stored directly (the staging registers would not fit beside the
+    // scalar loads)
+    const int64_t bA = (nA + kBlockRows - 1) / kBlockRows;
+    const int64_t nblk = bA + (nB + kBlockRows - 1) / kBlockRows;
+    for (int64_t b = (int64_t)blockIdx.x * kWaves + wave; b < nblk; b += W) {
+      const bool inA = b < bA;
+      const int64_t n = inA ? nA : nB;
+      float* P = inA ? PA + (size_t)d0 * nA : PB + (size_t)d0 * nB;
+      proj_block<DP, NB, TAIL, VEC>(inA ? A : B, n, (inA ? b : b - bA) * kBlockRows, D, us, nd, P);
+    }
+    return;
+  }
+  __shared__ float stg_all[kWaves][NDL * kStgStride];
+  const int64_t rA = (nA + RR - 1) / RR;
+  const int64_t nrun = rA + (nB + RR - 1) / RR;
+  const int lane = threadIdx.x & 63;
+  float* stg = stg_all[wave];
+  for (int64_t r = (int64_t)blockIdx.x * kWaves + wave; r < nrun; r += W) {
+    const bool inA = r < rA;
     const int64_t n = inA ? nA : nB;
+    const int64_t r0 = (inA ? r : r - rA) * RR;
     float* P = inA ? PA + (size_t)d0 * nA : PB + (size_t)d0 * nB;
-    proj_block<DP, NB, TAIL, VEC>(inA ? A : B, n, (inA ? b : b - bA) * kBlockRows, D, us, nd, P);
+    const float* X = inA ? A : B;
+#pragma unroll
+    for (int e = 0; e < kRunBlocks; ++e)
+      if (r0 + e * kBlockRows < n)   // uniform
+        proj_block<DP, NB, TAIL, VEC>(X, n, r0 + e * kBlockRows, D, us, nd, P, stg, e * kBlockRows);
+    // the staging rows were written by this wave only: its own LDS writes
+    // complete before the reads below (no barrier)
+    const bool live = r0 + lane < n;
+#pragma unroll 4
+    for (int d = 0; d < nd && d < NDL; ++d) {
+      const float v = stg[d * kStgStride + lane];
+      if (live) P[(int64_t)d * n + r0 + lane] = v;
+    }
   }
 }
 
@@ -236,11 +292,16 @@ ProjLayout proj_layout(Arena& ar, int64_t nA, int64_t nB, int D, int ndirs) {
 template <int DP, int NB, bool TAIL>
 prohd_status launch_group(const float* A, int64_t nA, const float* B, int64_t nB, int D,
                           const float* dirs, int d0, int nd, float* PA, float* PB, hipStream_t s) {
-  const int64_t wgs = cdiv(cdiv(nA, kBlockRows) + cdiv(nB, kBlockRows), kWaves);
   const bool vec = (D % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+  // work-groups with work: runs of kRunBlocks blocks (staged form), blocks otherwise
+  const int64_t rows_per = vec ? kRunBlocks * kBlockRows : kBlockRows;
+  const int64_t wgs = cdiv(cdiv(nA, rows_per) + cdiv(nB, rows_per), kWaves);
   if (vec) {
+    // eight times the resident work-groups: measured at 2M + 2M rows,
+    // D = 256, 17 directions, 0.87 ms at one resident round, 0.85 ms at
+    // eight (later work-groups start as earlier ones drain)
     static const int per = resident_grid(project_mfma<DP, NB, TAIL, true>, 1 << 30);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, per));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, (int64_t)per * 8));
     PROHD_LAUNCH("project_mfma", (project_mfma<DP, NB, TAIL, true>), dim3(grid), dim3(kThreads), 0, s,
                  A, nA, B, nB, D, dirs, d0, nd, PA, PB);
   } else {
