@@ -178,8 +178,10 @@ __host__ __device__ constexpr int tile_bn() { return DP == 256 ? 2 * kBN : kBN; 
 
 // One segment of the distance matrix: X rows [x0, x0 + kTileRows) against
 // Y rows [yb, ye).  Row minima go to rowmin, column minima (COLMIN) to colmin,
-// both as order-preserving bit patterns through atomicMin.
-template <int DP, bool COLMIN, bool GX = false>
+// both as order-preserving bit patterns through atomicMin.  BNT: Y rows per
+// LDS buffer (one 32-row subtile when Y has no more rows than that, so a
+// tile against a short Y does not multiply padding).
+template <int DP, bool COLMIN, bool GX = false, int BNT = tile_bn<DP>()>
 __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const float* __restrict__ xn,
                                          const int32_t* __restrict__ xidx,
                                          int64_t nX, const float* __restrict__ Yp,
@@ -188,7 +190,8 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
                                          uint32_t* __restrict__ colmin) {
   constexpr int KH = DP / 2;       // k values per half-wave
   constexpr int ST = DP + 4;       // LDS row stride (floats): conflict-free b128 reads
-  constexpr int BN = tile_bn<DP>();
+  constexpr int BN = BNT;
+  static_assert(BN % kBN == 0 && BN % 8 == 0, "whole subtiles");
   constexpr int NSUB = BN / kBN;   // subtiles per buffer
   constexpr bool DMA = DP == 256;  // rows of 1 KiB go straight into LDS
   constexpr int NV4 = BN * DP / 4;              // float4s per Y block
@@ -211,7 +214,40 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
   // A operand: row x0 + 32*wave + c, k in [g*KH, g*KH + KH) (GX: the row
   // of that position in the list xidx)
   float a[KH];
-  {
+  if constexpr (DMA) {
+    // 1 KiB rows: each wave copies its 32 rows into its slice of the second
+    // Y buffer (free until the first Y block is in, XR = BN / 8 rows) XR
+    // rows at a time, one row per instruction (64 lanes x 16 contiguous
+    // bytes; a row past nX has an empty range and reads zeros), then the
+    // lanes of those rows read their half rows.  Loaded straight into
+    // registers, each instruction touched 64 cache lines (every lane its
+    // own row).
+    constexpr int XR = BN / 8;
+    float* xs = ys1 + wave * XR * ST;
+#pragma unroll
+    for (int p8 = 0; p8 < 32 / XR; ++p8) {
+#pragma unroll
+      for (int r = 0; r < XR; ++r) {
+        const int64_t xr = x0 + 32 * wave + XR * p8 + r;
+        const int64_t xm = xr < nX ? (GX ? (int64_t)xidx[xr] : xr) : 0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(Xp + xm * DP), 0, xr < nX ? DP * 4 : 0, kBufferFlags);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(xs + r * ST), 16, 4 * lane * 4, 0, 0, 0);
+      }
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's row copies have landed
+      if (c / XR == p8) {
+        const float4* src = reinterpret_cast<const float4*>(xs + (c % XR) * ST + g * KH);
+#pragma unroll
+        for (int j = 0; j < KH / 4; ++j) {
+          const float4 v = src[j];
+          a[4 * j] = v.x; a[4 * j + 1] = v.y; a[4 * j + 2] = v.z; a[4 * j + 3] = v.w;
+        }
+      }
+      // the slice is refilled by the next pass: this wave's reads come first
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+  } else {
     const int64_t xr = x0 + 32 * wave + c;
     if (xr < nX) {
       const int64_t xm = GX ? (int64_t)xidx[xr] : xr;
@@ -447,7 +483,7 @@ __device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S
 // so the work-groups of an XCD (ids congruent modulo 8), which hold
 // consecutive items of one or two chunks, read each Y block at about the same
 // time and one L2 fill serves them all.
-template <int DP, bool COLMIN, bool GX = false>
+template <int DP, bool COLMIN, bool GX = false, int BNT = tile_bn<DP>()>
 __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
                                                  const float* __restrict__ xn,
                                                  const int32_t* __restrict__ xidx,
@@ -457,7 +493,7 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
                                                  const int64_t* __restrict__ dnY, int64_t hnY,
                                                  uint32_t* __restrict__ rowmin,
                                                  uint32_t* __restrict__ colmin) {
-  constexpr int BN = tile_bn<DP>();
+  constexpr int BN = BNT;
   const int64_t nX = dev_or(dnX, hnX);
   const int64_t nY = dev_or(dnY, hnY);
   const int64_t xt = (nX + kTileRows - 1) / kTileRows;
@@ -466,8 +502,8 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
   const int64_t S = tile_split(xt, nyb, gridDim.x);
   tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
     __syncthreads();  // LDS of the previous segment is no longer read
-    dist_seg<DP, COLMIN, GX>(Xp, xn, xidx, nX, Yp, yn, xblk * kTileRows, b0 * BN, min(nY, b1 * BN),
-                             rowmin, colmin);
+    dist_seg<DP, COLMIN, GX, BNT>(Xp, xn, xidx, nX, Yp, yn, xblk * kTileRows, b0 * BN,
+                                  min(nY, b1 * BN), rowmin, colmin);
   });
 }
 
@@ -1738,9 +1774,18 @@ prohd_status launch_tile_k(int fmt, PrepSet X, const int32_t* xidx, const int64_
   // "_gx" listed rows
   const dim3 T(512);
   if (fmt == FMT_F32) {
+    const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
+    if (tile_bn<DP>() > kBN && capY <= kBN) {
+      // at most one subtile of Y rows (a sparse pruning level): buffers of
+      // 32 rows, half the padded work of the two-subtile form
+      const int64_t items = cdiv(capX, kTileRows);
+      auto k = dist_tile<DP, COLMIN, GX, kBN>;
+      PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, xidx, dnX, capX,
+                   Y.p, Y.n, dnY, capY, rowmin, colmin);
+      return PROHD_OK;
+    }
     const int64_t items = cdiv(capX, kTileRows) * cdiv(capY, tile_bn<DP>());
     auto k = dist_tile<DP, COLMIN, GX>;
-    const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
     PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, xidx, dnX, capX,
                  Y.p, Y.n, dnY, capY, rowmin, colmin);
     return PROHD_OK;
