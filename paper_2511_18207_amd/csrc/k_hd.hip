@@ -226,6 +226,13 @@ __device__ __forceinline__ void dist_seg(const float* __restrict__ Xp, const flo
     float* xs = ys1 + wave * XR * ST;
 #pragma unroll
     for (int p8 = 0; p8 < 32 / XR; ++p8) {
+      if (x0 + 32 * wave + XR * p8 >= nX) {   // uniform: no live row in this pass
+        if (c / XR == p8) {
+#pragma unroll
+          for (int j = 0; j < KH; ++j) a[j] = 0.f;
+        }
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
         const int64_t xr = x0 + 32 * wave + XR * p8 + r;
@@ -1775,11 +1782,17 @@ prohd_status launch_tile_k(int fmt, PrepSet X, const int32_t* xidx, const int64_
   const dim3 T(512);
   if (fmt == FMT_F32) {
     const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
-    if (tile_bn<DP>() > kBN && capY <= kBN) {
-      // at most one subtile of Y rows (a sparse pruning level): buffers of
-      // 32 rows, half the padded work of the two-subtile form
-      const int64_t items = cdiv(capX, kTileRows);
-      auto k = dist_tile<DP, COLMIN, GX, kBN>;
+    auto k32 = dist_tile<DP, COLMIN, GX, kBN>;
+    const int64_t xt = cdiv(capX, kTileRows);
+    if (tile_bn<DP>() > kBN &&
+        (capY <= kBN || (capY <= 2 * kBN && xt <= 2 * tile_grid(k32, int64_t(1) << 40)))) {
+      // a sparse pruning level (at most 32 Y rows), or a short list against
+      // at most two rounds of row tiles: buffers of 32 rows, so padding
+      // does not double the work below 32 rows, and the items of a second,
+      // partial round are half-size (with more row tiles the second Y
+      // subtile's items would each load their X rows again)
+      const int64_t items = xt * cdiv(capY, kBN);
+      auto k = k32;
       PROHD_LAUNCH(name, k, dim3((unsigned)tile_grid(k, items)), T, 0, s, X.p, X.n, xidx, dnX, capX,
                    Y.p, Y.n, dnY, capY, rowmin, colmin);
       return PROHD_OK;
