@@ -57,8 +57,10 @@ struct EigShape {
   static constexpr bool REG = NT == 512 && DP >= 64;    // register-resident matrix
   static constexpr bool IN_LDS = LDSMAT && !REG;        // matrix in LDS
   static constexpr int SS = 4 * DP + 1;                 // LU slot stride (odd)
-  // LDS region reused: matrix (when in LDS), then LU slots, then reflector chunks
-  static constexpr int BIG = IN_LDS ? (DP * DP > SLOTS * SS ? DP * DP : SLOTS * SS) : SLOTS * SS;
+  // LDS region reused: matrix (when in LDS) or the register form's vectors
+  // and its last 64 x 64 block, then LU slots, then reflector chunks
+  static constexpr int BIG0 = IN_LDS ? (DP * DP > SLOTS * SS ? DP * DP : SLOTS * SS) : SLOTS * SS;
+  static constexpr int BIG = REG && BIG0 < 64 * 65 + 128 ? 64 * 65 + 128 : BIG0;
   static constexpr int VROWS = BIG / DP;                // reflector rows per chunk
 };
 
@@ -371,16 +373,111 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ Mg, doubl
       }
     }
   };
-  for (int j = 0; j < DP - 2; j += 2) {   // DP - 2 is even
+  // The last M - 2 steps (trailing block of at most M = 64 rows) go to one
+  // wave with the block in LDS: a step of the register form costs about the
+  // same whatever the trailing size (three barriers and the chain of short
+  // phases; about 7 500 cycles per step at D = 256 once the block is
+  // small), while one wave with its own row per lane needs no barrier.
+  constexpr int M = 64;
+  constexpr int J0 = DP - M;   // even
+  for (int j = 0; j < J0; j += 2) {
     step(j, std::integral_constant<int, 0>{});
     step(j + 1, std::integral_constant<int, 1>{});
   }
-  // trailing 2 x 2 block: rows / columns DP-2, DP-1 (diagonal tile NB-1 is
-  // tile u = NB of wave 0, whose row RB = NB-1; lane 63 holds rows 14-15)
-  if (wave == 0 && lane == 63) {
-    dd[DP - 2] = a[TPW - 1][0][0];
-    dd[DP - 1] = a[TPW - 1][1][1];
-    ee[DP - 2] = a[TPW - 1][1][0];
+  __syncthreads();   // every wave's last rank-2 update is done; pw is free
+  // the trailing M x M block (rows / columns J0 ..) into LDS, both
+  // triangles, row stride M + 1
+  constexpr int MS = M + 1;
+  double* Am = pw;
+  double* vs2 = pw + M * MS;
+  double* ws2 = vs2 + M;
+  if (owner) {
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int I = u <= RA ? RA : RB, J = u <= RA ? u : u - RA - 1;
+      if (16 * J >= J0) {   // then 16 I >= J0 as well (I >= J)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int r = 16 * I + 2 * rb + i - J0, cc = 16 * J + 2 * cb + q - J0;
+            Am[r * MS + cc] = a[u][i][q];
+            if (I > J) Am[cc * MS + r] = a[u][i][q];
+          }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int l = lane;   // local row
+    for (int j = J0; j < DP - 2; ++j) {
+      const int jl = j - J0;
+      const double ajl = Am[l * MS + jl];
+      const double alpha = Am[(jl + 1) * MS + jl];
+      const double sigma = wave_sum_dpp(l > jl + 1 ? ajl * ajl : 0.0);
+      double tj = 0.0, beta = alpha, scale = 0.0;
+      if (sigma > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      const double vk = l == jl + 1 ? 1.0 : (l > jl + 1 ? ajl * scale : 0.0);
+      if (l == 0) {
+        ee[j] = beta;
+        tau[j] = tj;
+        dd[j] = Am[jl * MS + jl];
+      }
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {   // entries J0 + l are in the last lane block
+        const int k = lane + 64 * r;
+        Vg[(size_t)j * DP + k] = k >= J0 ? vk : 0.0;
+      }
+      if (tj == 0.0) continue;   // uniform
+      vs2[l] = vk;
+      // p = tau A v over rows / columns past jl (this lane's row), then
+      // K = (tau / 2) p.v and w = p - K v
+      // (in chunks of 16 columns, the live ones only; the entries of v and
+      // w at or before jl are zero, so whole chunks need no masks)
+      double pp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < M; k0 += 16) {
+        if (k0 + 15 <= jl) continue;   // uniform
+        double av[16], vv2[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          av[q] = Am[l * MS + k0 + q];
+          vv2[q] = vs2[k0 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pp[q & 3] = fma(av[q], vv2[q], pp[q & 3]);
+      }
+      double p = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+      p = l > jl ? p * tj : 0.0;
+      const double K = 0.5 * tj * wave_sum_dpp(p * vk);
+      const double wk = l > jl ? p - K * vk : 0.0;
+      ws2[l] = wk;
+      // A -= v w^T + w v^T on this lane's row (two fused steps per element)
+      // (rows at or before jl have v = w = 0 and stay as they are)
+#pragma unroll
+      for (int k0 = 0; k0 < M; k0 += 16) {
+        if (k0 + 15 <= jl) continue;   // uniform
+        double av[16], vv2[16], wv2[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          av[q] = Am[l * MS + k0 + q];
+          vv2[q] = vs2[k0 + q];
+          wv2[q] = ws2[k0 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Am[l * MS + k0 + q] = fma(-wk, vv2[q], fma(-vk, wv2[q], av[q]));
+      }
+    }
+    if (l == 0) {
+      dd[DP - 2] = Am[(M - 2) * MS + M - 2];
+      dd[DP - 1] = Am[(M - 1) * MS + M - 1];
+      ee[DP - 2] = Am[(M - 1) * MS + M - 2];
+    }
   }
   if (tid == 0) {
     ee[DP - 1] = 0.0;
@@ -511,6 +608,7 @@ __device__ __forceinline__ void eig_body(
   } else if constexpr (S::REG) {
     static_assert(S::NQ >= 2, "the second column / p buffers live in part");
     static_assert(S::BIG >= 4 * (NT / 64) * DP, "per-wave p partials, v and w live in big");
+    static_assert(S::BIG >= 64 * 65 + 128, "the last 64 x 64 block and two vectors live in big");
     tridiag_reg<DP, NT>(Mg, Vg, vs, wv, part[0], part[1], big, red, dd, ee, tau);
   } else {
     const int ci = t % DP;        // column owned in the matvec / update
