@@ -187,6 +187,31 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
                           void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * prohd_top_keys -- the k <= 64 largest entries of one float32 array under
+ * the order of prohd_select (larger value first; equal values: smaller index
+ * first; -0.0 equals +0.0), as an ascending index list.  prohd_hd's pruned
+ * search takes its seed rows this way (the rows with the largest upper
+ * bounds); the ordering rule is that of the extreme step of Alg. 1 and
+ * Alg. 2.
+ *
+ *   vals   device float32, n entries, no NaN (+-inf allowed); may be NULL
+ *          when n is 0
+ *   n      host bound on the length, 0 <= n < 2^31
+ *   dev_n  device int64 or NULL: when non-null the length is min(*dev_n, n)
+ *          (a negative count is 0), read on the device
+ *   k      0 <= k <= 64
+ *   idx    device int32, at least k entries: output, ascending
+ *   count  device int64: output, min(k, length)
+ *   ws     device workspace, ws_bytes >= PROHD_TOPK_WS_BYTES
+ * Two kernel launches on `stream`, no host synchronisation.
+ * Errors: EINVAL (null pointers, n or k out of range), EWORKSPACE, EDEVICE.
+ */
+#define PROHD_TOPK_WS_BYTES ((size_t)(512u * 1024u + 256u))
+prohd_status prohd_top_keys(const float* vals, int64_t n, const int64_t* dev_n, int32_t k,
+                            int32_t* idx, int64_t* count, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
  * prohd_hd -- Hausdorff distance over the selected rows.
  *
  * Default: H-hat = max{ max_{a in A_sel} min_{b in B_sel} ||a-b||,

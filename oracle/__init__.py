@@ -47,6 +47,7 @@ from .prohd import (  # noqa: F401
     principal_directions,
     canonical_sign,
     extreme_indices,
+    largest_indices,
     select,
     subset_hd,
     prohd,

@@ -49,6 +49,7 @@ __all__ = [
     "principal_directions",
     "canonical_sign",
     "extreme_indices",
+    "largest_indices",
     "select",
     "subset_hd",
     "prohd",
@@ -116,6 +117,20 @@ def principal_directions(A, B, m: int):
     return U, w[order]
 
 
+def largest_indices(p, k: int) -> np.ndarray:
+    """Indices of the k largest entries of ``p`` (R3: the first k of the
+    order (-value, index); -0.0 equals +0.0), ascending.  ``k`` is clipped to
+    the length; an empty array or ``k = 0`` gives no index."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    if np.isnan(p).any():
+        raise ValueError("NaN entry")
+    k = min(int(k), p.size)
+    if k <= 0:
+        return np.zeros(0, dtype=np.int64)
+    p = p + 0.0  # -0.0 -> +0.0
+    return np.sort(np.lexsort((np.arange(p.size), -p))[:k])
+
+
 def extreme_indices(p, k: int) -> np.ndarray:
     """Indices of the k smallest and k largest entries of ``p`` (R3), unioned.
 
@@ -133,8 +148,7 @@ def extreme_indices(p, k: int) -> np.ndarray:
     p = p + 0.0  # -0.0 -> +0.0
     idx = np.arange(n)
     bottom = np.lexsort((idx, p))[:k]
-    top = np.lexsort((idx, -p))[:k]
-    return np.union1d(bottom, top)
+    return np.union1d(bottom, largest_indices(p, k))
 
 
 def select(projA, projB, kA, kB):

@@ -35,6 +35,8 @@ from ._lib import (  # noqa: F401
     mlp_train_step,
     centroid,
     select_scored,
+    top_keys,
+    TOPK_WS_BYTES,
     BatchPlan,
     certificate,
     profile_enable,

@@ -110,6 +110,8 @@ def lib() -> C.CDLL:
                                        vp, sz, vp]
     L.prohd_centroid.restype = C.c_int
     L.prohd_centroid.argtypes = [vp, i64, i32, vp, vp, sz, vp]
+    L.prohd_top_keys.restype = C.c_int
+    L.prohd_top_keys.argtypes = [vp, i64, vp, i32, vp, vp, vp, sz, vp]
     L.prohd_certificate_workspace_size.restype = sz
     L.prohd_certificate_workspace_size.argtypes = [i32, i32]
     L.prohd_certificate.restype = C.c_int
@@ -530,6 +532,26 @@ def centroid(X, out=None, ws=None):
     _check(lib().prohd_centroid(X.data_ptr(), n, D, out.data_ptr(), buf.data_ptr(), nbytes,
                                 _stream()))
     return out
+
+
+TOPK_WS_BYTES = 512 * 1024 + 256
+
+
+def top_keys(vals, k, dev_n=None, ws=None):
+    """The k <= 64 largest entries of a 1-D float32 device tensor (equal
+    values: smaller index first) through prohd_top_keys.  ``dev_n``: an
+    optional device int64 tensor holding the length (clipped to the size).
+    Returns ``(idx, count)``: ascending indices (capacity max(k, 1)) and the
+    device count min(k, length)."""
+    torch = _torch()
+    if vals.dtype != torch.float32 or vals.dim() != 1 or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous 1-D float32 tensor")
+    idx = torch.empty(max(int(k), 1), dtype=torch.int32, device=vals.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=vals.device)
+    buf, nbytes = _ws(ws, TOPK_WS_BYTES)
+    _check(lib().prohd_top_keys(vals.data_ptr(), vals.numel(), _ptr(dev_n), int(k), idx.data_ptr(),
+                                cnt.data_ptr(), buf.data_ptr(), nbytes, _stream()))
+    return idx, cnt
 
 
 def certificate(A, B, dirs, projA, projB, lower=None, ws=None):

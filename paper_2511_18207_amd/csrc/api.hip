@@ -258,6 +258,18 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
   return compact_flags(fB, nB, nullptr, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
 }
 
+prohd_status prohd_top_keys(const float* vals, int64_t n, const int64_t* dev_n, int32_t k,
+                            int32_t* idx, int64_t* count, void* ws, size_t ws_bytes,
+                            void* stream) {
+  if ((n > 0 && bad_ptr(vals)) || bad_ptr(idx) || bad_ptr(count) || bad_ptr(ws))
+    return fail(PROHD_EINVAL, "vals (when n > 0), idx, count and ws must be non-null");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(PROHD_EINVAL, "n must be in [0, 2^31)");
+  if (k < 0 || k > 64) return fail(PROHD_EINVAL, "k must be in [0, 64]");
+  if (ws_bytes < PROHD_TOPK_WS_BYTES) return fail(PROHD_EWORKSPACE, "workspace too small");
+  const TopSegment seg{reinterpret_cast<const uint32_t*>(vals), n, dev_n, k, idx, count};
+  return top_keys(&seg, 1, ws, ws_bytes, (hipStream_t)stream);
+}
+
 prohd_status prohd_hd(const float* A, int64_t nA, const float* B, int64_t nB, int32_t D,
                       const int32_t* idxA, const int64_t* nselA, const int32_t* idxB,
                       const int64_t* nselB, int64_t capA, int64_t capB, uint32_t flags,

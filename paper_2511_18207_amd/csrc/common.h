@@ -118,12 +118,20 @@ size_t compact_ws_bytes(int64_t n);
 prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n,
                            int32_t* idx, int64_t cap, int64_t* count, void* ws, size_t ws_bytes,
                            hipStream_t s);
-// Select, then compact, up to two small segments in one launch (one
-// work-group per segment, which also clears the segment's flags first):
-// meant for a few hundred thousand entries per segment or fewer.  Same
-// result as select_mark on cleared flags followed by compact_flags.
-prohd_status select_compact_small(const SelSegment* segs, int nseg, int32_t* const* idx,
-                                  int64_t cap, int64_t* const* count, hipStream_t s);
+// The k <= 64 largest keys of up to two arrays under the same order (larger
+// float value first; equal values: smaller index first), as ascending index
+// lists with a device count of min(k, length).  `keys` are float32 bit
+// patterns; the length is read from dev_n (clipped to n) when non-null.
+struct TopSegment {
+  const uint32_t* keys;
+  int64_t n;              // host bound on the length
+  const int64_t* dev_n;   // device length, or nullptr (use n)
+  int32_t k;              // entries to keep, at most 64
+  int32_t* idx;           // k entries
+  int64_t* count;         // 1 entry
+};
+size_t topk_ws_bytes(int64_t max_n);
+prohd_status top_keys(const TopSegment* segs, int nseg, void* ws, size_t ws_bytes, hipStream_t s);
 // flags[idx[i]] = 1 for the first *count entries (count clipped to cap).
 prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64_t cap,
                                  uint8_t* flags, hipStream_t s);

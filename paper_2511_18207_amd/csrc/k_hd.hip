@@ -48,7 +48,7 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kSeedRows = 64;      // rows that seed the lower bound
+constexpr int kSeedRows = 64;      // rows that seed the lower bound (at most 64: top_keys)
 constexpr int kShortList = 64;     // lists searched as the inner side of a tile
 constexpr uint32_t kInfBits = 0x7f800000u;
 
@@ -155,6 +155,23 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
 __global__ void fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// Several word fills in one launch (grid y = job): the clears and +inf
+// initialisations of a search, which would otherwise take a launch each.
+constexpr int kFillJobs = 8;
+struct FillJob {
+  uint32_t* p;
+  int64_t n;
+  uint32_t v;
+};
+struct FillPack {
+  FillJob j[kFillJobs];
+};
+__global__ void fill_multi(const FillPack P) {
+  const FillJob f = P.j[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.n; i += (int64_t)gridDim.x * blockDim.x)
+    f.p[i] = f.v;
 }
 
 __global__ void fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v) {
@@ -1838,7 +1855,6 @@ prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, P
 // Per direction: the seed rows of the pruned search (top-kSeedRows of the
 // first level's bounds) and the list of rows the float64 pass re-measures.
 struct DirWork {
-  uint8_t* flags;   // n bytes (selection marks)
   int32_t* cand;    // kSeedRows
   int64_t* count;   // 1
   int32_t* cand2;   // n: rows of the float64 pass (or of a pruning level)
@@ -1871,8 +1887,8 @@ struct HdLayout {
   PruneWork pw[2];
   int32_t* status;
   uint32_t* maxabs;        // largest |shifted value| (float bits), fp8 scale
-  void* sel_ws;
-  size_t sel_bytes;
+  void* top_ws;            // wave lists of the seed selection
+  size_t top_bytes;
 };
 
 void take_set(Arena& ar, PrepSet& o, int64_t rows, int DP, int fmt) {
@@ -1915,7 +1931,6 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
   L.dshort = ar.take<int64_t>(4);
   const int64_t caps[2] = {capA, capB};
   for (int d = 0; d < 2; ++d) {
-    L.w[d].flags = ar.take<uint8_t>(caps[d]);
     L.w[d].cand = ar.take<int32_t>(kSeedRows);
     L.w[d].count = ar.take<int64_t>(1);
     L.w[d].cand2 = ar.take<int32_t>(caps[d]);
@@ -1938,42 +1953,18 @@ HdLayout hd_layout(Arena& ar, int64_t capA, int64_t capB, int64_t nA, int64_t nB
       }
     }
   }
-  const int64_t mx = std::max(capA, capB);
-  L.sel_bytes = std::max(select_ws_bytes(2, mx), compact_ws_bytes(mx));
-  L.sel_ws = ar.take<char>(L.sel_bytes);
+  L.top_bytes = topk_ws_bytes(std::max(capA, capB));
+  L.top_ws = ar.take<char>(L.top_bytes);
   return L;
 }
 
-// Top-k rows of both directions' minima (`mins[d]`, device length dn[d] /
-// host n[d]) -> w[d].cand / w[d].count; one selection launch chain for both.
-// Segments up to this length take the one-launch selection.
-constexpr int64_t kSmallRows = 1 << 18;
-
+// Top-k rows (k <= 64) of both directions' minima (`mins[d]`, device length
+// dn[d], host bound n[d]) -> w[d].cand / w[d].count; two launches for both.
 prohd_status top_rows2(const uint32_t* const mins[2], const int64_t n[2], const int64_t* const dn[2],
-                       DirWork* w, void* sel_ws, size_t sel_bytes, hipStream_t s, int k) {
-  SelSegment seg[2];
-  if (std::max(n[0], n[1]) <= kSmallRows) {
-    int32_t* idx[2];
-    int64_t* cnt[2];
-    for (int d = 0; d < 2; ++d) {
-      seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, k, w[d].flags};
-      idx[d] = w[d].cand;
-      cnt[d] = w[d].count;
-    }
-    return select_compact_small(seg, 2, idx, k, cnt, s);
-  }
-  for (int d = 0; d < 2; ++d) {
-    prohd_status st = zero_bytes(w[d].flags, (size_t)n[d], s);
-    if (st) return st;
-    seg[d] = SelSegment{reinterpret_cast<const float*>(mins[d]), n[d], dn[d], 0, k, w[d].flags};
-  }
-  prohd_status st = select_mark(seg, 2, sel_ws, sel_bytes, s);
-  if (st) return st;
-  for (int d = 0; d < 2; ++d) {
-    st = compact_flags(w[d].flags, n[d], dn[d], w[d].cand, k, w[d].count, sel_ws, sel_bytes, s);
-    if (st) return st;
-  }
-  return PROHD_OK;
+                       DirWork* w, void* top_ws, size_t top_bytes, hipStream_t s, int k) {
+  TopSegment seg[2];
+  for (int d = 0; d < 2; ++d) seg[d] = TopSegment{mins[d], n[d], dn[d], k, w[d].cand, w[d].count};
+  return top_keys(seg, 2, top_ws, top_bytes, s);
 }
 
 // Bound keys in place of the row minima (see the certified refinement).
@@ -2042,9 +2033,16 @@ prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64
   return PROHD_OK;
 }
 
-prohd_status init_mins(uint32_t* p, int64_t n, hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 4096));
-  PROHD_LAUNCH("hd_fill", fill_u32, dim3(grid), dim3(256), 0, s, p, n, kInfBits);
+prohd_status fill_words(const FillJob* jobs, int njobs, hipStream_t s) {
+  if (njobs < 1 || njobs > kFillJobs) return fail(PROHD_EINVAL, "fill_words: 1 to 8 jobs");
+  FillPack P{};
+  int64_t mx = 1;
+  for (int i = 0; i < njobs; ++i) {
+    P.j[i] = jobs[i];
+    mx = std::max(mx, jobs[i].n);
+  }
+  const int grid = (int)std::min<int64_t>(1024, cdiv(mx, 256));
+  PROHD_LAUNCH("hd_fill", fill_multi, dim3(grid, njobs), dim3(256), 0, s, P);
   return PROHD_OK;
 }
 
@@ -2066,9 +2064,14 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   Arena ar(ws);
   HdLayout L = hd_layout(ar, capA, capB, nA, nB, DP, full, fmt, prune);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "hd: workspace too small");
-  PROHD_TRY(zero_bytes(L.status, 256, s));
-  PROHD_TRY(zero_bytes(L.maxabs, 256, s));
-  PROHD_TRY(zero_bytes(L.hlow, 256, s));
+  {
+    // status words, the fp8 scale and the lower bounds cleared; every row
+    // minimum (outer rows of both directions, seed rows) set to +inf
+    const FillJob f[7] = {{(uint32_t*)L.status, 64, 0u}, {L.maxabs, 64, 0u}, {L.hlow, 64, 0u},
+                          {L.rowA, capA, kInfBits},      {L.rowB, capB, kInfBits},
+                          {L.rowS[0], kSeedRows, kInfBits}, {L.rowS[1], kSeedRows, kInfBits}};
+    PROHD_TRY(fill_words(f, 7, s));
+  }
   uint32_t* mx = fmt == FMT_FP8 ? L.maxabs : nullptr;
   // common shift: the first (selected) row of A
   const int32_t* sidx = idxA;
@@ -2086,8 +2089,6 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
       PROHD_TRY(launch_quant<DP>(fmt, L.fb, nullptr, nB, L.maxabs, s));
     }
   }
-  PROHD_TRY(init_mins(L.rowA, capA, s));
-  PROHD_TRY(init_mins(L.rowB, capB, s));
   const uint32_t* const mins2[2] = {L.rowA, L.rowB};
   const int64_t caps2[2] = {capA, capB};
   const int64_t* const dns2[2] = {dnA, dnB};
@@ -2116,14 +2117,13 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   // (whose error bound is tight in every precision form), raise the lower
   // bound; `zero` lists the counts the next append fills.
   auto seeds = [&](int64_t* const zero[2]) -> prohd_status {
-    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.sel_ws, L.sel_bytes, s, kSeedRows));
+    PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.top_ws, L.top_bytes, s, kSeedRows));
     BoundPair sp{};
     for (int d = 0; d < 2; ++d) {
       // the seed rows as the inner side of a tile whose outer side is the
       // whole inner set: their minima come out as column minima
       PROHD_TRY(launch_gather_list<DP>(FMT_F32, xs[d], L.w[d].cand, L.w[d].count, kSeedRows, L.sh[d],
                                        L.dshort + 2 * d, nullptr, s));
-      PROHD_TRY(init_mins(L.rowS[d], kSeedRows, s));
       PROHD_TRY(launch_tile<DP>(FMT_F32, ys[d], ydn[d], ycap[d], L.sh[d], L.dshort + 2 * d, kSeedRows,
                                 L.maxabs, nullptr, L.rowS[d], s));
       sp.d[d] = BoundJob{L.rowS[d], xs[d].n, L.w[d].cand, L.w[d].count, kSeedRows, L.hlow + d, zero[d]};
@@ -2182,8 +2182,9 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
     for (int j = 1; j <= L.nlev; ++j) {
       const int b = (j - 1) & 1;   // list this level writes
       const bool last = j == L.nlev;
+      const FillJob fr[2] = {{L.pw[0].rowF, caps2[0], kInfBits}, {L.pw[1].rowF, caps2[1], kInfBits}};
+      PROHD_TRY(fill_words(fr, 2, s));
       for (int d = 0; d < 2; ++d) {
-        PROHD_TRY(init_mins(L.pw[d].rowF, caps2[d], s));
         if (!last) {
           PROHD_TRY(launch_tile<DP>(fmt, xs[d], count2[d], caps2[d], L.sub[d][j],
                                     L.dsub + d * kPruneMaxLevels + j, cdiv(ycap[d], prune_stride(L.nlev, j)),

@@ -571,31 +571,184 @@ __global__ __launch_bounds__(kSegT) void compact_seg(const CompactJob* __restric
   }
 }
 
-// Small selections (a few hundred thousand entries or fewer) in one launch:
-// work-group b clears the flags of segment b, selects, and compacts the
-// flags into its index list.  The jobs travel as a kernel argument.
-constexpr int kSmallSel = 2;
-struct SmallSelPack {
-  SegJob sel[kSmallSel];
-  CompactJob cmp[kSmallSel];
-  int32_t njobs;
+// The k <= 64 largest keys of an array under the order above (larger key
+// first; equal keys: smaller index first), in two launches.  An entry
+// becomes one 64-bit composite, the order-preserving key in the high word
+// and the complemented index in the low word, so composites are distinct
+// and compare in that order; 0 marks an empty slot (the low word of a real
+// entry is at least 2^31).  Every wave reduces blocks of 64 x kTopR entries
+// to the 64 largest composites seen so far, by extraction: each lane sorts
+// its entries, then 64 times the wave takes the largest head among the
+// lanes and the lane that held it moves to its next entry.  The second
+// launch reduces the waves' lists the same way in one work-group per array
+// and writes the k indices in ascending order with their count.
+constexpr int kTopR = 8;                  // entries per lane per block
+constexpr int kTopBlock = 64 * kTopR;     // entries per wave per block
+constexpr int kTopMaxWaves = 1024;        // wave lists per array
+constexpr int kTopT = 256;                // first launch: 4 waves per work-group
+constexpr int kTopFinalT = 1024;          // second launch: 16 waves
+constexpr int kTopFinalR = 16;            // its entries per lane per block
+
+struct TopDev {
+  const uint32_t* keys;
+  const int64_t* dev_n;
+  int64_t n;
+  int32_t* idx;
+  int64_t* count;
+  int32_t k;
+};
+struct TopPack {
+  TopDev s[2];
+  unsigned long long* part;   // [nseg][nwaves][64] wave lists
+  int32_t nwaves;             // per array (a multiple of 4)
+  int32_t nseg;
 };
 
-constexpr int kSmallT = 1024;   // threads of the one-launch selection
+__device__ __forceinline__ int64_t top_len(const TopDev& t) {
+  const int64_t n = t.dev_n ? min(*t.dev_n, t.n) : t.n;
+  return n > 0 ? n : 0;
+}
 
-__global__ __launch_bounds__(kSmallT) void select_compact_small(const SmallSelPack P) {
-  __shared__ uint32_t hist[2][kSegBins];
-  __shared__ uint32_t scan_lds[kSmallT / 64];
-  __shared__ uint32_t s_bin[2], s_before[2];
-  if ((int)blockIdx.x >= P.njobs) return;
-  const SegJob j = P.sel[blockIdx.x];
-  int64_t n = j.dn ? *j.dn : j.n;
-  n = n < j.n ? (n > 0 ? n : 0) : j.n;
-  for (int64_t i = threadIdx.x; i < n; i += kSmallT) j.flags[i] = 0;
-  __syncthreads();   // cleared flags are visible to the whole work-group
-  select_seg_body<kSmallT>(j, hist, scan_lds, s_bin, s_before);
+__device__ __forceinline__ unsigned long long top_comp(uint32_t bits, int64_t i) {
+  return ((unsigned long long)fkey(__uint_as_float(bits)) << 32) |
+         (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+// Largest value over the wave (all lanes active), wave-uniform: maxima
+// within rows of 16 lanes through DPP (xor 1, xor 2, mirror within 8,
+// rotate by 8 within 16: every lane has a source), then over the four rows.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true));
+  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true));
+  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, true));
+  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true));
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// The high word's maximum, then the low word's among the lanes holding it.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+  const uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
+  const uint32_t mh = wave_max_u32(hi);
+  const uint32_t ml = wave_max_u32(hi == mh ? lo : 0u);
+  return ((unsigned long long)mh << 32) | ml;
+}
+
+// The 64 largest of the wave's R x 64 entries e and its carried list c
+// (lane l: the l-th largest so far, 0 if none); lane l gets the l-th
+// largest (0 where fewer than l + 1 entries are non-empty).  Each lane
+// sorts its R + 1 entries and keeps all but the first two in `lst` (this
+// wave's (R + 2) x 64 LDS slots, the last row zero); the head and the two
+// entries after it stay in registers.  Called by the whole wave.
+template <int R>
+__device__ __forceinline__ unsigned long long wave_top64(const unsigned long long (&e)[R],
+                                                         unsigned long long c,
+                                                         unsigned long long* lst) {
+  constexpr int M = R + 1;
+  unsigned long long v[M];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = e[q];
+  v[R] = c;
+  // descending order per lane (odd-even transposition network)
+#pragma unroll
+  for (int p = 0; p < M; ++p)
+#pragma unroll
+    for (int q = p & 1; q + 1 < M; q += 2) {
+      const unsigned long long a = v[q], b = v[q + 1];
+      v[q] = a > b ? a : b;
+      v[q + 1] = a > b ? b : a;
+    }
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 2; q < M; ++q) lst[q * 64 + lane] = v[q];
+  lst[M * 64 + lane] = 0ull;   // past the end
+  unsigned long long head = v[0], next = v[1], pre = M > 2 ? v[2] : 0ull, out = 0;
+  int h = 2;   // position of `pre` (the entry after `next`) in the lane's list
+  for (int it = 0; it < 64; ++it) {
+    const unsigned long long w = wave_max_u64(head);
+    if (w == 0) break;   // uniform: nothing left
+    if (lane == it) out = w;
+    const bool win = head == w;   // one lane (composites are distinct)
+    head = win ? next : head;
+    next = win ? pre : next;
+    h += win ? 1 : 0;
+    // every lane reloads `pre`; the load completes while the next maximum
+    // is formed
+    pre = lst[(h < M ? h : M) * 64 + lane];
+  }
+  return out;
+}
+
+__global__ __launch_bounds__(kTopT) void top_part(const TopPack P) {
+  const TopDev t = P.s[blockIdx.y];
+  const int64_t n = top_len(t);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gw = blockIdx.x * (kTopT / 64) + wave;
+  __shared__ unsigned long long lst[kTopT / 64][(kTopR + 2) * 64];
+  // wave gw takes the blocks gw, gw + nwaves, ... (loads clamped, so the
+  // R loads of a lane are unconditional and in flight together)
+  const int64_t nblk = (n + kTopBlock - 1) / kTopBlock;
+  unsigned long long best = 0;
+  for (int64_t b = gw; b < nblk; b += P.nwaves) {
+    unsigned long long e[kTopR];
+#pragma unroll
+    for (int q = 0; q < kTopR; ++q) {
+      const int64_t i = b * kTopBlock + q * 64 + lane;
+      const uint32_t bits = t.keys[min(i, n - 1)];
+      e[q] = i < n ? top_comp(bits, i) : 0ull;
+    }
+    best = wave_top64<kTopR>(e, best, lst[wave]);
+  }
+  P.part[((size_t)blockIdx.y * P.nwaves + gw) * 64 + lane] = best;
+}
+
+__global__ __launch_bounds__(kTopFinalT) void top_final(const TopPack P) {
+  __shared__ unsigned long long lists[kTopFinalT / 64][64];
+  __shared__ unsigned long long lst[kTopFinalT / 64][(kTopFinalR + 2) * 64];
+  const TopDev t = P.s[blockIdx.x];
+  const unsigned long long* part = P.part + (size_t)blockIdx.x * P.nwaves * 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ncand = (int64_t)P.nwaves * 64;
+  constexpr int FB = 64 * kTopFinalR;
+  const int64_t nblk = (ncand + FB - 1) / FB;
+  unsigned long long best = 0;
+  for (int64_t b = wave; b < nblk; b += kTopFinalT / 64) {
+    unsigned long long e[kTopFinalR];
+#pragma unroll
+    for (int q = 0; q < kTopFinalR; ++q) {
+      const int64_t i = b * FB + q * 64 + lane;
+      e[q] = part[min(i, ncand - 1)];
+      e[q] = i < ncand ? e[q] : 0ull;
+    }
+    best = wave_top64<kTopFinalR>(e, best, lst[wave]);
+  }
+  lists[wave][lane] = best;
   __syncthreads();
-  compact_seg_body<kSmallT>(P.cmp[blockIdx.x], scan_lds);
+  if (wave != 0) return;
+  unsigned long long e[kTopFinalT / 64];
+#pragma unroll
+  for (int q = 0; q < kTopFinalT / 64; ++q) e[q] = lists[q][lane];
+  // wave 0's own slots serve again (16 lists: as many entries as a block)
+  static_assert(kTopFinalT / 64 == kTopFinalR, "the last pass reuses a wave's slots");
+  const unsigned long long top = wave_top64<kTopFinalT / 64>(e, 0ull, lst[0]);
+  const int64_t n = top_len(t);
+  const int k = (int)min<int64_t>(t.k, n);
+  // lanes below k hold the k largest; their indices in ascending order
+  const bool on = lane < k;
+  const uint32_t idx = on ? 0xFFFFFFFFu - (uint32_t)top : 0xFFFFFFFFu;
+  int rank = 0;
+  for (int j = 0; j < 64; ++j) rank += __shfl(idx, j) < idx ? 1 : 0;
+  if (on) t.idx[rank] = (int32_t)idx;
+  if (lane == 0) *t.count = k;
+}
+
+int top_waves(int64_t max_n) {
+  const int64_t w = std::min<int64_t>(kTopMaxWaves, std::max<int64_t>(1, cdiv(max_n, kTopBlock)));
+  return (int)cdiv(w, 4) * 4;
 }
 
 struct SelLayout {
@@ -694,18 +847,31 @@ prohd_status scatter_index_flags(const int32_t* idx, const int64_t* count, int64
   return PROHD_OK;
 }
 
-prohd_status select_compact_small(const SelSegment* segs, int nseg, int32_t* const* idx,
-                                  int64_t cap, int64_t* const* count, hipStream_t s) {
+size_t topk_ws_bytes(int64_t max_n) {
+  return (size_t)2 * top_waves(max_n) * 64 * sizeof(unsigned long long) + 256;
+}
+
+prohd_status top_keys(const TopSegment* segs, int nseg, void* ws, size_t ws_bytes, hipStream_t s) {
   if (nseg <= 0) return PROHD_OK;
-  if (nseg > kSmallSel) return fail(PROHD_EINVAL, "select_compact_small: at most 2 segments");
-  SmallSelPack P{};
+  if (nseg > 2) return fail(PROHD_EINVAL, "top_keys: at most 2 arrays");
+  int64_t max_n = 1;
   for (int i = 0; i < nseg; ++i) {
-    const SelSegment& g = segs[i];
-    P.sel[i] = SegJob{g.vals, g.n, g.dev_n, g.lo, g.hi, g.flags};
-    P.cmp[i] = CompactJob{g.flags, g.n, g.dev_n, idx[i], cap, count[i]};
+    if (segs[i].k < 0 || segs[i].k > 64) return fail(PROHD_EINVAL, "top_keys: k outside [0, 64]");
+    if (segs[i].n > INT32_MAX) return fail(PROHD_EINVAL, "top_keys: more than 2^31 - 1 entries");
+    max_n = std::max<int64_t>(max_n, segs[i].n);
   }
-  P.njobs = nseg;
-  PROHD_LAUNCH("select_small", select_compact_small, dim3(nseg), dim3(kSmallT), 0, s, P);
+  TopPack P{};
+  P.nwaves = top_waves(max_n);
+  P.nseg = nseg;
+  if ((size_t)nseg * P.nwaves * 64 * sizeof(unsigned long long) > ws_bytes)
+    return fail(PROHD_EWORKSPACE, "top_keys: workspace too small");
+  P.part = static_cast<unsigned long long*>(ws);
+  for (int i = 0; i < nseg; ++i) {
+    const TopSegment& g = segs[i];
+    P.s[i] = TopDev{g.keys, g.dev_n, g.n, g.idx, g.count, g.k};
+  }
+  PROHD_LAUNCH("top_part", top_part, dim3(P.nwaves / (kTopT / 64), nseg), dim3(kTopT), 0, s, P);
+  PROHD_LAUNCH("top_final", top_final, dim3(nseg), dim3(kTopFinalT), 0, s, P);
   return PROHD_OK;
 }
 

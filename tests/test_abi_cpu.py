@@ -82,6 +82,13 @@ FAKE = 0x1000  # never dereferenced: validation fails first
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 1 << 6, FAKE, FAKE, 1 << 24, None), 1, "flag"),
     (lambda L: L.prohd_hd(FAKE, 10, FAKE, 10, 4, FAKE, FAKE, FAKE, FAKE, 5, 5, 12, FAKE, FAKE, 1 << 24, None), 1, "exclusive"),
     (lambda L: L.exact_hd(FAKE, 10, FAKE, 10, 4, 2, FAKE, None, None, FAKE, 1 << 24, None), 1, "flag"),
+    (lambda L: L.prohd_top_keys(FAKE, 10, None, 65, FAKE, FAKE, FAKE, 1 << 20, None), 1, "k must"),
+    (lambda L: L.prohd_top_keys(FAKE, 10, None, -1, FAKE, FAKE, FAKE, 1 << 20, None), 1, "k must"),
+    (lambda L: L.prohd_top_keys(FAKE, -1, None, 4, FAKE, FAKE, FAKE, 1 << 20, None), 1, "n must"),
+    (lambda L: L.prohd_top_keys(FAKE, 1 << 31, None, 4, FAKE, FAKE, FAKE, 1 << 20, None), 1, "n must"),
+    (lambda L: L.prohd_top_keys(None, 10, None, 4, FAKE, FAKE, FAKE, 1 << 20, None), 1, "non-null"),
+    (lambda L: L.prohd_top_keys(FAKE, 10, None, 4, None, FAKE, FAKE, 1 << 20, None), 1, "non-null"),
+    (lambda L: L.prohd_top_keys(FAKE, 10, None, 4, FAKE, FAKE, FAKE, 1 << 18, None), 3, "workspace"),
 ])
 def test_validation_errors(call, code, msg):
     got, text = _err(call)

@@ -47,7 +47,8 @@ MUTATIONS = [
      "principal components: smallest eigenvalues"),
     ("prohd.py", "v = V[:, c] / np.linalg.norm(V[:, c])", "v = V[c, :] / np.linalg.norm(V[c, :])",
      "principal components: transposed eigenvectors"),
-    ("prohd.py", "top = np.lexsort((idx, -p))[:k]", "top = np.lexsort((idx, p))[-k:]",
+    ("prohd.py", "return np.sort(np.lexsort((np.arange(p.size), -p))[:k])",
+     "return np.sort(np.lexsort((np.arange(p.size), p))[-k:])",
      "selection: stable slice at the top end (ties to larger indices)"),
     ("prohd.py", "bottom = np.lexsort((idx, p))[:k]", "bottom = np.lexsort((idx, p))[:k - 1]",
      "selection: one short at the bottom end"),

@@ -207,6 +207,23 @@ def test_extreme_indices_against_rank_definition():
         assert list(got) == list(oracle.extreme_indices(-p, k))  # end symmetry
 
 
+def test_largest_indices_against_rank_definition():
+    # Brute force as above, the largest end alone: i is kept when fewer than
+    # k entries precede it in (-value, index); empty input and k = 0 keep none.
+    g = np.random.default_rng(16)
+    for trial in range(40):
+        n = int(g.integers(0, 30))
+        p = g.integers(-3, 4, size=n).astype(np.float64)
+        if trial % 4 == 0:
+            p[p == 0] = -0.0
+        if trial % 7 == 0 and n:
+            p[g.integers(0, n)] = np.inf
+        k = int(g.integers(0, n + 3))
+        want = [i for i in range(n)
+                if sum(1 for j in range(n) if (-p[j], j) < (-p[i], i)) < min(k, n)]
+        assert list(oracle.largest_indices(p, k)) == want, (p, k)
+
+
 def test_select_union_over_directions():
     P = np.array([[5.0, 1.0, 3.0, 2.0, 4.0], [0.0, 9.0, 8.0, 7.0, 6.0]])
     IA, IB = oracle.select(P, P[::-1], [1, 1], [2, 1])
