@@ -577,17 +577,17 @@ __global__ __launch_bounds__(kSegT) void compact_seg(const CompactJob* __restric
 // and the complemented index in the low word, so composites are distinct
 // and compare in that order; 0 marks an empty slot (the low word of a real
 // entry is at least 2^31).  Every wave reduces blocks of 64 x kTopR entries
-// to the 64 largest composites seen so far, by extraction: each lane sorts
-// its entries, then 64 times the wave takes the largest head among the
-// lanes and the lane that held it moves to its next entry.  The second
-// launch reduces the waves' lists the same way in one work-group per array
-// and writes the k indices in ascending order with their count.
+// to the 64 largest composites seen so far with bitonic networks across its
+// lanes (each register of 64 entries sorted, then sorted lists merged
+// pairwise, keeping the larger half).  The second launch merges the waves'
+// lists the same way in one work-group per array and writes the k indices
+// in ascending order with their count.
 constexpr int kTopR = 8;                  // entries per lane per block
 constexpr int kTopBlock = 64 * kTopR;     // entries per wave per block
 constexpr int kTopMaxWaves = 1024;        // wave lists per array
 constexpr int kTopT = 256;                // first launch: 4 waves per work-group
 constexpr int kTopFinalT = 1024;          // second launch: 16 waves
-constexpr int kTopFinalR = 16;            // its entries per lane per block
+constexpr int kTopFinalR = 16;            // its lists per wave per block
 
 struct TopDev {
   const uint32_t* keys;
@@ -614,81 +614,122 @@ __device__ __forceinline__ unsigned long long top_comp(uint32_t bits, int64_t i)
          (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
 }
 
-// Largest value over the wave (all lanes active), wave-uniform: maxima
-// within rows of 16 lanes through DPP (xor 1, xor 2, mirror within 8,
-// rotate by 8 within 16: every lane has a source), then over the four rows.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true));
-  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true));
-  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, true));
-  x = max(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true));
-  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
-  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
-  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
-  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
-  return max(max(a, b), max(c, d));
-}
-
-// The high word's maximum, then the low word's among the lanes holding it.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
-  const uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
-  const uint32_t mh = wave_max_u32(hi);
-  const uint32_t ml = wave_max_u32(hi == mh ? lo : 0u);
-  return ((unsigned long long)mh << 32) | ml;
-}
-
-// The 64 largest of the wave's R x 64 entries e and its carried list c
-// (lane l: the l-th largest so far, 0 if none); lane l gets the l-th
-// largest (0 where fewer than l + 1 entries are non-empty).  Each lane
-// sorts its R + 1 entries and keeps all but the first two in `lst` (this
-// wave's (R + 2) x 64 LDS slots, the last row zero); the head and the two
-// entries after it stay in registers.  Called by the whole wave.
-template <int R>
-__device__ __forceinline__ unsigned long long wave_top64(const unsigned long long (&e)[R],
-                                                         unsigned long long c,
-                                                         unsigned long long* lst) {
-  constexpr int M = R + 1;
-  unsigned long long v[M];
-#pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = e[q];
-  v[R] = c;
-  // descending order per lane (odd-even transposition network)
-#pragma unroll
-  for (int p = 0; p < M; ++p)
-#pragma unroll
-    for (int q = p & 1; q + 1 < M; q += 2) {
-      const unsigned long long a = v[q], b = v[q + 1];
-      v[q] = a > b ? a : b;
-      v[q + 1] = a > b ? b : a;
-    }
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int q = 2; q < M; ++q) lst[q * 64 + lane] = v[q];
-  lst[M * 64 + lane] = 0ull;   // past the end
-  unsigned long long head = v[0], next = v[1], pre = M > 2 ? v[2] : 0ull, out = 0;
-  int h = 2;   // position of `pre` (the entry after `next`) in the lane's list
-  for (int it = 0; it < 64; ++it) {
-    const unsigned long long w = wave_max_u64(head);
-    if (w == 0) break;   // uniform: nothing left
-    if (lane == it) out = w;
-    const bool win = head == w;   // one lane (composites are distinct)
-    head = win ? next : head;
-    next = win ? pre : next;
-    h += win ? 1 : 0;
-    // every lane reloads `pre`; the load completes while the next maximum
-    // is formed
-    pre = lst[(h < M ? h : M) * 64 + lane];
+// Lane l's value from lane l ^ J (both words): DPP for J = 1, 2 (quad
+// permutes) and 8 (rotation by 8 within a row of 16 lanes), a cross-lane
+// permute otherwise.  All lanes active.
+template <int J>
+__device__ __forceinline__ unsigned long long lane_xor(unsigned long long x) {
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  uint32_t l2, h2;
+  if constexpr (J == 1 || J == 2 || J == 8) {
+    constexpr int CTRL = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
+    l2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xF, 0xF, true);
+    h2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xF, 0xF, true);
+  } else {
+    l2 = __shfl_xor(lo, J);
+    h2 = __shfl_xor(hi, J);
   }
-  return out;
+  return ((unsigned long long)h2 << 32) | l2;
+}
+
+// Compare-exchange with lane l ^ J: the lower lane of the pair keeps the
+// larger value in a descending run (the smaller in an ascending one).
+template <int J>
+__device__ __forceinline__ unsigned long long cx(unsigned long long x, int lane, bool desc) {
+  const unsigned long long y = lane_xor<J>(x);
+  const bool keep_max = ((lane & J) == 0) == desc;
+  return keep_max == (x > y) ? x : y;
+}
+
+// A bitonic sequence across the 64 lanes into descending (DESC) or
+// ascending order.
+template <bool DESC>
+__device__ __forceinline__ unsigned long long bitonic_merge(unsigned long long x, int lane) {
+  x = cx<32>(x, lane, DESC);
+  x = cx<16>(x, lane, DESC);
+  x = cx<8>(x, lane, DESC);
+  x = cx<4>(x, lane, DESC);
+  x = cx<2>(x, lane, DESC);
+  return cx<1>(x, lane, DESC);
+}
+
+// Any 64 values across the lanes into descending (DESC) or ascending order:
+// runs of K = 2, 4, .., 32 lanes sorted in alternating directions (the
+// run's direction is DESC where lane & K is 0), each pair of runs then
+// merged as one bitonic run of 2K.
+template <bool DESC>
+__device__ __forceinline__ unsigned long long bitonic_sort(unsigned long long x, int lane) {
+  bool d = ((lane & 2) == 0) == DESC;
+  x = cx<1>(x, lane, d);
+  d = ((lane & 4) == 0) == DESC;
+  x = cx<2>(x, lane, d);
+  x = cx<1>(x, lane, d);
+  d = ((lane & 8) == 0) == DESC;
+  x = cx<4>(x, lane, d);
+  x = cx<2>(x, lane, d);
+  x = cx<1>(x, lane, d);
+  d = ((lane & 16) == 0) == DESC;
+  x = cx<8>(x, lane, d);
+  x = cx<4>(x, lane, d);
+  x = cx<2>(x, lane, d);
+  x = cx<1>(x, lane, d);
+  d = ((lane & 32) == 0) == DESC;
+  x = cx<16>(x, lane, d);
+  x = cx<8>(x, lane, d);
+  x = cx<4>(x, lane, d);
+  x = cx<2>(x, lane, d);
+  x = cx<1>(x, lane, d);
+  return bitonic_merge<DESC>(x, lane);
+}
+
+// The 64 largest of R >= 2 sorted lists across the lanes (list q descending
+// for even q, ascending for odd q), descending (DESC) or ascending.  The
+// lane-wise larger of a descending and an ascending list is a bitonic
+// sequence holding the 64 largest of the two; pairs are merged level by
+// level, the results again alternating in direction.
+template <int R, bool DESC>
+__device__ __forceinline__ unsigned long long top64_lists(unsigned long long (&e)[R], int lane) {
+  static_assert(R >= 2 && (R & (R - 1)) == 0, "R: a power of two, at least 2");
+#pragma unroll
+  for (int w = R; w > 1; w >>= 1) {
+#pragma unroll
+    for (int q = 0; q < w / 2; ++q) {
+      const unsigned long long a = e[2 * q], b = e[2 * q + 1];
+      const unsigned long long c = a > b ? a : b;
+      const bool d = w == 2 ? DESC : (q & 1) == 0;
+      e[q] = d ? bitonic_merge<true>(c, lane) : bitonic_merge<false>(c, lane);
+    }
+  }
+  return e[0];
+}
+
+// One block of a wave: the 64 largest of its R x 64 unsorted entries e and
+// its carried list c (descending), descending: lane l gets the l-th largest
+// (0 where fewer than l + 1 entries are non-empty).  Called by the whole
+// wave.
+template <int R>
+__device__ __forceinline__ unsigned long long block_top64(unsigned long long (&e)[R],
+                                                          unsigned long long c, int lane) {
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    e[q] = (q & 1) == 0 ? bitonic_sort<true>(e[q], lane) : bitonic_sort<false>(e[q], lane);
+  const unsigned long long t = top64_lists<R, false>(e, lane);
+  return bitonic_merge<true>(c > t ? c : t, lane);
+}
+
+// The same for R sorted lists (alternating directions, as top64_lists).
+template <int R>
+__device__ __forceinline__ unsigned long long lists_top64(unsigned long long (&e)[R],
+                                                          unsigned long long c, int lane) {
+  const unsigned long long t = top64_lists<R, false>(e, lane);
+  return bitonic_merge<true>(c > t ? c : t, lane);
 }
 
 __global__ __launch_bounds__(kTopT) void top_part(const TopPack P) {
   const TopDev t = P.s[blockIdx.y];
   const int64_t n = top_len(t);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int gw = blockIdx.x * (kTopT / 64) + wave;
-  __shared__ unsigned long long lst[kTopT / 64][(kTopR + 2) * 64];
+  const int gw = blockIdx.x * (kTopT / 64) + (threadIdx.x >> 6);
   // wave gw takes the blocks gw, gw + nwaves, ... (loads clamped, so the
   // R loads of a lane are unconditional and in flight together)
   const int64_t nblk = (n + kTopBlock - 1) / kTopBlock;
@@ -701,40 +742,38 @@ __global__ __launch_bounds__(kTopT) void top_part(const TopPack P) {
       const uint32_t bits = t.keys[min(i, n - 1)];
       e[q] = i < n ? top_comp(bits, i) : 0ull;
     }
-    best = wave_top64<kTopR>(e, best, lst[wave]);
+    best = block_top64<kTopR>(e, best, lane);
   }
   P.part[((size_t)blockIdx.y * P.nwaves + gw) * 64 + lane] = best;
 }
 
 __global__ __launch_bounds__(kTopFinalT) void top_final(const TopPack P) {
   __shared__ unsigned long long lists[kTopFinalT / 64][64];
-  __shared__ unsigned long long lst[kTopFinalT / 64][(kTopFinalR + 2) * 64];
   const TopDev t = P.s[blockIdx.x];
   const unsigned long long* part = P.part + (size_t)blockIdx.x * P.nwaves * 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t ncand = (int64_t)P.nwaves * 64;
-  constexpr int FB = 64 * kTopFinalR;
-  const int64_t nblk = (ncand + FB - 1) / FB;
+  // wave w merges the lists w R, .., w R + R - 1, then (w + 16) R, ..; odd
+  // lists of a block are read back to front (ascending)
+  constexpr int R = kTopFinalR;
+  const int nblk = (P.nwaves + R - 1) / R;
   unsigned long long best = 0;
-  for (int64_t b = wave; b < nblk; b += kTopFinalT / 64) {
-    unsigned long long e[kTopFinalR];
+  for (int b = wave; b < nblk; b += kTopFinalT / 64) {
+    unsigned long long e[R];
 #pragma unroll
-    for (int q = 0; q < kTopFinalR; ++q) {
-      const int64_t i = b * FB + q * 64 + lane;
-      e[q] = part[min(i, ncand - 1)];
-      e[q] = i < ncand ? e[q] : 0ull;
+    for (int q = 0; q < R; ++q) {
+      const int g = b * R + q;
+      const unsigned long long v = part[(size_t)min(g, P.nwaves - 1) * 64 + ((q & 1) ? 63 - lane : lane)];
+      e[q] = g < P.nwaves ? v : 0ull;
     }
-    best = wave_top64<kTopFinalR>(e, best, lst[wave]);
+    best = lists_top64<R>(e, best, lane);
   }
   lists[wave][lane] = best;
   __syncthreads();
   if (wave != 0) return;
   unsigned long long e[kTopFinalT / 64];
 #pragma unroll
-  for (int q = 0; q < kTopFinalT / 64; ++q) e[q] = lists[q][lane];
-  // wave 0's own slots serve again (16 lists: as many entries as a block)
-  static_assert(kTopFinalT / 64 == kTopFinalR, "the last pass reuses a wave's slots");
-  const unsigned long long top = wave_top64<kTopFinalT / 64>(e, 0ull, lst[0]);
+  for (int q = 0; q < kTopFinalT / 64; ++q) e[q] = lists[q][(q & 1) ? 63 - lane : lane];
+  const unsigned long long top = top64_lists<kTopFinalT / 64, true>(e, lane);
   const int64_t n = top_len(t);
   const int k = (int)min<int64_t>(t.k, n);
   // lanes below k hold the k largest; their indices in ascending order
