@@ -827,7 +827,12 @@ __device__ __forceinline__ void eig_body(
       // start vector (zero on padding rows keeps them exactly zero)
       for (int k = 0; k < DP; ++k) x[k] = (k < D) ? start_value(k, c) : 0.0;
     }
-    for (int it = 0; it < 5; ++it) {
+    // three iterations: the shifts are the bisection's eigenvalues (float64
+    // resolution), so one solve already leaves another eigenvector's share
+    // below (shift error) / (gap to it) and the next two take it to rounding
+    // (a gap under 1e-3 of the spectral radius makes a cluster, whose members
+    // are orthogonalised after every solve)
+    for (int it = 0; it < 3; ++it) {
       if (t < nr && ok) {
         // forward: apply the row interchanges and multipliers.  The running
         // row stays in a register; the operands of SB steps are read into
