@@ -1138,30 +1138,35 @@ __device__ __forceinline__ void refine_dyn_body(const float* __restrict__ Xp,
     refine_block<DP>(Xp, cand, R, Yp, nY, ysplit, ysi, cb, best);
 }
 
+// Both directions in one launch (grid y = direction).
+struct RefineDir {
+  const float* Xp;            // outer rows (prepared)
+  const int32_t* cand;        // listed outer rows
+  const int64_t* dR;          // their device count
+  const float* Yp;            // inner set (prepared)
+  const int64_t* dnY;         // its device length, or null
+  int64_t hnY;                // its host bound
+  unsigned long long* best;   // per listed row: (float bits of d^2, index)
+};
+struct RefinePair {
+  RefineDir d[2];
+};
+
 template <int DP>
-__global__ __launch_bounds__(256) void refine_rows_dyn(const float* __restrict__ Xp,
-                                                       const int32_t* __restrict__ cand,
-                                                       const int64_t* __restrict__ dR,
-                                                       const float* __restrict__ Yp,
-                                                       const int64_t* __restrict__ dnY, int64_t hnY,
-                                                       int ysplit,
-                                                       unsigned long long* __restrict__ best) {
-  refine_dyn_body<DP>(Xp, cand, dR, Yp, dnY, hnY, ysplit, best, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void refine_rows_dyn(const RefinePair P) {
+  const RefineDir d = P.d[blockIdx.y];
+  refine_dyn_body<DP>(d.Xp, d.cand, d.dR, d.Yp, d.dnY, d.hnY, gridDim.x, d.best, blockIdx.x, gridDim.x);
 }
 
 // The same pass for R <= kThinRows rows (a kernel of its own: it needs far
 // fewer registers than the matrix-core block, so more waves hide the
 // memory latency); with more rows it returns at once.
 template <int DP>
-__global__ __launch_bounds__(256) void refine_rows_thin(const float* __restrict__ Xp,
-                                                        const int32_t* __restrict__ cand,
-                                                        const int64_t* __restrict__ dR,
-                                                        const float* __restrict__ Yp,
-                                                        const int64_t* __restrict__ dnY, int64_t hnY,
-                                                        unsigned long long* __restrict__ best) {
-  const int64_t R = *dR;
+__global__ __launch_bounds__(256) void refine_rows_thin(const RefinePair P) {
+  const RefineDir d = P.d[blockIdx.y];
+  const int64_t R = *d.dR;
   if (R < 1 || R > kThinRows) return;
-  refine_thin<DP>(Xp, cand, R, Yp, dev_or(dnY, hnY), gridDim.x, blockIdx.x, best);
+  refine_thin<DP>(d.Xp, d.cand, R, d.Yp, dev_or(d.dnY, d.hnY), gridDim.x, blockIdx.x, d.best);
 }
 
 // ------------------------------------------------- certified refinement
@@ -2021,15 +2026,12 @@ prohd_status launch_gather_list(int fmt, PrepSet X, const int32_t* idx, const in
 // Second refinement pass of one direction: cand2 / count2 / best2 against
 // Y (device count known only on the device).
 template <int DP>
-prohd_status launch_refine_dyn(const float* Xp, const int32_t* cand, const int64_t* dR,
-                               const float* Yp, const int64_t* dnY, int64_t capY,
-                               unsigned long long* best, hipStream_t s) {
+prohd_status launch_refine_pair(const RefinePair& P, hipStream_t s) {
+  const int64_t capY = std::max(P.d[0].hnY, P.d[1].hnY);
   const int split = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)cu_count(), capY / 128));
-  PROHD_LAUNCH("hd_dyn_refine", refine_rows_dyn<DP>, dim3((unsigned)split), dim3(256), 0, s, Xp, cand,
-               dR, Yp, dnY, capY, split, best);
+  PROHD_LAUNCH("hd_dyn_refine", refine_rows_dyn<DP>, dim3((unsigned)split, 2), dim3(256), 0, s, P);
   const int tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(8 * (int64_t)cu_count(), capY / 256));
-  PROHD_LAUNCH("hd_dyn_refine", refine_rows_thin<DP>, dim3((unsigned)tsplit), dim3(256), 0, s, Xp, cand,
-               dR, Yp, dnY, capY, best);
+  PROHD_LAUNCH("hd_dyn_refine", refine_rows_thin<DP>, dim3((unsigned)tsplit, 2), dim3(256), 0, s, P);
   return PROHD_OK;
 }
 
@@ -2216,8 +2218,12 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
       }
     }
   }
-  PROHD_TRY(launch_refine_dyn<DP>(L.xa.p, cand2[0], count2[0], ysB.p, ydnB, ycapB, best2[0], s));
-  PROHD_TRY(launch_refine_dyn<DP>(L.xb.p, cand2[1], count2[1], ysA.p, ydnA, ycapA, best2[1], s));
+  {
+    RefinePair rp{};
+    rp.d[0] = RefineDir{L.xa.p, cand2[0], count2[0], ysB.p, ydnB, ycapB, best2[0]};
+    rp.d[1] = RefineDir{L.xb.p, cand2[1], count2[1], ysA.p, ydnA, ycapA, best2[1]};
+    PROHD_TRY(launch_refine_pair<DP>(rp, s));
+  }
   const DirIn ab{nullptr, nullptr, nullptr, best2[0], cand2[0], count2[0], idxA, full ? nullptr : idxB, A, B};
   const DirIn ba{nullptr, nullptr, nullptr, best2[1], cand2[1], count2[1], idxB, full ? nullptr : idxA, B, A};
   PROHD_LAUNCH("hd_finalize", finalize, dim3(1), dim3(256), 0, s, ab, ba, D, dnA, capA, dnB, capB,
