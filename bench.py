@@ -580,12 +580,14 @@ def main():
             float(nA + nB) * D * (D + 1), avg_ms("stats_gram"), 78.6, "TFLOP/s", 1)
     if lev and "hd_tile_rows" in kernels:
         # first pruning level: every candidate row against every F-th row of
-        # the other list, 2 D flops per pair, two launches (one per direction)
+        # the other list, 2 D flops per pair, both directions (one launch,
+        # or one per direction)
         F = 16 ** lev
-        tf = 2.0 * D * (nAs * math.ceil(nBs / F) + nBs * math.ceil(nAs / F)) / 2
+        nl = kernels["hd_tile_rows"]["launches_per_step"]
+        tf = 2.0 * D * (nAs * math.ceil(nBs / F) + nBs * math.ceil(nAs / F)) / nl
         path_roof["hd_tile"] = entry(
             f"dist_tile, first pruning level (F = {F}, float32 v_mfma_f32_32x32x2f32)", "mfma", tf,
-            avg_ms("hd_tile_rows"), PEAK_FP32_MFMA, "TFLOP/s", 2)
+            avg_ms("hd_tile_rows"), PEAK_FP32_MFMA, "TFLOP/s", nl)
     elif not lev and "hd_tile" in kernels:
         path_roof["hd_tile"] = entry(
             "dist_tile (candidate distance, float32 v_mfma_f32_32x32x2f32)", "mfma",

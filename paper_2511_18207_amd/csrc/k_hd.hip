@@ -473,12 +473,13 @@ __device__ __forceinline__ int64_t tile_split(int64_t xt, int64_t nyb, int64_t G
 // takes items b, b + G, ...), then its share of the leftover items' Y blocks.
 // seg(row tile, first block, end block) runs one segment; every thread of
 // the work-group reaches the same calls.
+// (bx, G: this work-group's place among the G that share the pair.)
 template <class Seg>
-__device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S, Seg&& seg) {
-  const int64_t G = gridDim.x;
+__device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S, int64_t bx, int64_t G,
+                                              Seg&& seg) {
   const int64_t items = xt * S;
   const int64_t full = items / G * G;
-  for (int64_t i = blockIdx.x; i < full; i += G) {
+  for (int64_t i = bx; i < full; i += G) {
     const int64_t ysi = i / xt, xblk = i - ysi * xt;
     seg(xblk, ysi * nyb / S, (ysi + 1) * nyb / S);
   }
@@ -488,8 +489,8 @@ __device__ __forceinline__ void tile_schedule(int64_t xt, int64_t nyb, int64_t S
   if (left == 0) return;
   const int64_t cmax = (nyb + S - 1) / S;
   const int64_t cells = left * cmax;
-  int64_t w = cells * blockIdx.x / G;
-  const int64_t hi = cells * (blockIdx.x + 1) / G;
+  int64_t w = cells * bx / G;
+  const int64_t hi = cells * (bx + 1) / G;
   while (w < hi) {
     const int64_t q = w / cmax;
     const int64_t end = min(hi, (q + 1) * cmax);
@@ -524,10 +525,53 @@ __global__ __launch_bounds__(512) void dist_tile(const float* __restrict__ Xp,
   const int64_t nyb = (nY + BN - 1) / BN;
   if (xt == 0 || nyb == 0) return;
   const int64_t S = tile_split(xt, nyb, gridDim.x);
-  tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
+  tile_schedule(xt, nyb, S, blockIdx.x, gridDim.x, [&](int64_t xblk, int64_t b0, int64_t b1) {
     __syncthreads();  // LDS of the previous segment is no longer read
     dist_seg<DP, COLMIN, GX, BNT>(Xp, xn, xidx, nX, Yp, yn, xblk * kTileRows, b0 * BN,
                                   min(nY, b1 * BN), rowmin, colmin);
+  });
+}
+
+// Both directions of a search in one launch: work-groups [0, g0) run the
+// first direction's schedule among themselves, the rest the second's (g0 a
+// multiple of 8 where the grid allows, so a work-group's XCD is the same
+// in both numberings).  Two directions of a few hundred row tiles each fill
+// the chip together where one alone leaves it half idle.
+struct TileDir {
+  const float* Xp;
+  const float* xn;
+  const int32_t* xidx;
+  const int64_t* dnX;
+  int64_t hnX;
+  const float* Yp;
+  const float* yn;
+  const int64_t* dnY;
+  int64_t hnY;
+  uint32_t* rowmin;
+  uint32_t* colmin;
+};
+struct TilePair {
+  TileDir d[2];
+  int32_t g0;
+};
+
+template <int DP, bool COLMIN, bool GX, int BNT>
+__global__ __launch_bounds__(512) void dist_tile2(const TilePair P) {
+  constexpr int BN = BNT;
+  const bool second = (int)blockIdx.x >= P.g0;   // uniform
+  const TileDir d = P.d[second ? 1 : 0];
+  const int64_t G = second ? (int64_t)gridDim.x - P.g0 : P.g0;
+  const int64_t bx = second ? (int64_t)blockIdx.x - P.g0 : blockIdx.x;
+  const int64_t nX = dev_or(d.dnX, d.hnX);
+  const int64_t nY = dev_or(d.dnY, d.hnY);
+  const int64_t xt = (nX + kTileRows - 1) / kTileRows;
+  const int64_t nyb = (nY + BN - 1) / BN;
+  if (xt == 0 || nyb == 0) return;
+  const int64_t S = tile_split(xt, nyb, G);
+  tile_schedule(xt, nyb, S, bx, G, [&](int64_t xblk, int64_t b0, int64_t b1) {
+    __syncthreads();  // LDS of the previous segment is no longer read
+    dist_seg<DP, COLMIN, GX, BNT>(d.Xp, d.xn, d.xidx, nX, d.Yp, d.yn, xblk * kTileRows, b0 * BN,
+                                  min(nY, b1 * BN), d.rowmin, d.colmin);
   });
 }
 
@@ -879,7 +923,7 @@ __global__ __launch_bounds__(512) void dist_tile_lp(const uint8_t* __restrict__ 
   const int64_t nyb = (nY + kLpBN - 1) / kLpBN;
   if (xt == 0 || nyb == 0) return;
   const int64_t S = tile_split(xt, nyb, gridDim.x);
-  tile_schedule(xt, nyb, S, [&](int64_t xblk, int64_t b0, int64_t b1) {
+  tile_schedule(xt, nyb, S, blockIdx.x, gridDim.x, [&](int64_t xblk, int64_t b0, int64_t b1) {
     __syncthreads();  // LDS of the previous segment is no longer read
     dist_seg_lp<DP, FMT, COLMIN, GX>(Xq, xn, xidx, nX, Yq, yn, xblk * kLpTileRows, b0 * kLpBN,
                                  min(nY, b1 * kLpBN), maxabs, rowmin, colmin);
@@ -1857,6 +1901,78 @@ prohd_status launch_tile(int fmt, PrepSet X, const int64_t* dnX, int64_t capX, P
 }
 
 
+// One direction of a tile search (the arguments of launch_tile).
+struct TileArgs {
+  PrepSet X;
+  const int64_t* dnX;
+  int64_t capX;
+  PrepSet Y;
+  const int64_t* dnY;
+  int64_t capY;
+  uint32_t* rowmin;
+  uint32_t* colmin;
+  const int32_t* xidx;
+};
+
+// Both directions of one kind in one float32 launch (dist_tile2) when they
+// take the same tile form; otherwise, or in the low-precision formats, one
+// launch each.
+template <int DP, bool COLMIN, bool GX>
+prohd_status launch_tile_pair_k(int fmt, const TileArgs& a, const TileArgs& b, const uint32_t* maxabs,
+                                hipStream_t s) {
+  auto one = [&](const TileArgs& t) {
+    return launch_tile_k<DP, COLMIN, GX>(fmt, t.X, t.xidx, t.dnX, t.capX, t.Y, t.dnY, t.capY, maxabs,
+                                         t.rowmin, t.colmin, s);
+  };
+  auto use32 = [&](const TileArgs& t) {
+    const int64_t xt = cdiv(t.capX, kTileRows);
+    return tile_bn<DP>() > kBN &&
+           (t.capY <= kBN || (t.capY <= 2 * kBN && xt <= 2 * tile_grid(dist_tile<DP, COLMIN, GX, kBN>,
+                                                                     int64_t(1) << 40)));
+  };
+  if (fmt != FMT_F32 || use32(a) != use32(b)) {
+    const prohd_status st = one(a);
+    return st != PROHD_OK ? st : one(b);
+  }
+  const bool b32 = use32(a);
+  const int bn = b32 ? kBN : tile_bn<DP>();
+  const int64_t ia = cdiv(a.capX, kTileRows) * cdiv(a.capY, bn);
+  const int64_t ib = cdiv(b.capX, kTileRows) * cdiv(b.capY, bn);
+  TilePair P{};
+  P.d[0] = TileDir{a.X.p, a.X.n, a.xidx, a.dnX, a.capX, a.Y.p, a.Y.n, a.dnY, a.capY, a.rowmin, a.colmin};
+  P.d[1] = TileDir{b.X.p, b.X.n, b.xidx, b.dnX, b.capX, b.Y.p, b.Y.n, b.dnY, b.capY, b.rowmin, b.colmin};
+  auto kp32 = dist_tile2<DP, COLMIN, GX, kBN>;
+  auto kp = dist_tile2<DP, COLMIN, GX, tile_bn<DP>()>;
+  const int64_t grid = b32 ? tile_grid(kp32, ia + ib) : tile_grid(kp, ia + ib);
+  if (grid < 2) {
+    const prohd_status st = one(a);
+    return st != PROHD_OK ? st : one(b);
+  }
+  int64_t g0 = grid * ia / (ia + ib);
+  if (grid >= 16) g0 = (g0 + 4) / 8 * 8;
+  P.g0 = (int32_t)std::min<int64_t>(grid - 1, std::max<int64_t>(1, g0));
+  const char* name = GX ? "hd_tile_gx" : COLMIN ? "hd_tile" : "hd_tile_rows";
+  if (b32) {
+    PROHD_LAUNCH(name, kp32, dim3((unsigned)grid), dim3(512), 0, s, P);
+  } else {
+    PROHD_LAUNCH(name, kp, dim3((unsigned)grid), dim3(512), 0, s, P);
+  }
+  return PROHD_OK;
+}
+
+template <int DP>
+prohd_status launch_tile_pair(int fmt, const TileArgs& a, const TileArgs& b, const uint32_t* maxabs,
+                              hipStream_t s) {
+  if ((a.xidx != nullptr) != (b.xidx != nullptr) || (a.colmin != nullptr) != (b.colmin != nullptr))
+    return fail(PROHD_EINVAL, "hd: a tile pair of two kinds");
+  if (a.xidx) {
+    if (a.colmin) return fail(PROHD_EINVAL, "hd: listed rows take row minima only");
+    return launch_tile_pair_k<DP, false, true>(fmt, a, b, maxabs, s);
+  }
+  if (a.colmin) return launch_tile_pair_k<DP, true, false>(fmt, a, b, maxabs, s);
+  return launch_tile_pair_k<DP, false, false>(fmt, a, b, maxabs, s);
+}
+
 // Per direction: the seed rows of the pruned search (top-kSeedRows of the
 // first level's bounds) and the list of rows the float64 pass re-measures.
 struct DirWork {
@@ -2121,15 +2237,17 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   auto seeds = [&](int64_t* const zero[2]) -> prohd_status {
     PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.top_ws, L.top_bytes, s, kSeedRows));
     BoundPair sp{};
+    TileArgs ta[2];
     for (int d = 0; d < 2; ++d) {
       // the seed rows as the inner side of a tile whose outer side is the
       // whole inner set: their minima come out as column minima
       PROHD_TRY(launch_gather_list<DP>(FMT_F32, xs[d], L.w[d].cand, L.w[d].count, kSeedRows, L.sh[d],
                                        L.dshort + 2 * d, nullptr, s));
-      PROHD_TRY(launch_tile<DP>(FMT_F32, ys[d], ydn[d], ycap[d], L.sh[d], L.dshort + 2 * d, kSeedRows,
-                                L.maxabs, nullptr, L.rowS[d], s));
+      ta[d] = TileArgs{ys[d], ydn[d], ycap[d], L.sh[d], L.dshort + 2 * d, kSeedRows, nullptr, L.rowS[d],
+                       nullptr};
       sp.d[d] = BoundJob{L.rowS[d], xs[d].n, L.w[d].cand, L.w[d].count, kSeedRows, L.hlow + d, zero[d]};
     }
+    PROHD_TRY(launch_tile_pair<DP>(FMT_F32, ta[0], ta[1], L.maxabs, s));
     return launch_bounds(sp, kSeedRows, DP, FMT_F32, L.maxabs, s);
   };
   int64_t* const zero2[2] = {L.w[0].count2, L.w[1].count2};
@@ -2165,9 +2283,13 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
       for (int j = 0; j < L.nlev; ++j)
         PROHD_TRY(launch_subset<DP>(fmt, ys[d], ydn[d], ycap[d], prune_stride(L.nlev, j), L.sub[d][j],
                                     L.dsub + d * kPruneMaxLevels + j, s));
-    for (int d = 0; d < 2; ++d)
-      PROHD_TRY(launch_tile<DP>(fmt, xs[d], dns2[d], caps2[d], L.sub[d][0], L.dsub + d * kPruneMaxLevels,
-                                cdiv(ycap[d], prune_stride(L.nlev, 0)), L.maxabs, rmin[d], nullptr, s));
+    {
+      TileArgs ta[2];
+      for (int d = 0; d < 2; ++d)
+        ta[d] = TileArgs{xs[d], dns2[d], caps2[d], L.sub[d][0], L.dsub + d * kPruneMaxLevels,
+                         cdiv(ycap[d], prune_stride(L.nlev, 0)), rmin[d], nullptr, nullptr};
+      PROHD_TRY(launch_tile_pair<DP>(fmt, ta[0], ta[1], L.maxabs, s));
+    }
     BoundPair bp{};
     for (int d = 0; d < 2; ++d)
       bp.d[d] = BoundJob{rmin[d], xs[d].n, nullptr, dns2[d], caps2[d], nullptr, nullptr};
@@ -2186,22 +2308,25 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
       const bool last = j == L.nlev;
       const FillJob fr[2] = {{L.pw[0].rowF, caps2[0], kInfBits}, {L.pw[1].rowF, caps2[1], kInfBits}};
       PROHD_TRY(fill_words(fr, 2, s));
-      for (int d = 0; d < 2; ++d) {
-        if (!last) {
-          PROHD_TRY(launch_tile<DP>(fmt, xs[d], count2[d], caps2[d], L.sub[d][j],
-                                    L.dsub + d * kPruneMaxLevels + j, cdiv(ycap[d], prune_stride(L.nlev, j)),
-                                    L.maxabs, L.pw[d].rowF, nullptr, s, cand2[d]));
-        } else {
-          // against the whole inner set: a short list as the inner side of
-          // a tile over the inner set, a long one as the outer side
+      if (!last) {
+        TileArgs ta[2];
+        for (int d = 0; d < 2; ++d)
+          ta[d] = TileArgs{xs[d], count2[d], caps2[d], L.sub[d][j], L.dsub + d * kPruneMaxLevels + j,
+                           cdiv(ycap[d], prune_stride(L.nlev, j)), L.pw[d].rowF, nullptr, cand2[d]};
+        PROHD_TRY(launch_tile_pair<DP>(fmt, ta[0], ta[1], L.maxabs, s));
+      } else {
+        // against the whole inner set: a short list as the inner side of
+        // a tile over the inner set, a long one as the outer side
+        TileArgs tc[2], tr[2];
+        for (int d = 0; d < 2; ++d) {
           int64_t* dsm = L.dshort + 2 * d;
           PROHD_TRY(launch_gather_list<DP>(fmt, xs[d], cand2[d], count2[d], kShortList, L.sh[d], dsm,
                                            dsm + 1, s));
-          PROHD_TRY(launch_tile<DP>(fmt, ys[d], ydn[d], ycap[d], L.sh[d], dsm, kShortList, L.maxabs, nullptr,
-                                    L.pw[d].rowF, s));
-          PROHD_TRY(launch_tile<DP>(fmt, xs[d], dsm + 1, caps2[d], ys[d], ydn[d], ycap[d], L.maxabs,
-                                    L.pw[d].rowF, nullptr, s, cand2[d]));
+          tc[d] = TileArgs{ys[d], ydn[d], ycap[d], L.sh[d], dsm, kShortList, nullptr, L.pw[d].rowF, nullptr};
+          tr[d] = TileArgs{xs[d], dsm + 1, caps2[d], ys[d], ydn[d], ycap[d], L.pw[d].rowF, nullptr, cand2[d]};
         }
+        PROHD_TRY(launch_tile_pair<DP>(fmt, tc[0], tc[1], L.maxabs, s));
+        PROHD_TRY(launch_tile_pair<DP>(fmt, tr[0], tr[1], L.maxabs, s));
       }
       for (int d = 0; d < 2; ++d) {
         bp.d[d] = BoundJob{L.pw[d].rowF, xs[d].n, cand2[d], count2[d], caps2[d], last ? L.hlow + d : nullptr,
