@@ -1454,36 +1454,48 @@ __global__ __launch_bounds__(256) void gather_subset(const float* __restrict__ X
 // of the tile (column minima), a long one with the listed rows as its outer
 // side; each launch sees an empty side when it is not the one.  One wave
 // per row.
+// Both directions' lists in one launch (grid y = direction).
+struct GatherJob {
+  const float* Xp;
+  const float* xn;
+  const uint8_t* Xq;
+  const float* xqn;
+  const int32_t* idx;
+  const int64_t* dcount;
+  float* Sp;
+  float* sn;
+  uint8_t* Sq;
+  float* sqn;
+  int64_t* dsmall;
+  int64_t* dbig;
+};
+struct GatherPair {
+  GatherJob j[2];
+  int32_t limit;
+};
+
 template <int DP, int FMT>
-__global__ __launch_bounds__(256) void gather_list(const float* __restrict__ Xp,
-                                                   const float* __restrict__ xn,
-                                                   const uint8_t* __restrict__ Xq,
-                                                   const float* __restrict__ xqn,
-                                                   const int32_t* __restrict__ idx,
-                                                   const int64_t* __restrict__ dcount, int limit,
-                                                   float* __restrict__ Sp, float* __restrict__ sn,
-                                                   uint8_t* __restrict__ Sq, float* __restrict__ sqn,
-                                                   int64_t* __restrict__ dsmall,
-                                                   int64_t* __restrict__ dbig) {
+__global__ __launch_bounds__(256) void gather_list(const GatherPair P) {
   constexpr int QB = FMT == FMT_F32 ? 0 : qdim(DP, FMT) * (FMT == FMT_BF16 ? 2 : 1);   // bytes per row
-  const int64_t n = *dcount;
-  const bool small = n <= limit;
+  const GatherJob J = P.j[blockIdx.y];
+  const int64_t n = *J.dcount;
+  const bool small = n <= P.limit;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *dsmall = small ? n : 0;
-    if (dbig) *dbig = small ? 0 : n;
+    *J.dsmall = small ? n : 0;
+    if (J.dbig) *J.dbig = small ? 0 : n;
   }
   if (!small) return;
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
-    const int64_t src = idx[i];
-    for (int k = lane; k < DP; k += 64) Sp[i * DP + k] = Xp[src * DP + k];
+    const int64_t src = J.idx[i];
+    for (int k = lane; k < DP; k += 64) J.Sp[i * DP + k] = J.Xp[src * DP + k];
     if constexpr (QB > 0) {
       for (int k = 4 * lane; k < QB; k += 256)
-        *reinterpret_cast<uint32_t*>(Sq + i * QB + k) = *reinterpret_cast<const uint32_t*>(Xq + src * QB + k);
+        *reinterpret_cast<uint32_t*>(J.Sq + i * QB + k) = *reinterpret_cast<const uint32_t*>(J.Xq + src * QB + k);
     }
     if (lane == 0) {
-      sn[i] = xn[src];
-      if constexpr (QB > 0) sqn[i] = xqn[src];
+      J.sn[i] = J.xn[src];
+      if constexpr (QB > 0) J.sqn[i] = J.xqn[src];
     }
   }
 }
@@ -2123,18 +2135,14 @@ prohd_status launch_subset(int fmt, PrepSet X, const int64_t* dn, int64_t cap, i
 }
 
 template <int DP>
-prohd_status launch_gather_list(int fmt, PrepSet X, const int32_t* idx, const int64_t* dcount, int limit,
-                                PrepSet S, int64_t* dsmall, int64_t* dbig, hipStream_t s) {
-  const int grid = (int)cdiv(limit, 4);
+prohd_status launch_gather_lists(int fmt, const GatherPair& P, hipStream_t s) {
+  const dim3 g((unsigned)cdiv(P.limit, 4), 2);
   if (fmt == FMT_F32) {
-    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_F32>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_F32>), g, dim3(256), 0, s, P);
   } else if (fmt == FMT_BF16) {
-    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_BF16>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_BF16>), g, dim3(256), 0, s, P);
   } else {
-    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_FP8>), dim3(grid), dim3(256), 0, s, X.p, X.n, X.q,
-                 X.qn, idx, dcount, limit, S.p, S.n, S.q, S.qn, dsmall, dbig);
+    PROHD_LAUNCH("hd_gather", (gather_list<DP, FMT_FP8>), g, dim3(256), 0, s, P);
   }
   return PROHD_OK;
 }
@@ -2238,15 +2246,18 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
     PROHD_TRY(top_rows2(mins2, caps2, dns2, L.w, L.top_ws, L.top_bytes, s, kSeedRows));
     BoundPair sp{};
     TileArgs ta[2];
+    GatherPair gp{};
+    gp.limit = kSeedRows;
     for (int d = 0; d < 2; ++d) {
       // the seed rows as the inner side of a tile whose outer side is the
       // whole inner set: their minima come out as column minima
-      PROHD_TRY(launch_gather_list<DP>(FMT_F32, xs[d], L.w[d].cand, L.w[d].count, kSeedRows, L.sh[d],
-                                       L.dshort + 2 * d, nullptr, s));
+      gp.j[d] = GatherJob{xs[d].p, xs[d].n, xs[d].q, xs[d].qn, L.w[d].cand, L.w[d].count, L.sh[d].p,
+                          L.sh[d].n, L.sh[d].q, L.sh[d].qn, L.dshort + 2 * d, nullptr};
       ta[d] = TileArgs{ys[d], ydn[d], ycap[d], L.sh[d], L.dshort + 2 * d, kSeedRows, nullptr, L.rowS[d],
                        nullptr};
       sp.d[d] = BoundJob{L.rowS[d], xs[d].n, L.w[d].cand, L.w[d].count, kSeedRows, L.hlow + d, zero[d]};
     }
+    PROHD_TRY(launch_gather_lists<DP>(FMT_F32, gp, s));
     PROHD_TRY(launch_tile_pair<DP>(FMT_F32, ta[0], ta[1], L.maxabs, s));
     return launch_bounds(sp, kSeedRows, DP, FMT_F32, L.maxabs, s);
   };
@@ -2318,13 +2329,16 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
         // against the whole inner set: a short list as the inner side of
         // a tile over the inner set, a long one as the outer side
         TileArgs tc[2], tr[2];
+        GatherPair gp{};
+        gp.limit = kShortList;
         for (int d = 0; d < 2; ++d) {
           int64_t* dsm = L.dshort + 2 * d;
-          PROHD_TRY(launch_gather_list<DP>(fmt, xs[d], cand2[d], count2[d], kShortList, L.sh[d], dsm,
-                                           dsm + 1, s));
+          gp.j[d] = GatherJob{xs[d].p, xs[d].n, xs[d].q, xs[d].qn, cand2[d], count2[d], L.sh[d].p, L.sh[d].n,
+                              L.sh[d].q, L.sh[d].qn, dsm, dsm + 1};
           tc[d] = TileArgs{ys[d], ydn[d], ycap[d], L.sh[d], dsm, kShortList, nullptr, L.pw[d].rowF, nullptr};
           tr[d] = TileArgs{xs[d], dsm + 1, caps2[d], ys[d], ydn[d], ycap[d], L.pw[d].rowF, nullptr, cand2[d]};
         }
+        PROHD_TRY(launch_gather_lists<DP>(fmt, gp, s));
         PROHD_TRY(launch_tile_pair<DP>(fmt, tc[0], tc[1], L.maxabs, s));
         PROHD_TRY(launch_tile_pair<DP>(fmt, tr[0], tr[1], L.maxabs, s));
       }
