@@ -253,9 +253,7 @@ prohd_status prohd_select(const float* projA, int64_t nA, const float* projB, in
   }
   st = select_mark(segs.data(), nseg, sel_ws, sel_bytes, s);
   if (st) return st;
-  st = compact_flags(fA, nA, nullptr, idxA, capA, nselA, cmp_ws, cmp_bytes, s);
-  if (st) return st;
-  return compact_flags(fB, nB, nullptr, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
+  return compact_flags2(fA, nA, idxA, capA, nselA, fB, nB, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
 }
 
 prohd_status prohd_top_keys(const float* vals, int64_t n, const int64_t* dev_n, int32_t k,
@@ -600,8 +598,7 @@ prohd_status prohd_select_scored(const float* scoresA, int64_t nA, int32_t sA,
       SelSegment{scoresA, nA, nullptr, 0, (int32_t)std::min<int64_t>(sA, nA), fA},
       SelSegment{scoresB, nB, nullptr, 0, (int32_t)std::min<int64_t>(sB, nB), fB}};
   st = select_mark(segs, 2, sel_ws, sel_bytes, s);
-  if (!st) st = compact_flags(fA, nA, nullptr, idxA, capA, nselA, cmp_ws, cmp_bytes, s);
-  if (!st) st = compact_flags(fB, nB, nullptr, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
+  if (!st) st = compact_flags2(fA, nA, idxA, capA, nselA, fB, nB, idxB, capB, nselB, cmp_ws, cmp_bytes, s);
   return st;
 }
 

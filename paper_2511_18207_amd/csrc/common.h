@@ -115,9 +115,10 @@ prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_b
 // Compaction of flag bytes into an ascending index list + device count;
 // at most `cap` entries are written (and counted).
 size_t compact_ws_bytes(int64_t n);
-prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n,
-                           int32_t* idx, int64_t cap, int64_t* count, void* ws, size_t ws_bytes,
-                           hipStream_t s);
+// Two arrays at once (host lengths; grid y = array).
+prohd_status compact_flags2(const uint8_t* fA, int64_t nA, int32_t* idxA, int64_t capA, int64_t* countA,
+                            const uint8_t* fB, int64_t nB, int32_t* idxB, int64_t capB, int64_t* countB,
+                            void* ws, size_t ws_bytes, hipStream_t s);
 // The k <= 64 largest keys of up to two arrays under the same order (larger
 // float value first; equal values: smaller index first), as ascending index
 // lists with a device count of min(k, length).  `keys` are float32 bit

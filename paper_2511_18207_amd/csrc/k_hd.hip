@@ -139,17 +139,30 @@ __device__ __forceinline__ void prep_body(const float* __restrict__ X, int D,
   }
 }
 
+// Both sets in one launch (grid y = set; the shift row is shared).
+struct PrepDir {
+  const float* X;
+  const int32_t* idx;
+  const int64_t* dn;
+  int64_t hn;
+  float* Xp;
+  float* xn;
+};
+struct PrepPair {
+  PrepDir j[2];
+  const float* S;
+  const int32_t* sidx;
+  const int64_t* sdn;
+  int32_t* status;
+  uint32_t* maxabs;
+  int D;
+};
+
 template <int DP>
-__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int D,
-                                                 const int32_t* __restrict__ idx,
-                                                 const int64_t* __restrict__ dn, int64_t hn,
-                                                 const float* __restrict__ S,
-                                                 const int32_t* __restrict__ sidx,
-                                                 const int64_t* __restrict__ sdn,
-                                                 float* __restrict__ Xp, float* __restrict__ xn,
-                                                 int32_t* __restrict__ status,
-                                                 uint32_t* __restrict__ maxabs) {
-  prep_body<DP>(X, D, idx, dn, hn, S, sidx, sdn, Xp, xn, status, maxabs, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void prep_rows(const PrepPair P) {
+  const PrepDir J = P.j[blockIdx.y];
+  prep_body<DP>(J.X, P.D, J.idx, J.dn, J.hn, P.S, P.sidx, P.sdn, J.Xp, J.xn, P.status, P.maxabs, blockIdx.x,
+                gridDim.x);
 }
 
 __global__ void fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -1812,12 +1825,10 @@ struct PrepSet {
 };
 
 template <int DP>
-prohd_status launch_prep(const float* X, int D, const int32_t* idx, const int64_t* dn, int64_t cap,
-                         const float* S, const int32_t* sidx, const int64_t* sdn, PrepSet o,
-                         int32_t* status, uint32_t* maxabs, hipStream_t s) {
+prohd_status launch_prep2(const PrepPair& P, hipStream_t s) {
+  const int64_t cap = std::max(P.j[0].hn, P.j[1].hn);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(cap, 4), 8 * cu_count()));
-  PROHD_LAUNCH("hd_prep", prep_rows<DP>, dim3(grid), dim3(256), 0, s, X, D, idx, dn, cap, S, sidx,
-               sdn, o.p, o.n, status, maxabs);
+  PROHD_LAUNCH("hd_prep", prep_rows<DP>, dim3(grid, 2), dim3(256), 0, s, P);
   return PROHD_OK;
 }
 
@@ -2201,11 +2212,15 @@ prohd_status run_hd(const float* A, int64_t nA, const float* B, int64_t nB, int 
   uint32_t* mx = fmt == FMT_FP8 ? L.maxabs : nullptr;
   // common shift: the first (selected) row of A
   const int32_t* sidx = idxA;
-  PROHD_TRY(launch_prep<DP>(A, D, idxA, dnA, capA, A, sidx, dnA, L.xa, L.status, mx, s));
-  PROHD_TRY(launch_prep<DP>(B, D, idxB, dnB, capB, A, sidx, dnA, L.xb, L.status, mx, s));
+  {
+    PrepPair pp{{PrepDir{A, idxA, dnA, capA, L.xa.p, L.xa.n}, PrepDir{B, idxB, dnB, capB, L.xb.p, L.xb.n}},
+                A, sidx, dnA, L.status, mx, D};
+    PROHD_TRY(launch_prep2<DP>(pp, s));
+  }
   if (full) {
-    PROHD_TRY(launch_prep<DP>(A, D, nullptr, nullptr, nA, A, sidx, dnA, L.fa, L.status, mx, s));
-    PROHD_TRY(launch_prep<DP>(B, D, nullptr, nullptr, nB, A, sidx, dnA, L.fb, L.status, mx, s));
+    PrepPair pf{{PrepDir{A, nullptr, nullptr, nA, L.fa.p, L.fa.n}, PrepDir{B, nullptr, nullptr, nB, L.fb.p, L.fb.n}},
+                A, sidx, dnA, L.status, mx, D};
+    PROHD_TRY(launch_prep2<DP>(pf, s));
   }
   if (fmt != FMT_F32) {
     PROHD_TRY(launch_quant<DP>(fmt, L.xa, dnA, capA, L.maxabs, s));

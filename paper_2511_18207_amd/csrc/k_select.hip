@@ -9,7 +9,7 @@
 // count is reached, so ties go to the smaller index at both ends.
 //
 // Kept entries set a flag byte; flags of several arrays (directions) may
-// point to one buffer, which yields their union.  compact_flags() turns the
+// point to one buffer, which yields their union.  compact_flags2() turns the
 // flags into an ascending index list with a device-side count.
 //
 // Every launch reads its array lengths from device memory when asked to, so
@@ -222,9 +222,8 @@ __global__ __launch_bounds__(kThreads) void tie_count(const SegPack P,
 }
 
 // Exclusive prefix over chunks (per segment and end), in place.
-__global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cnt, int nchunks,
-                                                      int64_t* __restrict__ total, int64_t cap) {
-  uint32_t* c = cnt + (size_t)blockIdx.x * nchunks;
+__device__ __forceinline__ void chunk_scan_body(uint32_t* __restrict__ c, int nchunks,
+                                                int64_t* __restrict__ total, int64_t cap) {
   __shared__ uint32_t part[kThreads];
   const int per = (nchunks + kThreads - 1) / kThreads;
   uint32_t s = 0;
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cn
       part[t] = acc;
       acc += x;
     }
-    if (total) total[blockIdx.x] = (int64_t)acc < cap ? (int64_t)acc : cap;
+    if (total) *total = (int64_t)acc < cap ? (int64_t)acc : cap;
   }
   __syncthreads();
   uint32_t acc = part[threadIdx.x];
@@ -253,6 +252,11 @@ __global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cn
       acc += x;
     }
   }
+}
+
+__global__ __launch_bounds__(kThreads) void chunk_scan(uint32_t* __restrict__ cnt, int nchunks,
+                                                      int64_t* __restrict__ total, int64_t cap) {
+  chunk_scan_body(cnt + (size_t)blockIdx.x * nchunks, nchunks, total ? total + blockIdx.x : nullptr, cap);
 }
 
 // Block-wide exclusive prefix of a 0/1 predicate in thread order; returns the
@@ -324,9 +328,9 @@ __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
 }
 
 // ------------------------------------------------------------- compaction
-__global__ __launch_bounds__(kThreads) void flag_count(const uint8_t* __restrict__ f, int64_t hn,
-                                                      const int64_t* __restrict__ dn,
-                                                      uint32_t* __restrict__ cnt) {
+__device__ __forceinline__ void flag_count_body(const uint8_t* __restrict__ f, int64_t hn,
+                                                const int64_t* __restrict__ dn,
+                                                uint32_t* __restrict__ cnt) {
   const int64_t n = dn ? min(*dn, hn) : hn;
   const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
   uint32_t m = 0;
@@ -339,10 +343,16 @@ __global__ __launch_bounds__(kThreads) void flag_count(const uint8_t* __restrict
   if (threadIdx.x == 0) cnt[blockIdx.x] = c;
 }
 
-__global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict__ f, int64_t hn,
+__global__ __launch_bounds__(kThreads) void flag_count(const uint8_t* __restrict__ f, int64_t hn,
                                                       const int64_t* __restrict__ dn,
-                                                      const uint32_t* __restrict__ off,
-                                                      int32_t* __restrict__ idx, int64_t cap) {
+                                                      uint32_t* __restrict__ cnt) {
+  flag_count_body(f, hn, dn, cnt);
+}
+
+__device__ __forceinline__ void flag_write_body(const uint8_t* __restrict__ f, int64_t hn,
+                                                const int64_t* __restrict__ dn,
+                                                const uint32_t* __restrict__ off,
+                                                int32_t* __restrict__ idx, int64_t cap) {
   const int64_t n = dn ? min(*dn, hn) : hn;
   const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
   if (base >= n) return;
@@ -356,6 +366,43 @@ __global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict
     if (p && (int64_t)(r + pre) < cap) idx[r + pre] = (int32_t)i;
     r += tot;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void flag_write(const uint8_t* __restrict__ f, int64_t hn,
+                                                      const int64_t* __restrict__ dn,
+                                                      const uint32_t* __restrict__ off,
+                                                      int32_t* __restrict__ idx, int64_t cap) {
+  flag_write_body(f, hn, dn, off, idx, cap);
+}
+
+// Two flag arrays compacted together (grid y = array; chunk counts of
+// array a at cnt + a * nchunks, nchunks covering the longer one).
+struct CompactDir {
+  const uint8_t* f;
+  int64_t n;
+  int32_t* idx;
+  int64_t cap;
+  int64_t* count;
+};
+struct CompactPair {
+  CompactDir d[2];
+  uint32_t* cnt;
+  int32_t nchunks;
+};
+
+__global__ __launch_bounds__(kThreads) void flag_count2(const CompactPair P) {
+  const CompactDir d = P.d[blockIdx.y];
+  flag_count_body(d.f, d.n, nullptr, P.cnt + (size_t)blockIdx.y * P.nchunks);
+}
+
+__global__ __launch_bounds__(kThreads) void chunk_scan2(const CompactPair P) {
+  const CompactDir d = P.d[blockIdx.x];
+  chunk_scan_body(P.cnt + (size_t)blockIdx.x * P.nchunks, P.nchunks, d.count, d.cap);
+}
+
+__global__ __launch_bounds__(kThreads) void flag_write2(const CompactPair P) {
+  const CompactDir d = P.d[blockIdx.y];
+  flag_write_body(d.f, d.n, nullptr, P.cnt + (size_t)blockIdx.y * P.nchunks, d.idx, d.cap);
 }
 
 // flags[idx[i]] = 1 for i < *count
@@ -862,20 +909,23 @@ prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_b
 
 size_t compact_ws_bytes(int64_t n) {
   Arena ar(nullptr);
-  ar.take<uint32_t>((size_t)std::max<int64_t>(1, cdiv(n, kMarkChunk)));
+  ar.take<uint32_t>((size_t)2 * std::max<int64_t>(1, cdiv(n, kMarkChunk)));   // room for a pair
   return ar.used + 256;
 }
 
-prohd_status compact_flags(const uint8_t* flags, int64_t n, const int64_t* dev_n, int32_t* idx,
-                           int64_t cap, int64_t* count, void* ws, size_t ws_bytes, hipStream_t s) {
-  const int nch = (int)std::max<int64_t>(1, cdiv(n, kMarkChunk));
+prohd_status compact_flags2(const uint8_t* fA, int64_t nA, int32_t* idxA, int64_t capA, int64_t* countA,
+                            const uint8_t* fB, int64_t nB, int32_t* idxB, int64_t capB, int64_t* countB,
+                            void* ws, size_t ws_bytes, hipStream_t s) {
+  CompactPair P{};
+  P.nchunks = (int)std::max<int64_t>(1, cdiv(std::max(nA, nB), kMarkChunk));
   Arena ar(ws);
-  uint32_t* cnt = ar.take<uint32_t>(nch);
+  P.cnt = ar.take<uint32_t>((size_t)2 * P.nchunks);
   if (ar.used > ws_bytes) return fail(PROHD_EWORKSPACE, "compact: workspace too small");
-  PROHD_LAUNCH("compact_count", flag_count, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt);
-  PROHD_LAUNCH("compact_scan", chunk_scan, dim3(1), dim3(kThreads), 0, s, cnt, nch, count, cap);
-  PROHD_LAUNCH("compact_write", flag_write, dim3(nch), dim3(kThreads), 0, s, flags, n, dev_n, cnt, idx,
-               cap);
+  P.d[0] = CompactDir{fA, nA, idxA, capA, countA};
+  P.d[1] = CompactDir{fB, nB, idxB, capB, countB};
+  PROHD_LAUNCH("compact_count", flag_count2, dim3(P.nchunks, 2), dim3(kThreads), 0, s, P);
+  PROHD_LAUNCH("compact_scan", chunk_scan2, dim3(2), dim3(kThreads), 0, s, P);
+  PROHD_LAUNCH("compact_write", flag_write2, dim3(P.nchunks, 2), dim3(kThreads), 0, s, P);
   return PROHD_OK;
 }
 
