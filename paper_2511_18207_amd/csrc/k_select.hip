@@ -33,7 +33,15 @@ struct EndState {
   int32_t active;   // 1 if this end selects anything
   int32_t eq;       // entries in the last located digit (after the final
                     // pass: entries equal to the k-th key)
+  int32_t buf;      // 1: after the second digit the entries sharing the
+                    // 22-bit prefix fit a buffer; the mark pass collects them
+                    // and buf_finish ranks them (no third pass)
 };
+
+// Entries of one end that share the 22-bit prefix, as (ranking key, index)
+// composites where a smaller composite ranks first: the key at the bottom
+// end, its complement at the top (equal keys then rank by index).
+constexpr int kBufCap = 1024;
 
 constexpr int kUnr = 8;   // loads in flight per thread in the streaming passes
 
@@ -65,7 +73,8 @@ __device__ __forceinline__ int64_t seg_len(const SegDev& s) {
   return s.dev_n ? min(*s.dev_n, s.n) : s.n;
 }
 
-__global__ void init_state(const SegPack P, EndState* __restrict__ st, uint32_t* __restrict__ hist) {
+__global__ void init_state(const SegPack P, EndState* __restrict__ st, uint32_t* __restrict__ hist,
+                           int32_t* __restrict__ bufn) {
   const int lid = blockIdx.x;
   if (lid >= P.nseg) return;
   const SegDev s = P.s[lid];
@@ -81,7 +90,9 @@ __global__ void init_state(const SegPack P, EndState* __restrict__ st, uint32_t*
     es.need = (int32_t)(need > 0 ? need : 0);
     es.active = need > 0 ? 1 : 0;
     es.eq = 0;
+    es.buf = 0;
     st[2 * sid + e] = es;
+    bufn[2 * sid + e] = 0;
   }
   uint32_t* h = hist + (size_t)sid * 2 * kBins;
   for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) h[i] = 0u;
@@ -100,13 +111,15 @@ __global__ __launch_bounds__(kThreads) void digit_hist(const SegPack P,
   const int64_t base = (int64_t)blockIdx.x * kHistChunk;
   if (base >= n) return;
   const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
-  if (!e0.active && !e1.active) return;
+  // buffered ends (see EndState::buf) need no further digit
+  const bool a0 = e0.active && !e0.buf, a1 = e1.active && !e1.buf;
+  if (!a0 && !a1) return;
   for (int i = threadIdx.x; i < 2 * kBins; i += kThreads) (&h[0][0])[i] = 0u;
   __syncthreads();
   const int64_t end = min(n, base + kHistChunk);
   // both ends still on the same prefix (always so in the first pass): one
   // histogram serves both
-  const bool same = e0.active && e1.active && e0.mask == e1.mask && e0.prefix == e1.prefix;
+  const bool same = a0 && a1 && e0.mask == e1.mask && e0.prefix == e1.prefix;
   for (int64_t i0 = base; i0 < end; i0 += (int64_t)kThreads * kUnr) {
     uint32_t keys[kUnr];
 #pragma unroll
@@ -116,8 +129,8 @@ __global__ __launch_bounds__(kThreads) void digit_hist(const SegPack P,
       if (i0 + u * kThreads + threadIdx.x >= end) continue;
       const uint32_t key = keys[u];
       const uint32_t d = (key >> shift) & dmask;
-      if (e0.active && (key & e0.mask) == e0.prefix) atomicAdd(&h[0][d], 1u);
-      if (!same && e1.active && (key & e1.mask) == e1.prefix) atomicAdd(&h[1][d], 1u);
+      if (a0 && (key & e0.mask) == e0.prefix) atomicAdd(&h[0][d], 1u);
+      if (!same && a1 && (key & e1.mask) == e1.prefix) atomicAdd(&h[1][d], 1u);
     }
   }
   __syncthreads();
@@ -161,7 +174,8 @@ __global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st
     }
   }
   __syncthreads();
-  if (es.active) {
+  const bool live = es.active && !es.buf;
+  if (live) {
     uint32_t acc = part[threadIdx.x];
     const uint32_t need = (uint32_t)es.need;
     for (int j = 0; j < per; ++j) {
@@ -175,11 +189,12 @@ __global__ __launch_bounds__(kThreads) void digit_scan(EndState* __restrict__ st
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && es.active) {
+  if (threadIdx.x == 0 && live) {
     es.prefix |= sel[0] << shift;
     es.mask |= dmask << shift;
     es.need -= (int32_t)sel[1];
     es.eq = (int32_t)sel[2];
+    if (shift == 10) es.buf = es.eq <= kBufCap ? 1 : 0;
     st[2 * sid + e] = es;
   }
   for (int i = threadIdx.x; i < kBins; i += kThreads) h[i] = 0u;
@@ -199,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void tie_count(const SegPack P,
   __syncthreads();
   const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
   // ends whose ties all fit (need == eq) take them without ranking: no count
-  const bool c0 = e0.active && e0.need < e0.eq, c1 = e1.active && e1.need < e1.eq;
+  const bool c0 = e0.active && !e0.buf && e0.need < e0.eq, c1 = e1.active && !e1.buf && e1.need < e1.eq;
   uint32_t m0 = 0, m1 = 0;
   const int64_t end = min(n, base + kMarkChunk);
   if (c0 || c1) {
@@ -281,7 +296,8 @@ __device__ __forceinline__ uint32_t block_excl_scan(bool p, uint32_t* wsum, uint
 __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
                                                 const EndState* __restrict__ st,
                                                 const uint32_t* __restrict__ toff,
-                                                int nchunks) {
+                                                int nchunks, int32_t* __restrict__ bufn,
+                                                unsigned long long* __restrict__ bufv) {
   const SegDev s = P.s[blockIdx.y];
   const int sid = P.base + blockIdx.y;
   const int64_t n = seg_len(s);
@@ -289,8 +305,34 @@ __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
   if (base >= n) return;
   const EndState e0 = st[2 * sid], e1 = st[2 * sid + 1];
   if (!e0.active && !e1.active) return;
-  if ((!e0.active || e0.need >= e0.eq) && (!e1.active || e1.need >= e1.eq)) {
-    // every tie fits at both ends: keep key <= k-th key (bottom) and
+  // buffered ends: keep what lies strictly beyond the 22-bit prefix, collect
+  // what shares it
+  const bool b0 = e0.active && e0.buf, b1 = e1.active && e1.buf;
+  auto buffered = [&](uint32_t key, int64_t i) {
+    bool keep = false;
+    if (b0) {
+      const uint32_t m = key & e0.mask;
+      keep |= m < e0.prefix;
+      if (m == e0.prefix) {
+        const int32_t at = atomicAdd(&bufn[2 * sid], 1);
+        if (at < kBufCap)
+          bufv[(size_t)(2 * sid) * kBufCap + at] = ((unsigned long long)key << 32) | (uint32_t)i;
+      }
+    }
+    if (b1) {
+      const uint32_t m = key & e1.mask;
+      keep |= m > e1.prefix;
+      if (m == e1.prefix) {
+        const int32_t at = atomicAdd(&bufn[2 * sid + 1], 1);
+        if (at < kBufCap)
+          bufv[(size_t)(2 * sid + 1) * kBufCap + at] = ((unsigned long long)(~key) << 32) | (uint32_t)i;
+      }
+    }
+    return keep;
+  };
+  const bool c0 = e0.active && !e0.buf, c1 = e1.active && !e1.buf;   // classic ends
+  if ((!c0 || e0.need >= e0.eq) && (!c1 || e1.need >= e1.eq)) {
+    // every tie of a classic end fits: keep key <= k-th key (bottom) and
     // key >= k-th key (top), no ranking
     const int64_t end = min(n, base + kMarkChunk);
     for (int64_t i0 = base; i0 < end; i0 += (int64_t)kThreads * kUnr) {
@@ -300,8 +342,10 @@ __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
 #pragma unroll
       for (int u = 0; u < kUnr; ++u) {
         const int64_t i = i0 + u * kThreads + threadIdx.x;
-        const bool keep = (e0.active && keys[u] <= e0.prefix) || (e1.active && keys[u] >= e1.prefix);
-        if (keep && i < end) s.flags[i] = 1;
+        if (i >= end) continue;
+        bool keep = (c0 && keys[u] <= e0.prefix) || (c1 && keys[u] >= e1.prefix);
+        if (b0 || b1) keep |= buffered(keys[u], i);
+        if (keep) s.flags[i] = 1;
       }
     }
     return;
@@ -313,17 +357,41 @@ __global__ __launch_bounds__(kThreads) void mark(const SegPack P,
     const int64_t i = base + (int64_t)it * kThreads + threadIdx.x;
     const bool in = i < n;
     const uint32_t key = in ? fkey(s.vals[i]) : 0u;
-    const bool t0 = in && e0.active && key == e0.prefix;
-    const bool t1 = in && e1.active && key == e1.prefix;
+    const bool t0 = in && c0 && key == e0.prefix;
+    const bool t1 = in && c1 && key == e1.prefix;
     uint32_t tot0, tot1;
     const uint32_t p0 = block_excl_scan(t0, wsum, &tot0);
     const uint32_t p1 = block_excl_scan(t1, wsum, &tot1);
     bool keep = false;
-    if (in && e0.active) keep |= key < e0.prefix || (t0 && r0 + p0 < (uint32_t)e0.need);
-    if (in && e1.active) keep |= key > e1.prefix || (t1 && r1 + p1 < (uint32_t)e1.need);
+    if (in && c0) keep |= key < e0.prefix || (t0 && r0 + p0 < (uint32_t)e0.need);
+    if (in && c1) keep |= key > e1.prefix || (t1 && r1 + p1 < (uint32_t)e1.need);
+    if (in && (b0 || b1)) keep |= buffered(key, i);
     if (keep) s.flags[i] = 1;
     r0 += tot0;
     r1 += tot1;
+  }
+}
+
+// The collected entries of each buffered end: an entry is kept when fewer
+// than `need` entries of its buffer rank before it (one work-group per
+// segment and end; at most kBufCap entries, ranked by counting).
+__global__ __launch_bounds__(kThreads) void buf_finish(const SegPack P, const EndState* __restrict__ st,
+                                                      const int32_t* __restrict__ bufn,
+                                                      const unsigned long long* __restrict__ bufv) {
+  const int lid = blockIdx.x >> 1, e = blockIdx.x & 1;
+  const int sid = P.base + lid;
+  const EndState es = st[2 * sid + e];
+  if (!es.active || !es.buf) return;
+  const int nb = min(bufn[2 * sid + e], kBufCap);
+  __shared__ unsigned long long v[kBufCap];
+  for (int j = threadIdx.x; j < nb; j += kThreads) v[j] = bufv[(size_t)(2 * sid + e) * kBufCap + j];
+  __syncthreads();
+  const SegDev s = P.s[lid];
+  for (int j = threadIdx.x; j < nb; j += kThreads) {
+    const unsigned long long mine = v[j];
+    int rank = 0;
+    for (int q = 0; q < nb; ++q) rank += v[q] < mine ? 1 : 0;
+    if (rank < es.need) s.flags[(uint32_t)mine] = 1;
   }
 }
 
@@ -841,6 +909,8 @@ struct SelLayout {
   EndState* st;
   uint32_t* hist;
   uint32_t* tie;
+  int32_t* bufn;                 // [nseg][2] collected entries
+  unsigned long long* bufv;      // [nseg][2][kBufCap]
   int nchunks;
 };
 
@@ -850,6 +920,8 @@ SelLayout sel_layout(Arena& ar, int nseg, int64_t max_n) {
   L.st = ar.take<EndState>(2 * nseg);
   L.hist = ar.take<uint32_t>((size_t)nseg * 2 * kBins);
   L.tie = ar.take<uint32_t>((size_t)nseg * 2 * L.nchunks);
+  L.bufn = ar.take<int32_t>(2 * nseg);
+  L.bufv = ar.take<unsigned long long>((size_t)2 * nseg * kBufCap);
   return L;
 }
 
@@ -890,7 +962,7 @@ prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_b
       P.s[i] = d;
     }
     const int ns = P.nseg;
-    PROHD_LAUNCH("select_init", init_state, dim3(ns), dim3(kThreads), 0, s, P, L.st, L.hist);
+    PROHD_LAUNCH("select_init", init_state, dim3(ns), dim3(kThreads), 0, s, P, L.st, L.hist, L.bufn);
     for (int p = 0; p < 3; ++p) {
       PROHD_LAUNCH("select_hist", digit_hist, dim3(hchunks, ns), dim3(kThreads), 0, s, P, L.st,
                    L.hist, shifts[p], masks[p]);
@@ -902,7 +974,8 @@ prohd_status select_mark(const SelSegment* segs, int nseg, void* ws, size_t ws_b
     PROHD_LAUNCH("select_tiescan", chunk_scan, dim3(2 * ns), dim3(kThreads), 0, s,
                  L.tie + (size_t)g0 * 2 * L.nchunks, L.nchunks, (int64_t*)nullptr, (int64_t)0);
     PROHD_LAUNCH("select_mark", mark, dim3(L.nchunks, ns), dim3(kThreads), 0, s, P, L.st, L.tie,
-                 L.nchunks);
+                 L.nchunks, L.bufn, L.bufv);
+    PROHD_LAUNCH("select_buf", buf_finish, dim3(2 * ns), dim3(kThreads), 0, s, P, L.st, L.bufn, L.bufv);
   }
   return PROHD_OK;
 }
