@@ -6,7 +6,9 @@
 // k-th key from each end is located (three histogram passes over 11/11/10
 // bits of an order-preserving 32-bit key), then every entry is compared with
 // it.  Entries equal to the k-th key are taken in index order until the
-// count is reached, so ties go to the smaller index at both ends.
+// count is reached, so ties go to the smaller index at both ends.  When few
+// entries share the first 22 bits with the k-th key, the third pass is
+// skipped: the compare pass collects them and a small kernel ranks them.
 //
 // Kept entries set a flag byte; flags of several arrays (directions) may
 // point to one buffer, which yields their union.  compact_flags2() turns the
