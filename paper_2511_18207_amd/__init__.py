@@ -35,6 +35,7 @@ from ._lib import (  # noqa: F401
     mlp_train_step,
     centroid,
     select_scored,
+    prohd_top_keys,
     top_keys,
     TOPK_WS_BYTES,
     BatchPlan,

@@ -537,7 +537,7 @@ def centroid(X, out=None, ws=None):
 TOPK_WS_BYTES = 512 * 1024 + 256
 
 
-def top_keys(vals, k, dev_n=None, ws=None):
+def prohd_top_keys(vals, k, dev_n=None, ws=None):
     """The k <= 64 largest entries of a 1-D float32 device tensor (equal
     values: smaller index first) through prohd_top_keys.  ``dev_n``: an
     optional device int64 tensor holding the length (clipped to the size).
@@ -552,6 +552,9 @@ def top_keys(vals, k, dev_n=None, ws=None):
     _check(lib().prohd_top_keys(vals.data_ptr(), vals.numel(), _ptr(dev_n), int(k), idx.data_ptr(),
                                 cnt.data_ptr(), buf.data_ptr(), nbytes, _stream()))
     return idx, cnt
+
+
+top_keys = prohd_top_keys
 
 
 def certificate(A, B, dirs, projA, projB, lower=None, ws=None):
