@@ -502,6 +502,7 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, size_t words, uint8_t* __r
 constexpr int kSegT = 256;
 constexpr int kSegBins = 2048;
 constexpr int kSegUnr = 8;   // loads in flight per thread in the streaming passes
+constexpr int kSegBufCap = 512;   // collected entries per end (LDS)
 
 // Exclusive prefix over the work-group (NT threads); *total gets the sum.
 template <int NT>
@@ -532,17 +533,24 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint
 template <int NT>
 __device__ __forceinline__ void select_seg_body(const SegJob& j, uint32_t (*hist)[kSegBins],
                                                 uint32_t* scan_lds, uint32_t* s_bin,
-                                                uint32_t* s_before) {
+                                                uint32_t* s_before,
+                                                unsigned long long (*sbuf)[kSegBufCap],
+                                                uint32_t* sbn) {
   const int tid = threadIdx.x;
   int64_t n = j.dn ? *j.dn : j.n;
   n = n < j.n ? (n > 0 ? n : 0) : j.n;
   const uint32_t k[2] = {(uint32_t)min<int64_t>(j.lo, n), (uint32_t)min<int64_t>(j.hi, n)};
   if (n == 0 || (k[0] == 0 && k[1] == 0)) return;
   uint32_t pre[2] = {0u, 0u}, rem[2] = {k[0], k[1]}, eq[2] = {0u, 0u};
+  // buffered end: after the second digit at most kSegBufCap entries share
+  // its 22-bit prefix; the mark pass collects them in LDS and ranks them,
+  // and the third digit is skipped
+  bool buf[2] = {false, false};
   const int shifts[3] = {21, 10, 0};
   const uint32_t masks[3] = {0x7FFu, 0x7FFu, 0x3FFu};
   const uint32_t pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
   for (int p = 0; p < 3; ++p) {
+    if (p == 2 && (!k[0] || buf[0]) && (!k[1] || buf[1])) break;   // uniform
     __syncthreads();
     for (int b = tid; b < 2 * kSegBins; b += NT) (&hist[0][0])[b] = 0u;
     __syncthreads();
@@ -558,14 +566,15 @@ __device__ __forceinline__ void select_seg_body(const SegJob& j, uint32_t (*hist
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const uint32_t ke = e ? ~keys[u] : keys[u];
-          if (k[e] && (ke & pmasks[p]) == pre[e]) atomicAdd(&hist[e][(ke >> shifts[p]) & masks[p]], 1u);
+          if (k[e] && !buf[e] && (ke & pmasks[p]) == pre[e])
+            atomicAdd(&hist[e][(ke >> shifts[p]) & masks[p]], 1u);
         }
       }
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      if (!k[e]) continue;   // uniform
+      if (!k[e] || buf[e]) continue;   // uniform
       uint32_t loc = 0;
 #pragma unroll
       for (int b = 0; b < kSegBins / NT; ++b) loc += hist[e][tid * (kSegBins / NT) + b];
@@ -587,14 +596,17 @@ __device__ __forceinline__ void select_seg_body(const SegJob& j, uint32_t (*hist
       __syncthreads();
       pre[e] |= s_bin[e] << shifts[p];
       rem[e] -= s_before[e];
-      if (p == 2) eq[e] = hist[e][s_bin[e]];
+      if (p >= 1) eq[e] = hist[e][s_bin[e]];
+      if (p == 1) buf[e] = eq[e] <= (uint32_t)kSegBufCap;
       __syncthreads();
     }
   }
   // mark: below the k-th key, and ties when all of them fit
   bool ordered[2];
 #pragma unroll
-  for (int e = 0; e < 2; ++e) ordered[e] = k[e] && rem[e] < eq[e];
+  for (int e = 0; e < 2; ++e) ordered[e] = k[e] && !buf[e] && rem[e] < eq[e];
+  if (tid < 2) sbn[tid] = 0u;
+  __syncthreads();
   for (int64_t i0 = 0; i0 < n; i0 += (int64_t)NT * kSegUnr) {
     uint32_t keys[kSegUnr];
 #pragma unroll
@@ -606,9 +618,31 @@ __device__ __forceinline__ void select_seg_body(const SegJob& j, uint32_t (*hist
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const uint32_t ke = e ? ~keys[u] : keys[u];
-        if (k[e]) f |= ke < pre[e] || (ke == pre[e] && !ordered[e]);
+        if (k[e] && !buf[e]) f |= ke < pre[e] || (ke == pre[e] && !ordered[e]);
+        if (k[e] && buf[e] && i < n) {
+          const uint32_t m = ke & 0xFFFFFC00u;
+          f |= m < pre[e];
+          if (m == pre[e]) {
+            const uint32_t at = atomicAdd(&sbn[e], 1u);
+            if (at < (uint32_t)kSegBufCap) sbuf[e][at] = ((unsigned long long)ke << 32) | (uint32_t)i;
+          }
+        }
       }
       if (f && i < n) j.flags[i] = 1;
+    }
+  }
+  // buffered ends: an entry is kept when fewer than rem entries of its
+  // buffer rank before it (composites: key, then index)
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (!k[e] || !buf[e]) continue;   // uniform
+    const uint32_t nb = min(sbn[e], (uint32_t)kSegBufCap);
+    for (uint32_t q = tid; q < nb; q += NT) {
+      const unsigned long long mine = sbuf[e][q];
+      uint32_t rank = 0;
+      for (uint32_t r = 0; r < nb; ++r) rank += sbuf[e][r] < mine ? 1u : 0u;
+      if (rank < rem[e]) j.flags[(uint32_t)mine] = 1;
     }
   }
   // ties that do not all fit: rank them in index order
@@ -636,9 +670,11 @@ __global__ __launch_bounds__(kSegT) void select_seg(const SegJob* __restrict__ j
   __shared__ uint32_t hist[2][kSegBins];
   __shared__ uint32_t scan_lds[kSegT / 64];
   __shared__ uint32_t s_bin[2], s_before[2];
+  __shared__ unsigned long long sbuf[2][kSegBufCap];
+  __shared__ uint32_t sbn[2];
   for (int it = blockIdx.x; it < njobs; it += gridDim.x) {
     const SegJob j = jobs[it];
-    select_seg_body<kSegT>(j, hist, scan_lds, s_bin, s_before);
+    select_seg_body<kSegT>(j, hist, scan_lds, s_bin, s_before, sbuf, sbn);
   }
 }
 
